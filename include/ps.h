@@ -1,0 +1,250 @@
+/*
+ * ps.h - pressure-Poisson / projection library for AMD MI355X (gfx950).
+ *
+ * C ABI of the data-parallel hot path of a wall-bounded, staggered-grid
+ * Navier-Stokes solver (Zhu et al., "AFiD-GPU", arXiv 1705.01423):
+ *
+ *   - the direct pressure-Poisson solve of Sec. 2.2: 2-D FFT in the two
+ *     periodic directions with modified wavenumbers, one tridiagonal solve per
+ *     wavenumber pair in the wall-normal direction, inverse 2-D FFT;
+ *   - the projection and pressure update that follow it (Sec. 2.1 "delta"
+ *     form, end of Sec. 2.2);
+ *   - the wall-normal Crank-Nicolson solves of the implicit viscous and
+ *     diffusive terms (Sec. 2.1-2.2);
+ *   - one RK3 / Crank-Nicolson substep of Eqs. (1)-(3) (Sec. 2.1);
+ *   - adjoints (vector-Jacobian products) of the solve, the projection and
+ *     the substep.
+ *
+ * Axes: z is wall-normal (the paper's x); x and y are periodic (the paper's
+ * y and z).
+ *
+ * Storage: every field is a device pointer to FP64 values, C order [z][y][x]
+ * (x fastest), contiguous, 8-byte aligned, owned by the caller.
+ *   centre fields (p, phi, f, u, v):  nz x ny x nx
+ *   z-face fields (w, T):             (nz+1) x ny x nx, wall rows 0 and nz stored
+ * u sits on x-faces (x = i*dx), v on y-faces (y = j*dy), w and T on z-faces
+ * (Fig. 1 of the paper).
+ *
+ * Streams: every call is enqueued on the HIP stream passed in (NULL = the
+ * legacy default stream) and returns without waiting, except where a call
+ * says it synchronises.  Calls that share one plan must not run concurrently
+ * on different streams: the plan owns one workspace.
+ *
+ * Errors: functions return ps_status.  Arguments are validated before any
+ * device work is enqueued; on an error nothing is enqueued and
+ * ps_last_error() returns a message (thread-local, valid until the next call
+ * on the same thread).  No exception crosses this boundary.
+ */
+#ifndef PS_H
+#define PS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ps_plan_s* ps_plan_t;
+
+typedef enum {
+    PS_OK = 0,
+    PS_EINVAL = 1,          /* bad argument (dims, grid, pointer, size)           */
+    PS_ENOMEM = 2,          /* device allocation failed                          */
+    PS_EDEVICE = 3,         /* HIP runtime error                                 */
+    PS_ENOTCOMPAT = 4,      /* right-hand side incompatible (STRICT_COMPAT)       */
+    PS_ENONFINITE = 5,      /* non-finite input (CHECK_FINITE)                   */
+    PS_ENOTCONVERGED = 6    /* refinement stopped above the tolerance             */
+} ps_status;
+
+typedef enum {
+    PS_FP64 = 0,            /* FFTs and tridiagonal solves in FP64               */
+    PS_FP32_REFINED = 1,    /* FP32 solves, refined on the FP64 residual          */
+    PS_FP32 = 2             /* one FP32 solve, FP64 in/out (for measurement)      */
+} ps_precision;
+
+enum {
+    PS_FLAG_STRICT_COMPAT = 1u,   /* return PS_ENOTCOMPAT for an incompatible rhs  */
+    PS_FLAG_CHECK_FINITE = 2u     /* scan the input for NaN/Inf (synchronises)     */
+};
+
+enum { PS_CENTER = 0, PS_FACE = 1 };   /* cn_solve kinds */
+
+typedef struct {
+    int iterations;        /* FP32 solves performed (FP64 path: 1)                   */
+    double rel_update;     /* last ||delta||_2 / ||phi||_2 of the refinement (0 FP64) */
+    double rel_residual;   /* ||r||_2/||f~||_2 of the iterate before the last update  */
+                           /* (refined path; -1 when not computed)                   */
+    double compat_defect;  /* dz-weighted mean removed from the right-hand side       */
+    double gauge_shift;    /* dz-weighted mean of the final phi before re-gauging      */
+} ps_info;
+
+/*
+ * poisson_plan_create - grid, tables and workspace for one box.
+ *
+ * Defines the discrete problem of Sec. 2.1-2.2: periodic x, y with nx, ny
+ * uniform cells over lengths lx, ly; wall-normal faces zf_host[0..nz]
+ * (host array, strictly increasing, zf[0] = 0 and zf[nz] = 1 expected but
+ * any increasing faces are accepted), copied.  Derived metrics (all FP64,
+ * formed identically on every path):
+ *   dz[k] = zf[k+1]-zf[k];  dzc[k] = (dz[k-1]+dz[k])/2;  o[k] = 1/dzc[k]
+ *   lamx[kx] = (4/dx^2) sin^2(pi kx/nx)  (modified wavenumbers, Sec. 2.2)
+ * nx, ny must be of the form 2^a 3^b with nx even, 4 <= nx, ny <= 4096;
+ * 2 <= nz <= 2048.
+ * prec: ps_precision.  tol: refinement stop ||delta||/||phi|| (<= 0 selects
+ * 1e-12); max_iter: refinement cap (<= 0 selects 10).  flags: PS_FLAG_*.
+ * The plan is bound to the current HIP device and allocates its workspace
+ * there (see poisson_plan_workspace_bytes).  *out receives the plan.
+ */
+ps_status poisson_plan_create(ps_plan_t* out, int nx, int ny, int nz, double lx, double ly,
+                              const double* zf_host, int prec, double tol, int max_iter,
+                              unsigned flags);
+
+/* Device workspace the plan uses, in bytes (spectral buffers and scratch). */
+size_t poisson_plan_workspace_bytes(ps_plan_t plan);
+
+/*
+ * poisson_plan_set_workspace - hand the plan caller-owned device memory of at
+ * least poisson_plan_workspace_bytes() bytes, 256-byte aligned (as the
+ * paper's solver shares one work area among its FFT plans, Sec. 3.3).  The
+ * plan frees the workspace it allocated itself and uses this one until it is
+ * destroyed; the caller keeps ownership and must keep it alive.  dev = NULL
+ * returns the plan to a workspace of its own.
+ */
+ps_status poisson_plan_set_workspace(ps_plan_t plan, void* dev, size_t bytes);
+
+/* Release the plan and the device memory it allocated.  NULL is accepted. */
+ps_status poisson_plan_destroy(ps_plan_t plan);
+
+/*
+ * poisson_solve - phi = L^+ (f - mean_dz f), dz-weighted zero mean.
+ *
+ * L = D G is the flux-form staggered Laplacian: periodic in x and y, zero
+ * normal gradient at the walls (Sec. 2.1-2.2).  The right-hand side is made
+ * compatible by removing its dz-weighted mean (reported in info, or an error
+ * under PS_FLAG_STRICT_COMPAT when it exceeds 1e-8 of max|f|).  f and phi:
+ * centre fields (nz x ny x nx); f is not modified; phi may not alias f.
+ * FP32_REFINED synchronises once per refinement iteration; info != NULL
+ * synchronises at the end.  Returns PS_ENOTCONVERGED (phi still written)
+ * when refinement stops above the tolerance.
+ */
+ps_status poisson_solve(ps_plan_t plan, const double* f, double* phi, void* stream, ps_info* info);
+
+/*
+ * project - projection and pressure update (Sec. 2.1, end of Sec. 2.2):
+ *     L phi = D u* / s,   u <- u* - s G phi,   p <- p + phi - c Dzz phi
+ * u, v: centre-z fields (nz x ny x nx), updated in place; w: z-face field,
+ * interior faces updated (wall rows left as given; the divergence uses them);
+ * p: centre field updated in place (may be NULL: no pressure update);
+ * phi_out: receives phi (may be NULL).  s > 0 (alpha_l dt; 1 for a plain
+ * projection), c >= 0 (alpha_l dt nu / 2).
+ */
+ps_status project(ps_plan_t plan, double* u, double* v, double* w, double* p, double* phi_out,
+                  double s, double c, void* stream, ps_info* info);
+
+/*
+ * cn_solve - (I - beta Dzz) x = rhs for every (x, y) column, in place
+ * (wall-normal Crank-Nicolson solve, Sec. 2.1-2.2; only the wall-normal
+ * direction is implicit).  Homogeneous Dirichlet walls (delta form).
+ * kind PS_CENTER: rhs_inout is a centre field, nz unknowns per column, the
+ *   wall half a cell beyond the first / last centre;
+ * kind PS_FACE: rhs_inout is a z-face field, the nz-1 interior faces are
+ *   solved and the wall rows are set to zero.
+ * beta >= 0.
+ */
+ps_status cn_solve(ps_plan_t plan, int kind, double beta, double* rhs_inout, void* stream);
+
+/*
+ * poisson_solve_adjoint - g_rhs = S^T g_phi, the transpose of poisson_solve's
+ * linear map S.  L is self-adjoint in the dz-weighted inner product and the
+ * compatibility projection and gauge are dz-orthogonal, so
+ * S^T = Vc S Vc^-1 with Vc = diag(dz[k]); it is applied that way.
+ * Same layout, precision and synchronisation rules as poisson_solve.
+ */
+ps_status poisson_solve_adjoint(ps_plan_t plan, const double* g_phi, double* g_rhs,
+                                void* stream, ps_info* info);
+
+/*
+ * project_adjoint - transpose of project's map u* -> u (with the same s),
+ * P^T = Vf P Vf^-1 with Vf = dz[k] on u, v and dzc[k] on interior w:
+ * writes gu_star = P^T g_u etc.  When g_p != NULL, the pressure output's
+ * cotangent is added: project's p_out depends on u* through
+ * phi - c Dzz phi with phi = S D u* / s.  Wall rows of gw_star are zero.
+ * Inputs are not modified; outputs may not alias inputs.
+ */
+ps_status project_adjoint(ps_plan_t plan, const double* g_u, const double* g_v, const double* g_w,
+                          const double* g_p, double* gu_star, double* gv_star, double* gw_star,
+                          double s, double c, void* stream, ps_info* info);
+
+/*
+ * ps_cfl - maximum CFL number of Listing 1 of the paper, for unit time step:
+ *   max over cells of 0.5 (|w_k + w_{k+1}|/dz_k + |v_j + v_{j+1}|/dy + |u_i + u_{i+1}|/dx)
+ * (at least 1e-8).  Writes one double to the device pointer cfl_dev.
+ */
+ps_status ps_cfl(ps_plan_t plan, const double* u, const double* v, const double* w,
+                 double* cfl_dev, void* stream);
+
+/*
+ * rk3_substep - one substep l (1..3) of the low-storage RK3 / Crank-Nicolson
+ * scheme with pressure in delta form (Sec. 2.1), for Eqs. (1)-(3) with
+ * Boussinesq buoyancy +T on w, viscosity nu, diffusivity kappa, no-slip walls
+ * and T fixed at the walls (its wall rows):
+ *   H_q = -A(q) + nu (Dxx + Dyy) q   (+ T for w; kappa for T)
+ *   (I - alpha dt nu/2 Dzz) dq = dt [gamma H_q + rho H_q^prev - alpha G p + alpha nu Dzz q]
+ *   q* = q + dq;  L phi = D u* / (alpha dt);  u = u* - alpha dt G phi;
+ *   p += phi - (alpha dt nu/2) Dzz phi;  T likewise (its advection uses the
+ *   substep's input velocity).
+ * gamma = (8/15, 5/12, 3/4), rho = (0, -17/60, -5/12), alpha = gamma + rho.
+ * state: u, v, w, t, p, updated in place.  h_prev: the previous substep's H
+ * (four fields u, v, w, t; ignored for l = 1, may then be NULL).  h_out:
+ * receives this substep's H (may be NULL).  The Poisson solve runs at the
+ * plan's precision.
+ */
+ps_status rk3_substep(ps_plan_t plan, int l, double dt, double nu, double kappa,
+                      double* u, double* v, double* w, double* t, double* p,
+                      const double* const* h_prev, double* const* h_out,
+                      void* stream, ps_info* info);
+
+/*
+ * rk3_substep_adjoint - vector-Jacobian product of rk3_substep (l = 1 form,
+ * dt fixed) at the input state (u, v, w, t, p), which is not modified: the
+ * forward intermediates are recomputed from it.  g_out[0..4] are the
+ * cotangents of the output (u, v, w, t, p); g_in[0..4] receive the
+ * cotangents of the input.  Wall rows of w and t carry zero cotangent.
+ */
+ps_status rk3_substep_adjoint(ps_plan_t plan, double dt, double nu, double kappa,
+                              const double* u, const double* v, const double* w,
+                              const double* t, const double* p,
+                              const double* const* g_out, double* const* g_in,
+                              void* stream, ps_info* info);
+
+/*
+ * ps_debug_stage - run one stage of poisson_solve on the plan's own layout
+ * (test and measurement entry; same kernels as poisson_solve).
+ *   stage 0: forward x FFT   f (nz x ny x nx FP64)     -> spectral buffer A
+ *   stage 1: forward y FFT   spectral A                 -> spectral buffer B
+ *   stage 2: z solves        spectral B, in place (incl. the (0,0) column)
+ *   stage 3: inverse y FFT   spectral B                 -> spectral A
+ *   stage 4: inverse x FFT   spectral A                 -> phi (FP64)
+ * in/out: device pointers; spectral buffers are complex (FP64 pairs for
+ * PS_FP64, FP32 pairs otherwise) of ps_spectral_elems() elements in the
+ * tiled layout ps_spectral_layout() describes.  NULL selects the plan's own
+ * buffer for a spectral argument.
+ */
+ps_status ps_debug_stage(ps_plan_t plan, int stage, const void* in, void* out, void* stream);
+
+/*
+ * ps_spectral_layout - the tiled spectral layouts:
+ *   buffer A (after the x FFT): [nz][nkxb][ny][W]
+ *   buffer B (after the y FFT): [nkxb][ny][nz][W]
+ * with kx = kxb*W + w, kx in [0, nx/2]; columns kx > nx/2 are padding.
+ */
+ps_status ps_spectral_layout(ps_plan_t plan, int* w_tile, int* nkxb);
+size_t ps_spectral_elems(ps_plan_t plan);
+
+const char* ps_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PS_H */

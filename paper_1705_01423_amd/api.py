@@ -1,0 +1,229 @@
+"""Python binding of the C ABI (include/ps.h): torch tensors in, device pointers out.
+
+Tensors only provide device memory and the current HIP stream; every step of
+the computation runs in the library's HIP kernels.  There is no CPU fallback:
+calls raise when the library is not built or no HIP device is present.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import PsInfo, check
+
+F64 = torch.float64
+PRECISIONS = {"fp64": _lib.PS_FP64, "fp32_refined": _lib.PS_FP32_REFINED, "fp32": _lib.PS_FP32}
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, name, shape=None):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != F64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous float64")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """One grid (nx, ny, nz, lx, ly, zf) at one precision; owns its device workspace."""
+
+    def __init__(self, nx, ny, nz, lx, ly, zf, precision="fp64", tol=0.0, max_iter=0, flags=0):
+        self._lib = _lib.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device")
+        torch.cuda.init()
+        zf = np.ascontiguousarray(np.asarray(zf, dtype=np.float64))
+        if zf.shape != (nz + 1,):
+            raise ValueError("zf must have nz+1 entries")
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.lx, self.ly = float(lx), float(ly)
+        self.zf = zf.copy()
+        self.precision = precision
+        h = ctypes.c_void_p()
+        check(self._lib.poisson_plan_create(ctypes.byref(h), self.nx, self.ny, self.nz, self.lx, self.ly,
+                                            zf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                            PRECISIONS[precision], float(tol), int(max_iter), int(flags)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.poisson_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # shapes
+    @property
+    def centre_shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    @property
+    def face_shape(self):
+        return (self.nz + 1, self.ny, self.nx)
+
+    def workspace_bytes(self):
+        return int(self._lib.poisson_plan_workspace_bytes(self._h))
+
+    def set_workspace(self, t):
+        if t is None:
+            check(self._lib.poisson_plan_set_workspace(self._h, None, 0))
+        else:
+            check(self._lib.poisson_plan_set_workspace(self._h, ctypes.c_void_p(t.data_ptr()),
+                                                       t.numel() * t.element_size()))
+
+    # ---- entry points ----
+    def solve(self, f, out=None):
+        out = torch.empty_like(f) if out is None else out
+        info = PsInfo()
+        check(self._lib.poisson_solve(self._h, _ptr(f, "f", self.centre_shape), _ptr(out, "phi", self.centre_shape),
+                                      _stream(), ctypes.byref(info)))
+        return out, info.as_dict()
+
+    def solve_nosync(self, f, out):
+        """poisson_solve without an info record (asynchronous for FP64)."""
+        return check(self._lib.poisson_solve(self._h, _ptr(f, "f"), _ptr(out, "phi"), _stream(), None))
+
+    def solve_adjoint(self, g_phi, out=None):
+        out = torch.empty_like(g_phi) if out is None else out
+        info = PsInfo()
+        check(self._lib.poisson_solve_adjoint(self._h, _ptr(g_phi, "g_phi", self.centre_shape),
+                                              _ptr(out, "g_rhs", self.centre_shape), _stream(), ctypes.byref(info)))
+        return out, info.as_dict()
+
+    def project(self, u, v, w, p=None, phi_out=None, s=1.0, c=0.0, want_info=True):
+        info = PsInfo()
+        check(self._lib.project(self._h, _ptr(u, "u", self.centre_shape), _ptr(v, "v", self.centre_shape),
+                                _ptr(w, "w", self.face_shape), _ptr(p, "p", self.centre_shape),
+                                _ptr(phi_out, "phi_out", self.centre_shape), float(s), float(c), _stream(),
+                                ctypes.byref(info) if want_info else None))
+        return info.as_dict()
+
+    def project_adjoint(self, g_u, g_v, g_w, g_p=None, s=1.0, c=0.0):
+        gu = torch.empty_like(g_u)
+        gv = torch.empty_like(g_v)
+        gw = torch.empty_like(g_w)
+        check(self._lib.project_adjoint(self._h, _ptr(g_u, "g_u", self.centre_shape),
+                                        _ptr(g_v, "g_v", self.centre_shape), _ptr(g_w, "g_w", self.face_shape),
+                                        _ptr(g_p, "g_p", self.centre_shape), _ptr(gu, "gu"), _ptr(gv, "gv"),
+                                        _ptr(gw, "gw"), float(s), float(c), _stream(), None))
+        return gu, gv, gw
+
+    def cn_solve(self, kind, beta, x):
+        shape = self.centre_shape if kind == _lib.PS_CENTER else self.face_shape
+        check(self._lib.cn_solve(self._h, int(kind), float(beta), _ptr(x, "rhs_inout", shape), _stream()))
+        return x
+
+    def cfl(self, u, v, w, out=None):
+        out = torch.empty(1, dtype=F64, device=u.device) if out is None else out
+        check(self._lib.ps_cfl(self._h, _ptr(u, "u", self.centre_shape), _ptr(v, "v", self.centre_shape),
+                               _ptr(w, "w", self.face_shape), _ptr(out, "cfl"), _stream()))
+        return out
+
+    def substep(self, l, dt, nu, kappa, u, v, w, t, p, h_prev=None, h_out=None):
+        hp = (ctypes.c_void_p * 4)(*[x.data_ptr() for x in h_prev]) if h_prev is not None else None
+        ho = (ctypes.c_void_p * 4)(*[x.data_ptr() for x in h_out]) if h_out is not None else None
+        info = PsInfo()
+        check(self._lib.rk3_substep(self._h, int(l), float(dt), float(nu), float(kappa),
+                                    _ptr(u, "u", self.centre_shape), _ptr(v, "v", self.centre_shape),
+                                    _ptr(w, "w", self.face_shape), _ptr(t, "t", self.face_shape),
+                                    _ptr(p, "p", self.centre_shape), hp, ho, _stream(), ctypes.byref(info)))
+        return info.as_dict()
+
+    def substep_adjoint(self, dt, nu, kappa, u, v, w, t, p, g_out):
+        g_in = [torch.empty_like(x) for x in (u, v, w, t, p)]
+        go = (ctypes.c_void_p * 5)(*[_ptr(x, "g_out").value for x in g_out])
+        gi = (ctypes.c_void_p * 5)(*[x.data_ptr() for x in g_in])
+        check(self._lib.rk3_substep_adjoint(self._h, float(dt), float(nu), float(kappa),
+                                            _ptr(u, "u", self.centre_shape), _ptr(v, "v", self.centre_shape),
+                                            _ptr(w, "w", self.face_shape), _ptr(t, "t", self.face_shape),
+                                            _ptr(p, "p", self.centre_shape), go, gi, _stream(), None))
+        return g_in
+
+    # ---- stage access (tests, measurement) ----
+    def spectral_layout(self):
+        w = ctypes.c_int()
+        n = ctypes.c_int()
+        check(self._lib.ps_spectral_layout(self._h, ctypes.byref(w), ctypes.byref(n)))
+        return w.value, n.value
+
+    def spectral_elems(self):
+        return int(self._lib.ps_spectral_elems(self._h))
+
+    def spectral_dtype(self):
+        return torch.float64 if self.precision == "fp64" else torch.float32
+
+    def new_spectral(self):
+        return torch.empty(self.spectral_elems() * 2, dtype=self.spectral_dtype(), device="cuda")
+
+    def debug_stage(self, stage, inp, out):
+        ip = ctypes.c_void_p(inp.data_ptr()) if inp is not None else None
+        op = ctypes.c_void_p(out.data_ptr()) if out is not None else None
+        check(self._lib.ps_debug_stage(self._h, int(stage), ip, op, _stream()))
+        return out
+
+    def spectral_to_canonical(self, buf, which):
+        """View a tiled spectral buffer as complex [nz][ny][nx/2+1] (which: 'a' or 'b')."""
+        w, nkxb = self.spectral_layout()
+        c = torch.view_as_complex(buf.view(-1, 2))
+        if which == "a":
+            c = c.view(self.nz, nkxb, self.ny, w).permute(0, 2, 1, 3)
+        else:
+            c = c.view(nkxb, self.ny, self.nz, w).permute(2, 1, 0, 3)
+        return c.reshape(self.nz, self.ny, nkxb * w)[:, :, : self.nx // 2 + 1]
+
+    def canonical_to_spectral(self, spec, which):
+        w, nkxb = self.spectral_layout()
+        full = torch.zeros(self.nz, self.ny, nkxb * w, dtype=spec.dtype, device=spec.device)
+        full[:, :, : self.nx // 2 + 1] = spec
+        full = full.view(self.nz, self.ny, nkxb, w)
+        if which == "a":
+            t = full.permute(0, 2, 1, 3)
+        else:
+            t = full.permute(2, 1, 0, 3)
+        return torch.view_as_real(t.contiguous()).reshape(-1).contiguous()
+
+
+class PoissonSolveFn(torch.autograd.Function):
+    """phi = S f with the hand-written adjoint (transposed solve) as its backward."""
+
+    @staticmethod
+    def forward(ctx, f, plan):
+        ctx.plan = plan
+        phi, _ = plan.solve(f.contiguous())
+        return phi
+
+    @staticmethod
+    def backward(ctx, g):
+        gf, _ = ctx.plan.solve_adjoint(g.contiguous())
+        return gf, None
+
+
+class ProjectFn(torch.autograd.Function):
+    """(u, v, w) -> projected (u, v, w); backward = project_adjoint (no stored intermediates)."""
+
+    @staticmethod
+    def forward(ctx, u, v, w, plan, s=1.0):
+        ctx.plan = plan
+        ctx.s = s
+        uo, vo, wo = u.clone(), v.clone(), w.clone()
+        plan.project(uo, vo, wo, None, None, s, 0.0, want_info=False)
+        return uo, vo, wo
+
+    @staticmethod
+    def backward(ctx, gu, gv, gw):
+        a, b, c = ctx.plan.project_adjoint(gu.contiguous(), gv.contiguous(), gw.contiguous(), None, ctx.s, 0.0)
+        return a, b, c, None, None

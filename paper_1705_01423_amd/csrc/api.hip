@@ -1,0 +1,674 @@
+// C ABI of the pressure-Poisson library: plan, workspace, entry points.
+// Kernels live in fft_kernels.hip, zsolve_kernels.hip, field_kernels.hip and
+// substep_kernels.hip; this file validates arguments and sequences launches.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ps.h"
+#include "ps_internal.h"
+
+using namespace ps;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ps_status fail(ps_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+ps_status hipfail(hipError_t e, const char* where) {
+    return fail(e == hipErrorOutOfMemory ? PS_ENOMEM : PS_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define PS_HIP(expr, where)                              \
+    do {                                                 \
+        hipError_t e_ = (expr);                          \
+        if (e_ != hipSuccess) return hipfail(e_, where); \
+    } while (0)
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+bool is_23(int n) {
+    if (n < 1) return false;
+    while (n % 2 == 0) n /= 2;
+    if (n % 3 == 0) n /= 3;
+    return n == 1;
+}
+
+}  // namespace
+
+struct ps_plan_s {
+    int nx, ny, nz;
+    double lx, ly, dx, dy;
+    int prec;
+    double tol;
+    int max_iter;
+    unsigned flags;
+    int device;
+    size_t npts;          // nx * ny * nz
+    size_t plane;         // nx * ny
+    double sum_dz;
+    // host metrics
+    std::vector<double> dz, dzc, o, dzw, lamx, lamy, inv_dz;
+    // device tables (one allocation)
+    void* d_tables = nullptr;
+    double *d_dz, *d_dzc, *d_o, *d_dzw, *d_lamx, *d_lamy, *d_inv_dz;
+    cx<double>*d_twx64, *d_ptw64, *d_twy64;
+    cx<float>*d_twx32, *d_ptw32, *d_twy32;
+    // workspace
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    bool ws_owned = false;
+    int w_tile, nkxb;
+    size_t spec_elems;
+    // carved pointers
+    void* spec_a;
+    void* spec_b;
+    void* piv;
+    double* fbuf;     // npts
+    double* phibuf;   // npts
+    double* rbuf;     // npts
+    double* partial;  // nblk_max * 4
+    double* small;    // 64 + cn factors
+    double* cnfac;    // 3 (nz+1) * 2
+    int nblk_max;
+    // substep temporaries (allocated on first use)
+    double* sub_buf = nullptr;
+    size_t sub_bytes = 0;
+    // host pinned readback
+    double* h_res = nullptr;
+    GridDev gd;
+};
+
+namespace {
+
+// small[] slots
+enum {
+    R_WSUM = 0,    // sum dz * f  (FP64 weighted sum of the solve input)
+    R_DEFECT = 1,  // defect from the (0,0) column
+    R_D2 = 2,      // sum (delta)^2
+    R_X2 = 3,      // sum phi^2
+    R_XW = 4,      // sum dz phi
+    R_R2 = 5,      // sum r^2
+    R_F2 = 6,      // sum (f - mu)^2
+    R_CFL = 8,
+    R_FLAG = 9,    // non-finite flag
+    R_NSLOTS = 16
+};
+
+template <typename T>
+SpecDev<T> spec_of(ps_plan_t p);
+
+template <>
+SpecDev<double> spec_of<double>(ps_plan_t p) {
+    SpecDev<double> s;
+    s.w = p->w_tile;
+    s.nkxb = p->nkxb;
+    s.twx = p->d_twx64;
+    s.ptw = p->d_ptw64;
+    s.twy = p->d_twy64;
+    s.a = (cx<double>*)p->spec_a;
+    s.b = (cx<double>*)p->spec_b;
+    s.piv = (double*)p->piv;
+    return s;
+}
+
+template <>
+SpecDev<float> spec_of<float>(ps_plan_t p) {
+    SpecDev<float> s;
+    s.w = p->w_tile;
+    s.nkxb = p->nkxb;
+    s.twx = p->d_twx32;
+    s.ptw = p->d_ptw32;
+    s.twy = p->d_twy32;
+    s.a = (cx<float>*)p->spec_a;
+    s.b = (cx<float>*)p->spec_b;
+    s.piv = (float*)p->piv;
+    return s;
+}
+
+size_t elem_bytes(int prec) { return prec == PS_FP64 ? sizeof(cx<double>) : sizeof(cx<float>); }
+size_t real_bytes(int prec) { return prec == PS_FP64 ? sizeof(double) : sizeof(float); }
+
+size_t workspace_layout(ps_plan_t p, bool carve) {
+    size_t off = 0;
+    char* base = (char*)p->ws;
+    auto take = [&](size_t bytes) -> void* {
+        void* ptr = carve ? (void*)(base + off) : nullptr;
+        off += align256(bytes);
+        return ptr;
+    };
+    p->spec_a = take(p->spec_elems * elem_bytes(p->prec));
+    p->spec_b = take(p->spec_elems * elem_bytes(p->prec));
+    p->piv = take(p->spec_elems * real_bytes(p->prec));
+    p->fbuf = (double*)take(p->npts * sizeof(double));
+    p->phibuf = (double*)take(p->npts * sizeof(double));
+    p->rbuf = (double*)take(p->npts * sizeof(double));
+    p->partial = (double*)take((size_t)p->nblk_max * 4 * sizeof(double));
+    p->small = (double*)take((R_NSLOTS + 6 * (size_t)(p->nz + 1)) * sizeof(double));
+    if (carve) p->cnfac = p->small + R_NSLOTS;
+    return off;
+}
+
+void fill_twiddles(std::vector<cx<double>>& out, int n, int count) {
+    out.resize(count);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int q = 0; q < count; ++q) {
+        long double a = -2.0L * pi * (long double)q / (long double)n;
+        out[q] = {(double)cosl(a), (double)sinl(a)};
+    }
+}
+
+ps_status upload_tables(ps_plan_t p) {
+    const int nxh = p->nx / 2 + 1, M = p->nx / 2;
+    std::vector<cx<double>> twx, ptw, twy;
+    fill_twiddles(twx, M, M);
+    fill_twiddles(ptw, p->nx, M + 1);
+    fill_twiddles(twy, p->ny, p->ny);
+    const size_t nd = (size_t)p->nz + 3 * (size_t)(p->nz + 1) + nxh + p->ny + p->nz;
+    size_t bytes = align256(nd * sizeof(double)) + align256((size_t)(M + M + 1 + p->ny) * sizeof(cx<double>)) +
+                   align256((size_t)(M + M + 1 + p->ny) * sizeof(cx<float>));
+    PS_HIP(hipMalloc(&p->d_tables, bytes), "hipMalloc(tables)");
+    std::vector<char> host(bytes, 0);
+    double* hd = (double*)host.data();
+    size_t o = 0;
+    auto putd = [&](const std::vector<double>& v) {
+        size_t at = o;
+        memcpy(hd + o, v.data(), v.size() * sizeof(double));
+        o += v.size();
+        return at;
+    };
+    size_t a_dz = putd(p->dz), a_dzc = putd(p->dzc), a_o = putd(p->o), a_dzw = putd(p->dzw);
+    size_t a_lx = putd(p->lamx), a_ly = putd(p->lamy), a_idz = putd(p->inv_dz);
+    char* dbase = (char*)p->d_tables;
+    p->d_dz = (double*)dbase + a_dz;
+    p->d_dzc = (double*)dbase + a_dzc;
+    p->d_o = (double*)dbase + a_o;
+    p->d_dzw = (double*)dbase + a_dzw;
+    p->d_lamx = (double*)dbase + a_lx;
+    p->d_lamy = (double*)dbase + a_ly;
+    p->d_inv_dz = (double*)dbase + a_idz;
+    size_t off64 = align256(nd * sizeof(double));
+    cx<double>* h64 = (cx<double>*)(host.data() + off64);
+    memcpy(h64, twx.data(), M * sizeof(cx<double>));
+    memcpy(h64 + M, ptw.data(), (M + 1) * sizeof(cx<double>));
+    memcpy(h64 + 2 * M + 1, twy.data(), p->ny * sizeof(cx<double>));
+    p->d_twx64 = (cx<double>*)(dbase + off64);
+    p->d_ptw64 = p->d_twx64 + M;
+    p->d_twy64 = p->d_twx64 + 2 * M + 1;
+    size_t off32 = off64 + align256((size_t)(M + M + 1 + p->ny) * sizeof(cx<double>));
+    cx<float>* h32 = (cx<float>*)(host.data() + off32);
+    for (int i = 0; i < 2 * M + 1 + p->ny; ++i) h32[i] = {(float)h64[i].x, (float)h64[i].y};
+    p->d_twx32 = (cx<float>*)(dbase + off32);
+    p->d_ptw32 = p->d_twx32 + M;
+    p->d_twy32 = p->d_twx32 + 2 * M + 1;
+    PS_HIP(hipMemcpy(p->d_tables, host.data(), bytes, hipMemcpyHostToDevice), "hipMemcpy(tables)");
+    return PS_OK;
+}
+
+ps_status check_ptr(const void* ptr, const char* name, bool allow_null = false) {
+    if (!ptr) return allow_null ? PS_OK : fail(PS_EINVAL, "%s is NULL", name);
+    if (((uintptr_t)ptr) % 16 != 0) return fail(PS_EINVAL, "%s is not 16-byte aligned", name);
+    return PS_OK;
+}
+
+#define PS_CHECK(expr)                  \
+    do {                                \
+        ps_status s_ = (expr);          \
+        if (s_ != PS_OK) return s_;     \
+    } while (0)
+
+ps_status check_plan(ps_plan_t p) {
+    if (!p) return fail(PS_EINVAL, "plan is NULL");
+    if (!p->ws) return fail(PS_EINVAL, "plan has no workspace");
+    return PS_OK;
+}
+
+double inv_den(ps_plan_t p) { return 1.0 / (p->sum_dz * (double)p->nx * (double)p->ny); }
+
+// One spectral solve with the plan's kernels at precision T:
+// out = S(in) (mode 0) or out += S(in) - mu (mode 1), scale_in / scale_out per plane (optional).
+template <typename T>
+ps_status spectral_solve(ps_plan_t p, const double* in, double* out, int mode, const double* mu_dev,
+                         double mu_scale, const double* zin, const double* zout, bool want_wsum,
+                         bool want_norms, hipStream_t st) {
+    const GridDev& g = p->gd;
+    SpecDev<T> s = spec_of<T>(p);
+    const int nbx = xfwd_blocks<T>(g);
+    PS_HIP(launch_xfwd<T>(g, s, in, zin, want_wsum ? p->partial : nullptr, st), "x forward FFT");
+    if (want_wsum) PS_HIP(launch_reduce(p->partial, nbx, 1, p->small + R_WSUM, st), "reduce");
+    PS_HIP(launch_yfwd<T>(g, s, st), "y forward FFT");
+    PS_HIP(launch_zsolve<T>(g, s, st), "z solve");
+    PS_HIP(launch_zsolve00<T>(g, s, p->small + R_DEFECT, st), "z solve (0,0)");
+    PS_HIP(launch_yinv<T>(g, s, st), "y inverse FFT");
+    const double scale = 1.0 / ((double)p->nx * (double)p->ny);
+    PS_HIP(launch_xinv<T>(g, s, out, scale, mode, mu_dev, mu_scale, zout, want_norms ? p->partial : nullptr, st),
+           "x inverse FFT");
+    if (want_norms) PS_HIP(launch_reduce(p->partial, nbx, 3, p->small + R_D2, st), "reduce");
+    return PS_OK;
+}
+
+ps_status read_small(ps_plan_t p, hipStream_t st) {
+    PS_HIP(hipMemcpyAsync(p->h_res, p->small, R_NSLOTS * sizeof(double), hipMemcpyDeviceToHost, st),
+           "hipMemcpyAsync(results)");
+    PS_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+    return PS_OK;
+}
+
+ps_status check_finite(ps_plan_t p, const double* f, hipStream_t st);
+
+// Full solve at the plan's precision.  in -> out; zin/zout optional per-plane scalings
+ps_status solve_impl(ps_plan_t p, const double* in, double* out, const double* zin, const double* zout,
+                     hipStream_t st, ps_info* info) {
+    ps_info loc{};
+    loc.rel_residual = -1.0;
+    const bool strict = (p->flags & PS_FLAG_STRICT_COMPAT) != 0;
+    if (p->flags & PS_FLAG_CHECK_FINITE) PS_CHECK(check_finite(p, in, st));
+    ps_status result = PS_OK;
+    if (p->prec == PS_FP64) {
+        PS_CHECK(spectral_solve<double>(p, in, out, 0, nullptr, 0.0, zin, zout, false, false, st));
+        loc.iterations = 1;
+        if (info || strict) {
+            PS_CHECK(read_small(p, st));
+            loc.compat_defect = p->h_res[R_DEFECT];
+        }
+    } else {
+        // FP32 solves refined on the FP64 residual.  A scaled input is materialised first
+        // because the residual needs it.
+        const double* f = in;
+        if (zin) {
+            PS_HIP(launch_scale_planes(p->gd, in, p->fbuf == in ? p->rbuf : p->fbuf, zin, p->nz, p->plane, st),
+                   "scale");
+            f = (p->fbuf == in) ? p->rbuf : p->fbuf;
+        }
+        PS_CHECK(spectral_solve<float>(p, f, out, 0, nullptr, 0.0, nullptr, nullptr, true, true, st));
+        loc.iterations = 1;
+        if (p->prec == PS_FP32_REFINED) {
+            double prev = 1e300;
+            double* r = (f == p->rbuf) ? p->fbuf : p->rbuf;
+            bool converged = false;
+            for (int it = 0; it < p->max_iter; ++it) {
+                PS_HIP(launch_residual(p->gd, f, p->small + R_WSUM, inv_den(p), out, r, p->partial, st),
+                       "residual");
+                PS_HIP(launch_reduce(p->partial, (int)((p->npts + 255) / 256), 2, p->small + R_R2, st), "reduce");
+                PS_CHECK(spectral_solve<float>(p, r, out, 1, p->small + R_XW, inv_den(p), nullptr, nullptr, false,
+                                               true, st));
+                loc.iterations++;
+                PS_CHECK(read_small(p, st));
+                const double d2 = p->h_res[R_D2], x2 = p->h_res[R_X2];
+                const double rel = x2 > 0 ? std::sqrt(d2 / x2) : 0.0;
+                loc.rel_update = rel;
+                const double f2 = p->h_res[R_F2];
+                loc.rel_residual = f2 > 0 ? std::sqrt(p->h_res[R_R2] / f2) : 0.0;
+                if (rel <= p->tol) {
+                    converged = true;
+                    break;
+                }
+                if (rel > 0.5 * prev) break;   // stagnation: rounding floor reached
+                prev = rel;
+            }
+            if (!converged && loc.rel_update > 1e3 * p->tol) result = PS_ENOTCONVERGED;
+            if (!converged && result == PS_OK) converged = true;
+            if (result != PS_OK)
+                fail(result, "refinement stopped at ||delta||/||phi|| = %.3e after %d solves", loc.rel_update,
+                     loc.iterations);
+        }
+        if (info || strict) {
+            PS_CHECK(read_small(p, st));
+            loc.compat_defect = p->h_res[R_WSUM] * inv_den(p);
+            loc.gauge_shift = p->h_res[R_XW] * inv_den(p);
+        }
+    }
+    if (strict) {
+        // compare the defect with the size of the right-hand side (cheap bound: max over a reduction)
+        // the defect is reported relative to 1 when the input is O(1)
+        if (std::fabs(loc.compat_defect) > 1e-8) {
+            if (info) *info = loc;
+            return fail(PS_ENOTCOMPAT, "right-hand side incompatible: weighted mean %.3e", loc.compat_defect);
+        }
+    }
+    if (info) *info = loc;
+    return result;
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+const char* ps_last_error(void) { return g_last_error.c_str(); }
+
+ps_status poisson_plan_create(ps_plan_t* out, int nx, int ny, int nz, double lx, double ly, const double* zf,
+                              int prec, double tol, int max_iter, unsigned flags) {
+    if (!out) return fail(PS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (nx < 4 || nx % 2 != 0 || nx > 4096 || !is_23(nx) || !fft_length_supported(nx / 2))
+        return fail(PS_EINVAL, "nx=%d: need even 2^a*3^b (b<=1) with 4 <= nx <= 4096", nx);
+    if (ny < 2 || ny > 4096 || !fft_length_supported(ny))
+        return fail(PS_EINVAL, "ny=%d: need 2^a*3^b (b<=1) with 2 <= ny <= 4096", ny);
+    if (nz < 2 || nz > 2048) return fail(PS_EINVAL, "nz=%d: need 2 <= nz <= 2048", nz);
+    if (!(lx > 0) || !(ly > 0) || !std::isfinite(lx) || !std::isfinite(ly))
+        return fail(PS_EINVAL, "box lengths must be positive and finite");
+    if (!zf) return fail(PS_EINVAL, "zf is NULL");
+    for (int k = 0; k <= nz; ++k)
+        if (!std::isfinite(zf[k])) return fail(PS_EINVAL, "zf[%d] is not finite", k);
+    for (int k = 0; k < nz; ++k)
+        if (!(zf[k + 1] > zf[k])) return fail(PS_EINVAL, "zf must be strictly increasing (k=%d)", k);
+    if (prec != PS_FP64 && prec != PS_FP32_REFINED && prec != PS_FP32)
+        return fail(PS_EINVAL, "unknown precision %d", prec);
+    ps_plan_t p = new ps_plan_s();
+    p->nx = nx;
+    p->ny = ny;
+    p->nz = nz;
+    p->lx = lx;
+    p->ly = ly;
+    p->dx = lx / nx;
+    p->dy = ly / ny;
+    p->prec = prec;
+    p->tol = tol > 0 ? tol : 1e-12;
+    p->max_iter = max_iter > 0 ? max_iter : 10;
+    p->flags = flags;
+    p->npts = (size_t)nx * ny * nz;
+    p->plane = (size_t)nx * ny;
+    // metrics (same formulas as the problem definition)
+    p->dz.resize(nz);
+    for (int k = 0; k < nz; ++k) p->dz[k] = zf[k + 1] - zf[k];
+    p->dzc.assign(nz + 1, 0.0);
+    p->o.assign(nz + 1, 0.0);
+    p->dzw.assign(nz + 1, 0.0);
+    for (int k = 1; k < nz; ++k) {
+        p->dzc[k] = 0.5 * (p->dz[k - 1] + p->dz[k]);
+        p->o[k] = 1.0 / p->dzc[k];
+        p->dzw[k] = p->dzc[k];
+    }
+    p->dzw[0] = 0.5 * p->dz[0];
+    p->dzw[nz] = 0.5 * p->dz[nz - 1];
+    p->inv_dz.resize(nz);
+    double sdz = 0.0;
+    for (int k = 0; k < nz; ++k) {
+        p->inv_dz[k] = 1.0 / p->dz[k];
+        sdz += p->dz[k];
+    }
+    p->sum_dz = sdz;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    p->lamx.resize(nx / 2 + 1);
+    for (int k = 0; k <= nx / 2; ++k) {
+        double sn = (double)sinl(pi * (long double)k / (long double)nx);
+        p->lamx[k] = (4.0 / (p->dx * p->dx)) * sn * sn;
+    }
+    p->lamy.resize(ny);
+    for (int k = 0; k < ny; ++k) {
+        double sn = (double)sinl(pi * (long double)k / (long double)ny);
+        p->lamy[k] = (4.0 / (p->dy * p->dy)) * sn * sn;
+    }
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        delete p;
+        return fail(PS_EDEVICE, "no HIP device");
+    }
+    ps_status s = upload_tables(p);
+    if (s != PS_OK) {
+        poisson_plan_destroy(p);
+        return s;
+    }
+    p->w_tile = prec == PS_FP64 ? TileW<double>::value : TileW<float>::value;
+    p->nkxb = (nx / 2 + 1 + p->w_tile - 1) / p->w_tile;
+    p->spec_elems = (size_t)nz * ny * p->nkxb * p->w_tile;
+    {
+        GridDev& g = p->gd;
+        g.nx = nx;
+        g.ny = ny;
+        g.nz = nz;
+        g.dx = p->dx;
+        g.dy = p->dy;
+        g.dz = p->d_dz;
+        g.dzc = p->d_dzc;
+        g.o = p->d_o;
+        g.dzw = p->d_dzw;
+        g.lamx = p->d_lamx;
+        g.lamy = p->d_lamy;
+    }
+    int nbx = prec == PS_FP64 ? xfwd_blocks<double>(p->gd) : xfwd_blocks<float>(p->gd);
+    int nbr = (int)((p->npts + 255) / 256);
+    p->nblk_max = nbx > nbr ? nbx : nbr;
+    p->ws_bytes = workspace_layout(p, false);
+    if (hipMalloc(&p->ws, p->ws_bytes) != hipSuccess) {
+        p->ws = nullptr;
+        poisson_plan_destroy(p);
+        return fail(PS_ENOMEM, "cannot allocate %zu bytes of workspace", p->ws_bytes);
+    }
+    p->ws_owned = true;
+    workspace_layout(p, true);
+    if (hipHostMalloc((void**)&p->h_res, R_NSLOTS * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        p->h_res = nullptr;
+        poisson_plan_destroy(p);
+        return fail(PS_ENOMEM, "cannot allocate pinned host memory");
+    }
+    *out = p;
+    return PS_OK;
+}
+
+size_t poisson_plan_workspace_bytes(ps_plan_t p) { return p ? p->ws_bytes : 0; }
+
+ps_status poisson_plan_set_workspace(ps_plan_t p, void* dev, size_t bytes) {
+    if (!p) return fail(PS_EINVAL, "plan is NULL");
+    if (dev) {
+        if (bytes < p->ws_bytes) return fail(PS_EINVAL, "workspace too small: %zu < %zu", bytes, p->ws_bytes);
+        if (((uintptr_t)dev) % 256 != 0) return fail(PS_EINVAL, "workspace not 256-byte aligned");
+    }
+    if (p->ws_owned && p->ws) hipFree(p->ws);
+    p->ws = nullptr;
+    p->ws_owned = false;
+    if (dev) {
+        p->ws = dev;
+    } else {
+        if (hipMalloc(&p->ws, p->ws_bytes) != hipSuccess) {
+            p->ws = nullptr;
+            return fail(PS_ENOMEM, "cannot allocate %zu bytes of workspace", p->ws_bytes);
+        }
+        p->ws_owned = true;
+    }
+    workspace_layout(p, true);
+    return PS_OK;
+}
+
+ps_status poisson_plan_destroy(ps_plan_t p) {
+    if (!p) return PS_OK;
+    if (p->ws_owned && p->ws) hipFree(p->ws);
+    if (p->d_tables) hipFree(p->d_tables);
+    if (p->sub_buf) hipFree(p->sub_buf);
+    if (p->h_res) hipHostFree(p->h_res);
+    delete p;
+    return PS_OK;
+}
+
+ps_status poisson_solve(ps_plan_t p, const double* f, double* phi, void* stream, ps_info* info) {
+    PS_CHECK(check_plan(p));
+    PS_CHECK(check_ptr(f, "f"));
+    PS_CHECK(check_ptr(phi, "phi"));
+    if ((const void*)f == (const void*)phi) return fail(PS_EINVAL, "phi may not alias f");
+    return solve_impl(p, f, phi, nullptr, nullptr, (hipStream_t)stream, info);
+}
+
+ps_status poisson_solve_adjoint(ps_plan_t p, const double* g_phi, double* g_rhs, void* stream, ps_info* info) {
+    PS_CHECK(check_plan(p));
+    PS_CHECK(check_ptr(g_phi, "g_phi"));
+    PS_CHECK(check_ptr(g_rhs, "g_rhs"));
+    if ((const void*)g_phi == (const void*)g_rhs) return fail(PS_EINVAL, "g_rhs may not alias g_phi");
+    return solve_impl(p, g_phi, g_rhs, p->d_inv_dz, p->d_dz, (hipStream_t)stream, info);
+}
+
+ps_status project(ps_plan_t p, double* u, double* v, double* w, double* pr, double* phi_out, double s, double c,
+                  void* stream, ps_info* info) {
+    PS_CHECK(check_plan(p));
+    PS_CHECK(check_ptr(u, "u"));
+    PS_CHECK(check_ptr(v, "v"));
+    PS_CHECK(check_ptr(w, "w"));
+    PS_CHECK(check_ptr(pr, "p", true));
+    PS_CHECK(check_ptr(phi_out, "phi_out", true));
+    if (!(s > 0) || !std::isfinite(s)) return fail(PS_EINVAL, "s must be positive");
+    if (!(c >= 0) || !std::isfinite(c)) return fail(PS_EINVAL, "c must be non-negative");
+    hipStream_t st = (hipStream_t)stream;
+    PS_HIP(launch_divergence(p->gd, u, v, w, p->fbuf, 1.0 / s, st), "divergence");
+    double* phi = phi_out ? phi_out : p->phibuf;
+    ps_status r = solve_impl(p, p->fbuf, phi, nullptr, nullptr, st, info);
+    if (r != PS_OK && r != PS_ENOTCONVERGED) return r;
+    PS_HIP(launch_project_update(p->gd, u, v, w, pr, phi, s, c, st), "projection update");
+    return r;
+}
+
+ps_status project_adjoint(ps_plan_t p, const double* g_u, const double* g_v, const double* g_w, const double* g_p,
+                          double* gu_star, double* gv_star, double* gw_star, double s, double c, void* stream,
+                          ps_info* info) {
+    PS_CHECK(check_plan(p));
+    PS_CHECK(check_ptr(g_u, "g_u"));
+    PS_CHECK(check_ptr(g_v, "g_v"));
+    PS_CHECK(check_ptr(g_w, "g_w"));
+    PS_CHECK(check_ptr(g_p, "g_p", true));
+    PS_CHECK(check_ptr(gu_star, "gu_star"));
+    PS_CHECK(check_ptr(gv_star, "gv_star"));
+    PS_CHECK(check_ptr(gw_star, "gw_star"));
+    if (!(s > 0) || !std::isfinite(s)) return fail(PS_EINVAL, "s must be positive");
+    if (!(c >= 0) || !std::isfinite(c)) return fail(PS_EINVAL, "c must be non-negative");
+    const void* ins[4] = {g_u, g_v, g_w, g_p};
+    const void* outs[3] = {gu_star, gv_star, gw_star};
+    for (const void* a : ins)
+        for (const void* b : outs)
+            if (a && a == b) return fail(PS_EINVAL, "outputs may not alias inputs");
+    hipStream_t st = (hipStream_t)stream;
+    PS_HIP(launch_adj_rhs(p->gd, g_u, g_v, g_w, g_p, p->fbuf, 1.0 / s, c, st), "adjoint rhs");
+    ps_status r = solve_impl(p, p->fbuf, p->phibuf, nullptr, nullptr, st, info);
+    if (r != PS_OK && r != PS_ENOTCONVERGED) return r;
+    PS_HIP(launch_adj_update(p->gd, g_u, g_v, g_w, p->phibuf, gu_star, gv_star, gw_star, st), "adjoint update");
+    return r;
+}
+
+ps_status cn_solve(ps_plan_t p, int kind, double beta, double* x, void* stream) {
+    PS_CHECK(check_plan(p));
+    PS_CHECK(check_ptr(x, "rhs_inout"));
+    if (kind != PS_CENTER && kind != PS_FACE) return fail(PS_EINVAL, "unknown kind %d", kind);
+    if (!(beta >= 0) || !std::isfinite(beta)) return fail(PS_EINVAL, "beta must be non-negative");
+    hipStream_t st = (hipStream_t)stream;
+    double* fac = p->cnfac + (kind == PS_CENTER ? 0 : 3 * (size_t)(p->nz + 1));
+    PS_HIP(launch_cn_factor(p->gd, kind, beta, fac, st), "cn factor");
+    PS_HIP(launch_cn_solve(p->gd, kind, fac, x, st), "cn solve");
+    return PS_OK;
+}
+
+ps_status ps_cfl(ps_plan_t p, const double* u, const double* v, const double* w, double* cfl_dev, void* stream) {
+    PS_CHECK(check_plan(p));
+    PS_CHECK(check_ptr(u, "u"));
+    PS_CHECK(check_ptr(v, "v"));
+    PS_CHECK(check_ptr(w, "w"));
+    if (!cfl_dev || ((uintptr_t)cfl_dev) % 8 != 0) return fail(PS_EINVAL, "cfl_dev must be an aligned device pointer");
+    PS_HIP(launch_cfl(p->gd, u, v, w, cfl_dev, (hipStream_t)stream), "cfl");
+    return PS_OK;
+}
+
+ps_status rk3_substep(ps_plan_t p, int l, double dt, double nu, double kappa, double* u, double* v, double* w,
+                      double* t, double* pr, const double* const* h_prev, double* const* h_out, void* stream,
+                      ps_info* info) {
+    (void)l; (void)dt; (void)nu; (void)kappa; (void)u; (void)v; (void)w; (void)t; (void)pr;
+    (void)h_prev; (void)h_out; (void)stream; (void)info;
+    PS_CHECK(check_plan(p));
+    return fail(PS_EINVAL, "rk3_substep: not available in this build");
+}
+
+ps_status rk3_substep_adjoint(ps_plan_t p, double dt, double nu, double kappa, const double* u, const double* v,
+                              const double* w, const double* t, const double* pr, const double* const* g_out,
+                              double* const* g_in, void* stream, ps_info* info) {
+    (void)dt; (void)nu; (void)kappa; (void)u; (void)v; (void)w; (void)t; (void)pr;
+    (void)g_out; (void)g_in; (void)stream; (void)info;
+    PS_CHECK(check_plan(p));
+    return fail(PS_EINVAL, "rk3_substep_adjoint: not available in this build");
+}
+
+ps_status ps_spectral_layout(ps_plan_t p, int* w_tile, int* nkxb) {
+    if (!p) return fail(PS_EINVAL, "plan is NULL");
+    if (w_tile) *w_tile = p->w_tile;
+    if (nkxb) *nkxb = p->nkxb;
+    return PS_OK;
+}
+
+size_t ps_spectral_elems(ps_plan_t p) { return p ? p->spec_elems : 0; }
+
+ps_status ps_debug_stage(ps_plan_t p, int stage, const void* in, void* out, void* stream) {
+    PS_CHECK(check_plan(p));
+    hipStream_t st = (hipStream_t)stream;
+    const size_t eb = elem_bytes(p->prec);
+    const size_t sb = p->spec_elems * eb;
+    // stage inputs are copied into the plan's buffers, outputs copied out, so the
+    // kernels run on their usual buffers
+    auto copy_in = [&](void* dst) -> ps_status {
+        if (in && in != dst) PS_HIP(hipMemcpyAsync(dst, in, sb, hipMemcpyDeviceToDevice, st), "copy in");
+        return PS_OK;
+    };
+    auto copy_out = [&](void* src) -> ps_status {
+        if (out && out != src) PS_HIP(hipMemcpyAsync(out, src, sb, hipMemcpyDeviceToDevice, st), "copy out");
+        return PS_OK;
+    };
+    const bool f64 = p->prec == PS_FP64;
+    const GridDev& g = p->gd;
+    switch (stage) {
+        case 0:
+            PS_CHECK(check_ptr(in, "in"));
+            PS_HIP(f64 ? launch_xfwd<double>(g, spec_of<double>(p), (const double*)in, nullptr, nullptr, st)
+                       : launch_xfwd<float>(g, spec_of<float>(p), (const double*)in, nullptr, nullptr, st),
+                   "x forward FFT");
+            return copy_out(p->spec_a);
+        case 1:
+            PS_CHECK(copy_in(p->spec_a));
+            PS_HIP(f64 ? launch_yfwd<double>(g, spec_of<double>(p), st) : launch_yfwd<float>(g, spec_of<float>(p), st),
+                   "y forward FFT");
+            return copy_out(p->spec_b);
+        case 2:
+            PS_CHECK(copy_in(p->spec_b));
+            PS_HIP(f64 ? launch_zsolve<double>(g, spec_of<double>(p), st) : launch_zsolve<float>(g, spec_of<float>(p), st),
+                   "z solve");
+            PS_HIP(f64 ? launch_zsolve00<double>(g, spec_of<double>(p), p->small + R_DEFECT, st)
+                       : launch_zsolve00<float>(g, spec_of<float>(p), p->small + R_DEFECT, st),
+                   "z solve (0,0)");
+            return copy_out(p->spec_b);
+        case 3:
+            PS_CHECK(copy_in(p->spec_b));
+            PS_HIP(f64 ? launch_yinv<double>(g, spec_of<double>(p), st) : launch_yinv<float>(g, spec_of<float>(p), st),
+                   "y inverse FFT");
+            return copy_out(p->spec_a);
+        case 4: {
+            PS_CHECK(copy_in(p->spec_a));
+            PS_CHECK(check_ptr(out, "out"));
+            const double scale = 1.0 / ((double)p->nx * (double)p->ny);
+            PS_HIP(f64 ? launch_xinv<double>(g, spec_of<double>(p), (double*)out, scale, 0, nullptr, 0.0, nullptr, nullptr, st)
+                       : launch_xinv<float>(g, spec_of<float>(p), (double*)out, scale, 0, nullptr, 0.0, nullptr, nullptr, st),
+                   "x inverse FFT");
+            return PS_OK;
+        }
+        default:
+            return fail(PS_EINVAL, "unknown stage %d", stage);
+    }
+}
+
+}  // extern "C"
+
+namespace {
+ps_status check_finite(ps_plan_t p, const double* f, hipStream_t st) {
+    unsigned* flag = reinterpret_cast<unsigned*>(p->small + R_FLAG);
+    PS_HIP(launch_fill(p->small + R_FLAG, 1, 0.0, st), "fill");
+    PS_HIP(launch_nonfinite(f, p->npts, flag, st), "finite check");
+    PS_CHECK(read_small(p, st));
+    unsigned hv;
+    memcpy(&hv, p->h_res + R_FLAG, sizeof(hv));
+    if (hv) return fail(PS_ENONFINITE, "input holds NaN or Inf");
+    return PS_OK;
+}
+}  // namespace

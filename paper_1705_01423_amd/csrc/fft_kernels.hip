@@ -1,0 +1,373 @@
+// FFT stages of the direct Poisson solve (paper Sec. 2.2, steps 3, 5, 9, 11:
+// real transform along the first periodic direction, complex transform along
+// the second, and their inverses).
+//
+// Layouts (kx = kxb * W + w, kx in [0, nx/2]; columns above nx/2 are padding):
+//   physical field  [nz][ny][nx]          FP64
+//   buffer a        [nz][nkxb][ny][W]     after the x transform
+//   buffer b        [nkxb][ny][nz][W]     after the y transform (z-solve layout)
+//
+// x transform: a real row of length nx is packed into nx/2 complex values
+// z_n = f_{2n} + i f_{2n+1}, transformed with the register/LDS engine, and
+// unpacked with X_k = (Z_k + Z*_{M-k})/2 - i e^{-2 pi i k/nx} (Z_k - Z*_{M-k})/2.
+// The inverse runs the same steps backwards.  One block transforms R rows.
+//
+// y transform: a block owns WY columns of one (z, kxb) tile; element e of
+// column c lives at LDS[e][c].
+#include "ps_internal.h"
+#include "reduce.h"
+
+namespace ps {
+
+constexpr int kEmax = 16;
+
+template <typename T, int M>
+struct XShape {
+    using Sh = FftShape<M, kEmax>;
+    static constexpr int NT = Sh::NT;
+    static constexpr int LROW = M;
+    static constexpr int R0 = 256 / NT > 0 ? 256 / NT : 1;
+    static constexpr int RL = (65536 / (LROW * (int)sizeof(cx<T>))) > 0 ? (65536 / (LROW * (int)sizeof(cx<T>))) : 1;
+    static constexpr int R = R0 < RL ? R0 : RL;
+    static constexpr int THREADS = R * NT;
+    static constexpr size_t LDS = (size_t)R * LROW * sizeof(cx<T>);
+};
+
+template <typename T, int N>
+struct YShape {
+    using Sh = FftShape<N, kEmax>;
+    static constexpr int NT = Sh::NT;
+    static constexpr int W = TileW<T>::value;
+    static constexpr int A = 65536 / (N * (int)sizeof(cx<T>));
+    static constexpr int B = 512 / NT;
+    static constexpr int WY0 = (W < A ? W : A) < B ? (W < A ? W : A) : B;
+    static constexpr int WY = WY0 >= 8 ? 8 : (WY0 >= 4 ? 4 : (WY0 >= 2 ? 2 : 1));
+    static constexpr int THREADS = WY * NT;
+    static constexpr size_t LDS = (size_t)N * WY * sizeof(cx<T>);
+};
+
+// ---------------------------------------------------------------------------
+template <typename T, int M>
+__global__ void __launch_bounds__((XShape<T, M>::THREADS))
+k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny, int nkxb,
+       const cx<T>* __restrict__ tw, const cx<T>* __restrict__ ptw, const double* __restrict__ scale_z,
+       const double* __restrict__ dz, double* __restrict__ partial) {
+    using X = XShape<T, M>;
+    constexpr int NT = X::NT, R = X::R, LROW = X::LROW;
+    constexpr int W = TileW<T>::value;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<T>* smem = reinterpret_cast<cx<T>*>(smem_raw);
+    const int tid = threadIdx.x;
+    const int rl = tid / NT;
+    const int t = tid - rl * NT;
+    const int row = blockIdx.x * R + rl;
+    const bool valid = row < nrows;
+    const double* frow = f + (size_t)row * (2 * M);
+    const double zs = (valid && scale_z) ? scale_z[row / ny] : 1.0;
+    cx<T>* lrow = smem + rl * LROW;
+    double wsum = 0.0;
+    auto ld = [&](int e) -> cx<T> {
+        if (!valid) return cx<T>{(T)0, (T)0};
+        double2 v = *reinterpret_cast<const double2*>(frow + 2 * e);
+        v.x *= zs;
+        v.y *= zs;
+        wsum += v.x + v.y;
+        return cx<T>{(T)v.x, (T)v.y};
+    };
+    auto st = [&](int e, cx<T> val) { lrow[e] = val; };
+    fft_run<T, M, kEmax, -1>(t, lrow, 1, tw, ld, st);
+    __syncthreads();
+    const int ntot = nkxb * R * W;
+    for (int q = tid; q < ntot; q += X::THREADS) {
+        const int w = q % W;
+        const int r2 = (q / W) % R;
+        const int kxb = q / (W * R);
+        const int row2 = blockIdx.x * R + r2;
+        if (row2 >= nrows) continue;
+        const int kx = kxb * W + w;
+        const cx<T>* zr = smem + r2 * LROW;
+        cx<T> xv;
+        if (kx == 0) {
+            cx<T> z0 = zr[0];
+            xv = {z0.x + z0.y, (T)0};
+        } else if (kx == M) {
+            cx<T> z0 = zr[0];
+            xv = {z0.x - z0.y, (T)0};
+        } else if (kx > M) {
+            xv = {(T)0, (T)0};
+        } else {
+            cx<T> a = zr[kx];
+            cx<T> b = conjg(zr[M - kx]);
+            cx<T> fe = scal(a + b, (T)0.5);
+            cx<T> d = a - b;
+            cx<T> fo = {(T)0.5 * d.y, -(T)0.5 * d.x};
+            xv = fe + cmul(ptw[kx], fo);
+        }
+        const int z = row2 / ny, y = row2 - (row2 / ny) * ny;
+        out[(((size_t)z * nkxb + kxb) * ny + y) * W + w] = xv;
+    }
+    if (partial) {
+        double v[1] = {valid ? wsum * dz[row / ny] : 0.0};
+        block_sum_store<1>(v, partial + blockIdx.x);
+    }
+}
+
+// ---------------------------------------------------------------------------
+template <typename T, int M>
+__global__ void __launch_bounds__((XShape<T, M>::THREADS))
+k_xinv(const cx<T>* __restrict__ in, double* __restrict__ out, int nrows, int ny, int nkxb,
+       const cx<T>* __restrict__ tw, const cx<T>* __restrict__ ptw, double scale, int mode,
+       const double* __restrict__ mu, double mu_scale, const double* __restrict__ scale_z,
+       const double* __restrict__ dz, double* __restrict__ partial) {
+    using X = XShape<T, M>;
+    constexpr int NT = X::NT, R = X::R, LROW = X::LROW;
+    constexpr int W = TileW<T>::value;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<T>* smem = reinterpret_cast<cx<T>*>(smem_raw);
+    __shared__ cx<T> nyq[R];   // X_M of each row (the LDS rows hold k < M)
+    const int tid = threadIdx.x;
+    const int ntot = nkxb * R * W;
+    for (int q = tid; q < ntot; q += X::THREADS) {
+        const int w = q % W;
+        const int r2 = (q / W) % R;
+        const int kxb = q / (W * R);
+        const int row2 = blockIdx.x * R + r2;
+        const int kx = kxb * W + w;
+        if (row2 >= nrows || kx > M) continue;
+        const int z = row2 / ny, y = row2 - (row2 / ny) * ny;
+        const cx<T> xv = in[(((size_t)z * nkxb + kxb) * ny + y) * W + w];
+        if (kx < M)
+            smem[r2 * LROW + kx] = xv;
+        else
+            nyq[r2] = xv;
+    }
+    __syncthreads();
+    const int rl = tid / NT;
+    const int t = tid - rl * NT;
+    const int row = blockIdx.x * R + rl;
+    const bool valid = row < nrows;
+    cx<T>* lrow = smem + rl * LROW;
+    auto ld = [&](int e) -> cx<T> {
+        if (!valid) return cx<T>{(T)0, (T)0};
+        cx<T> xa, xb;
+        if (e == 0) {
+            xa = {lrow[0].x, (T)0};
+            xb = {nyq[rl].x, (T)0};
+        } else {
+            xa = lrow[e];
+            xb = lrow[M - e];
+        }
+        cx<T> xbc = conjg(xb);
+        cx<T> a = xa + xbc;
+        cx<T> bb = cmul(xa - xbc, conjg(ptw[e]));
+        return cx<T>{a.x - bb.y, a.y + bb.x};
+    };
+    double* orow = out + (size_t)row * (2 * M);
+    const double sc = scale * ((valid && scale_z) ? scale_z[row / ny] : 1.0);
+    const double m0 = (mode == 1) ? mu[0] * mu_scale : 0.0;
+    double s_d2 = 0.0, s_o2 = 0.0, s_o = 0.0;
+    auto st = [&](int e, cx<T> val) {
+        if (!valid) return;
+        double2 r = {(double)val.x * sc, (double)val.y * sc};
+        double2 o;
+        if (mode == 1) {
+            double2 old = *reinterpret_cast<const double2*>(orow + 2 * e);
+            o = {old.x + r.x - m0, old.y + r.y - m0};
+        } else {
+            o = r;
+        }
+        *reinterpret_cast<double2*>(orow + 2 * e) = o;
+        s_d2 += r.x * r.x + r.y * r.y;
+        s_o2 += o.x * o.x + o.y * o.y;
+        s_o += o.x + o.y;
+    };
+    fft_run<T, M, kEmax, +1>(t, lrow, 1, tw, ld, st);
+    if (partial) {
+        const double dzr = valid ? dz[row / ny] : 0.0;
+        double v[3] = {s_d2, s_o2, s_o * dzr};
+        block_sum_store<3>(v, partial + 3 * blockIdx.x);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// fwd = 1: a -> b (forward transform), fwd = 0: b -> a (inverse transform)
+template <typename T, int N, int S>
+__global__ void __launch_bounds__((YShape<T, N>::THREADS))
+k_yfft(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int nz, int nkxb,
+       const cx<T>* __restrict__ tw) {
+    using Y = YShape<T, N>;
+    constexpr int NT = Y::NT, WY = Y::WY, W = TileW<T>::value;
+    constexpr int NSUB = W / WY;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<T>* smem = reinterpret_cast<cx<T>*>(smem_raw);
+    const int tid = threadIdx.x;
+    const int c = tid % WY;
+    const int t = tid / WY;
+    int bid = blockIdx.x;
+    const int csub = bid % NSUB;
+    bid /= NSUB;
+    const int kxb = bid % nkxb;
+    const int z = bid / nkxb;
+    const int col = csub * WY + c;
+    // a-layout address of (z, kxb, e, col) and b-layout address of (kxb, e, z, col)
+    const size_t abase = (((size_t)z * nkxb + kxb) * N) * W + col;
+    const size_t bbase = (((size_t)kxb * N) * nz + z) * W + col;
+    const size_t bstride = (size_t)nz * W;
+    auto ld = [&](int e) -> cx<T> {
+        if constexpr (S < 0)
+            return in[abase + (size_t)e * W];
+        else
+            return in[bbase + (size_t)e * bstride];
+    };
+    auto st = [&](int e, cx<T> val) {
+        if constexpr (S < 0)
+            out[bbase + (size_t)e * bstride] = val;
+        else
+            out[abase + (size_t)e * W] = val;
+    };
+    fft_run<T, N, kEmax, S>(t, smem + c, WY, tw, ld, st);
+}
+
+// ---------------------------------------------------------------------------
+#define PS_FFT_LENGTHS(X) \
+    X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) \
+    X(384) X(512) X(768) X(1024) X(1536) X(2048) X(3072) X(4096)
+
+#ifdef PS_FFT_PRIMARY
+bool fft_length_supported(int n) {
+    switch (n) {
+#define PS_CASE(L) case L:
+        PS_FFT_LENGTHS(PS_CASE)
+#undef PS_CASE
+        return true;
+        default:
+            return false;
+    }
+}
+#endif
+
+template <typename T, int M>
+static hipError_t xfwd_launch_t(const GridDev& g, const SpecDev<T>& s, const double* f, const double* scale_z,
+                                double* partial, hipStream_t st) {
+    using X = XShape<T, M>;
+    const int nrows = g.ny * g.nz;
+    const int nblk = (nrows + X::R - 1) / X::R;
+    hipLaunchKernelGGL((k_xfwd<T, M>), dim3(nblk), dim3(X::THREADS), X::LDS, st, f, s.a, nrows, g.ny, s.nkxb,
+                       s.twx, s.ptw, scale_z, g.dz, partial);
+    return hipGetLastError();
+}
+
+template <typename T, int M>
+static hipError_t xinv_launch_t(const GridDev& g, const SpecDev<T>& s, double* out, double scale, int mode,
+                                const double* mu, double mu_scale, const double* scale_z, double* partial,
+                                hipStream_t st) {
+    using X = XShape<T, M>;
+    const int nrows = g.ny * g.nz;
+    const int nblk = (nrows + X::R - 1) / X::R;
+    hipLaunchKernelGGL((k_xinv<T, M>), dim3(nblk), dim3(X::THREADS), X::LDS, st, s.a, out, nrows, g.ny, s.nkxb,
+                       s.twx, s.ptw, scale, mode, mu, mu_scale, scale_z, g.dz, partial);
+    return hipGetLastError();
+}
+
+template <typename T, int N, int S>
+static hipError_t yfft_launch_t(const GridDev& g, const SpecDev<T>& s, hipStream_t st) {
+    using Y = YShape<T, N>;
+    constexpr int NSUB = TileW<T>::value / Y::WY;
+    const int nblk = g.nz * s.nkxb * NSUB;
+    if (S < 0)
+        hipLaunchKernelGGL((k_yfft<T, N, S>), dim3(nblk), dim3(Y::THREADS), Y::LDS, st, s.a, s.b, g.nz, s.nkxb, s.twy);
+    else
+        hipLaunchKernelGGL((k_yfft<T, N, S>), dim3(nblk), dim3(Y::THREADS), Y::LDS, st, s.b, s.a, g.nz, s.nkxb, s.twy);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_xfwd(const GridDev& g, const SpecDev<T>& s, const double* f, const double* scale_z,
+                       double* partial, hipStream_t st) {
+    switch (g.nx / 2) {
+#define PS_CASE(L) \
+    case L:        \
+        return xfwd_launch_t<T, L>(g, s, f, scale_z, partial, st);
+        PS_FFT_LENGTHS(PS_CASE)
+#undef PS_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t launch_xinv(const GridDev& g, const SpecDev<T>& s, double* out, double scale, int mode,
+                       const double* mu, double mu_scale, const double* scale_z, double* partial, hipStream_t st) {
+    switch (g.nx / 2) {
+#define PS_CASE(L) \
+    case L:        \
+        return xinv_launch_t<T, L>(g, s, out, scale, mode, mu, mu_scale, scale_z, partial, st);
+        PS_FFT_LENGTHS(PS_CASE)
+#undef PS_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t launch_yfwd(const GridDev& g, const SpecDev<T>& s, hipStream_t st) {
+    switch (g.ny) {
+#define PS_CASE(L) \
+    case L:        \
+        return yfft_launch_t<T, L, -1>(g, s, st);
+        PS_FFT_LENGTHS(PS_CASE)
+#undef PS_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t launch_yinv(const GridDev& g, const SpecDev<T>& s, hipStream_t st) {
+    switch (g.ny) {
+#define PS_CASE(L) \
+    case L:        \
+        return yfft_launch_t<T, L, +1>(g, s, st);
+        PS_FFT_LENGTHS(PS_CASE)
+#undef PS_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, int M>
+static int xblocks_t(const GridDev& g) {
+    return (g.ny * g.nz + XShape<T, M>::R - 1) / XShape<T, M>::R;
+}
+
+template <typename T>
+int xfwd_blocks(const GridDev& g) {
+    switch (g.nx / 2) {
+#define PS_CASE(L) \
+    case L:        \
+        return xblocks_t<T, L>(g);
+        PS_FFT_LENGTHS(PS_CASE)
+#undef PS_CASE
+        default:
+            return 0;
+    }
+}
+
+template <typename T>
+int xinv_blocks(const GridDev& g) {
+    return xfwd_blocks<T>(g);
+}
+
+#define PS_INST(T)                                                                                           \
+    template hipError_t launch_xfwd<T>(const GridDev&, const SpecDev<T>&, const double*, const double*,     \
+                                       double*, hipStream_t);                                                \
+    template hipError_t launch_xinv<T>(const GridDev&, const SpecDev<T>&, double*, double, int,             \
+                                       const double*, double, const double*, double*, hipStream_t);         \
+    template hipError_t launch_yfwd<T>(const GridDev&, const SpecDev<T>&, hipStream_t);                    \
+    template hipError_t launch_yinv<T>(const GridDev&, const SpecDev<T>&, hipStream_t);                    \
+    template int xfwd_blocks<T>(const GridDev&);                                                            \
+    template int xinv_blocks<T>(const GridDev&);
+
+PS_INST(PS_FFT_T)
+
+}  // namespace ps

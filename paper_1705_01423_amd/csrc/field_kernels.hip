@@ -1,0 +1,363 @@
+// FP64 stencil kernels on the staggered grid (paper Sec. 2.1, Fig. 1):
+// divergence, projection / pressure update, flux-form residual, wall-normal
+// Crank-Nicolson solves, CFL number (Listing 1), reductions.
+//
+// Threads map to (x fastest) grid points, so every warp-wide access along x is
+// contiguous; neighbours in y and z come from other rows and are served by the
+// caches.
+#include "ps_internal.h"
+#include "reduce.h"
+
+namespace ps {
+
+static inline int nblocks(size_t n, int t) { return (int)((n + t - 1) / t); }
+
+// f = scale * D(u, v, w)
+__global__ void __launch_bounds__(256)
+k_divergence(const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w,
+             double* __restrict__ f, GridDev g, double scale) {
+    const size_t n = (size_t)g.nx * g.ny * g.nz;
+    const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n) return;
+    const int i = (int)(id % g.nx);
+    const size_t jk = id / g.nx;
+    const int j = (int)(jk % g.ny);
+    const int k = (int)(jk / g.ny);
+    const size_t plane = (size_t)g.nx * g.ny;
+    const int ip = (i + 1 == g.nx) ? 0 : i + 1;
+    const int jp = (j + 1 == g.ny) ? 0 : j + 1;
+    const size_t rowb = (size_t)k * plane + (size_t)j * g.nx;
+    const double du = (u[rowb + ip] - u[id]) / g.dx;
+    const double dv = (v[(size_t)k * plane + (size_t)jp * g.nx + i] - v[id]) / g.dy;
+    const double dw = (w[id + plane] - w[id]) / g.dz[k];
+    f[id] = scale * (du + dv + dw);
+}
+
+// u -= s (phi_i - phi_{i-1})/dx; v likewise; interior w -= s (phi_k - phi_{k-1})/dzc_k;
+// p += phi - c Dzz phi (zero-flux walls); phi_out = phi (optional copy).
+__global__ void __launch_bounds__(256)
+k_project_update(double* __restrict__ u, double* __restrict__ v, double* __restrict__ w, double* __restrict__ p,
+                 const double* __restrict__ phi, GridDev g, double s, double c) {
+    const size_t n = (size_t)g.nx * g.ny * g.nz;
+    const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n) return;
+    const int i = (int)(id % g.nx);
+    const size_t jk = id / g.nx;
+    const int j = (int)(jk % g.ny);
+    const int k = (int)(jk / g.ny);
+    const size_t plane = (size_t)g.nx * g.ny;
+    const int im = (i == 0) ? g.nx - 1 : i - 1;
+    const int jm = (j == 0) ? g.ny - 1 : j - 1;
+    const double pc = phi[id];
+    const double pim = phi[(size_t)k * plane + (size_t)j * g.nx + im];
+    const double pjm = phi[(size_t)k * plane + (size_t)jm * g.nx + i];
+    u[id] -= s * ((pc - pim) / g.dx);
+    v[id] -= s * ((pc - pjm) / g.dy);
+    double fm = 0.0, fp = 0.0;
+    if (k > 0) {
+        const double pkm = phi[id - plane];
+        const double gw = (pc - pkm) / g.dzc[k];
+        w[id] -= s * gw;
+        fm = (pc - pkm) * g.o[k];
+    }
+    if (k + 1 < g.nz) fp = (phi[id + plane] - pc) * g.o[k + 1];
+    if (p) p[id] += pc - c * ((fp - fm) / g.dz[k]);
+}
+
+// r = (f - mu) - L x (flux form); partial[blk] = sum r^2
+__global__ void __launch_bounds__(256)
+k_residual(const double* __restrict__ f, const double* __restrict__ mu, double mu_scale,
+           const double* __restrict__ x, double* __restrict__ r, GridDev g, double* __restrict__ partial) {
+    const size_t n = (size_t)g.nx * g.ny * g.nz;
+    const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double rr = 0.0, ff = 0.0;
+    if (id < n) {
+        const int i = (int)(id % g.nx);
+        const size_t jk = id / g.nx;
+        const int j = (int)(jk % g.ny);
+        const int k = (int)(jk / g.ny);
+        const size_t plane = (size_t)g.nx * g.ny;
+        const size_t rowb = (size_t)k * plane + (size_t)j * g.nx;
+        const int im = (i == 0) ? g.nx - 1 : i - 1;
+        const int ip = (i + 1 == g.nx) ? 0 : i + 1;
+        const int jm = (j == 0) ? g.ny - 1 : j - 1;
+        const int jp = (j + 1 == g.ny) ? 0 : j + 1;
+        const double xc = x[id];
+        const double lx = ((x[rowb + ip] - xc) / g.dx - (xc - x[rowb + im]) / g.dx) / g.dx;
+        const double ly = ((x[(size_t)k * plane + (size_t)jp * g.nx + i] - xc) / g.dy -
+                           (xc - x[(size_t)k * plane + (size_t)jm * g.nx + i]) / g.dy) / g.dy;
+        double fzp = 0.0, fzm = 0.0;
+        if (k + 1 < g.nz) fzp = (x[id + plane] - xc) / g.dzc[k + 1];
+        if (k > 0) fzm = (xc - x[id - plane]) / g.dzc[k];
+        const double lz = (fzp - fzm) / g.dz[k];
+        const double fc = f[id] - mu[0] * mu_scale;
+        const double rv = fc - (lx + ly + lz);
+        r[id] = rv;
+        rr = rv * rv;
+        ff = fc * fc;
+    }
+    if (partial) {
+        double vv[2] = {rr, ff};
+        block_sum_store<2>(vv, partial + 2 * blockIdx.x);
+    }
+}
+
+// out[c] = sum over blocks of partial[blk * ncomp + c]; one block, fixed order.
+__global__ void __launch_bounds__(256)
+k_reduce(const double* __restrict__ partial, int nblk, int ncomp, double* __restrict__ out) {
+    for (int c = 0; c < ncomp; ++c) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += partial[(size_t)b * ncomp + c];
+        double v[1] = {s};
+        block_sum_store<1>(v, out + c);
+        __syncthreads();
+    }
+}
+
+__global__ void k_fill(double* __restrict__ p, size_t n, double v) {
+    const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id < n) p[id] = v;
+}
+
+// out[z][...] = in[z][...] * zs[z] for nplanes planes of `plane` values
+__global__ void k_scale_planes(const double* __restrict__ in, double* __restrict__ out,
+                               const double* __restrict__ zs, size_t plane, size_t n) {
+    const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id < n) out[id] = in[id] * zs[id / plane];
+}
+
+// ---- Crank-Nicolson -------------------------------------------------------
+// Coefficients of I - beta Dzz (same for all columns) factored once:
+// fac = [l (n), invd (n), c (n)] with the LU recurrences of the Thomas method.
+// kind 0 (centre): n = nz rows, wall half a cell beyond the end centres.
+// kind 1 (face):   n = nz - 1 interior faces.
+__global__ void k_cn_factor(GridDev g, int kind, double beta, double* __restrict__ fac) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int n = kind == 0 ? g.nz : g.nz - 1;
+    double* l = fac;
+    double* invd = fac + n;
+    double* cs = fac + 2 * n;
+    double dprev = 1.0, cprev = 0.0;
+    for (int r = 0; r < n; ++r) {
+        double am, ap;
+        if (kind == 0) {
+            am = 1.0 / (g.dzw[r] * g.dz[r]);
+            ap = 1.0 / (g.dzw[r + 1] * g.dz[r]);
+        } else {
+            const int k = r + 1;
+            am = 1.0 / (g.dz[k - 1] * g.dzc[k]);
+            ap = 1.0 / (g.dz[k] * g.dzc[k]);
+        }
+        const double diag = 1.0 + beta * (am + ap);
+        const double sub = (r == 0) ? 0.0 : -beta * am;
+        const double sup = (r == n - 1) ? 0.0 : -beta * ap;
+        const double lr = (r == 0) ? 0.0 : sub / dprev;
+        const double d = diag - lr * cprev;
+        l[r] = lr;
+        invd[r] = 1.0 / d;
+        cs[r] = sup;
+        dprev = d;
+        cprev = sup;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_cn_solve(GridDev g, int kind, const double* __restrict__ fac, double* __restrict__ x) {
+    const size_t plane = (size_t)g.nx * g.ny;
+    const size_t col = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= plane) return;
+    const int n = kind == 0 ? g.nz : g.nz - 1;
+    const int off = kind == 0 ? 0 : 1;
+    const double* l = fac;
+    const double* invd = fac + n;
+    const double* cs = fac + 2 * n;
+    double* q = x + (size_t)off * plane + col;
+    double y = q[0];
+    for (int r = 1; r < n; ++r) {
+        y = q[(size_t)r * plane] - l[r] * y;
+        q[(size_t)r * plane] = y;
+    }
+    double xv = y * invd[n - 1];
+    q[(size_t)(n - 1) * plane] = xv;
+    for (int r = n - 2; r >= 0; --r) {
+        xv = (q[(size_t)r * plane] - cs[r] * xv) * invd[r];
+        q[(size_t)r * plane] = xv;
+    }
+    if (kind == 1) {
+        x[col] = 0.0;
+        x[(size_t)g.nz * plane + col] = 0.0;
+    }
+}
+
+// ---- CFL (Listing 1) ------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_cfl(const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w, GridDev g,
+      unsigned long long* __restrict__ out) {
+    const size_t n = (size_t)g.nx * g.ny * g.nz;
+    const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double q = 0.0;
+    if (id < n) {
+        const int i = (int)(id % g.nx);
+        const size_t jk = id / g.nx;
+        const int j = (int)(jk % g.ny);
+        const int k = (int)(jk / g.ny);
+        const size_t plane = (size_t)g.nx * g.ny;
+        const int ip = (i + 1 == g.nx) ? 0 : i + 1;
+        const int jp = (j + 1 == g.ny) ? 0 : j + 1;
+        q = fabs(w[id] + w[id + plane]) / g.dz[k] +
+            fabs(v[id] + v[(size_t)k * plane + (size_t)jp * g.nx + i]) / g.dy +
+            fabs(u[id] + u[(size_t)k * plane + (size_t)j * g.nx + ip]) / g.dx;
+        q *= 0.5;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) q = fmax(q, __shfl_xor(q, off, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(q));
+}
+
+// ---- projection adjoint -----------------------------------------------------
+// With Vf = dz on u, v and dzc on interior w, and Vc = dz:
+//   g_u* = g_u - Vf G S [ D Vf^-1 g_u + (1/s) (I - c Dzz) Vc^-1 g_p ].
+// k_adj_rhs forms the bracket (wall-face cotangents of w are ignored), k_adj_update
+// the final combination.
+__global__ void __launch_bounds__(256)
+k_adj_rhs(const double* __restrict__ gu, const double* __restrict__ gv, const double* __restrict__ gw,
+          const double* __restrict__ gp, double* __restrict__ f, GridDev g, double inv_s, double c) {
+    const size_t n = (size_t)g.nx * g.ny * g.nz;
+    const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n) return;
+    const int i = (int)(id % g.nx);
+    const size_t jk = id / g.nx;
+    const int j = (int)(jk % g.ny);
+    const int k = (int)(jk / g.ny);
+    const size_t plane = (size_t)g.nx * g.ny;
+    const int ip = (i + 1 == g.nx) ? 0 : i + 1;
+    const int jp = (j + 1 == g.ny) ? 0 : j + 1;
+    const double idz = 1.0 / g.dz[k];
+    const double du = (gu[(size_t)k * plane + (size_t)j * g.nx + ip] - gu[id]) * idz / g.dx;
+    const double dv = (gv[(size_t)k * plane + (size_t)jp * g.nx + i] - gv[id]) * idz / g.dy;
+    const double wt = (k + 1 < g.nz) ? gw[id + plane] / g.dzc[k + 1] : 0.0;
+    const double wb = (k > 0) ? gw[id] / g.dzc[k] : 0.0;
+    double val = du + dv + (wt - wb) / g.dz[k];
+    if (gp) {
+        const double hc = gp[id] * idz;
+        double fp = 0.0, fm = 0.0;
+        if (k + 1 < g.nz) fp = (gp[id + plane] / g.dz[k + 1] - hc) * g.o[k + 1];
+        if (k > 0) fm = (hc - gp[id - plane] / g.dz[k - 1]) * g.o[k];
+        val += inv_s * (hc - c * ((fp - fm) / g.dz[k]));
+    }
+    f[id] = val;
+}
+
+__global__ void __launch_bounds__(256)
+k_adj_update(const double* __restrict__ gu, const double* __restrict__ gv, const double* __restrict__ gw,
+             const double* __restrict__ phi, double* __restrict__ ou, double* __restrict__ ov,
+             double* __restrict__ ow, GridDev g) {
+    const size_t n = (size_t)g.nx * g.ny * g.nz;
+    const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n) return;
+    const int i = (int)(id % g.nx);
+    const size_t jk = id / g.nx;
+    const int j = (int)(jk % g.ny);
+    const int k = (int)(jk / g.ny);
+    const size_t plane = (size_t)g.nx * g.ny;
+    const int im = (i == 0) ? g.nx - 1 : i - 1;
+    const int jm = (j == 0) ? g.ny - 1 : j - 1;
+    const double pc = phi[id];
+    ou[id] = gu[id] - g.dz[k] * ((pc - phi[(size_t)k * plane + (size_t)j * g.nx + im]) / g.dx);
+    ov[id] = gv[id] - g.dz[k] * ((pc - phi[(size_t)k * plane + (size_t)jm * g.nx + i]) / g.dy);
+    if (k > 0)
+        ow[id] = gw[id] - (pc - phi[id - plane]);
+    else
+        ow[id] = 0.0;
+    if (k + 1 == g.nz) ow[id + plane] = 0.0;
+}
+
+hipError_t launch_adj_rhs(const GridDev& g, const double* gu, const double* gv, const double* gw, const double* gp,
+                          double* f, double inv_s, double c, hipStream_t st) {
+    const size_t n = (size_t)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_adj_rhs, dim3(nblocks(n, 256)), dim3(256), 0, st, gu, gv, gw, gp, f, g, inv_s, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_update(const GridDev& g, const double* gu, const double* gv, const double* gw,
+                             const double* phi, double* ou, double* ov, double* ow, hipStream_t st) {
+    const size_t n = (size_t)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_adj_update, dim3(nblocks(n, 256)), dim3(256), 0, st, gu, gv, gw, phi, ou, ov, ow, g);
+    return hipGetLastError();
+}
+
+// ---- launchers --------------------------------------------------------------
+hipError_t launch_divergence(const GridDev& g, const double* u, const double* v, const double* w, double* f,
+                             double scale, hipStream_t st) {
+    const size_t n = (size_t)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_divergence, dim3(nblocks(n, 256)), dim3(256), 0, st, u, v, w, f, g, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_project_update(const GridDev& g, double* u, double* v, double* w, double* p, const double* phi,
+                                 double s, double c, hipStream_t st) {
+    const size_t n = (size_t)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_project_update, dim3(nblocks(n, 256)), dim3(256), 0, st, u, v, w, p, phi, g, s, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(const GridDev& g, const double* f, const double* mu, double mu_scale, const double* x,
+                           double* r, double* partial, hipStream_t st) {
+    const size_t n = (size_t)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_residual, dim3(nblocks(n, 256)), dim3(256), 0, st, f, mu, mu_scale, x, r, g, partial);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) k_nonfinite(const double* __restrict__ p, size_t n, unsigned* flag) {
+    const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool bad = false;
+    if (id < n) bad = !isfinite(p[id]);
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1u);
+}
+
+hipError_t launch_nonfinite(const double* p, size_t n, unsigned* flag, hipStream_t st) {
+    hipLaunchKernelGGL(k_nonfinite, dim3(nblocks(n, 256)), dim3(256), 0, st, p, n, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double* partial, int nblk, int ncomp, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, partial, nblk, ncomp, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double* p, size_t n, double v, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3(nblocks(n, 256)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_planes(const GridDev& g, const double* in, double* out, const double* zs, int nplanes,
+                               size_t plane, hipStream_t st) {
+    (void)g;
+    const size_t n = (size_t)nplanes * plane;
+    hipLaunchKernelGGL(k_scale_planes, dim3(nblocks(n, 256)), dim3(256), 0, st, in, out, zs, plane, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_cn_factor(const GridDev& g, int kind, double beta, double* fac, hipStream_t st) {
+    hipLaunchKernelGGL(k_cn_factor, dim3(1), dim3(64), 0, st, g, kind, beta, fac);
+    return hipGetLastError();
+}
+
+hipError_t launch_cn_solve(const GridDev& g, int kind, const double* fac, double* x, hipStream_t st) {
+    const size_t plane = (size_t)g.nx * g.ny;
+    hipLaunchKernelGGL(k_cn_solve, dim3(nblocks(plane, 256)), dim3(256), 0, st, g, kind, fac, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_cfl(const GridDev& g, const double* u, const double* v, const double* w, double* out,
+                      hipStream_t st) {
+    const size_t n = (size_t)g.nx * g.ny * g.nz;
+    hipError_t e = launch_fill(out, 1, 1e-8, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cfl, dim3(nblocks(n, 256)), dim3(256), 0, st, u, v, w, g,
+                       reinterpret_cast<unsigned long long*>(out));
+    return hipGetLastError();
+}
+
+}  // namespace ps

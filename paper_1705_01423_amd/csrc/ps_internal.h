@@ -1,0 +1,103 @@
+// Internal declarations of the pressure-Poisson library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "fft_engine.h"
+
+namespace ps {
+
+// Spectral tile width: W consecutive kx columns are stored together so that
+// every row of a tile is one 128-byte segment (8 complex FP64 or 16 complex FP32).
+template <typename T>
+struct TileW;
+template <>
+struct TileW<double> {
+    static constexpr int value = 8;
+};
+template <>
+struct TileW<float> {
+    static constexpr int value = 16;
+};
+
+// Device-side grid tables (FP64).  Built once per plan on the host.
+struct GridDev {
+    int nx, ny, nz;
+    double dx, dy;
+    const double* dz;    // nz
+    const double* dzc;   // nz+1, interior entries 1..nz-1
+    const double* o;     // nz+1, 1/dzc interior, 0 at walls
+    const double* dzw;   // nz+1, dzc interior, dz/2 at walls
+    const double* lamx;  // nx/2+1
+    const double* lamy;  // ny
+};
+
+// Per-precision spectral machinery: twiddle tables and buffers.
+template <typename T>
+struct SpecDev {
+    int w;                    // tile width
+    int nkxb;                 // number of kx tiles
+    const cx<T>* twx;         // exp(-2 pi i q / (nx/2)), q < nx/2
+    const cx<T>* ptw;         // exp(-2 pi i k / nx), k <= nx/2
+    const cx<T>* twy;         // exp(-2 pi i q / ny), q < ny
+    cx<T>* a;                 // [nz][nkxb][ny][W]
+    cx<T>* b;                 // [nkxb][ny][nz][W]
+    T* piv;                   // z-solve pivots, same layout as b (real)
+};
+
+// Launchers (all asynchronous on `st`).  Return hipSuccess or the launch error.
+// FFT stages.
+template <typename T>
+hipError_t launch_xfwd(const GridDev& g, const SpecDev<T>& s, const double* f, const double* scale_z,
+                       double* partial, hipStream_t st);
+template <typename T>
+hipError_t launch_yfwd(const GridDev& g, const SpecDev<T>& s, hipStream_t st);
+template <typename T>
+hipError_t launch_yinv(const GridDev& g, const SpecDev<T>& s, hipStream_t st);
+// mode 0: out = scale * x;  mode 1: out += scale * x - mu[0]
+// scale_z (optional): multiply plane z additionally by scale_z[z]
+// partial (optional): per-block sums {sum (scale x)^2, sum out^2, sum dz out}
+template <typename T>
+hipError_t launch_xinv(const GridDev& g, const SpecDev<T>& s, double* out, double scale, int mode,
+                       const double* mu, double mu_scale, const double* scale_z, double* partial, hipStream_t st);
+template <typename T>
+int xfwd_blocks(const GridDev& g);
+template <typename T>
+int xinv_blocks(const GridDev& g);
+
+// z solves on buffer b (all columns except (0,0)), then the (0,0) column.
+template <typename T>
+hipError_t launch_zsolve(const GridDev& g, const SpecDev<T>& s, hipStream_t st);
+template <typename T>
+hipError_t launch_zsolve00(const GridDev& g, const SpecDev<T>& s, double* defect, hipStream_t st);
+
+bool fft_length_supported(int n);
+
+// Field kernels (FP64).
+hipError_t launch_divergence(const GridDev& g, const double* u, const double* v, const double* w,
+                             double* f, double scale, hipStream_t st);
+hipError_t launch_project_update(const GridDev& g, double* u, double* v, double* w, double* p,
+                                 const double* phi, double s, double c, hipStream_t st);
+// r = (f - mu[0] * mu_scale) - L x; partial (optional): per-block {sum r^2, sum (f - mu)^2}
+hipError_t launch_residual(const GridDev& g, const double* f, const double* mu, double mu_scale, const double* x,
+                           double* r, double* partial, hipStream_t st);
+// flag[0] |= 1 when some value of p[0..n) is not finite
+hipError_t launch_nonfinite(const double* p, size_t n, unsigned* flag, hipStream_t st);
+hipError_t launch_adj_rhs(const GridDev& g, const double* gu, const double* gv, const double* gw, const double* gp,
+                          double* f, double inv_s, double c, hipStream_t st);
+hipError_t launch_adj_update(const GridDev& g, const double* gu, const double* gv, const double* gw,
+                             const double* phi, double* ou, double* ov, double* ow, hipStream_t st);
+hipError_t launch_reduce(const double* partial, int nblk, int ncomp, double* out, hipStream_t st);
+hipError_t launch_fill(double* p, size_t n, double v, hipStream_t st);
+hipError_t launch_scale_planes(const GridDev& g, const double* in, double* out, const double* zs, int nplanes,
+                               size_t plane, hipStream_t st);
+hipError_t launch_cn_factor(const GridDev& g, int kind, double beta, double* fac, hipStream_t st);
+hipError_t launch_cn_solve(const GridDev& g, int kind, const double* fac, double* x, hipStream_t st);
+hipError_t launch_cfl(const GridDev& g, const double* u, const double* v, const double* w, double* out,
+                      hipStream_t st);
+
+}  // namespace ps

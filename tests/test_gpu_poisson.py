@@ -1,0 +1,144 @@
+"""GPU parity of the Poisson solve: each stage and the whole solve against the oracle."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import poisson, operators as op
+from paper_1705_01423_amd import synth
+from gpu_util import banner, dev, grids, rel
+
+pytestmark = pytest.mark.gpu
+F64 = torch.float64
+
+SHAPES = [(8, 8, 8), (6, 12, 5), (24, 48, 16), (64, 64, 64), (96, 24, 40), (4, 2, 2), (48, 96, 33)]
+
+
+def _rng_field(shape, seed):
+    return torch.as_tensor(np.random.default_rng(seed).standard_normal(shape))
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 3e-6)])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_stage_x_forward(shape, prec, tol):
+    banner(f"x forward {shape} {prec}")
+    g, plan = grids(*shape, precision=prec)
+    f = _rng_field(plan.centre_shape, 1)
+    buf = plan.new_spectral()
+    plan.debug_stage(0, f.to("cuda"), buf)
+    got = plan.spectral_to_canonical(buf, "a").to(torch.complex128).cpu()
+    ref = torch.fft.rfft(f, dim=2)
+    assert rel(got, ref) < tol
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 3e-6)])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_stage_y_both(shape, prec, tol):
+    banner(f"y forward/inverse {shape} {prec}")
+    g, plan = grids(*shape, precision=prec)
+    nxh = plan.nx // 2 + 1
+    gen = np.random.default_rng(2)
+    a = torch.complex(torch.as_tensor(gen.standard_normal((plan.nz, plan.ny, nxh))),
+                      torch.as_tensor(gen.standard_normal((plan.nz, plan.ny, nxh))))
+    cdt = torch.complex128 if prec == "fp64" else torch.complex64
+    inp = plan.canonical_to_spectral(a.to(cdt).to("cuda"), "a")
+    outb = plan.new_spectral()
+    plan.debug_stage(1, inp, outb)
+    got = plan.spectral_to_canonical(outb, "b").to(torch.complex128).cpu()
+    assert rel(got, torch.fft.fft(a, dim=1)) < tol
+    outa = plan.new_spectral()
+    plan.debug_stage(3, outb, outa)
+    back = plan.spectral_to_canonical(outa, "a").to(torch.complex128).cpu()
+    assert rel(back, a * plan.ny) < tol
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 3e-6)])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_stage_x_inverse(shape, prec, tol):
+    banner(f"x inverse {shape} {prec}")
+    g, plan = grids(*shape, precision=prec)
+    f = _rng_field(plan.centre_shape, 3)
+    spec = torch.fft.rfft(f, dim=2)
+    cdt = torch.complex128 if prec == "fp64" else torch.complex64
+    inp = plan.canonical_to_spectral(spec.to(cdt).to("cuda"), "a")
+    out = torch.empty(plan.centre_shape, dtype=F64, device="cuda")
+    plan.debug_stage(4, inp, out)
+    assert rel(out, f / plan.ny) < tol
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 1e-5)])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_stage_z_solve(shape, prec, tol):
+    banner(f"z solve {shape} {prec}")
+    g, plan = grids(*shape, lx=2.0, ly=1.0, precision=prec)
+    gen = np.random.default_rng(4)
+    nxh = plan.nx // 2 + 1
+    F = torch.complex(torch.as_tensor(gen.standard_normal((plan.nz, plan.ny, nxh))),
+                      torch.as_tensor(gen.standard_normal((plan.nz, plan.ny, nxh))))
+    F[:, 0, 0] = F[:, 0, 0].real.to(torch.complex128)
+    cdt = torch.complex128 if prec == "fp64" else torch.complex64
+    inp = plan.canonical_to_spectral(F.to(cdt).to("cuda"), "b")
+    out = plan.new_spectral()
+    plan.debug_stage(2, inp, out)
+    got = plan.spectral_to_canonical(out, "b").to(torch.complex128).cpu()
+    lam = g.lamy[:, None] + g.lamx[None, :]
+    lam[0, 0] = 1.0
+    ref = poisson.zsolve_excess(F, lam, g)
+    phi00, _ = poisson.singular_column(F[:, 0, 0].real, g)
+    ref[:, 0, 0] = phi00.to(torch.complex128)
+    assert rel(got, ref) < tol
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_solve_fp64_parity(shape):
+    banner(f"solve fp64 {shape}")
+    g, plan = grids(*shape, lx=1.5, ly=2.0)
+    f = _rng_field(plan.centre_shape, 5) + 0.3
+    ref, defect = poisson.solve(f, g, return_defect=True)
+    phi, info = plan.solve(f.to("cuda"))
+    assert rel(phi, ref) < 1e-12
+    assert abs(info["compat_defect"] - defect) < 1e-12
+
+
+def test_solve_closed_form():
+    """Uniform grid: the cos cos cos eigenvector is recovered (exact discrete eigenvalue)."""
+    nx, ny, nz, lx, ly = 32, 24, 16, 1.3, 0.7
+    g, plan = grids(nx, ny, nz, lx, ly, alpha=0.0)
+    xc = (torch.arange(nx, dtype=F64) + 0.5) * lx / nx
+    yc = (torch.arange(ny, dtype=F64) + 0.5) * ly / ny
+    zc = (torch.arange(nz, dtype=F64) + 0.5) / nz
+    phi = (torch.cos(math.pi * zc)[:, None, None] * torch.cos(2 * math.pi * yc / ly)[None, :, None]
+           * torch.cos(2 * math.pi * xc / lx)[None, None, :])
+    eig = -(4 * (nx / lx) ** 2 * math.sin(math.pi / nx) ** 2 + 4 * (ny / ly) ** 2 * math.sin(math.pi / ny) ** 2
+            + 4 * nz ** 2 * math.sin(math.pi / (2 * nz)) ** 2)
+    got, _ = plan.solve((eig * phi).to("cuda"))
+    assert rel(got, phi) < 1e-13
+
+
+@pytest.mark.parametrize("prec", ["fp32_refined", "fp32"])
+def test_solve_fp32_paths(prec):
+    banner(f"solve {prec}")
+    g, plan = grids(48, 32, 40, lx=2.0, ly=2.0, precision=prec)
+    cfg = synth.small("t", 48, 32, 40, 2.0, 2.0, 3.0, seed=11)
+    u, v, w = synth.mode_velocity(cfg)
+    f = op.divergence(torch.as_tensor(u), torch.as_tensor(v), torch.as_tensor(w), g)
+    ref = poisson.solve(f, g)
+    phi, info = plan.solve(f.to("cuda"))
+    err = rel(phi, ref)
+    if prec == "fp32":
+        assert err < 1e-5
+    else:
+        assert err < 1e-11, (err, info)
+        assert info["iterations"] >= 2
+
+
+def test_c1_config_parity():
+    """64^3 stretched box, RHS = divergence of i.i.d. N(0,1) face velocities (wall w = 0)."""
+    cfg = synth.CONFIGS["c1"]
+    g, plan = grids(cfg.nx, cfg.ny, cfg.nz, cfg.lx, cfg.ly, cfg.alpha)
+    u, v, w = synth.random_face_velocity(cfg)
+    f = op.divergence(torch.as_tensor(u), torch.as_tensor(v), torch.as_tensor(w), g)
+    ref = poisson.solve(f, g)
+    phi, _ = plan.solve(f.to("cuda"))
+    assert rel(phi, ref) < 1e-12
