@@ -1,0 +1,214 @@
+#!/usr/bin/env python3
+"""Benchmark: direct pressure-Poisson solves on the 1024 x 1024 x 512 wall-bounded slab.
+
+One step = one FP64 ``poisson_solve`` (x FFT, y FFT, z solves, inverse y FFT,
+inverse x FFT) on the plane-Couette-like slab (Lx = Ly = 4, tanh stretching 3),
+right-hand side = divergence of a seeded 64-mode k^-5/3 velocity field with
+noise and the Couette base flow.  Inputs are resident in HBM before timing.
+
+Also reported on the same input: the FP32-refined solve (solves/s, iterations,
+difference from the FP64 result), per-stage kernel times measured with HIP
+events, the roofline position of the dominant kernel, a same-run device copy
+rate, full-size parity against the CPU oracle, and the oracle's own rate on the
+host (CPU baseline).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c3")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-refined", action="store_true")
+    ap.add_argument("--stage-reps", type=int, default=10)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this library runs one box on one GPU; runs on more than one GPU are not supported",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1705_01423_amd import synth
+    from paper_1705_01423_amd.api import Plan
+
+    cfg = synth.CONFIGS[args.config]
+    nx, ny, nz = cfg.nx, cfg.ny, cfg.nz
+    npts = nx * ny * nz
+    zf = synth.zfaces(nz, cfg.alpha)
+    log(f"generating inputs {nx}x{ny}x{nz}")
+    t0 = time.time()
+    u, v, w = synth.mode_velocity(cfg)
+    log(f"inputs ready in {time.time() - t0:.1f}s")
+    dev = torch.device("cuda")
+    # Right-hand side: discrete divergence of the synthetic field (input preparation with
+    # plain torch ops, outside the timed region).
+    dx, dy = cfg.lx / nx, cfg.ly / ny
+    dzt = torch.as_tensor(np.diff(zf)).to(dev)
+    ug = torch.as_tensor(u).to(dev)
+    f = (torch.roll(ug, -1, 2) - ug) / dx
+    del ug
+    vg = torch.as_tensor(v).to(dev)
+    f += (torch.roll(vg, -1, 1) - vg) / dy
+    del vg
+    wg = torch.as_tensor(w).to(dev)
+    f += (wg[1:] - wg[:-1]) / dzt[:, None, None]
+    del wg
+    f = f.contiguous()
+    torch.cuda.synchronize()
+
+    plan = Plan(nx, ny, nz, cfg.lx, cfg.ly, zf, precision="fp64")
+    phi = torch.empty_like(f)
+    stream = torch.cuda.current_stream()
+    log("fp64 warmup")
+    for _ in range(args.warmup):
+        plan.solve_nosync(f, phi)
+    torch.cuda.synchronize()
+    log(f"fp64 timing {args.steps} solves")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.solve_nosync(f, phi)
+    torch.cuda.synchronize()
+    t_fp64 = (time.perf_counter() - t0) / args.steps
+    _, info64 = plan.solve(f, phi)
+    torch.cuda.synchronize()
+
+    # per-stage kernel times (HIP events on the launch stream)
+    log("stage timing")
+    names = ["x_fft_fwd", "y_fft_fwd", "z_solve", "y_fft_inv", "x_fft_inv"]
+    stage_ms = {}
+    for s, name in enumerate(names):
+        ins = f if s == 0 else None
+        outs = phi if s == 4 else None
+        for _ in range(2):
+            plan.debug_stage(s, ins, outs)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.stage_reps):
+            plan.debug_stage(s, ins, outs)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        stage_ms[name] = e0.elapsed_time(e1) / args.stage_reps
+    # restore phi after the stage runs overwrote the plan buffers
+    plan.solve_nosync(f, phi)
+    torch.cuda.synchronize()
+
+    # copy reference: read + write one field
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    tmp = torch.empty_like(f)
+    tmp.copy_(f)
+    e0.record(stream)
+    for _ in range(5):
+        tmp.copy_(f)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * f.numel() * 8 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del tmp
+
+    dominant = max(stage_ms, key=stage_ms.get)
+    alg_bytes = 16.0 * npts        # one read + one write of the field's spectral/physical data
+    achieved = alg_bytes / (stage_ms[dominant] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "alg_bytes_per_launch": alg_bytes}
+    solve_bytes = 80.0 * npts
+    total_gbs = solve_bytes / t_fp64 / 1e9
+
+    refined = None
+    if not args.no_refined:
+        log("fp32-refined timing")
+        plan32 = Plan(nx, ny, nz, cfg.lx, cfg.ly, zf, precision="fp32_refined")
+        phi32 = torch.empty_like(f)
+        for _ in range(max(1, args.warmup)):
+            plan32.solve(f, phi32)
+        torch.cuda.synchronize()
+        nref = max(3, args.steps // 2)
+        t0 = time.perf_counter()
+        for _ in range(nref):
+            _, inf32 = plan32.solve(f, phi32)
+        torch.cuda.synchronize()
+        t_ref = (time.perf_counter() - t0) / nref
+        diff = float((phi32 - phi).norm() / phi.norm())
+        refined = {"solves_per_s": round(1.0 / t_ref, 3), "ms_per_solve": round(t_ref * 1e3, 3),
+                   "gpoints_per_s": round(npts / t_ref / 1e9, 3), "iterations": inf32["iterations"],
+                   "rel_update": inf32["rel_update"], "rel_l2_vs_fp64_gpu": diff,
+                   "speedup_vs_fp64": round(t_fp64 / t_ref, 3)}
+        plan32.close()
+        del phi32
+        torch.cuda.empty_cache()
+
+    cpu_baseline = None
+    parity = None
+    if not args.no_cpu_baseline:
+        import torch as _t
+        from oracle import Grid, operators as op, poisson
+        log("oracle (CPU) divergence and solve at full size")
+        g = Grid(nx, ny, nz, cfg.lx, cfg.ly, zf)
+        fo = op.divergence(_t.as_tensor(u), _t.as_tensor(v), _t.as_tensor(w), g)
+        del u, v, w
+        t0 = time.perf_counter()
+        ref = poisson.solve(fo, g)
+        t_cpu = time.perf_counter() - t0
+        cpu_baseline = {"value": round(1.0 / t_cpu, 5), "unit": "solves/s", "cores": _t.get_num_threads(),
+                        "kind": "oracle", "gpoints_per_s": round(npts / t_cpu / 1e9, 4),
+                        "sample": f"one full {nx}x{ny}x{nz} FP64 solve ({t_cpu:.1f} s)"}
+        phih = phi.cpu()
+        parity = {"fp64_rel_l2_vs_oracle": float((phih - ref).norm() / ref.norm()),
+                  "rhs_rel_diff_gpu_vs_oracle": float((f.cpu() - fo).norm() / fo.norm())}
+        log(f"parity {parity}")
+
+    out = {
+        "metric": "Poisson solves/s at 1024x1024x512 (FP64)",
+        "value": round(1.0 / t_fp64, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_fp64 * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"poisson_solve {nx}x{ny}x{nz} Lx={cfg.lx} Ly={cfg.ly} tanh-stretched z "
+                               f"(alpha={cfg.alpha}); rhs = divergence of seeded 64-mode k^-5/3 field + "
+                               f"N(0,1e-2) + Couette profile", "nx": nx, "ny": ny, "nz": nz},
+        "gpoints_per_s": round(npts / t_fp64 / 1e9, 3),
+        "model_bytes_per_solve": solve_bytes,
+        "model_gbs": round(total_gbs, 1),
+        "model_frac_hbm": round(total_gbs / HBM_PEAK_GBS, 4),
+        "stages_ms": {k: round(x, 4) for k, x in stage_ms.items()},
+        "copy_gbs": round(copy_gbs, 1),
+        "fp32_refined": refined,
+        "roofline": roofline,
+        "cpu_baseline": cpu_baseline,
+        "parity": parity,
+        "compat_defect": info64["compat_defect"],
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -6,7 +6,7 @@ import os
 from ctypes import POINTER, c_double, c_int, c_size_t, c_uint, c_void_p
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libps_mi355x.so")
+LIB_PATH = os.environ.get("PS_LIB_PATH") or os.path.join(HERE, "libps_mi355x.so")
 
 PS_OK, PS_EINVAL, PS_ENOMEM, PS_EDEVICE, PS_ENOTCOMPAT, PS_ENONFINITE, PS_ENOTCONVERGED = range(7)
 STATUS_NAMES = {0: "PS_OK", 1: "PS_EINVAL", 2: "PS_ENOMEM", 3: "PS_EDEVICE", 4: "PS_ENOTCOMPAT",

@@ -80,6 +80,7 @@ struct ps_plan_s {
     double* phibuf;   // npts
     double* rbuf;     // npts
     double* partial;  // nblk_max * 4
+    double* red_scratch;  // 1024 * 4
     double* small;    // 64 + cn factors
     double* cnfac;    // 3 (nz+1) * 2
     int nblk_max;
@@ -156,7 +157,8 @@ size_t workspace_layout(ps_plan_t p, bool carve) {
     p->phibuf = (double*)take(p->npts * sizeof(double));
     p->rbuf = (double*)take(p->npts * sizeof(double));
     p->partial = (double*)take((size_t)p->nblk_max * 4 * sizeof(double));
-    p->small = (double*)take((R_NSLOTS + 6 * (size_t)(p->nz + 1)) * sizeof(double));
+    p->red_scratch = (double*)take(1024 * 4 * sizeof(double));
+    p->small = (double*)take((R_NSLOTS + 9 * (size_t)(p->nz + 1)) * sizeof(double));
     if (carve) p->cnfac = p->small + R_NSLOTS;
     return off;
 }
@@ -237,6 +239,34 @@ ps_status check_plan(ps_plan_t p) {
 
 double inv_den(ps_plan_t p) { return 1.0 / (p->sum_dz * (double)p->nx * (double)p->ny); }
 
+int residual_blocks(ps_plan_t p) { return (int)((p->npts + 255) / 256); }
+
+// Low-storage RK3 coefficients (Rai & Moin / Wray): gamma, rho; alpha = gamma + rho.
+const double kGamma[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
+const double kRho[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
+
+// Crank-Nicolson factor slots (3 (nz+1) doubles each): 0 centre, 1 face, 2 face (diffusivity)
+double* cn_slot(ps_plan_t p, int s) { return p->cnfac + (size_t)s * 3 * (p->nz + 1); }
+
+constexpr int kSubFields = 8;
+
+// Field-sized temporaries of the substep and its adjoint, allocated on first use.
+ps_status ensure_substep_buffers(ps_plan_t p) {
+    if (p->sub_buf) return PS_OK;
+    const size_t per = align256((p->npts + p->plane) * sizeof(double));
+    if (hipMalloc((void**)&p->sub_buf, per * kSubFields) != hipSuccess) {
+        p->sub_buf = nullptr;
+        return fail(PS_ENOMEM, "cannot allocate %zu bytes of substep temporaries", per * kSubFields);
+    }
+    p->sub_bytes = per * kSubFields;
+    return PS_OK;
+}
+
+double* sub_field(ps_plan_t p, int q) {
+    const size_t per = align256((p->npts + p->plane) * sizeof(double));
+    return (double*)((char*)p->sub_buf + per * q);
+}
+
 // One spectral solve with the plan's kernels at precision T:
 // out = S(in) (mode 0) or out += S(in) - mu (mode 1), scale_in / scale_out per plane (optional).
 template <typename T>
@@ -247,7 +277,7 @@ ps_status spectral_solve(ps_plan_t p, const double* in, double* out, int mode, c
     SpecDev<T> s = spec_of<T>(p);
     const int nbx = xfwd_blocks<T>(g);
     PS_HIP(launch_xfwd<T>(g, s, in, zin, want_wsum ? p->partial : nullptr, st), "x forward FFT");
-    if (want_wsum) PS_HIP(launch_reduce(p->partial, nbx, 1, p->small + R_WSUM, st), "reduce");
+    if (want_wsum) PS_HIP(launch_reduce2(p->partial, nbx, 1, p->red_scratch, p->small + R_WSUM, st), "reduce");
     PS_HIP(launch_yfwd<T>(g, s, st), "y forward FFT");
     PS_HIP(launch_zsolve<T>(g, s, st), "z solve");
     PS_HIP(launch_zsolve00<T>(g, s, p->small + R_DEFECT, st), "z solve (0,0)");
@@ -255,7 +285,7 @@ ps_status spectral_solve(ps_plan_t p, const double* in, double* out, int mode, c
     const double scale = 1.0 / ((double)p->nx * (double)p->ny);
     PS_HIP(launch_xinv<T>(g, s, out, scale, mode, mu_dev, mu_scale, zout, want_norms ? p->partial : nullptr, st),
            "x inverse FFT");
-    if (want_norms) PS_HIP(launch_reduce(p->partial, nbx, 3, p->small + R_D2, st), "reduce");
+    if (want_norms) PS_HIP(launch_reduce2(p->partial, nbx, 3, p->red_scratch, p->small + R_D2, st), "reduce");
     return PS_OK;
 }
 
@@ -295,13 +325,15 @@ ps_status solve_impl(ps_plan_t p, const double* in, double* out, const double* z
         PS_CHECK(spectral_solve<float>(p, f, out, 0, nullptr, 0.0, nullptr, nullptr, true, true, st));
         loc.iterations = 1;
         if (p->prec == PS_FP32_REFINED) {
-            double prev = 1e300;
+            // Linear convergence: with contraction rho = |d_i| / |d_{i-1}| (|d_0| = |x|), the error
+            // left after correction i is about rho |d_i|; stop when that estimate meets the tolerance.
+            double prev = 1.0;
             double* r = (f == p->rbuf) ? p->fbuf : p->rbuf;
             bool converged = false;
             for (int it = 0; it < p->max_iter; ++it) {
                 PS_HIP(launch_residual(p->gd, f, p->small + R_WSUM, inv_den(p), out, r, p->partial, st),
                        "residual");
-                PS_HIP(launch_reduce(p->partial, (int)((p->npts + 255) / 256), 2, p->small + R_R2, st), "reduce");
+                PS_HIP(launch_reduce2(p->partial, residual_blocks(p), 2, p->red_scratch, p->small + R_R2, st), "reduce");
                 PS_CHECK(spectral_solve<float>(p, r, out, 1, p->small + R_XW, inv_den(p), nullptr, nullptr, false,
                                                true, st));
                 loc.iterations++;
@@ -311,7 +343,8 @@ ps_status solve_impl(ps_plan_t p, const double* in, double* out, const double* z
                 loc.rel_update = rel;
                 const double f2 = p->h_res[R_F2];
                 loc.rel_residual = f2 > 0 ? std::sqrt(p->h_res[R_R2] / f2) : 0.0;
-                if (rel <= p->tol) {
+                const double rho = rel / prev;
+                if (rel <= p->tol || rho * rel <= p->tol) {
                     converged = true;
                     break;
                 }
@@ -437,6 +470,7 @@ ps_status poisson_plan_create(ps_plan_t* out, int nx, int ny, int nz, double lx,
         g.dzw = p->d_dzw;
         g.lamx = p->d_lamx;
         g.lamy = p->d_lamy;
+        g.idz = p->d_inv_dz;
     }
     int nbx = prec == PS_FP64 ? xfwd_blocks<double>(p->gd) : xfwd_blocks<float>(p->gd);
     int nbr = (int)((p->npts + 255) / 256);
@@ -559,7 +593,7 @@ ps_status cn_solve(ps_plan_t p, int kind, double beta, double* x, void* stream) 
     if (kind != PS_CENTER && kind != PS_FACE) return fail(PS_EINVAL, "unknown kind %d", kind);
     if (!(beta >= 0) || !std::isfinite(beta)) return fail(PS_EINVAL, "beta must be non-negative");
     hipStream_t st = (hipStream_t)stream;
-    double* fac = p->cnfac + (kind == PS_CENTER ? 0 : 3 * (size_t)(p->nz + 1));
+    double* fac = cn_slot(p, kind == PS_CENTER ? 0 : 1);
     PS_HIP(launch_cn_factor(p->gd, kind, beta, fac, st), "cn factor");
     PS_HIP(launch_cn_solve(p->gd, kind, fac, x, st), "cn solve");
     return PS_OK;
@@ -578,19 +612,143 @@ ps_status ps_cfl(ps_plan_t p, const double* u, const double* v, const double* w,
 ps_status rk3_substep(ps_plan_t p, int l, double dt, double nu, double kappa, double* u, double* v, double* w,
                       double* t, double* pr, const double* const* h_prev, double* const* h_out, void* stream,
                       ps_info* info) {
-    (void)l; (void)dt; (void)nu; (void)kappa; (void)u; (void)v; (void)w; (void)t; (void)pr;
-    (void)h_prev; (void)h_out; (void)stream; (void)info;
     PS_CHECK(check_plan(p));
-    return fail(PS_EINVAL, "rk3_substep: not available in this build");
+    if (l < 1 || l > 3) return fail(PS_EINVAL, "substep index l=%d must be 1, 2 or 3", l);
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(PS_EINVAL, "dt must be positive");
+    if (!(nu >= 0) || !(kappa >= 0) || !std::isfinite(nu) || !std::isfinite(kappa))
+        return fail(PS_EINVAL, "nu and kappa must be non-negative");
+    PS_CHECK(check_ptr(u, "u"));
+    PS_CHECK(check_ptr(v, "v"));
+    PS_CHECK(check_ptr(w, "w"));
+    PS_CHECK(check_ptr(t, "t"));
+    PS_CHECK(check_ptr(pr, "p"));
+    const double gam = kGamma[l - 1], rho = kRho[l - 1], alp = gam + rho;
+    if (rho != 0.0) {
+        if (!h_prev) return fail(PS_EINVAL, "h_prev is required for l=%d", l);
+        for (int q = 0; q < 4; ++q) PS_CHECK(check_ptr(h_prev[q], "h_prev[q]"));
+    }
+    if (h_out)
+        for (int q = 0; q < 4; ++q) PS_CHECK(check_ptr(h_out[q], "h_out[q]"));
+    PS_CHECK(ensure_substep_buffers(p));
+    hipStream_t st = (hipStream_t)stream;
+    double* ru = sub_field(p, 0);
+    double* rv = sub_field(p, 1);
+    double* rw = sub_field(p, 2);
+    double* rt = sub_field(p, 3);
+    SubstepArgs a{};
+    a.u = u;
+    a.v = v;
+    a.w = w;
+    a.t = t;
+    a.p = pr;
+    if (rho != 0.0) {
+        a.hpu = h_prev[0];
+        a.hpv = h_prev[1];
+        a.hpw = h_prev[2];
+        a.hpt = h_prev[3];
+    }
+    a.ru = ru;
+    a.rv = rv;
+    a.rw = rw;
+    a.rt = rt;
+    if (h_out) {
+        a.hu = h_out[0];
+        a.hv = h_out[1];
+        a.hw = h_out[2];
+        a.ht = h_out[3];
+    }
+    a.dt = dt;
+    a.nu = nu;
+    a.ka = kappa;
+    a.gam = gam;
+    a.rho = rho;
+    a.alp = alp;
+    PS_HIP(launch_explicit(p->gd, a, st), "explicit terms");
+    const double bnu = alp * dt * nu / 2.0, bka = alp * dt * kappa / 2.0;
+    double* fc = cn_slot(p, 0);
+    double* ff = cn_slot(p, 1);
+    double* fk = cn_slot(p, 2);
+    PS_HIP(launch_cn_factor(p->gd, PS_CENTER, bnu, fc, st), "cn factor");
+    PS_HIP(launch_cn_factor(p->gd, PS_FACE, bnu, ff, st), "cn factor");
+    PS_HIP(launch_cn_factor(p->gd, PS_FACE, bka, fk, st), "cn factor");
+    PS_HIP(launch_cn_solve_add(p->gd, PS_CENTER, fc, ru, u, st), "cn solve u");
+    PS_HIP(launch_cn_solve_add(p->gd, PS_CENTER, fc, rv, v, st), "cn solve v");
+    PS_HIP(launch_cn_solve_add(p->gd, PS_FACE, ff, rw, w, st), "cn solve w");
+    PS_HIP(launch_cn_solve_add(p->gd, PS_FACE, fk, rt, t, st), "cn solve T");
+    return project(p, u, v, w, pr, nullptr, alp * dt, bnu, stream, info);
 }
 
 ps_status rk3_substep_adjoint(ps_plan_t p, double dt, double nu, double kappa, const double* u, const double* v,
                               const double* w, const double* t, const double* pr, const double* const* g_out,
                               double* const* g_in, void* stream, ps_info* info) {
-    (void)dt; (void)nu; (void)kappa; (void)u; (void)v; (void)w; (void)t; (void)pr;
-    (void)g_out; (void)g_in; (void)stream; (void)info;
     PS_CHECK(check_plan(p));
-    return fail(PS_EINVAL, "rk3_substep_adjoint: not available in this build");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(PS_EINVAL, "dt must be positive");
+    if (!(nu >= 0) || !(kappa >= 0) || !std::isfinite(nu) || !std::isfinite(kappa))
+        return fail(PS_EINVAL, "nu and kappa must be non-negative");
+    PS_CHECK(check_ptr(u, "u"));
+    PS_CHECK(check_ptr(v, "v"));
+    PS_CHECK(check_ptr(w, "w"));
+    PS_CHECK(check_ptr(t, "t"));
+    PS_CHECK(check_ptr(pr, "p"));
+    if (!g_out || !g_in) return fail(PS_EINVAL, "g_out and g_in are required");
+    for (int q = 0; q < 5; ++q) {
+        PS_CHECK(check_ptr(g_out[q], "g_out[q]"));
+        PS_CHECK(check_ptr(g_in[q], "g_in[q]"));
+        for (int r = 0; r < 5; ++r)
+            if ((const void*)g_in[q] == (const void*)g_out[r]) return fail(PS_EINVAL, "g_in may not alias g_out");
+    }
+    PS_CHECK(ensure_substep_buffers(p));
+    hipStream_t st = (hipStream_t)stream;
+    const double gam = kGamma[0], alp = kGamma[0] + kRho[0];
+    const double bnu = alp * dt * nu / 2.0, bka = alp * dt * kappa / 2.0;
+    double* du = sub_field(p, 0);
+    double* dv = sub_field(p, 1);
+    double* dw = sub_field(p, 2);
+    double* lu = sub_field(p, 3);
+    double* lv = sub_field(p, 4);
+    double* lw = sub_field(p, 5);
+    double* lt = sub_field(p, 6);
+    // projection (linear in u*): cotangents of u*, v*, w*
+    ps_status r = project_adjoint(p, g_out[0], g_out[1], g_out[2], g_out[4], du, dv, dw, alp * dt, bnu, stream, info);
+    if (r != PS_OK && r != PS_ENOTCONVERGED) return r;
+    // Crank-Nicolson solves (linear): cotangents of the right-hand sides
+    double* fc = cn_slot(p, 0);
+    double* ff = cn_slot(p, 1);
+    double* fk = cn_slot(p, 2);
+    PS_HIP(launch_cn_factor(p->gd, PS_CENTER, bnu, fc, st), "cn factor");
+    PS_HIP(launch_cn_factor(p->gd, PS_FACE, bnu, ff, st), "cn factor");
+    PS_HIP(launch_cn_factor(p->gd, PS_FACE, bka, fk, st), "cn factor");
+    PS_HIP(launch_cn_solve_t(p->gd, PS_CENTER, fc, du, lu, st), "cn adjoint u");
+    PS_HIP(launch_cn_solve_t(p->gd, PS_CENTER, fc, dv, lv, st), "cn adjoint v");
+    PS_HIP(launch_cn_solve_t(p->gd, PS_FACE, ff, dw, lw, st), "cn adjoint w");
+    PS_HIP(launch_cn_solve_t(p->gd, PS_FACE, fk, g_out[3], lt, st), "cn adjoint T");
+    // explicit terms (bilinear advection at the input state, linear operators, buoyancy, pressure)
+    SubstepAdjArgs a{};
+    a.u = u;
+    a.v = v;
+    a.w = w;
+    a.t = t;
+    a.lu = lu;
+    a.lv = lv;
+    a.lw = lw;
+    a.lt = lt;
+    a.du = du;
+    a.dv = dv;
+    a.dw = dw;
+    a.dt_ = g_out[3];
+    a.dp = g_out[4];
+    a.gu = g_in[0];
+    a.gv = g_in[1];
+    a.gw = g_in[2];
+    a.gt = g_in[3];
+    a.gp = g_in[4];
+    a.dt = dt;
+    a.nu = nu;
+    a.ka = kappa;
+    a.gam = gam;
+    a.alp = alp;
+    PS_HIP(launch_explicit_adj(p->gd, a, st), "explicit adjoint");
+    return r;
 }
 
 ps_status ps_spectral_layout(ps_plan_t p, int* w_tile, int* nkxb) {

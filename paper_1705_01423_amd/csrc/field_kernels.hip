@@ -83,13 +83,14 @@ k_residual(const double* __restrict__ f, const double* __restrict__ mu, double m
         const int jm = (j == 0) ? g.ny - 1 : j - 1;
         const int jp = (j + 1 == g.ny) ? 0 : j + 1;
         const double xc = x[id];
-        const double lx = ((x[rowb + ip] - xc) / g.dx - (xc - x[rowb + im]) / g.dx) / g.dx;
-        const double ly = ((x[(size_t)k * plane + (size_t)jp * g.nx + i] - xc) / g.dy -
-                           (xc - x[(size_t)k * plane + (size_t)jm * g.nx + i]) / g.dy) / g.dy;
-        double fzp = 0.0, fzm = 0.0;
-        if (k + 1 < g.nz) fzp = (x[id + plane] - xc) / g.dzc[k + 1];
-        if (k > 0) fzm = (xc - x[id - plane]) / g.dzc[k];
-        const double lz = (fzp - fzm) / g.dz[k];
+        const double idx2 = 1.0 / (g.dx * g.dx), idy2 = 1.0 / (g.dy * g.dy);
+        const double lx = ((x[rowb + ip] - xc) - (xc - x[rowb + im])) * idx2;
+        const double ly = ((x[(size_t)k * plane + (size_t)jp * g.nx + i] - xc) -
+                           (xc - x[(size_t)k * plane + (size_t)jm * g.nx + i])) * idy2;
+        // o = 1/dzc at interior faces, 0 at the walls (zero flux)
+        const double fzp = (k + 1 < g.nz) ? (x[id + plane] - xc) * g.o[k + 1] : 0.0;
+        const double fzm = (k > 0) ? (xc - x[id - plane]) * g.o[k] : 0.0;
+        const double lz = (fzp - fzm) * g.idz[k];
         const double fc = f[id] - mu[0] * mu_scale;
         const double rv = fc - (lx + ly + lz);
         r[id] = rv;
@@ -102,14 +103,17 @@ k_residual(const double* __restrict__ f, const double* __restrict__ mu, double m
     }
 }
 
-// out[c] = sum over blocks of partial[blk * ncomp + c]; one block, fixed order.
+// out[blockIdx.x * ncomp + c] = sum of partial[b * ncomp + c] over the block's contiguous
+// range of b; fixed order for a fixed launch shape.
 __global__ void __launch_bounds__(256)
-k_reduce(const double* __restrict__ partial, int nblk, int ncomp, double* __restrict__ out) {
+k_reduce(const double* __restrict__ partial, int nblk, int ncomp, int per_block, double* __restrict__ out) {
+    const int b0 = blockIdx.x * per_block;
+    const int b1 = min(nblk, b0 + per_block);
     for (int c = 0; c < ncomp; ++c) {
         double s = 0.0;
-        for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += partial[(size_t)b * ncomp + c];
+        for (int b = b0 + threadIdx.x; b < b1; b += blockDim.x) s += partial[(size_t)b * ncomp + c];
         double v[1] = {s};
-        block_sum_store<1>(v, out + c);
+        block_sum_store<1>(v, out + (size_t)blockIdx.x * ncomp + c);
         __syncthreads();
     }
 }
@@ -320,8 +324,18 @@ hipError_t launch_nonfinite(const double* p, size_t n, unsigned* flag, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_reduce(const double* partial, int nblk, int ncomp, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, partial, nblk, ncomp, out);
+// Two passes when there are many partials: 1024-way split into `scratch`, then one block.
+hipError_t launch_reduce2(const double* partial, int nblk, int ncomp, double* scratch, double* out, hipStream_t st) {
+    if (nblk > 4096) {
+        const int nb1 = 1024;
+        const int per = (nblk + nb1 - 1) / nb1;
+        hipLaunchKernelGGL(k_reduce, dim3(nb1), dim3(256), 0, st, partial, nblk, ncomp, per, scratch);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, (const double*)scratch, nb1, ncomp, nb1, out);
+    } else {
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, partial, nblk, ncomp, nblk, out);
+    }
     return hipGetLastError();
 }
 

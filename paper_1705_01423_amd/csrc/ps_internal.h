@@ -34,6 +34,7 @@ struct GridDev {
     const double* dzw;   // nz+1, dzc interior, dz/2 at walls
     const double* lamx;  // nx/2+1
     const double* lamy;  // ny
+    const double* idz;   // nz, 1/dz
 };
 
 // Per-precision spectral machinery: twiddle tables and buffers.
@@ -91,7 +92,8 @@ hipError_t launch_adj_rhs(const GridDev& g, const double* gu, const double* gv, 
                           double* f, double inv_s, double c, hipStream_t st);
 hipError_t launch_adj_update(const GridDev& g, const double* gu, const double* gv, const double* gw,
                              const double* phi, double* ou, double* ov, double* ow, hipStream_t st);
-hipError_t launch_reduce(const double* partial, int nblk, int ncomp, double* out, hipStream_t st);
+// out[0..ncomp) = sums over nblk blocks of partial[b * ncomp + c]; scratch holds 1024 * ncomp doubles.
+hipError_t launch_reduce2(const double* partial, int nblk, int ncomp, double* scratch, double* out, hipStream_t st);
 hipError_t launch_fill(double* p, size_t n, double v, hipStream_t st);
 hipError_t launch_scale_planes(const GridDev& g, const double* in, double* out, const double* zs, int nplanes,
                                size_t plane, hipStream_t st);
@@ -99,5 +101,30 @@ hipError_t launch_cn_factor(const GridDev& g, int kind, double beta, double* fac
 hipError_t launch_cn_solve(const GridDev& g, int kind, const double* fac, double* x, hipStream_t st);
 hipError_t launch_cfl(const GridDev& g, const double* u, const double* v, const double* w, double* out,
                       hipStream_t st);
+
+// RK3 substep (substep_kernels.hip)
+struct SubstepArgs {
+    const double *u, *v, *w, *t, *p;
+    const double *hpu, *hpv, *hpw, *hpt;   // previous H (rho != 0)
+    double *ru, *rv, *rw, *rt;             // right-hand sides
+    double *hu, *hv, *hw, *ht;             // this substep's H (optional)
+    double dt, nu, ka, gam, rho, alp;
+};
+
+struct SubstepAdjArgs {
+    const double *u, *v, *w, *t;           // input state (advection is evaluated there)
+    const double *lu, *lv, *lw, *lt;       // cotangents of the right-hand sides
+    const double *du, *dv, *dw, *dt_, *dp; // direct cotangents of q* (and T', p')
+    double *gu, *gv, *gw, *gt, *gp;        // outputs
+    double dt, nu, ka, gam, alp;
+};
+
+hipError_t launch_explicit(const GridDev& g, const SubstepArgs& a, hipStream_t st);
+hipError_t launch_explicit_adj(const GridDev& g, const SubstepAdjArgs& a, hipStream_t st);
+// q += (I - beta Dzz)^-1 rhs (rhs is overwritten)
+hipError_t launch_cn_solve_add(const GridDev& g, int kind, const double* fac, double* rhs, double* q, hipStream_t st);
+// out = V (I - beta Dzz)^-1 V^-1 in  (transpose of the CN solve)
+hipError_t launch_cn_solve_t(const GridDev& g, int kind, const double* fac, const double* in, double* out,
+                             hipStream_t st);
 
 }  // namespace ps

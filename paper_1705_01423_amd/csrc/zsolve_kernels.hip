@@ -61,6 +61,258 @@ k_zsolve_seq(cx<T>* __restrict__ b, T* __restrict__ piv, int nz, int ny, int nkx
     }
 }
 
+// ---------------------------------------------------------------------------
+// Tiled z solve: one block per (kx tile, ky); the nz x W tile is read once into
+// registers and written once.  Lane (l, c) owns rows [l K, l K + K) of column c.
+// The sequential elimination is split into three chunked scans over l:
+//  (A) excesses: e_k = s_k + o_k e_{k-1} / (o_k + e_{k-1}) is the Moebius map of
+//      the non-negative matrix [[s_k + o_k, s_k o_k], [1, o_k]] (row 0: [[0, s_0],
+//      [0, 1]]), so chunk maps compose by 2x2 products of non-negative numbers
+//      (still subtraction-free); products are rescaled by powers of two.
+//  (B) forward sweep y_k = g_k + m_k y_{k-1}: affine maps, prefix scan.
+//  (C) back substitution P_k = rp_k y_k + o_{k+1} rp_k P_{k+1}: affine maps,
+//      suffix scan.
+// Each scan: sequential composition inside the lane, shuffles across the lanes
+// of one wave, and an LDS pass across waves.
+template <typename T>
+struct Mob {
+    T a, b, c, d;   // [[a, b], [c, d]]
+};
+
+template <typename T>
+__device__ __forceinline__ Mob<T> mob_mul(const Mob<T>& L, const Mob<T>& E) {
+    return {L.a * E.a + L.b * E.c, L.a * E.b + L.b * E.d, L.c * E.a + L.d * E.c, L.c * E.b + L.d * E.d};
+}
+
+template <typename T>
+__device__ __forceinline__ void mob_norm(Mob<T>& m) {
+    T mx = fmax(fmax(m.a, m.b), fmax(m.c, m.d));
+    if (mx > (T)0) {
+        int ex;
+        frexp(mx, &ex);
+        m.a = ldexp(m.a, -ex);
+        m.b = ldexp(m.b, -ex);
+        m.c = ldexp(m.c, -ex);
+        m.d = ldexp(m.d, -ex);
+    }
+}
+
+template <typename T>
+struct Aff {
+    T a;
+    cx<T> b;   // x -> a x + b
+};
+
+// L after E (L outer)
+template <typename T>
+__device__ __forceinline__ Aff<T> aff_mul(const Aff<T>& L, const Aff<T>& E) {
+    return {L.a * E.a, {L.a * E.b.x + L.b.x, L.a * E.b.y + L.b.y}};
+}
+
+template <typename T>
+__device__ __forceinline__ Mob<T> shfl_up_mob(const Mob<T>& m, int d) {
+    return {__shfl_up(m.a, d, 64), __shfl_up(m.b, d, 64), __shfl_up(m.c, d, 64), __shfl_up(m.d, d, 64)};
+}
+template <typename T>
+__device__ __forceinline__ Aff<T> shfl_up_aff(const Aff<T>& m, int d) {
+    return {__shfl_up(m.a, d, 64), {__shfl_up(m.b.x, d, 64), __shfl_up(m.b.y, d, 64)}};
+}
+template <typename T>
+__device__ __forceinline__ Aff<T> shfl_down_aff(const Aff<T>& m, int d) {
+    return {__shfl_down(m.a, d, 64), {__shfl_down(m.b.x, d, 64), __shfl_down(m.b.y, d, 64)}};
+}
+
+template <typename T, int K>
+__global__ void __launch_bounds__(1024)
+k_zsolve_scan(cx<T>* __restrict__ b, int nz, int ny, int nxh, const double* __restrict__ dz,
+              const double* __restrict__ o, const double* __restrict__ lamx, const double* __restrict__ lamy) {
+    constexpr int W = TileW<T>::value;
+    constexpr int LPW = 64 / W;   // lanes of one column inside a wave
+    __shared__ T xs[16 * W * 4];  // per-wave totals
+    const int tid = threadIdx.x;
+    const int c = tid % W;
+    const int l = tid / W;
+    const int wave = tid >> 6;
+    const int nwave = blockDim.x >> 6;
+    const int lw = l % LPW;
+    const int ky = blockIdx.x % ny;
+    const int kxb = blockIdx.x / ny;
+    const int kx = kxb * W + c;
+    const bool store = kx < nxh && !(kx == 0 && ky == 0);
+    const T lam = store ? (T)(lamx[kx] + lamy[ky]) : (T)1;
+    cx<T>* tile = b + (size_t)blockIdx.x * nz * W + c;
+    const int k0 = l * K;
+
+    cx<T> v[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int k = k0 + i;
+        v[i] = (k < nz) ? tile[(size_t)k * W] : cx<T>{(T)0, (T)0};
+    }
+
+    // ---- (A) excesses -------------------------------------------------------
+    Mob<T> acc = {(T)1, (T)0, (T)0, (T)1};
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int k = k0 + i;
+        if (k < nz) {
+            const T s = lam * (T)dz[k];
+            Mob<T> m;
+            if (k == 0) {
+                m = {(T)0, s, (T)0, (T)1};
+            } else {
+                const T ok = (T)o[k];
+                m = {s + ok, s * ok, (T)1, ok};
+            }
+            acc = mob_mul(m, acc);
+            mob_norm(acc);
+        }
+    }
+    Mob<T> inc = acc;
+#pragma unroll
+    for (int d = 1; d < LPW; d <<= 1) {
+        Mob<T> oth = shfl_up_mob(inc, d * W);
+        if (lw >= d) {
+            inc = mob_mul(inc, oth);
+            mob_norm(inc);
+        }
+    }
+    if (lw == LPW - 1) {
+        T* q = xs + (wave * W + c) * 4;
+        q[0] = inc.a;
+        q[1] = inc.b;
+        q[2] = inc.c;
+        q[3] = inc.d;
+    }
+    Mob<T> ex = shfl_up_mob(inc, W);
+    if (lw == 0) ex = {(T)1, (T)0, (T)0, (T)1};
+    __syncthreads();
+    Mob<T> pw = {(T)1, (T)0, (T)0, (T)1};
+    for (int w2 = 0; w2 < wave; ++w2) {
+        const T* q = xs + (w2 * W + c) * 4;
+        pw = mob_mul(Mob<T>{q[0], q[1], q[2], q[3]}, pw);
+        mob_norm(pw);
+    }
+    ex = mob_mul(ex, pw);
+    T eprev = (ex.d != (T)0) ? ex.b / ex.d : (T)0;   // e_{k0-1}
+    __syncthreads();
+
+    // ---- pivots and multipliers ----------------------------------------------
+    T mk[K], rp[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int k = k0 + i;
+        mk[i] = (T)0;
+        rp[i] = (T)0;
+        if (k < nz) {
+            const T s = lam * (T)dz[k];
+            T e;
+            if (k == 0) {
+                e = s;
+            } else {
+                const T ok = (T)o[k];
+                const T mm = (i == 0) ? ok / (ok + eprev) : ok * rp[i - 1];
+                mk[i] = mm;
+                e = s + mm * eprev;
+            }
+            rp[i] = (T)1 / ((T)o[k + 1] + e);
+            eprev = e;
+        }
+    }
+
+    // ---- (B) forward sweep ------------------------------------------------------
+    Aff<T> fa = {(T)1, {(T)0, (T)0}};
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int k = k0 + i;
+        if (k < nz) {
+            const T g = -(T)dz[k];
+            v[i] = {g * v[i].x, g * v[i].y};   // g_k = -dz_k F_k
+            fa = {mk[i] * fa.a, {mk[i] * fa.b.x + v[i].x, mk[i] * fa.b.y + v[i].y}};
+        }
+    }
+    Aff<T> finc = fa;
+#pragma unroll
+    for (int d = 1; d < LPW; d <<= 1) {
+        Aff<T> oth = shfl_up_aff(finc, d * W);
+        if (lw >= d) finc = aff_mul(finc, oth);
+    }
+    if (lw == LPW - 1) {
+        T* q = xs + (wave * W + c) * 4;
+        q[0] = finc.a;
+        q[1] = finc.b.x;
+        q[2] = finc.b.y;
+    }
+    Aff<T> fex = shfl_up_aff(finc, W);
+    if (lw == 0) fex = {(T)1, {(T)0, (T)0}};
+    __syncthreads();
+    Aff<T> fpw = {(T)1, {(T)0, (T)0}};
+    for (int w2 = 0; w2 < wave; ++w2) {
+        const T* q = xs + (w2 * W + c) * 4;
+        fpw = aff_mul(Aff<T>{q[0], {q[1], q[2]}}, fpw);
+    }
+    fex = aff_mul(fex, fpw);
+    cx<T> y = fex.b;   // y_{k0-1} (y_{-1} = 0)
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int k = k0 + i;
+        if (k < nz) {
+            y = {v[i].x + mk[i] * y.x, v[i].y + mk[i] * y.y};
+            v[i] = y;
+        }
+    }
+    __syncthreads();
+
+    // ---- (C) back substitution -------------------------------------------------
+    Aff<T> ba = {(T)1, {(T)0, (T)0}};
+#pragma unroll
+    for (int i = K - 1; i >= 0; --i) {
+        const int k = k0 + i;
+        if (k < nz) {
+            const T ak = (T)o[k + 1] * rp[i];
+            ba = {ak * ba.a, {ak * ba.b.x + rp[i] * v[i].x, ak * ba.b.y + rp[i] * v[i].y}};
+        }
+    }
+    Aff<T> binc = ba;
+#pragma unroll
+    for (int d = 1; d < LPW; d <<= 1) {
+        Aff<T> oth = shfl_down_aff(binc, d * W);
+        if (lw + d < LPW) binc = aff_mul(binc, oth);
+    }
+    if (lw == 0) {
+        T* q = xs + (wave * W + c) * 4;
+        q[0] = binc.a;
+        q[1] = binc.b.x;
+        q[2] = binc.b.y;
+    }
+    Aff<T> bex = shfl_down_aff(binc, W);
+    if (lw == LPW - 1) bex = {(T)1, {(T)0, (T)0}};
+    __syncthreads();
+    Aff<T> bpw = {(T)1, {(T)0, (T)0}};
+    for (int w2 = nwave - 1; w2 > wave; --w2) {
+        const T* q = xs + (w2 * W + c) * 4;
+        bpw = aff_mul(Aff<T>{q[0], {q[1], q[2]}}, bpw);
+    }
+    bex = aff_mul(bex, bpw);
+    cx<T> x = bex.b;   // solution just above this chunk (zero above the top wall)
+#pragma unroll
+    for (int i = K - 1; i >= 0; --i) {
+        const int k = k0 + i;
+        if (k < nz) {
+            const T ak = (T)o[k + 1] * rp[i];
+            x = {rp[i] * v[i].x + ak * x.x, rp[i] * v[i].y + ak * x.y};
+            v[i] = x;
+        }
+    }
+    if (store) {
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const int k = k0 + i;
+            if (k < nz) tile[(size_t)k * W] = v[i];
+        }
+    }
+}
+
 // inclusive scan over the 64 lanes of one wave
 __device__ __forceinline__ double wave_scan_incl(double v) {
     const int lane = threadIdx.x & 63;
@@ -148,6 +400,30 @@ k_zsolve00(cx<T>* __restrict__ b, int nz, int nxny, const double* __restrict__ d
 
 template <typename T>
 hipError_t launch_zsolve(const GridDev& g, const SpecDev<T>& s, hipStream_t st) {
+    constexpr int W = TileW<T>::value;
+    constexpr int LPW = 64 / W;
+    auto lanes = [&](int K) {
+        int lc = (g.nz + K - 1) / K;
+        return (lc + LPW - 1) / LPW * LPW;
+    };
+    const int nblk = s.nkxb * g.ny;
+    const int nxh = g.nx / 2 + 1;
+    if (W * lanes(8) <= 1024) {
+        hipLaunchKernelGGL((k_zsolve_scan<T, 8>), dim3(nblk), dim3(W * lanes(8)), 0, st, s.b, g.nz, g.ny, nxh, g.dz,
+                           g.o, g.lamx, g.lamy);
+    } else if (W * lanes(16) <= 1024) {
+        hipLaunchKernelGGL((k_zsolve_scan<T, 16>), dim3(nblk), dim3(W * lanes(16)), 0, st, s.b, g.nz, g.ny, nxh,
+                           g.dz, g.o, g.lamx, g.lamy);
+    } else {
+        hipLaunchKernelGGL((k_zsolve_scan<T, 32>), dim3(nblk), dim3(W * lanes(32)), 0, st, s.b, g.nz, g.ny, nxh,
+                           g.dz, g.o, g.lamx, g.lamy);
+    }
+    return hipGetLastError();
+}
+
+// Reference lane-per-column sweep (kept for measurement comparisons).
+template <typename T>
+hipError_t launch_zsolve_seq(const GridDev& g, const SpecDev<T>& s, hipStream_t st) {
     constexpr int W = TileW<T>::value;
     const size_t ncol = (size_t)s.nkxb * g.ny * W;
     const int nblk = (int)((ncol + 255) / 256);
