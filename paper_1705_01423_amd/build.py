@@ -13,9 +13,11 @@ from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-BUILD = os.path.join(HERE, "_build")
-LIB = os.path.join(HERE, "libps_mi355x.so")
+BUILD = os.environ.get("PS_BUILD_DIR") or os.path.join(HERE, "_build")
+LIB = os.environ.get("PS_LIB_OUT") or os.path.join(HERE, "libps_mi355x.so")
 ARCH = os.environ.get("PS_OFFLOAD_ARCH", "gfx950")
+# extra compile flags, e.g. launch-shape defines (-DPS_X_LDS=...) for tuning builds
+EXTRA = os.environ.get("PS_EXTRA_FLAGS", "").split()
 
 # (source, output object, extra defines)
 UNITS = [
@@ -42,7 +44,7 @@ def flags():
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-Wno-unused-command-line-argument",
         "-I", os.path.join(HERE, "..", "include"),
-    ]
+    ] + EXTRA
 
 
 def _compile(unit):

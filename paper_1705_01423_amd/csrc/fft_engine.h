@@ -261,9 +261,14 @@ __device__ __forceinline__ void pass_compute(cx<T>* v, int t, const cx<T>* __res
     }
 }
 
+// LDS slot of element e: one padding slot after every 16 elements, so that the
+// stride-r writes after a radix-r pass (r <= 16) spread over the LDS banks.
+__host__ __device__ constexpr int lds_pad(int e) { return e + (e >> 4); }
+__host__ __device__ constexpr int lds_len(int n) { return n + (n >> 4) + 1; }
+
 // Full transform.  base/stride address this transform's LDS scratch
-// (element e at base[e * stride], N elements).  All threads of the block must
-// call this (it synchronises the block between passes).
+// (element e at base[lds_pad(e) * stride], lds_len(N) slots).  All threads of
+// the block must call this (it synchronises the block between passes).
 template <typename T, int N, int EMAX, int S, class Ld, class St>
 __device__ __forceinline__ void fft_run(int t, cx<T>* base, int stride, const cx<T>* __restrict__ tw,
                                         Ld&& ld, St&& st) {
@@ -293,13 +298,13 @@ __device__ __forceinline__ void fft_run(int t, cx<T>* base, int stride, const cx
             const int k = j % Lp;
             const int o0 = (j - k) * rp + k;
 #pragma unroll
-            for (int m = 0; m < rp; ++m) base[(o0 + m * Lp) * stride] = v[b * rp + m];
+            for (int m = 0; m < rp; ++m) base[lds_pad(o0 + m * Lp) * stride] = v[b * rp + m];
         }
         __syncthreads();
 #pragma unroll
         for (int b = 0; b < E / r; ++b) {
 #pragma unroll
-            for (int m = 0; m < r; ++m) v[b * r + m] = base[(t + b * NT + m * (N / r)) * stride];
+            for (int m = 0; m < r; ++m) v[b * r + m] = base[lds_pad(t + b * NT + m * (N / r)) * stride];
         }
         pass_compute<T, N, EMAX, S, I>(v, t, tw);
     });

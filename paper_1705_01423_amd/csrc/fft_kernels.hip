@@ -19,31 +19,66 @@
 
 namespace ps {
 
-constexpr int kEmax = 16;
+// Elements per thread (the largest radix schedule fitting this many registers):
+// x transforms hold whole rows in LDS, so fewer elements per thread (one row per
+// wave) means less LDS per wave and more waves per CU.
+#ifndef PS_X_EMAX64
+#define PS_X_EMAX64 8
+#endif
+#ifndef PS_X_EMAX32
+#define PS_X_EMAX32 16
+#endif
+#ifndef PS_Y_EMAX
+#define PS_Y_EMAX 16
+#endif
+template <typename T>
+struct XEmax {
+    static constexpr int value = sizeof(T) == 8 ? PS_X_EMAX64 : PS_X_EMAX32;
+};
+constexpr int kYEmax = PS_Y_EMAX;
 
+// Launch shapes (tunable at build time; results do not depend on them).
+#ifndef PS_X_THREADS
+#define PS_X_THREADS 64
+#endif
+#ifndef PS_X_LDS
+#define PS_X_LDS 72000
+#endif
+#ifndef PS_Y_THREADS
+#define PS_Y_THREADS 512
+#endif
+#ifndef PS_Y_LDS
+#define PS_Y_LDS 140000
+#endif
+
+// Rows of one block: LDS row = lds_len(M) slots (odd for M >= 16, so that rows
+// start in different banks).
 template <typename T, int M>
 struct XShape {
-    using Sh = FftShape<M, kEmax>;
+    static constexpr int EM = XEmax<T>::value;
+    using Sh = FftShape<M, EM>;
     static constexpr int NT = Sh::NT;
-    static constexpr int LROW = M;
-    static constexpr int R0 = 256 / NT > 0 ? 256 / NT : 1;
-    static constexpr int RL = (65536 / (LROW * (int)sizeof(cx<T>))) > 0 ? (65536 / (LROW * (int)sizeof(cx<T>))) : 1;
+    static constexpr int LROW = lds_len(M);
+    static constexpr int R0 = PS_X_THREADS / NT > 0 ? PS_X_THREADS / NT : 1;
+    static constexpr int RL0 = PS_X_LDS / (LROW * (int)sizeof(cx<T>));
+    static constexpr int RL = RL0 > 0 ? RL0 : 1;
     static constexpr int R = R0 < RL ? R0 : RL;
     static constexpr int THREADS = R * NT;
     static constexpr size_t LDS = (size_t)R * LROW * sizeof(cx<T>);
 };
 
+// Columns of one block (a power of two dividing the tile width).
 template <typename T, int N>
 struct YShape {
-    using Sh = FftShape<N, kEmax>;
+    using Sh = FftShape<N, kYEmax>;
     static constexpr int NT = Sh::NT;
     static constexpr int W = TileW<T>::value;
-    static constexpr int A = 65536 / (N * (int)sizeof(cx<T>));
-    static constexpr int B = 512 / NT;
+    static constexpr int A = PS_Y_LDS / (lds_len(N) * (int)sizeof(cx<T>));
+    static constexpr int B = PS_Y_THREADS / NT;
     static constexpr int WY0 = (W < A ? W : A) < B ? (W < A ? W : A) : B;
-    static constexpr int WY = WY0 >= 8 ? 8 : (WY0 >= 4 ? 4 : (WY0 >= 2 ? 2 : 1));
+    static constexpr int WY = WY0 >= 16 ? 16 : (WY0 >= 8 ? 8 : (WY0 >= 4 ? 4 : (WY0 >= 2 ? 2 : 1)));
     static constexpr int THREADS = WY * NT;
-    static constexpr size_t LDS = (size_t)N * WY * sizeof(cx<T>);
+    static constexpr size_t LDS = (size_t)lds_len(N) * WY * sizeof(cx<T>);
 };
 
 // ---------------------------------------------------------------------------
@@ -74,15 +109,17 @@ k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny,
         wsum += v.x + v.y;
         return cx<T>{(T)v.x, (T)v.y};
     };
-    auto st = [&](int e, cx<T> val) { lrow[e] = val; };
-    fft_run<T, M, kEmax, -1>(t, lrow, 1, tw, ld, st);
+    auto st = [&](int e, cx<T> val) { lrow[lds_pad(e)] = val; };
+    fft_run<T, M, X::EM, -1>(t, lrow, 1, tw, ld, st);
     __syncthreads();
     const int ntot = nkxb * R * W;
+    const int row0 = blockIdx.x * R;
+    const int z0 = row0 / ny, y0 = row0 - z0 * ny;
     for (int q = tid; q < ntot; q += X::THREADS) {
         const int w = q % W;
         const int r2 = (q / W) % R;
         const int kxb = q / (W * R);
-        const int row2 = blockIdx.x * R + r2;
+        const int row2 = row0 + r2;
         if (row2 >= nrows) continue;
         const int kx = kxb * W + w;
         const cx<T>* zr = smem + r2 * LROW;
@@ -96,14 +133,18 @@ k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny,
         } else if (kx > M) {
             xv = {(T)0, (T)0};
         } else {
-            cx<T> a = zr[kx];
-            cx<T> b = conjg(zr[M - kx]);
+            cx<T> a = zr[lds_pad(kx)];
+            cx<T> b = conjg(zr[lds_pad(M - kx)]);
             cx<T> fe = scal(a + b, (T)0.5);
             cx<T> d = a - b;
             cx<T> fo = {(T)0.5 * d.y, -(T)0.5 * d.x};
             xv = fe + cmul(ptw[kx], fo);
         }
-        const int z = row2 / ny, y = row2 - (row2 / ny) * ny;
+        int z = z0, y = y0 + r2;
+        if (y >= ny) {   // the block's rows cross into the next plane(s)
+            z += y / ny;
+            y -= (y / ny) * ny;
+        }
         out[(((size_t)z * nkxb + kxb) * ny + y) * W + w] = xv;
     }
     if (partial) {
@@ -127,17 +168,23 @@ k_xinv(const cx<T>* __restrict__ in, double* __restrict__ out, int nrows, int ny
     __shared__ cx<T> nyq[R];   // X_M of each row (the LDS rows hold k < M)
     const int tid = threadIdx.x;
     const int ntot = nkxb * R * W;
+    const int row0 = blockIdx.x * R;
+    const int z0 = row0 / ny, y0 = row0 - z0 * ny;
     for (int q = tid; q < ntot; q += X::THREADS) {
         const int w = q % W;
         const int r2 = (q / W) % R;
         const int kxb = q / (W * R);
-        const int row2 = blockIdx.x * R + r2;
+        const int row2 = row0 + r2;
         const int kx = kxb * W + w;
         if (row2 >= nrows || kx > M) continue;
-        const int z = row2 / ny, y = row2 - (row2 / ny) * ny;
+        int z = z0, y = y0 + r2;
+        if (y >= ny) {   // the block's rows cross into the next plane(s)
+            z += y / ny;
+            y -= (y / ny) * ny;
+        }
         const cx<T> xv = in[(((size_t)z * nkxb + kxb) * ny + y) * W + w];
         if (kx < M)
-            smem[r2 * LROW + kx] = xv;
+            smem[r2 * LROW + lds_pad(kx)] = xv;
         else
             nyq[r2] = xv;
     }
@@ -154,8 +201,8 @@ k_xinv(const cx<T>* __restrict__ in, double* __restrict__ out, int nrows, int ny
             xa = {lrow[0].x, (T)0};
             xb = {nyq[rl].x, (T)0};
         } else {
-            xa = lrow[e];
-            xb = lrow[M - e];
+            xa = lrow[lds_pad(e)];
+            xb = lrow[lds_pad(M - e)];
         }
         cx<T> xbc = conjg(xb);
         cx<T> a = xa + xbc;
@@ -181,7 +228,7 @@ k_xinv(const cx<T>* __restrict__ in, double* __restrict__ out, int nrows, int ny
         s_o2 += o.x * o.x + o.y * o.y;
         s_o += o.x + o.y;
     };
-    fft_run<T, M, kEmax, +1>(t, lrow, 1, tw, ld, st);
+    fft_run<T, M, X::EM, +1>(t, lrow, 1, tw, ld, st);
     if (partial) {
         const double dzr = valid ? dz[row / ny] : 0.0;
         double v[3] = {s_d2, s_o2, s_o * dzr};
@@ -203,7 +250,7 @@ k_yfft(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int nz, int nkxb,
     const int tid = threadIdx.x;
     const int c = tid % WY;
     const int t = tid / WY;
-    int bid = blockIdx.x;
+    int bid = xcd_remap(blockIdx.x, gridDim.x);
     const int csub = bid % NSUB;
     bid /= NSUB;
     const int kxb = bid % nkxb;
@@ -225,7 +272,7 @@ k_yfft(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int nz, int nkxb,
         else
             out[abase + (size_t)e * W] = val;
     };
-    fft_run<T, N, kEmax, S>(t, smem + c, WY, tw, ld, st);
+    fft_run<T, N, kYEmax, S>(t, smem + c, WY, tw, ld, st);
 }
 
 // ---------------------------------------------------------------------------

@@ -24,6 +24,14 @@ struct TileW<float> {
     static constexpr int value = 16;
 };
 
+// Workgroups are dealt to the 8 XCDs round-robin; renumber them so that blocks
+// with neighbouring logical indices (which share cache lines) run on one XCD and
+// share its L2.  Identity when the grid is not a multiple of 8.
+__device__ __forceinline__ int xcd_remap(int bid, int nblk) {
+    if (nblk % 8 != 0) return bid;
+    return (bid % 8) * (nblk / 8) + bid / 8;
+}
+
 // Device-side grid tables (FP64).  Built once per plan on the host.
 struct GridDev {
     int nx, ny, nz;

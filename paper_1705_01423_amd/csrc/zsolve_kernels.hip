@@ -122,25 +122,43 @@ __device__ __forceinline__ Aff<T> shfl_down_aff(const Aff<T>& m, int d) {
     return {__shfl_down(m.a, d, 64), {__shfl_down(m.b.x, d, 64), __shfl_down(m.b.y, d, 64)}};
 }
 
+// Rows per lane: 4 for FP64 (72 VGPRs), 8 for FP32; blocks of up to 1024 threads,
+// so columns of up to 512 rows run tiled (taller ones use the lane-per-column sweep).
+template <typename T>
+struct ZRows {
+    static constexpr int value = sizeof(T) == 8 ? 4 : 8;
+};
+// Columns per block: half a tile, so that 512-thread blocks at nz = 512 let two or
+// more blocks share a CU and overlap one block's loads with another's scans.
+template <typename T>
+struct ZCols {
+    static constexpr int value = TileW<T>::value / 2;
+};
+
 template <typename T, int K>
 __global__ void __launch_bounds__(1024)
 k_zsolve_scan(cx<T>* __restrict__ b, int nz, int ny, int nxh, const double* __restrict__ dz,
               const double* __restrict__ o, const double* __restrict__ lamx, const double* __restrict__ lamy) {
     constexpr int W = TileW<T>::value;
-    constexpr int LPW = 64 / W;   // lanes of one column inside a wave
-    __shared__ T xs[16 * W * 4];  // per-wave totals
+    constexpr int WZ = ZCols<T>::value;   // columns of this block (a sub-tile of the W-wide tile)
+    constexpr int NSUB = W / WZ;
+    constexpr int LPW = 64 / WZ;          // lanes of one column inside a wave
+    __shared__ T xs[16 * WZ * 4];         // per-wave totals
     const int tid = threadIdx.x;
-    const int c = tid % W;
-    const int l = tid / W;
+    const int c = tid % WZ;
+    const int l = tid / WZ;
     const int wave = tid >> 6;
     const int nwave = blockDim.x >> 6;
     const int lw = l % LPW;
-    const int ky = blockIdx.x % ny;
-    const int kxb = blockIdx.x / ny;
-    const int kx = kxb * W + c;
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int csub = bid % NSUB;
+    const int tile_id = bid / NSUB;
+    const int ky = tile_id % ny;
+    const int kxb = tile_id / ny;
+    const int kx = kxb * W + csub * WZ + c;
     const bool store = kx < nxh && !(kx == 0 && ky == 0);
     const T lam = store ? (T)(lamx[kx] + lamy[ky]) : (T)1;
-    cx<T>* tile = b + (size_t)blockIdx.x * nz * W + c;
+    cx<T>* tile = b + (size_t)tile_id * nz * W + csub * WZ + c;
     const int k0 = l * K;
 
     cx<T> v[K];
@@ -171,25 +189,25 @@ k_zsolve_scan(cx<T>* __restrict__ b, int nz, int ny, int nxh, const double* __re
     Mob<T> inc = acc;
 #pragma unroll
     for (int d = 1; d < LPW; d <<= 1) {
-        Mob<T> oth = shfl_up_mob(inc, d * W);
+        Mob<T> oth = shfl_up_mob(inc, d * WZ);
         if (lw >= d) {
             inc = mob_mul(inc, oth);
             mob_norm(inc);
         }
     }
     if (lw == LPW - 1) {
-        T* q = xs + (wave * W + c) * 4;
+        T* q = xs + (wave * WZ + c) * 4;
         q[0] = inc.a;
         q[1] = inc.b;
         q[2] = inc.c;
         q[3] = inc.d;
     }
-    Mob<T> ex = shfl_up_mob(inc, W);
+    Mob<T> ex = shfl_up_mob(inc, WZ);
     if (lw == 0) ex = {(T)1, (T)0, (T)0, (T)1};
     __syncthreads();
     Mob<T> pw = {(T)1, (T)0, (T)0, (T)1};
     for (int w2 = 0; w2 < wave; ++w2) {
-        const T* q = xs + (w2 * W + c) * 4;
+        const T* q = xs + (w2 * WZ + c) * 4;
         pw = mob_mul(Mob<T>{q[0], q[1], q[2], q[3]}, pw);
         mob_norm(pw);
     }
@@ -234,21 +252,21 @@ k_zsolve_scan(cx<T>* __restrict__ b, int nz, int ny, int nxh, const double* __re
     Aff<T> finc = fa;
 #pragma unroll
     for (int d = 1; d < LPW; d <<= 1) {
-        Aff<T> oth = shfl_up_aff(finc, d * W);
+        Aff<T> oth = shfl_up_aff(finc, d * WZ);
         if (lw >= d) finc = aff_mul(finc, oth);
     }
     if (lw == LPW - 1) {
-        T* q = xs + (wave * W + c) * 4;
+        T* q = xs + (wave * WZ + c) * 4;
         q[0] = finc.a;
         q[1] = finc.b.x;
         q[2] = finc.b.y;
     }
-    Aff<T> fex = shfl_up_aff(finc, W);
+    Aff<T> fex = shfl_up_aff(finc, WZ);
     if (lw == 0) fex = {(T)1, {(T)0, (T)0}};
     __syncthreads();
     Aff<T> fpw = {(T)1, {(T)0, (T)0}};
     for (int w2 = 0; w2 < wave; ++w2) {
-        const T* q = xs + (w2 * W + c) * 4;
+        const T* q = xs + (w2 * WZ + c) * 4;
         fpw = aff_mul(Aff<T>{q[0], {q[1], q[2]}}, fpw);
     }
     fex = aff_mul(fex, fpw);
@@ -276,21 +294,21 @@ k_zsolve_scan(cx<T>* __restrict__ b, int nz, int ny, int nxh, const double* __re
     Aff<T> binc = ba;
 #pragma unroll
     for (int d = 1; d < LPW; d <<= 1) {
-        Aff<T> oth = shfl_down_aff(binc, d * W);
+        Aff<T> oth = shfl_down_aff(binc, d * WZ);
         if (lw + d < LPW) binc = aff_mul(binc, oth);
     }
     if (lw == 0) {
-        T* q = xs + (wave * W + c) * 4;
+        T* q = xs + (wave * WZ + c) * 4;
         q[0] = binc.a;
         q[1] = binc.b.x;
         q[2] = binc.b.y;
     }
-    Aff<T> bex = shfl_down_aff(binc, W);
+    Aff<T> bex = shfl_down_aff(binc, WZ);
     if (lw == LPW - 1) bex = {(T)1, {(T)0, (T)0}};
     __syncthreads();
     Aff<T> bpw = {(T)1, {(T)0, (T)0}};
     for (int w2 = nwave - 1; w2 > wave; --w2) {
-        const T* q = xs + (w2 * W + c) * 4;
+        const T* q = xs + (w2 * WZ + c) * 4;
         bpw = aff_mul(Aff<T>{q[0], {q[1], q[2]}}, bpw);
     }
     bex = aff_mul(bex, bpw);
@@ -401,33 +419,24 @@ k_zsolve00(cx<T>* __restrict__ b, int nz, int nxny, const double* __restrict__ d
 template <typename T>
 hipError_t launch_zsolve(const GridDev& g, const SpecDev<T>& s, hipStream_t st) {
     constexpr int W = TileW<T>::value;
-    constexpr int LPW = 64 / W;
+    constexpr int WZ = ZCols<T>::value;
+    constexpr int LPW = 64 / WZ;
     auto lanes = [&](int K) {
         int lc = (g.nz + K - 1) / K;
         return (lc + LPW - 1) / LPW * LPW;
     };
-    const int nblk = s.nkxb * g.ny;
+    const int nblk = s.nkxb * g.ny * (W / WZ);
     const int nxh = g.nx / 2 + 1;
-    if (W * lanes(8) <= 1024) {
-        hipLaunchKernelGGL((k_zsolve_scan<T, 8>), dim3(nblk), dim3(W * lanes(8)), 0, st, s.b, g.nz, g.ny, nxh, g.dz,
+    constexpr int K = ZRows<T>::value;
+    if (WZ * lanes(K) <= 1024) {
+        hipLaunchKernelGGL((k_zsolve_scan<T, K>), dim3(nblk), dim3(WZ * lanes(K)), 0, st, s.b, g.nz, g.ny, nxh, g.dz,
                            g.o, g.lamx, g.lamy);
-    } else if (W * lanes(16) <= 1024) {
-        hipLaunchKernelGGL((k_zsolve_scan<T, 16>), dim3(nblk), dim3(W * lanes(16)), 0, st, s.b, g.nz, g.ny, nxh,
-                           g.dz, g.o, g.lamx, g.lamy);
-    } else {
-        hipLaunchKernelGGL((k_zsolve_scan<T, 32>), dim3(nblk), dim3(W * lanes(32)), 0, st, s.b, g.nz, g.ny, nxh,
-                           g.dz, g.o, g.lamx, g.lamy);
+        return hipGetLastError();
     }
-    return hipGetLastError();
-}
-
-// Reference lane-per-column sweep (kept for measurement comparisons).
-template <typename T>
-hipError_t launch_zsolve_seq(const GridDev& g, const SpecDev<T>& s, hipStream_t st) {
-    constexpr int W = TileW<T>::value;
+    // taller columns: one lane per column, pivots kept in the scratch buffer
     const size_t ncol = (size_t)s.nkxb * g.ny * W;
-    const int nblk = (int)((ncol + 255) / 256);
-    hipLaunchKernelGGL((k_zsolve_seq<T>), dim3(nblk), dim3(256), 0, st, s.b, s.piv, g.nz, g.ny, s.nkxb,
+    const int nblk_seq = (int)((ncol + 255) / 256);
+    hipLaunchKernelGGL((k_zsolve_seq<T>), dim3(nblk_seq), dim3(256), 0, st, s.b, s.piv, g.nz, g.ny, s.nkxb,
                        g.nx / 2 + 1, g.dz, g.o, g.lamx, g.lamy);
     return hipGetLastError();
 }

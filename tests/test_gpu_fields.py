@@ -67,7 +67,7 @@ def test_cn_solve(kind):
 
 
 def test_cfl():
-    g, plan = grids(20, 12, 9)
+    g, plan = grids(24, 12, 9)
     rng = np.random.default_rng(4)
     u = torch.as_tensor(rng.standard_normal(plan.centre_shape))
     v = torch.as_tensor(rng.standard_normal(plan.centre_shape))
@@ -79,7 +79,7 @@ def test_cfl():
 
 def test_solve_adjoint_vs_autograd():
     banner("solve adjoint")
-    g, plan = grids(24, 20, 18, 1.5, 1.0)
+    g, plan = grids(24, 24, 18, 1.5, 1.0)
     rng = np.random.default_rng(5)
     f = torch.as_tensor(rng.standard_normal(plan.centre_shape)).requires_grad_(True)
     gphi = torch.as_tensor(rng.standard_normal(plan.centre_shape))
@@ -191,8 +191,8 @@ def test_substep_increment_parity():
 
 def test_substep_adjoint_vs_autograd():
     banner("substep adjoint")
-    g, plan = grids(12, 10, 8, precision="fp64")
-    state = _rb(12, 10, 8, seed=13, unoise=0.1)
+    g, plan = grids(12, 12, 8, precision="fp64")
+    state = _rb(12, 12, 8, seed=13, unoise=0.1)
     dt, nu, ka = 2e-2, 1e-2, 8e-3
     rng = np.random.default_rng(14)
     cot = [torch.as_tensor(rng.standard_normal(x.shape)) for x in state]

@@ -90,6 +90,12 @@ def test_stage_z_solve(shape, prec, tol):
     assert rel(got, ref) < tol
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 1e-5)])
+def test_stage_z_solve_tall(prec, tol):
+    """Columns taller than one block's tile (lane-per-column fallback)."""
+    test_stage_z_solve((8, 6, 600), prec, tol)
+
+
 @pytest.mark.parametrize("shape", SHAPES)
 def test_solve_fp64_parity(shape):
     banner(f"solve fp64 {shape}")
