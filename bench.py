@@ -40,6 +40,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-refined", action="store_true")
     ap.add_argument("--stage-reps", type=int, default=10)
+    ap.add_argument("--no-extra", action="store_true", help="skip the projection/adjoint/substep legs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this library runs one box on one GPU; runs on more than one GPU are not supported",
@@ -179,6 +180,10 @@ def main():
                   "rhs_rel_diff_gpu_vs_oracle": float((f.cpu() - fo).norm() / fo.norm())}
         log(f"parity {parity}")
 
+    del f, phi, plan
+    torch.cuda.empty_cache()
+    extra = {} if args.no_extra else other_workloads(args)
+
     out = {
         "metric": "Poisson solves/s at 1024x1024x512 (FP64)",
         "value": round(1.0 / t_fp64, 3),
@@ -206,8 +211,109 @@ def main():
         "cpu_baseline": cpu_baseline,
         "parity": parity,
         "compat_defect": info64["compat_defect"],
+        "other_workloads": extra,
     }
     print(json.dumps(out), flush=True)
+
+
+def _event_ms(fn, reps):
+    import torch
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        fn()
+    e1.record(st)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def other_workloads(args):
+    """Projection (512^2 x 384), adjoint/forward ratio (256^2 x 192), RK3 substep and its
+    adjoint (768^2 x 512, FP32-refined Poisson), each on its own seeded input."""
+    import math
+    import torch
+
+    from paper_1705_01423_amd import synth
+    from paper_1705_01423_amd.api import Plan
+
+    res = {}
+    # ---- projection + pressure update, 512 x 512 x 384 ----
+    cfg = synth.CONFIGS["c2"]
+    zf = synth.zfaces(cfg.nz, cfg.alpha)
+    log("projection 512x512x384")
+    u, v, w = (torch.as_tensor(a).to("cuda") for a in synth.mode_velocity(cfg))
+    plan = Plan(cfg.nx, cfg.ny, cfg.nz, cfg.lx, cfg.ly, zf, precision="fp64")
+    us, vs, ws = u.clone(), v.clone(), w.clone()
+    p = torch.zeros_like(u)
+
+    def proj():
+        u.copy_(us)
+        v.copy_(vs)
+        w.copy_(ws)
+        plan.project(u, v, w, p, None, 1.0, 0.0, want_info=False)
+
+    proj()
+    copy_ms = _event_ms(lambda: (u.copy_(us), v.copy_(vs), w.copy_(ws)), 3)
+    t = _event_ms(proj, 5) - copy_ms
+    npts = cfg.nx * cfg.ny * cfg.nz
+    res["project_512x512x384"] = {"ms": round(t, 3), "gpoints_per_s": round(npts / t / 1e6, 3),
+                                  "model_bytes_per_point": 184, "model_gbs": round(184 * npts / t / 1e6, 1)}
+    del u, v, w, us, vs, ws, p, plan
+    torch.cuda.empty_cache()
+
+    # ---- adjoint / forward cost, 256 x 256 x 192 ----
+    cfg = synth.CONFIGS["c4"]
+    zf = synth.zfaces(cfg.nz, cfg.alpha)
+    log("projection adjoint 256x256x192")
+    u, v, w = (torch.as_tensor(a).to("cuda") for a in synth.mode_velocity(cfg))
+    om = [torch.as_tensor(a).to("cuda") for a in synth.face_weights(cfg)]
+    plan = Plan(cfg.nx, cfg.ny, cfg.nz, cfg.lx, cfg.ly, zf, precision="fp64")
+    us, vs, ws = u.clone(), v.clone(), w.clone()
+    fwd = _event_ms(lambda: plan.project(us, vs, ws, None, None, 1.0, 0.0, want_info=False), 10)
+    adj = _event_ms(lambda: plan.project_adjoint(om[0], om[1], om[2], None, 1.0, 0.0), 10)
+    res["adjoint_256x256x192"] = {"forward_ms": round(fwd, 3), "adjoint_ms": round(adj, 3),
+                                  "adjoint_over_forward": round(adj / fwd, 3)}
+    del u, v, w, us, vs, ws, om, plan
+    torch.cuda.empty_cache()
+
+    # ---- RK3 substep and its adjoint, 768 x 768 x 512, Ra = 1e8, Pr = 1 ----
+    cfg = synth.CONFIGS["c5"]
+    zf = synth.zfaces(cfg.nz, cfg.alpha)
+    log("rk3 substep 768x768x512")
+    ra, pr = cfg.extra["ra"], cfg.extra["pr"]
+    nu, ka = math.sqrt(pr / ra), 1.0 / math.sqrt(ra * pr)
+    saved = [torch.as_tensor(a).to("cuda") for a in synth.rb_state(cfg)]
+    st = [a.clone() for a in saved]
+    plan = Plan(cfg.nx, cfg.ny, cfg.nz, cfg.lx, cfg.ly, zf, precision="fp32_refined")
+    dt = 1.3 / float(plan.cfl(saved[0], saved[1], saved[2]).item())   # CFL 1.3 (Listing 1 number)
+
+    def reset():
+        for a, b in zip(st, saved):
+            a.copy_(b)
+
+    infos = []
+
+    def step():
+        reset()
+        infos.append(plan.substep(1, dt, nu, ka, *st))
+
+    step()
+    reset_ms = _event_ms(reset, 3)
+    fwd = _event_ms(step, 3) - reset_ms
+    cot = [torch.randn_like(a) for a in saved]
+    for c in (cot[2], cot[3]):
+        c[0] = 0
+        c[-1] = 0
+    plan.substep_adjoint(dt, nu, ka, *saved, cot)
+    adj = _event_ms(lambda: plan.substep_adjoint(dt, nu, ka, *saved, cot), 3)
+    npts = cfg.nx * cfg.ny * cfg.nz
+    res["rk3_substep_768x768x512"] = {"dt": dt, "forward_ms": round(fwd, 3), "adjoint_ms": round(adj, 3),
+                                      "adjoint_over_forward": round(adj / fwd, 3),
+                                      "poisson_iterations": infos[-1]["iterations"],
+                                      "gpoints_per_s": round(npts / fwd / 1e6, 3)}
+    return res
 
 
 if __name__ == "__main__":

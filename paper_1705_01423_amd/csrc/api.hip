@@ -1,9 +1,11 @@
 // C ABI of the pressure-Poisson library: plan, workspace, entry points.
 // Kernels live in fft_kernels.hip, zsolve_kernels.hip, field_kernels.hip and
 // substep_kernels.hip; this file validates arguments and sequences launches.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -84,6 +86,7 @@ struct ps_plan_s {
     double* small;    // 64 + cn factors
     double* cnfac;    // 3 (nz+1) * 2
     int nblk_max;
+    int chunk = 0;    // planes per x/y chunk (0: whole box per launch)
     // substep temporaries (allocated on first use)
     double* sub_buf = nullptr;
     size_t sub_bytes = 0;
@@ -272,19 +275,47 @@ double* sub_field(ps_plan_t p, int q) {
 template <typename T>
 ps_status spectral_solve(ps_plan_t p, const double* in, double* out, int mode, const double* mu_dev,
                          double mu_scale, const double* zin, const double* zout, bool want_wsum,
-                         bool want_norms, hipStream_t st) {
+                         bool want_norms, hipStream_t st, const double* resid_x = nullptr) {
+    // resid_x != NULL: the transformed input is the refinement residual (in - mean) - L resid_x,
+    // formed inside the x transform; its norms go to R_R2 / R_F2.
     const GridDev& g = p->gd;
     SpecDev<T> s = spec_of<T>(p);
     const int nbx = xfwd_blocks<T>(g);
-    PS_HIP(launch_xfwd<T>(g, s, in, zin, want_wsum ? p->partial : nullptr, st), "x forward FFT");
+    const double scale = 1.0 / ((double)p->nx * (double)p->ny);
+    // Plane chunks: the x and y stages run chunk by chunk through the first planes of
+    // buffer a, so that this small intermediate can stay in the last-level cache.
+    const int P = (p->chunk > 0 && p->chunk < g.nz && nbx % g.nz == 0) ? p->chunk : g.nz;
+    const int bpp = nbx / g.nz;   // x-stage blocks per plane (when chunking)
+    for (int z0 = 0; z0 < g.nz; z0 += P) {
+        SpecDev<T> sc = s;
+        if (P < g.nz) {
+            sc.z0 = z0;
+            sc.nzc = std::min(P, g.nz - z0);
+        }
+        if (resid_x)
+            PS_HIP(launch_xfwd<T>(g, sc, in, nullptr, p->partial + (size_t)2 * bpp * z0, st, resid_x,
+                                  p->small + R_WSUM, inv_den(p)),
+                   "x forward FFT (residual)");
+        else
+            PS_HIP(launch_xfwd<T>(g, sc, in, zin, want_wsum ? p->partial + (size_t)bpp * z0 : nullptr, st),
+                   "x forward FFT");
+        PS_HIP(launch_yfwd<T>(g, sc, st), "y forward FFT");
+    }
+    if (resid_x) PS_HIP(launch_reduce2(p->partial, nbx, 2, p->red_scratch, p->small + R_R2, st), "reduce");
     if (want_wsum) PS_HIP(launch_reduce2(p->partial, nbx, 1, p->red_scratch, p->small + R_WSUM, st), "reduce");
-    PS_HIP(launch_yfwd<T>(g, s, st), "y forward FFT");
     PS_HIP(launch_zsolve<T>(g, s, st), "z solve");
     PS_HIP(launch_zsolve00<T>(g, s, p->small + R_DEFECT, st), "z solve (0,0)");
-    PS_HIP(launch_yinv<T>(g, s, st), "y inverse FFT");
-    const double scale = 1.0 / ((double)p->nx * (double)p->ny);
-    PS_HIP(launch_xinv<T>(g, s, out, scale, mode, mu_dev, mu_scale, zout, want_norms ? p->partial : nullptr, st),
-           "x inverse FFT");
+    for (int z0 = 0; z0 < g.nz; z0 += P) {
+        SpecDev<T> sc = s;
+        if (P < g.nz) {
+            sc.z0 = z0;
+            sc.nzc = std::min(P, g.nz - z0);
+        }
+        PS_HIP(launch_yinv<T>(g, sc, st), "y inverse FFT");
+        PS_HIP(launch_xinv<T>(g, sc, out, scale, mode, mu_dev, mu_scale, zout,
+                              want_norms ? p->partial + (size_t)3 * bpp * z0 : nullptr, st),
+               "x inverse FFT");
+    }
     if (want_norms) PS_HIP(launch_reduce2(p->partial, nbx, 3, p->red_scratch, p->small + R_D2, st), "reduce");
     return PS_OK;
 }
@@ -328,14 +359,12 @@ ps_status solve_impl(ps_plan_t p, const double* in, double* out, const double* z
             // Linear convergence: with contraction rho = |d_i| / |d_{i-1}| (|d_0| = |x|), the error
             // left after correction i is about rho |d_i|; stop when that estimate meets the tolerance.
             double prev = 1.0;
-            double* r = (f == p->rbuf) ? p->fbuf : p->rbuf;
             bool converged = false;
             for (int it = 0; it < p->max_iter; ++it) {
-                PS_HIP(launch_residual(p->gd, f, p->small + R_WSUM, inv_den(p), out, r, p->partial, st),
-                       "residual");
-                PS_HIP(launch_reduce2(p->partial, residual_blocks(p), 2, p->red_scratch, p->small + R_R2, st), "reduce");
-                PS_CHECK(spectral_solve<float>(p, r, out, 1, p->small + R_XW, inv_den(p), nullptr, nullptr, false,
-                                               true, st));
+                // correction: residual of the current iterate (formed in the x transform), FP32 solve,
+                // FP64 update with the gauge re-imposed
+                PS_CHECK(spectral_solve<float>(p, f, out, 1, p->small + R_XW, inv_den(p), nullptr, nullptr, false,
+                                               true, st, out));
                 loc.iterations++;
                 PS_CHECK(read_small(p, st));
                 const double d2 = p->h_res[R_D2], x2 = p->h_res[R_X2];
@@ -475,6 +504,7 @@ ps_status poisson_plan_create(ps_plan_t* out, int nx, int ny, int nz, double lx,
     int nbx = prec == PS_FP64 ? xfwd_blocks<double>(p->gd) : xfwd_blocks<float>(p->gd);
     int nbr = (int)((p->npts + 255) / 256);
     p->nblk_max = nbx > nbr ? nbx : nbr;
+    if (const char* ev = getenv("PS_CHUNK_PLANES")) p->chunk = atoi(ev);
     p->ws_bytes = workspace_layout(p, false);
     if (hipMalloc(&p->ws, p->ws_bytes) != hipSuccess) {
         p->ws = nullptr;

@@ -82,11 +82,20 @@ struct YShape {
 };
 
 // ---------------------------------------------------------------------------
-template <typename T, int M>
+// Residual of the flux-form Laplacian evaluated while loading (refinement step):
+// input = (f - mu) - L x, with L x read from the FP64 iterate x around each point.
+struct ResidIn {
+    const double* x;      // current iterate (whole box; the f pointer is offset to the launch's first plane)
+    const double* mu;     // mu[0] * mu_scale = weighted mean of f
+    double mu_scale;
+    int z0;               // first plane of this launch (for the z neighbours)
+};
+
+template <typename T, int M, bool RESID>
 __global__ void __launch_bounds__((XShape<T, M>::THREADS))
 k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny, int nkxb,
        const cx<T>* __restrict__ tw, const cx<T>* __restrict__ ptw, const double* __restrict__ scale_z,
-       const double* __restrict__ dz, double* __restrict__ partial) {
+       const double* __restrict__ dz, double* __restrict__ partial, ResidIn rin, GridDev g) {
     using X = XShape<T, M>;
     constexpr int NT = X::NT, R = X::R, LROW = X::LROW;
     constexpr int W = TileW<T>::value;
@@ -95,25 +104,63 @@ k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny,
     const int tid = threadIdx.x;
     const int rl = tid / NT;
     const int t = tid - rl * NT;
-    const int row = blockIdx.x * R + rl;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);   // neighbouring rows on one XCD
+    const int row = blk * R + rl;
     const bool valid = row < nrows;
     const double* frow = f + (size_t)row * (2 * M);
     const double zs = (valid && scale_z) ? scale_z[row / ny] : 1.0;
     cx<T>* lrow = smem + rl * LROW;
-    double wsum = 0.0;
+    double acc0 = 0.0, acc1 = 0.0;
+    // residual mode: row (z, y) of the whole box and its neighbours
+    const int zl = valid ? row / ny : 0;
+    const int zg = rin.z0 + zl;
+    const int yr = row - zl * ny;
+    const size_t plane = (size_t)ny * (2 * M);
+    const double* xrow = RESID ? rin.x + (size_t)zg * plane + (size_t)yr * (2 * M) : nullptr;
+    const double* xjm = RESID ? rin.x + (size_t)zg * plane + (size_t)(yr == 0 ? ny - 1 : yr - 1) * (2 * M) : nullptr;
+    const double* xjp = RESID ? rin.x + (size_t)zg * plane + (size_t)(yr + 1 == ny ? 0 : yr + 1) * (2 * M) : nullptr;
+    const double mu = RESID ? rin.mu[0] * rin.mu_scale : 0.0;
     auto ld = [&](int e) -> cx<T> {
         if (!valid) return cx<T>{(T)0, (T)0};
         double2 v = *reinterpret_cast<const double2*>(frow + 2 * e);
-        v.x *= zs;
-        v.y *= zs;
-        wsum += v.x + v.y;
+        if constexpr (RESID) {
+            const int n = 2 * M;
+            const double2 c = *reinterpret_cast<const double2*>(xrow + 2 * e);
+            const double xl = xrow[e == 0 ? n - 1 : 2 * e - 1];
+            const double xr = xrow[2 * e + 2 == n ? 0 : 2 * e + 2];
+            const double2 a = *reinterpret_cast<const double2*>(xjm + 2 * e);
+            const double2 b = *reinterpret_cast<const double2*>(xjp + 2 * e);
+            const double idx2 = 1.0 / (g.dx * g.dx), idy2 = 1.0 / (g.dy * g.dy);
+            double lz0 = 0.0, lz1 = 0.0;
+            if (zg + 1 < g.nz) {
+                const double2 q = *reinterpret_cast<const double2*>(xrow + plane + 2 * e);
+                lz0 += (q.x - c.x) * g.o[zg + 1];
+                lz1 += (q.y - c.y) * g.o[zg + 1];
+            }
+            if (zg > 0) {
+                const double2 q = *reinterpret_cast<const double2*>(xrow - plane + 2 * e);
+                lz0 -= (c.x - q.x) * g.o[zg];
+                lz1 -= (c.y - q.y) * g.o[zg];
+            }
+            const double l0 = ((c.y - c.x) - (c.x - xl)) * idx2 + ((b.x - c.x) - (c.x - a.x)) * idy2 + lz0 * g.idz[zg];
+            const double l1 = ((xr - c.y) - (c.y - c.x)) * idx2 + ((b.y - c.y) - (c.y - a.y)) * idy2 + lz1 * g.idz[zg];
+            const double f0 = v.x - mu, f1 = v.y - mu;
+            v.x = f0 - l0;
+            v.y = f1 - l1;
+            acc0 += v.x * v.x + v.y * v.y;
+            acc1 += f0 * f0 + f1 * f1;
+        } else {
+            v.x *= zs;
+            v.y *= zs;
+            acc0 += v.x + v.y;
+        }
         return cx<T>{(T)v.x, (T)v.y};
     };
     auto st = [&](int e, cx<T> val) { lrow[lds_pad(e)] = val; };
     fft_run<T, M, X::EM, -1>(t, lrow, 1, tw, ld, st);
     __syncthreads();
     const int ntot = nkxb * R * W;
-    const int row0 = blockIdx.x * R;
+    const int row0 = blk * R;
     const int z0 = row0 / ny, y0 = row0 - z0 * ny;
     for (int q = tid; q < ntot; q += X::THREADS) {
         const int w = q % W;
@@ -148,8 +195,13 @@ k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny,
         out[(((size_t)z * nkxb + kxb) * ny + y) * W + w] = xv;
     }
     if (partial) {
-        double v[1] = {valid ? wsum * dz[row / ny] : 0.0};
-        block_sum_store<1>(v, partial + blockIdx.x);
+        if constexpr (RESID) {
+            double v[2] = {acc0, acc1};   // sum r^2, sum (f - mu)^2
+            block_sum_store<2>(v, partial + 2 * blockIdx.x);
+        } else {
+            double v[1] = {valid ? acc0 * dz[row / ny] : 0.0};   // sum dz f
+            block_sum_store<1>(v, partial + blockIdx.x);
+        }
     }
 }
 
@@ -240,7 +292,7 @@ k_xinv(const cx<T>* __restrict__ in, double* __restrict__ out, int nrows, int ny
 // fwd = 1: a -> b (forward transform), fwd = 0: b -> a (inverse transform)
 template <typename T, int N, int S>
 __global__ void __launch_bounds__((YShape<T, N>::THREADS))
-k_yfft(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int nz, int nkxb,
+k_yfft(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int nzs, int nkxb,
        const cx<T>* __restrict__ tw) {
     using Y = YShape<T, N>;
     constexpr int NT = Y::NT, WY = Y::WY, W = TileW<T>::value;
@@ -258,8 +310,9 @@ k_yfft(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int nz, int nkxb,
     const int col = csub * WY + c;
     // a-layout address of (z, kxb, e, col) and b-layout address of (kxb, e, z, col)
     const size_t abase = (((size_t)z * nkxb + kxb) * N) * W + col;
-    const size_t bbase = (((size_t)kxb * N) * nz + z) * W + col;
-    const size_t bstride = (size_t)nz * W;
+    // b has nzs planes per (kxb, ky) column; the pointer is already offset to this launch's first plane
+    const size_t bbase = (((size_t)kxb * N) * nzs + z) * W + col;
+    const size_t bstride = (size_t)nzs * W;
     auto ld = [&](int e) -> cx<T> {
         if constexpr (S < 0)
             return in[abase + (size_t)e * W];
@@ -295,12 +348,25 @@ bool fft_length_supported(int n) {
 
 template <typename T, int M>
 static hipError_t xfwd_launch_t(const GridDev& g, const SpecDev<T>& s, const double* f, const double* scale_z,
-                                double* partial, hipStream_t st) {
+                                double* partial, const ResidIn* rin, hipStream_t st) {
     using X = XShape<T, M>;
-    const int nrows = g.ny * g.nz;
+    const int nzl = s.nzc > 0 ? s.nzc : g.nz;
+    const size_t zoff = (size_t)s.z0 * g.nx * g.ny;
+    const int nrows = g.ny * nzl;
     const int nblk = (nrows + X::R - 1) / X::R;
-    hipLaunchKernelGGL((k_xfwd<T, M>), dim3(nblk), dim3(X::THREADS), X::LDS, st, f, s.a, nrows, g.ny, s.nkxb,
-                       s.twx, s.ptw, scale_z, g.dz, partial);
+    if (rin) {
+        // the residual form is used by the refinement, which runs its solves in FP32
+        if constexpr (std::is_same<T, float>::value) {
+            ResidIn r = *rin;
+            r.z0 = s.z0;
+            hipLaunchKernelGGL((k_xfwd<T, M, true>), dim3(nblk), dim3(X::THREADS), X::LDS, st, f + zoff, s.a, nrows,
+                               g.ny, s.nkxb, s.twx, s.ptw, nullptr, g.dz + s.z0, partial, r, g);
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL((k_xfwd<T, M, false>), dim3(nblk), dim3(X::THREADS), X::LDS, st, f + zoff, s.a, nrows, g.ny,
+                       s.nkxb, s.twx, s.ptw, scale_z ? scale_z + s.z0 : nullptr, g.dz + s.z0, partial, ResidIn{}, g);
     return hipGetLastError();
 }
 
@@ -309,10 +375,13 @@ static hipError_t xinv_launch_t(const GridDev& g, const SpecDev<T>& s, double* o
                                 const double* mu, double mu_scale, const double* scale_z, double* partial,
                                 hipStream_t st) {
     using X = XShape<T, M>;
-    const int nrows = g.ny * g.nz;
+    const int nzl = s.nzc > 0 ? s.nzc : g.nz;
+    const size_t zoff = (size_t)s.z0 * g.nx * g.ny;
+    const int nrows = g.ny * nzl;
     const int nblk = (nrows + X::R - 1) / X::R;
-    hipLaunchKernelGGL((k_xinv<T, M>), dim3(nblk), dim3(X::THREADS), X::LDS, st, s.a, out, nrows, g.ny, s.nkxb,
-                       s.twx, s.ptw, scale, mode, mu, mu_scale, scale_z, g.dz, partial);
+    hipLaunchKernelGGL((k_xinv<T, M>), dim3(nblk), dim3(X::THREADS), X::LDS, st, s.a, out + zoff, nrows, g.ny,
+                       s.nkxb, s.twx, s.ptw, scale, mode, mu, mu_scale, scale_z ? scale_z + s.z0 : nullptr,
+                       g.dz + s.z0, partial);
     return hipGetLastError();
 }
 
@@ -320,21 +389,26 @@ template <typename T, int N, int S>
 static hipError_t yfft_launch_t(const GridDev& g, const SpecDev<T>& s, hipStream_t st) {
     using Y = YShape<T, N>;
     constexpr int NSUB = TileW<T>::value / Y::WY;
-    const int nblk = g.nz * s.nkxb * NSUB;
+    const int nzl = s.nzc > 0 ? s.nzc : g.nz;
+    const int nblk = nzl * s.nkxb * NSUB;
+    cx<T>* b0 = s.b + (size_t)s.z0 * TileW<T>::value;
     if (S < 0)
-        hipLaunchKernelGGL((k_yfft<T, N, S>), dim3(nblk), dim3(Y::THREADS), Y::LDS, st, s.a, s.b, g.nz, s.nkxb, s.twy);
+        hipLaunchKernelGGL((k_yfft<T, N, S>), dim3(nblk), dim3(Y::THREADS), Y::LDS, st, s.a, b0, g.nz, s.nkxb, s.twy);
     else
-        hipLaunchKernelGGL((k_yfft<T, N, S>), dim3(nblk), dim3(Y::THREADS), Y::LDS, st, s.b, s.a, g.nz, s.nkxb, s.twy);
+        hipLaunchKernelGGL((k_yfft<T, N, S>), dim3(nblk), dim3(Y::THREADS), Y::LDS, st, b0, s.a, g.nz, s.nkxb, s.twy);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_xfwd(const GridDev& g, const SpecDev<T>& s, const double* f, const double* scale_z,
-                       double* partial, hipStream_t st) {
+                       double* partial, hipStream_t st, const double* resid_x, const double* resid_mu,
+                       double mu_scale) {
+    ResidIn rin{resid_x, resid_mu, mu_scale, 0};
+    const ResidIn* rp = resid_x ? &rin : nullptr;
     switch (g.nx / 2) {
 #define PS_CASE(L) \
     case L:        \
-        return xfwd_launch_t<T, L>(g, s, f, scale_z, partial, st);
+        return xfwd_launch_t<T, L>(g, s, f, scale_z, partial, rp, st);
         PS_FFT_LENGTHS(PS_CASE)
 #undef PS_CASE
         default:
@@ -407,7 +481,7 @@ int xinv_blocks(const GridDev& g) {
 
 #define PS_INST(T)                                                                                           \
     template hipError_t launch_xfwd<T>(const GridDev&, const SpecDev<T>&, const double*, const double*,     \
-                                       double*, hipStream_t);                                                \
+                                       double*, hipStream_t, const double*, const double*, double);         \
     template hipError_t launch_xinv<T>(const GridDev&, const SpecDev<T>&, double*, double, int,             \
                                        const double*, double, const double*, double*, hipStream_t);         \
     template hipError_t launch_yfwd<T>(const GridDev&, const SpecDev<T>&, hipStream_t);                    \

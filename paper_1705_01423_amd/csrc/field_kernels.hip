@@ -17,7 +17,7 @@ __global__ void __launch_bounds__(256)
 k_divergence(const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w,
              double* __restrict__ f, GridDev g, double scale) {
     const size_t n = (size_t)g.nx * g.ny * g.nz;
-    const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t id = (size_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (id >= n) return;
     const int i = (int)(id % g.nx);
     const size_t jk = id / g.nx;
@@ -39,7 +39,7 @@ __global__ void __launch_bounds__(256)
 k_project_update(double* __restrict__ u, double* __restrict__ v, double* __restrict__ w, double* __restrict__ p,
                  const double* __restrict__ phi, GridDev g, double s, double c) {
     const size_t n = (size_t)g.nx * g.ny * g.nz;
-    const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t id = (size_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (id >= n) return;
     const int i = (int)(id % g.nx);
     const size_t jk = id / g.nx;
@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(256)
 k_residual(const double* __restrict__ f, const double* __restrict__ mu, double mu_scale,
            const double* __restrict__ x, double* __restrict__ r, GridDev g, double* __restrict__ partial) {
     const size_t n = (size_t)g.nx * g.ny * g.nz;
-    const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t id = (size_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     double rr = 0.0, ff = 0.0;
     if (id < n) {
         const int i = (int)(id % g.nx);
@@ -119,14 +119,14 @@ k_reduce(const double* __restrict__ partial, int nblk, int ncomp, int per_block,
 }
 
 __global__ void k_fill(double* __restrict__ p, size_t n, double v) {
-    const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t id = (size_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (id < n) p[id] = v;
 }
 
 // out[z][...] = in[z][...] * zs[z] for nplanes planes of `plane` values
 __global__ void k_scale_planes(const double* __restrict__ in, double* __restrict__ out,
                                const double* __restrict__ zs, size_t plane, size_t n) {
-    const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t id = (size_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (id < n) out[id] = in[id] * zs[id / plane];
 }
 
@@ -198,7 +198,7 @@ __global__ void __launch_bounds__(256)
 k_cfl(const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w, GridDev g,
       unsigned long long* __restrict__ out) {
     const size_t n = (size_t)g.nx * g.ny * g.nz;
-    const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t id = (size_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     double q = 0.0;
     if (id < n) {
         const int i = (int)(id % g.nx);
@@ -227,7 +227,7 @@ __global__ void __launch_bounds__(256)
 k_adj_rhs(const double* __restrict__ gu, const double* __restrict__ gv, const double* __restrict__ gw,
           const double* __restrict__ gp, double* __restrict__ f, GridDev g, double inv_s, double c) {
     const size_t n = (size_t)g.nx * g.ny * g.nz;
-    const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t id = (size_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (id >= n) return;
     const int i = (int)(id % g.nx);
     const size_t jk = id / g.nx;
@@ -257,7 +257,7 @@ k_adj_update(const double* __restrict__ gu, const double* __restrict__ gv, const
              const double* __restrict__ phi, double* __restrict__ ou, double* __restrict__ ov,
              double* __restrict__ ow, GridDev g) {
     const size_t n = (size_t)g.nx * g.ny * g.nz;
-    const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t id = (size_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (id >= n) return;
     const int i = (int)(id % g.nx);
     const size_t jk = id / g.nx;
@@ -313,7 +313,7 @@ hipError_t launch_residual(const GridDev& g, const double* f, const double* mu, 
 }
 
 __global__ void __launch_bounds__(256) k_nonfinite(const double* __restrict__ p, size_t n, unsigned* flag) {
-    const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t id = (size_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     bool bad = false;
     if (id < n) bad = !isfinite(p[id]);
     if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1u);

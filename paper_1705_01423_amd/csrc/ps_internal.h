@@ -56,13 +56,20 @@ struct SpecDev {
     cx<T>* a;                 // [nz][nkxb][ny][W]
     cx<T>* b;                 // [nkxb][ny][nz][W]
     T* piv;                   // z-solve pivots, same layout as b (real)
+    // Plane range of the x / y stages: planes [z0, z0 + nzc) (nzc = 0: all).  Buffer a
+    // is then indexed relative to z0 (it may hold just those planes); b stays absolute.
+    int z0 = 0;
+    int nzc = 0;
 };
 
 // Launchers (all asynchronous on `st`).  Return hipSuccess or the launch error.
 // FFT stages.
+// resid_x != NULL (FP32 only): the transformed input is the residual (f - mu) - L x, with
+// mu = resid_mu[0] * mu_scale, and partial receives {sum r^2, sum (f - mu)^2} per block.
 template <typename T>
 hipError_t launch_xfwd(const GridDev& g, const SpecDev<T>& s, const double* f, const double* scale_z,
-                       double* partial, hipStream_t st);
+                       double* partial, hipStream_t st, const double* resid_x = nullptr,
+                       const double* resid_mu = nullptr, double mu_scale = 0.0);
 template <typename T>
 hipError_t launch_yfwd(const GridDev& g, const SpecDev<T>& s, hipStream_t st);
 template <typename T>

@@ -39,7 +39,7 @@ __device__ __forceinline__ double sq(double a) { return a * a; }
 // its bottom z-face k (interior faces only; wall rows are zeroed).
 __global__ void __launch_bounds__(256) k_explicit(SubstepArgs a, GridDev g) {
     const size_t n = (size_t)g.nx * g.ny * g.nz;
-    const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t id = (size_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (id >= n) return;
     const int i = (int)(id % g.nx);
     const size_t jk = id / g.nx;
@@ -235,7 +235,7 @@ k_cn_solve_t(GridDev g, int kind, const double* __restrict__ fac, const double* 
 // F = U Q sends Lambda U dQ and Lambda Q dU to the points averaged into Q and U.
 __global__ void __launch_bounds__(256) k_explicit_adj(SubstepAdjArgs a, GridDev g) {
     const size_t n = (size_t)g.nx * g.ny * g.nz;
-    const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t id = (size_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (id >= n) return;
     const int i = (int)(id % g.nx);
     const size_t jk = id / g.nx;

@@ -122,17 +122,18 @@ __device__ __forceinline__ Aff<T> shfl_down_aff(const Aff<T>& m, int d) {
     return {__shfl_down(m.a, d, 64), {__shfl_down(m.b.x, d, 64), __shfl_down(m.b.y, d, 64)}};
 }
 
-// Rows per lane: 4 for FP64 (72 VGPRs), 8 for FP32; blocks of up to 1024 threads,
-// so columns of up to 512 rows run tiled (taller ones use the lane-per-column sweep).
+// Rows per lane; blocks of up to 1024 threads, so columns of up to 1024 rows run
+// tiled (taller ones use the lane-per-column sweep).
 template <typename T>
 struct ZRows {
-    static constexpr int value = sizeof(T) == 8 ? 4 : 8;
+    static constexpr int value = 4;   // 74 VGPRs (FP64), 65 (FP32); 8 rows spill
 };
-// Columns per block: half a tile, so that 512-thread blocks at nz = 512 let two or
-// more blocks share a CU and overlap one block's loads with another's scans.
+// Columns per block: 4 (half an FP64 tile, a quarter of an FP32 tile), so that
+// 512-thread blocks at nz = 512 let three blocks share a CU and overlap one block's
+// loads with another's scans.
 template <typename T>
 struct ZCols {
-    static constexpr int value = TileW<T>::value / 2;
+    static constexpr int value = 4;
 };
 
 template <typename T, int K>

@@ -107,6 +107,19 @@ def test_solve_fp64_parity(shape):
     assert abs(info["compat_defect"] - defect) < 1e-12
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32_refined", 1e-11)])
+@pytest.mark.parametrize("shape,chunk", [((64, 64, 64), 8), ((48, 96, 33), 16), ((24, 48, 16), 5)])
+def test_solve_plane_chunks(shape, chunk, prec, tol, monkeypatch):
+    """x/y stages run in plane chunks (last chunk partial) give the same solve."""
+    banner(f"chunked solve {shape} chunk={chunk} {prec}")
+    monkeypatch.setenv("PS_CHUNK_PLANES", str(chunk))
+    g, plan = grids(*shape, lx=1.5, ly=2.0, precision=prec)
+    f = _rng_field(plan.centre_shape, 8)
+    ref = poisson.solve(f, g)
+    phi, _ = plan.solve(f.to("cuda"))
+    assert rel(phi, ref) < tol
+
+
 def test_solve_closed_form():
     """Uniform grid: the cos cos cos eigenvector is recovered (exact discrete eigenvalue)."""
     nx, ny, nz, lx, ly = 32, 24, 16, 1.3, 0.7
