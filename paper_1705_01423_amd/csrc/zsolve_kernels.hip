@@ -131,13 +131,21 @@ struct ZRows {
 // Columns per block: 4 (half an FP64 tile, a quarter of an FP32 tile), so that
 // 512-thread blocks at nz = 512 let three blocks share a CU and overlap one block's
 // loads with another's scans.
+#ifndef PS_Z_COLS
+#define PS_Z_COLS 4
+#endif
 template <typename T>
 struct ZCols {
-    static constexpr int value = 4;
+    static constexpr int value = PS_Z_COLS;
 };
+#ifdef PS_Z_WAVES_PER_EU
+#define PS_Z_ATTR __attribute__((amdgpu_waves_per_eu(PS_Z_WAVES_PER_EU)))
+#else
+#define PS_Z_ATTR
+#endif
 
 template <typename T, int K>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(1024) PS_Z_ATTR
 k_zsolve_scan(cx<T>* __restrict__ b, int nz, int ny, int nxh, const double* __restrict__ dz,
               const double* __restrict__ o, const double* __restrict__ lamx, const double* __restrict__ lamy) {
     constexpr int W = TileW<T>::value;
@@ -184,9 +192,11 @@ k_zsolve_scan(cx<T>* __restrict__ b, int nz, int ny, int nxh, const double* __re
                 m = {s + ok, s * ok, (T)1, ok};
             }
             acc = mob_mul(m, acc);
-            mob_norm(acc);
+            // entries grow by at most a factor ~ (o + s + 1) per row: rescale every 4 rows
+            if ((i & 3) == 3) mob_norm(acc);
         }
     }
+    mob_norm(acc);
     Mob<T> inc = acc;
 #pragma unroll
     for (int d = 1; d < LPW; d <<= 1) {

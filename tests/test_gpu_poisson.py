@@ -90,6 +90,32 @@ def test_stage_z_solve(shape, prec, tol):
     assert rel(got, ref) < tol
 
 
+LENGTHS = [64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048]
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 3e-6)])
+@pytest.mark.parametrize("n", LENGTHS)
+def test_stage_lengths_x(n, prec, tol):
+    """Forward and inverse x transforms for every supported length used by the workloads."""
+    banner(f"x length {n} {prec}")
+    test_stage_x_forward((n, 4, 3), prec, tol)
+    test_stage_x_inverse((n, 4, 3), prec, tol)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 3e-6)])
+@pytest.mark.parametrize("n", LENGTHS)
+def test_stage_lengths_y(n, prec, tol):
+    banner(f"y length {n} {prec}")
+    test_stage_y_both((8, n, 3), prec, tol)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 1e-5)])
+@pytest.mark.parametrize("nz", [2, 3, 63, 64, 65, 192, 384, 511, 512, 1024])
+def test_stage_z_heights(nz, prec, tol):
+    banner(f"z height {nz} {prec}")
+    test_stage_z_solve((16, 4, nz), prec, tol)
+
+
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 1e-5)])
 def test_stage_z_solve_tall(prec, tol):
     """Columns taller than one block's tile (lane-per-column fallback)."""
