@@ -25,6 +25,35 @@ import sys
 import time
 
 HBM_PEAK_GBS = 8000.0
+ROOT = os.path.dirname(os.path.abspath(__file__))
+
+
+def kernel_source_hash():
+    """sha256 (first 16 hex) of the HIP sources, in the form the traffic record stores."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1705_01423_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            h.update(name.encode())
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(stage):
+    """HBM bytes per launch of ``stage`` from the committed counter record, or None when the
+    kernels have changed since the counters were taken (hash mismatch) or no record exists."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except OSError:
+        return None
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(stage)
+    return None if k is None else k["traffic_bytes"]
 
 
 def log(msg):
@@ -132,7 +161,7 @@ def main():
     alg_bytes = 16.0 * npts        # one read + one write of the field's spectral/physical data
     achieved = alg_bytes / (stage_ms[dominant] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(dominant),
                 "alg_bytes_per_launch": alg_bytes}
     solve_bytes = 80.0 * npts
     total_gbs = solve_bytes / t_fp64 / 1e9

@@ -90,8 +90,11 @@ typedef struct {
  *   lamx[kx] = (4/dx^2) sin^2(pi kx/nx)  (modified wavenumbers, Sec. 2.2)
  * nx, ny must be of the form 2^a 3^b with nx even, 4 <= nx, ny <= 4096;
  * 2 <= nz <= 2048.
- * prec: ps_precision.  tol: refinement stop ||delta||/||phi|| (<= 0 selects
- * 1e-12); max_iter: refinement cap (<= 0 selects 10).  flags: PS_FLAG_*.
+ * prec: ps_precision.  tol: relative error target of the refinement (<= 0
+ * selects 1e-12): it stops when the last correction ||delta_i||/||phi|| is
+ * <= tol, or, from the second correction on, when the error it predicts is,
+ * rho_i ||delta_i||/||phi|| with rho_i = ||delta_i|| / ||delta_{i-1}||.
+ * max_iter: refinement cap (<= 0 selects 10).  flags: PS_FLAG_*.
  * The plan is bound to the current HIP device and allocates its workspace
  * there (see poisson_plan_workspace_bytes).  *out receives the plan.
  */

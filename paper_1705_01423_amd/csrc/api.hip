@@ -356,8 +356,10 @@ ps_status solve_impl(ps_plan_t p, const double* in, double* out, const double* z
         PS_CHECK(spectral_solve<float>(p, f, out, 0, nullptr, 0.0, nullptr, nullptr, true, true, st));
         loc.iterations = 1;
         if (p->prec == PS_FP32_REFINED) {
-            // Linear convergence: with contraction rho = |d_i| / |d_{i-1}| (|d_0| = |x|), the error
-            // left after correction i is about rho |d_i|; stop when that estimate meets the tolerance.
+            // Linear convergence: the error left after correction i is about rho |d_i| with the
+            // contraction rho = |d_i| / |d_{i-1}|.  The first correction has no predecessor (|d_1|/|x|
+            // measures the FP32 solve's error, not the contraction), so it stops only if |d_1| itself
+            // meets the tolerance.
             double prev = 1.0;
             bool converged = false;
             for (int it = 0; it < p->max_iter; ++it) {
@@ -373,7 +375,7 @@ ps_status solve_impl(ps_plan_t p, const double* in, double* out, const double* z
                 const double f2 = p->h_res[R_F2];
                 loc.rel_residual = f2 > 0 ? std::sqrt(p->h_res[R_R2] / f2) : 0.0;
                 const double rho = rel / prev;
-                if (rel <= p->tol || rho * rel <= p->tol) {
+                if (rel <= p->tol || (it > 0 && rho * rel <= p->tol)) {
                     converged = true;
                     break;
                 }

@@ -50,6 +50,9 @@ constexpr int kYEmax = PS_Y_EMAX;
 #ifndef PS_Y_LDS
 #define PS_Y_LDS 140000
 #endif
+#ifndef PS_Y_ZFAST
+#define PS_Y_ZFAST 1
+#endif
 
 // Rows of one block: LDS row = lds_len(M) slots (odd for M >= 16, so that rows
 // start in different banks).
@@ -105,7 +108,20 @@ k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny,
     const int rl = tid / NT;
     const int t = tid - rl * NT;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);   // neighbouring rows on one XCD
-    const int row = blk * R + rl;
+    int row0 = blk * R;
+    if constexpr (RESID) {
+        // The residual stencil reads the iterate's rows at y +- 1 and z +- 1.  Blocks walk
+        // tiles of kYT row groups in y, then z, then the next tile, so that the rows a block
+        // needs were loaded a few blocks earlier on the same XCD (L2 hits, not refetches).
+        constexpr int kYT = 8;
+        const int nzb = nrows / ny, nyb = ny / R;
+        if (ny % R == 0 && nyb % kYT == 0 && nzb * nyb == (int)gridDim.x) {
+            const int yi = blk % kYT, tz = blk / kYT;
+            const int zz = tz % nzb, yt = tz / nzb;
+            row0 = zz * ny + (yt * kYT + yi) * R;
+        }
+    }
+    const int row = row0 + rl;
     const bool valid = row < nrows;
     const double* frow = f + (size_t)row * (2 * M);
     const double zs = (valid && scale_z) ? scale_z[row / ny] : 1.0;
@@ -160,7 +176,6 @@ k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny,
     fft_run<T, M, X::EM, -1>(t, lrow, 1, tw, ld, st);
     __syncthreads();
     const int ntot = nkxb * R * W;
-    const int row0 = blk * R;
     const int z0 = row0 / ny, y0 = row0 - z0 * ny;
     for (int q = tid; q < ntot; q += X::THREADS) {
         const int w = q % W;
@@ -305,8 +320,16 @@ k_yfft(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int nzs, int nkxb,
     int bid = xcd_remap(blockIdx.x, gridDim.x);
     const int csub = bid % NSUB;
     bid /= NSUB;
+#if PS_Y_ZFAST
+    // z fastest: the blocks running together on one XCD touch neighbouring z rows of the
+    // same (kx tile, ky) runs of the b layout, so its strided side hits open DRAM pages
+    const int nzl = (int)gridDim.x / (NSUB * nkxb);
+    const int z = bid % nzl;
+    const int kxb = bid / nzl;
+#else
     const int kxb = bid % nkxb;
     const int z = bid / nkxb;
+#endif
     const int col = csub * WY + c;
     // a-layout address of (z, kxb, e, col) and b-layout address of (kxb, e, z, col)
     const size_t abase = (((size_t)z * nkxb + kxb) * N) * W + col;
