@@ -96,7 +96,12 @@ typedef struct {
  * rho_i ||delta_i||/||phi|| with rho_i = ||delta_i|| / ||delta_{i-1}||.
  * max_iter: refinement cap (<= 0 selects 10).  flags: PS_FLAG_*.
  * The plan is bound to the current HIP device and allocates its workspace
- * there (see poisson_plan_workspace_bytes).  *out receives the plan.
+ * there (see poisson_plan_workspace_bytes).  It also allocates its own
+ * tables: metrics, twiddles and the pivot excesses entering each 8-row chunk
+ * of every z column (8 bytes FP64 / 4 bytes FP32 per entry, (nx/2+1 rounded
+ * up to 8 / 16) * ny * ceil(nz/8) entries, 0.27 GB at 1024^2 x 512 FP64),
+ * formed by one kernel on the null stream before the call returns.  *out
+ * receives the plan.
  */
 ps_status poisson_plan_create(ps_plan_t* out, int nx, int ny, int nz, double lx, double ly,
                               const double* zf_host, int prec, double tol, int max_iter,

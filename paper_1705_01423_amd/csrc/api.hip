@@ -68,6 +68,7 @@ struct ps_plan_s {
     double *d_dz, *d_dzc, *d_o, *d_dzw, *d_lamx, *d_lamy, *d_inv_dz;
     cx<double>*d_twx64, *d_ptw64, *d_twy64;
     cx<float>*d_twx32, *d_ptw32, *d_twy32;
+    void* d_etab = nullptr;   // z-solve excess table (tiled solves), in the plan's precision
     // workspace
     void* ws = nullptr;
     size_t ws_bytes = 0;
@@ -125,6 +126,7 @@ SpecDev<double> spec_of<double>(ps_plan_t p) {
     s.a = (cx<double>*)p->spec_a;
     s.b = (cx<double>*)p->spec_b;
     s.piv = (double*)p->piv;
+    s.etab = (const double*)p->d_etab;
     return s;
 }
 
@@ -139,6 +141,7 @@ SpecDev<float> spec_of<float>(ps_plan_t p) {
     s.a = (cx<float>*)p->spec_a;
     s.b = (cx<float>*)p->spec_b;
     s.piv = (float*)p->piv;
+    s.etab = (const float*)p->d_etab;
     return s;
 }
 
@@ -155,7 +158,9 @@ size_t workspace_layout(ps_plan_t p, bool carve) {
     };
     p->spec_a = take(p->spec_elems * elem_bytes(p->prec));
     p->spec_b = take(p->spec_elems * elem_bytes(p->prec));
-    p->piv = take(p->spec_elems * real_bytes(p->prec));
+    // pivot scratch: only the lane-per-column solve of tall columns needs it
+    const bool tiled = p->prec == PS_FP64 ? zsolve_tiled<double>(p->gd) : zsolve_tiled<float>(p->gd);
+    p->piv = take(tiled ? 0 : p->spec_elems * real_bytes(p->prec));
     p->fbuf = (double*)take(p->npts * sizeof(double));
     p->phibuf = (double*)take(p->npts * sizeof(double));
     p->rbuf = (double*)take(p->npts * sizeof(double));
@@ -503,6 +508,24 @@ ps_status poisson_plan_create(ps_plan_t* out, int nx, int ny, int nz, double lx,
         g.lamy = p->d_lamy;
         g.idz = p->d_inv_dz;
     }
+    {
+        // per-plan z-solve excess table (formed once, on the null stream)
+        const size_t ne = prec == PS_FP64 ? zexcess_elems<double>(p->gd, p->nkxb) : zexcess_elems<float>(p->gd, p->nkxb);
+        if (ne > 0) {
+            if (hipMalloc(&p->d_etab, ne * real_bytes(prec)) != hipSuccess) {
+                p->d_etab = nullptr;
+                poisson_plan_destroy(p);
+                return fail(PS_ENOMEM, "cannot allocate the %zu-byte z-solve table", ne * real_bytes(prec));
+            }
+            hipError_t e = prec == PS_FP64 ? launch_zexcess<double>(p->gd, p->nkxb, (double*)p->d_etab, nullptr)
+                                           : launch_zexcess<float>(p->gd, p->nkxb, (float*)p->d_etab, nullptr);
+            if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+            if (e != hipSuccess) {
+                poisson_plan_destroy(p);
+                return hipfail(e, "z-solve table");
+            }
+        }
+    }
     int nbx = prec == PS_FP64 ? xfwd_blocks<double>(p->gd) : xfwd_blocks<float>(p->gd);
     int nbr = (int)((p->npts + 255) / 256);
     p->nblk_max = nbx > nbr ? nbx : nbr;
@@ -552,6 +575,7 @@ ps_status poisson_plan_destroy(ps_plan_t p) {
     if (!p) return PS_OK;
     if (p->ws_owned && p->ws) hipFree(p->ws);
     if (p->d_tables) hipFree(p->d_tables);
+    if (p->d_etab) hipFree(p->d_etab);
     if (p->sub_buf) hipFree(p->sub_buf);
     if (p->h_res) hipHostFree(p->h_res);
     delete p;

@@ -138,7 +138,7 @@ k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny,
     const double mu = RESID ? rin.mu[0] * rin.mu_scale : 0.0;
     auto ld = [&](int e) -> cx<T> {
         if (!valid) return cx<T>{(T)0, (T)0};
-        double2 v = *reinterpret_cast<const double2*>(frow + 2 * e);
+        double2 v = ld_stream2<PS_NT_XF>(frow + 2 * e);
         if constexpr (RESID) {
             const int n = 2 * M;
             const double2 c = *reinterpret_cast<const double2*>(xrow + 2 * e);
@@ -207,7 +207,7 @@ k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny,
             z += y / ny;
             y -= (y / ny) * ny;
         }
-        out[(((size_t)z * nkxb + kxb) * ny + y) * W + w] = xv;
+        st_stream<PS_NT_XF>(out + (((size_t)z * nkxb + kxb) * ny + y) * W + w, xv);
     }
     if (partial) {
         if constexpr (RESID) {
@@ -234,26 +234,41 @@ k_xinv(const cx<T>* __restrict__ in, double* __restrict__ out, int nrows, int ny
     cx<T>* smem = reinterpret_cast<cx<T>*>(smem_raw);
     __shared__ cx<T> nyq[R];   // X_M of each row (the LDS rows hold k < M)
     const int tid = threadIdx.x;
-    const int ntot = nkxb * R * W;
+    // the R rows' half spectra (nkxb = (M + W) / W tiles of W): all loads of a thread are
+    // issued before the first is consumed
+    constexpr int NTOT = ((M + W) / W) * R * W;
+    constexpr int NIT = (NTOT + X::THREADS - 1) / X::THREADS;
     const int row0 = blockIdx.x * R;
     const int z0 = row0 / ny, y0 = row0 - z0 * ny;
-    for (int q = tid; q < ntot; q += X::THREADS) {
+    cx<T> buf[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int q = tid + it * X::THREADS;
         const int w = q % W;
         const int r2 = (q / W) % R;
         const int kxb = q / (W * R);
         const int row2 = row0 + r2;
         const int kx = kxb * W + w;
-        if (row2 >= nrows || kx > M) continue;
-        int z = z0, y = y0 + r2;
-        if (y >= ny) {   // the block's rows cross into the next plane(s)
-            z += y / ny;
-            y -= (y / ny) * ny;
+        buf[it] = cx<T>{(T)0, (T)0};
+        if (q < NTOT && row2 < nrows && kx <= M) {
+            int z = z0, y = y0 + r2;
+            if (y >= ny) {   // the block's rows cross into the next plane(s)
+                z += y / ny;
+                y -= (y / ny) * ny;
+            }
+            buf[it] = ld_stream<PS_NT_XI>(in + (((size_t)z * nkxb + kxb) * ny + y) * W + w);
         }
-        const cx<T> xv = in[(((size_t)z * nkxb + kxb) * ny + y) * W + w];
-        if (kx < M)
-            smem[r2 * LROW + lds_pad(kx)] = xv;
-        else
-            nyq[r2] = xv;
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int q = tid + it * X::THREADS;
+        const int w = q % W;
+        const int r2 = (q / W) % R;
+        const int kx = (q / (W * R)) * W + w;
+        if (q < NTOT && kx < M)
+            smem[r2 * LROW + lds_pad(kx)] = buf[it];
+        else if (q < NTOT && kx == M)
+            nyq[r2] = buf[it];
     }
     __syncthreads();
     const int rl = tid / NT;
@@ -290,7 +305,7 @@ k_xinv(const cx<T>* __restrict__ in, double* __restrict__ out, int nrows, int ny
         } else {
             o = r;
         }
-        *reinterpret_cast<double2*>(orow + 2 * e) = o;
+        st_stream2<PS_NT_XI>(orow + 2 * e, o);
         s_d2 += r.x * r.x + r.y * r.y;
         s_o2 += o.x * o.x + o.y * o.y;
         s_o += o.x + o.y;
@@ -336,17 +351,18 @@ k_yfft(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int nzs, int nkxb,
     // b has nzs planes per (kxb, ky) column; the pointer is already offset to this launch's first plane
     const size_t bbase = (((size_t)kxb * N) * nzs + z) * W + col;
     const size_t bstride = (size_t)nzs * W;
+    constexpr bool kYiLoad = sizeof(T) == 8 ? PS_NT_YI_LOAD64 : PS_NT_YI_LOAD32;
     auto ld = [&](int e) -> cx<T> {
         if constexpr (S < 0)
-            return in[abase + (size_t)e * W];
+            return ld_stream<PS_NT_YF>(in + abase + (size_t)e * W);
         else
-            return in[bbase + (size_t)e * bstride];
+            return ld_stream<kYiLoad>(in + bbase + (size_t)e * bstride);
     };
     auto st = [&](int e, cx<T> val) {
         if constexpr (S < 0)
-            out[bbase + (size_t)e * bstride] = val;
+            st_stream<PS_NT_YF>(out + bbase + (size_t)e * bstride, val);
         else
-            out[abase + (size_t)e * W] = val;
+            st_stream<PS_NT_YI_STORE>(out + abase + (size_t)e * W, val);
     };
     fft_run<T, N, kYEmax, S>(t, smem + c, WY, tw, ld, st);
 }

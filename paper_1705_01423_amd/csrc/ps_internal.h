@@ -32,6 +32,77 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblk) {
     return (bid % 8) * (nblk / 8) + bid / 8;
 }
 
+// Streaming accesses: each value of a stage's input is read once and each output
+// written once.  With NT set they carry the non-temporal hint; which stages gain from
+// it was measured per kernel (the x transforms and the inverse y transform do, the
+// forward y transform and the z solve do not).
+template <typename T>
+using vec2_t = T __attribute__((ext_vector_type(2)));
+
+template <bool NT, typename T>
+__device__ __forceinline__ cx<T> ld_stream(const cx<T>* p) {
+    if constexpr (NT) {
+        const vec2_t<T> v = __builtin_nontemporal_load(reinterpret_cast<const vec2_t<T>*>(p));
+        return cx<T>{v.x, v.y};
+    } else {
+        return *p;
+    }
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st_stream(cx<T>* p, cx<T> v) {
+    if constexpr (NT) {
+        vec2_t<T> w;
+        w.x = v.x;
+        w.y = v.y;
+        __builtin_nontemporal_store(w, reinterpret_cast<vec2_t<T>*>(p));
+    } else {
+        *p = v;
+    }
+}
+template <bool NT>
+__device__ __forceinline__ double2 ld_stream2(const double* p) {
+    if constexpr (NT) {
+        const vec2_t<double> v = __builtin_nontemporal_load(reinterpret_cast<const vec2_t<double>*>(p));
+        return double2{v.x, v.y};
+    } else {
+        return *reinterpret_cast<const double2*>(p);
+    }
+}
+template <bool NT>
+__device__ __forceinline__ void st_stream2(double* p, double2 v) {
+    if constexpr (NT) {
+        vec2_t<double> w;
+        w.x = v.x;
+        w.y = v.y;
+        __builtin_nontemporal_store(w, reinterpret_cast<vec2_t<double>*>(p));
+    } else {
+        *reinterpret_cast<double2*>(p) = v;
+    }
+}
+
+// Non-temporal choice per stage (build-time overrides for measurement).
+#ifndef PS_NT_XF
+#define PS_NT_XF 1
+#endif
+#ifndef PS_NT_YF
+#define PS_NT_YF 0
+#endif
+#ifndef PS_NT_YI_LOAD64
+#define PS_NT_YI_LOAD64 1
+#endif
+#ifndef PS_NT_YI_LOAD32
+#define PS_NT_YI_LOAD32 0
+#endif
+#ifndef PS_NT_YI_STORE
+#define PS_NT_YI_STORE 1
+#endif
+#ifndef PS_NT_Z
+#define PS_NT_Z 0
+#endif
+#ifndef PS_NT_XI
+#define PS_NT_XI 1
+#endif
+
 // Device-side grid tables (FP64).  Built once per plan on the host.
 struct GridDev {
     int nx, ny, nz;
@@ -55,7 +126,8 @@ struct SpecDev {
     const cx<T>* twy;         // exp(-2 pi i q / ny), q < ny
     cx<T>* a;                 // [nz][nkxb][ny][W]
     cx<T>* b;                 // [nkxb][ny][nz][W]
-    T* piv;                   // z-solve pivots, same layout as b (real)
+    T* piv;                   // z-solve pivots, same layout as b (real); tall columns only
+    const T* etab = nullptr;  // pivot excess entering each lane chunk of the tiled z solve
     // Plane range of the x / y stages: planes [z0, z0 + nzc) (nzc = 0: all).  Buffer a
     // is then indexed relative to z0 (it may hold just those planes); b stays absolute.
     int z0 = 0;
@@ -88,6 +160,17 @@ int xinv_blocks(const GridDev& g);
 // z solves on buffer b (all columns except (0,0)), then the (0,0) column.
 template <typename T>
 hipError_t launch_zsolve(const GridDev& g, const SpecDev<T>& s, hipStream_t st);
+// The tiled z solve (columns of up to 1024 rows) starts each lane's chunk of rows from the
+// pivot excess of the row above it.  The excesses depend only on the grid and the
+// wavenumbers, so they are formed once per plan (sequential FP64 recurrence per column) into
+// a table of zexcess_elems() entries [kx tile][ky][chunk][W]; 0 entries when the columns are
+// too tall for the tiled solve.
+template <typename T>
+bool zsolve_tiled(const GridDev& g);
+template <typename T>
+size_t zexcess_elems(const GridDev& g, int nkxb);
+template <typename T>
+hipError_t launch_zexcess(const GridDev& g, int nkxb, T* etab, hipStream_t st);
 template <typename T>
 hipError_t launch_zsolve00(const GridDev& g, const SpecDev<T>& s, double* defect, hipStream_t st);
 

@@ -62,41 +62,44 @@ k_zsolve_seq(cx<T>* __restrict__ b, T* __restrict__ piv, int nz, int ny, int nkx
 }
 
 // ---------------------------------------------------------------------------
+// Pivot excesses at the lane-chunk boundaries of the tiled solve: entry
+// [tile][l][w] is e_{lK-1} of column (tile, w) (0 for l = 0), formed by the
+// sequential excess recurrence in FP64.  They depend only on the grid and
+// lam = lamx + lamy, so a plan forms them once.  One lane per column.
+template <typename T, int K>
+__global__ void __launch_bounds__(256)
+k_zexcess(T* __restrict__ etab, int nz, int ny, int nkxb, int nxh, const double* __restrict__ dz,
+          const double* __restrict__ o, const double* __restrict__ lamx, const double* __restrict__ lamy) {
+    constexpr int W = TileW<T>::value;
+    const int nchunk = (nz + K - 1) / K;
+    const size_t col = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= (size_t)nkxb * ny * W) return;
+    const int w = (int)(col % W);
+    const size_t tile = col / W;
+    const int ky = (int)(tile % ny);
+    const int kx = (int)(tile / ny) * W + w;
+    // padding columns (kx > nx/2) are never stored; any finite excess serves them
+    const double lam = kx < nxh ? lamx[kx] + lamy[ky] : 1.0;
+    T* out = etab + tile * (size_t)nchunk * W + w;
+    out[0] = (T)0;
+    double e = lam * dz[0];
+    for (int k = 1; k < nz; ++k) {
+        if (k % K == 0) out[(size_t)(k / K) * W] = (T)e;
+        const double m = o[k] / (o[k] + e);
+        e = lam * dz[k] + m * e;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Tiled z solve: one block per (kx tile, ky); the nz x W tile is read once into
 // registers and written once.  Lane (l, c) owns rows [l K, l K + K) of column c.
-// The sequential elimination is split into three chunked scans over l:
-//  (A) excesses: e_k = s_k + o_k e_{k-1} / (o_k + e_{k-1}) is the Moebius map of
-//      the non-negative matrix [[s_k + o_k, s_k o_k], [1, o_k]] (row 0: [[0, s_0],
-//      [0, 1]]), so chunk maps compose by 2x2 products of non-negative numbers
-//      (still subtraction-free); products are rescaled by powers of two.
+//  (A) pivots: from the excess entering the chunk (per-plan table), the lane forms
+//      its own excesses e_k = s_k + m_k e_{k-1} and pivots p_k = o_{k+1} + e_k.
 //  (B) forward sweep y_k = g_k + m_k y_{k-1}: affine maps, prefix scan.
 //  (C) back substitution P_k = rp_k y_k + o_{k+1} rp_k P_{k+1}: affine maps,
 //      suffix scan.
 // Each scan: sequential composition inside the lane, shuffles across the lanes
 // of one wave, and an LDS pass across waves.
-template <typename T>
-struct Mob {
-    T a, b, c, d;   // [[a, b], [c, d]]
-};
-
-template <typename T>
-__device__ __forceinline__ Mob<T> mob_mul(const Mob<T>& L, const Mob<T>& E) {
-    return {L.a * E.a + L.b * E.c, L.a * E.b + L.b * E.d, L.c * E.a + L.d * E.c, L.c * E.b + L.d * E.d};
-}
-
-template <typename T>
-__device__ __forceinline__ void mob_norm(Mob<T>& m) {
-    T mx = fmax(fmax(m.a, m.b), fmax(m.c, m.d));
-    if (mx > (T)0) {
-        int ex;
-        frexp(mx, &ex);
-        m.a = ldexp(m.a, -ex);
-        m.b = ldexp(m.b, -ex);
-        m.c = ldexp(m.c, -ex);
-        m.d = ldexp(m.d, -ex);
-    }
-}
-
 template <typename T>
 struct Aff {
     T a;
@@ -110,10 +113,6 @@ __device__ __forceinline__ Aff<T> aff_mul(const Aff<T>& L, const Aff<T>& E) {
 }
 
 template <typename T>
-__device__ __forceinline__ Mob<T> shfl_up_mob(const Mob<T>& m, int d) {
-    return {__shfl_up(m.a, d, 64), __shfl_up(m.b, d, 64), __shfl_up(m.c, d, 64), __shfl_up(m.d, d, 64)};
-}
-template <typename T>
 __device__ __forceinline__ Aff<T> shfl_up_aff(const Aff<T>& m, int d) {
     return {__shfl_up(m.a, d, 64), {__shfl_up(m.b.x, d, 64), __shfl_up(m.b.y, d, 64)}};
 }
@@ -122,34 +121,39 @@ __device__ __forceinline__ Aff<T> shfl_down_aff(const Aff<T>& m, int d) {
     return {__shfl_down(m.a, d, 64), {__shfl_down(m.b.x, d, 64), __shfl_down(m.b.y, d, 64)}};
 }
 
-// Rows per lane; blocks of up to 1024 threads, so columns of up to 1024 rows run
-// tiled (taller ones use the lane-per-column sweep).
+// Rows per lane (K) and columns per block (WZ), per precision.  A block holds
+// WZ columns of nz rows in WZ * ceil(nz / K) lanes (rounded up to whole per-wave
+// lane groups), at most 1024 threads: tall columns run in narrower blocks (WZ/2,
+// WZ/4), and only columns too tall for those use the lane-per-column sweep (never
+// with the default shapes, which tile every nz <= 2048).
+#ifndef PS_Z_ROWS64
+#define PS_Z_ROWS64 8
+#endif
+#ifndef PS_Z_ROWS32
+#define PS_Z_ROWS32 8
+#endif
+#ifndef PS_Z_COLS64
+#define PS_Z_COLS64 8
+#endif
+#ifndef PS_Z_COLS32
+#define PS_Z_COLS32 16
+#endif
 template <typename T>
 struct ZRows {
-    static constexpr int value = 4;   // 74 VGPRs (FP64), 65 (FP32); 8 rows spill
+    static constexpr int value = sizeof(T) == 8 ? PS_Z_ROWS64 : PS_Z_ROWS32;
 };
-// Columns per block: 4 (half an FP64 tile, a quarter of an FP32 tile), so that
-// 512-thread blocks at nz = 512 let three blocks share a CU and overlap one block's
-// loads with another's scans.
-#ifndef PS_Z_COLS
-#define PS_Z_COLS 4
-#endif
 template <typename T>
 struct ZCols {
-    static constexpr int value = PS_Z_COLS;
+    static constexpr int value = sizeof(T) == 8 ? PS_Z_COLS64 : PS_Z_COLS32;
 };
-#ifdef PS_Z_WAVES_PER_EU
-#define PS_Z_ATTR __attribute__((amdgpu_waves_per_eu(PS_Z_WAVES_PER_EU)))
-#else
-#define PS_Z_ATTR
-#endif
 
-template <typename T, int K>
-__global__ void __launch_bounds__(1024) PS_Z_ATTR
-k_zsolve_scan(cx<T>* __restrict__ b, int nz, int ny, int nxh, const double* __restrict__ dz,
-              const double* __restrict__ o, const double* __restrict__ lamx, const double* __restrict__ lamy) {
+template <typename T, int K, int WZ, int MAXT>
+__global__ void __launch_bounds__(MAXT)
+k_zsolve_scan(cx<T>* __restrict__ b, const T* __restrict__ etab, int nz, int ny, int nxh,
+              const double* __restrict__ dz, const double* __restrict__ o, const double* __restrict__ lamx,
+              const double* __restrict__ lamy) {
     constexpr int W = TileW<T>::value;
-    constexpr int WZ = ZCols<T>::value;   // columns of this block (a sub-tile of the W-wide tile)
+    static_assert(W % WZ == 0, "columns per block must divide the tile width");   // WZ: a sub-tile
     constexpr int NSUB = W / WZ;
     constexpr int LPW = 64 / WZ;          // lanes of one column inside a wave
     __shared__ T xs[16 * WZ * 4];         // per-wave totals
@@ -169,69 +173,27 @@ k_zsolve_scan(cx<T>* __restrict__ b, int nz, int ny, int nxh, const double* __re
     const T lam = store ? (T)(lamx[kx] + lamy[ky]) : (T)1;
     cx<T>* tile = b + (size_t)tile_id * nz * W + csub * WZ + c;
     const int k0 = l * K;
+    const int nchunk = (nz + K - 1) / K;
 
     cx<T> v[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         const int k = k0 + i;
-        v[i] = (k < nz) ? tile[(size_t)k * W] : cx<T>{(T)0, (T)0};
+        v[i] = (k < nz) ? ld_stream<PS_NT_Z>(tile + (size_t)k * W) : cx<T>{(T)0, (T)0};
     }
+    // ---- (A) excess entering the chunk: e_{k0-1} -----------------------------------
+    T eprev = (T)0;
+    if (l < nchunk) eprev = etab[((size_t)tile_id * nchunk + l) * W + csub * WZ + c];
 
-    // ---- (A) excesses -------------------------------------------------------
-    Mob<T> acc = {(T)1, (T)0, (T)0, (T)1};
+    // ---- pivots: rp_k = 1 / p_k; the chunk's first multiplier m0 = o_k0 / p_{k0-1} --------
+    // Only rp and the scaled right-hand side stay in registers; the multipliers
+    // m_k = o_k rp_{k-1} and the back-substitution coefficients o_{k+1} rp_k are re-formed
+    // where they are used.
+    T rp[K];
+    T m0 = (T)0;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         const int k = k0 + i;
-        if (k < nz) {
-            const T s = lam * (T)dz[k];
-            Mob<T> m;
-            if (k == 0) {
-                m = {(T)0, s, (T)0, (T)1};
-            } else {
-                const T ok = (T)o[k];
-                m = {s + ok, s * ok, (T)1, ok};
-            }
-            acc = mob_mul(m, acc);
-            // entries grow by at most a factor ~ (o + s + 1) per row: rescale every 4 rows
-            if ((i & 3) == 3) mob_norm(acc);
-        }
-    }
-    mob_norm(acc);
-    Mob<T> inc = acc;
-#pragma unroll
-    for (int d = 1; d < LPW; d <<= 1) {
-        Mob<T> oth = shfl_up_mob(inc, d * WZ);
-        if (lw >= d) {
-            inc = mob_mul(inc, oth);
-            mob_norm(inc);
-        }
-    }
-    if (lw == LPW - 1) {
-        T* q = xs + (wave * WZ + c) * 4;
-        q[0] = inc.a;
-        q[1] = inc.b;
-        q[2] = inc.c;
-        q[3] = inc.d;
-    }
-    Mob<T> ex = shfl_up_mob(inc, WZ);
-    if (lw == 0) ex = {(T)1, (T)0, (T)0, (T)1};
-    __syncthreads();
-    Mob<T> pw = {(T)1, (T)0, (T)0, (T)1};
-    for (int w2 = 0; w2 < wave; ++w2) {
-        const T* q = xs + (w2 * WZ + c) * 4;
-        pw = mob_mul(Mob<T>{q[0], q[1], q[2], q[3]}, pw);
-        mob_norm(pw);
-    }
-    ex = mob_mul(ex, pw);
-    T eprev = (ex.d != (T)0) ? ex.b / ex.d : (T)0;   // e_{k0-1}
-    __syncthreads();
-
-    // ---- pivots and multipliers ----------------------------------------------
-    T mk[K], rp[K];
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
-        const int k = k0 + i;
-        mk[i] = (T)0;
         rp[i] = (T)0;
         if (k < nz) {
             const T s = lam * (T)dz[k];
@@ -241,13 +203,16 @@ k_zsolve_scan(cx<T>* __restrict__ b, int nz, int ny, int nxh, const double* __re
             } else {
                 const T ok = (T)o[k];
                 const T mm = (i == 0) ? ok / (ok + eprev) : ok * rp[i - 1];
-                mk[i] = mm;
+                if (i == 0) m0 = mm;
                 e = s + mm * eprev;
             }
             rp[i] = (T)1 / ((T)o[k + 1] + e);
             eprev = e;
+            const T g = -(T)dz[k];
+            v[i] = {g * v[i].x, g * v[i].y};   // g_k = -dz_k F_k
         }
     }
+    auto mult = [&](int i, int k) -> T { return i == 0 ? m0 : (T)o[k] * rp[i - 1]; };
 
     // ---- (B) forward sweep ------------------------------------------------------
     Aff<T> fa = {(T)1, {(T)0, (T)0}};
@@ -255,9 +220,8 @@ k_zsolve_scan(cx<T>* __restrict__ b, int nz, int ny, int nxh, const double* __re
     for (int i = 0; i < K; ++i) {
         const int k = k0 + i;
         if (k < nz) {
-            const T g = -(T)dz[k];
-            v[i] = {g * v[i].x, g * v[i].y};   // g_k = -dz_k F_k
-            fa = {mk[i] * fa.a, {mk[i] * fa.b.x + v[i].x, mk[i] * fa.b.y + v[i].y}};
+            const T m = mult(i, k);
+            fa = {m * fa.a, {m * fa.b.x + v[i].x, m * fa.b.y + v[i].y}};
         }
     }
     Aff<T> finc = fa;
@@ -286,7 +250,8 @@ k_zsolve_scan(cx<T>* __restrict__ b, int nz, int ny, int nxh, const double* __re
     for (int i = 0; i < K; ++i) {
         const int k = k0 + i;
         if (k < nz) {
-            y = {v[i].x + mk[i] * y.x, v[i].y + mk[i] * y.y};
+            const T m = mult(i, k);
+            y = {v[i].x + m * y.x, v[i].y + m * y.y};
             v[i] = y;
         }
     }
@@ -337,7 +302,7 @@ k_zsolve_scan(cx<T>* __restrict__ b, int nz, int ny, int nxh, const double* __re
 #pragma unroll
         for (int i = 0; i < K; ++i) {
             const int k = k0 + i;
-            if (k < nz) tile[(size_t)k * W] = v[i];
+            if (k < nz) st_stream<PS_NT_Z>(tile + (size_t)k * W, v[i]);
         }
     }
 }
@@ -427,28 +392,89 @@ k_zsolve00(cx<T>* __restrict__ b, int nz, int nxny, const double* __restrict__ d
     if (lane == 0 && defect) defect[0] = mean_plane / (double)nxny;
 }
 
+// Lanes of one column (a whole number of per-wave lane groups) and whether a block of
+// WZ columns fits in 1024 threads.
+template <int K, int WZ>
+int zscan_threads(int nz) {
+    constexpr int LPW = 64 / WZ;
+    const int lc = (nz + K - 1) / K;
+    return WZ * ((lc + LPW - 1) / LPW * LPW);
+}
+
+template <typename T, int K, int WZ>
+hipError_t zscan_launch(const GridDev& g, const SpecDev<T>& s, hipStream_t st) {
+    constexpr int W = TileW<T>::value;
+    const int threads = zscan_threads<K, WZ>(g.nz);
+    const int nblk = s.nkxb * g.ny * (W / WZ);
+    const int nxh = g.nx / 2 + 1;
+#define PS_ZSCAN(MAXT)                                                                                           \
+    hipLaunchKernelGGL((k_zsolve_scan<T, K, WZ, MAXT>), dim3(nblk), dim3(threads), 0, st, s.b, s.etab, g.nz, g.ny, \
+                       nxh, g.dz, g.o, g.lamx, g.lamy)
+    if (threads <= 256)
+        PS_ZSCAN(256);
+    else if (threads <= 512)
+        PS_ZSCAN(512);
+    else
+        PS_ZSCAN(1024);
+#undef PS_ZSCAN
+    return hipGetLastError();
+}
+
+// Tiled solve with the widest block (ZCols, ZCols/2, ZCols/4 columns) that holds whole
+// columns in 1024 threads: 0 when none does.
+template <typename T>
+int zscan_cols(const GridDev& g) {
+    constexpr int K = ZRows<T>::value, C = ZCols<T>::value;
+    if (zscan_threads<K, C>(g.nz) <= 1024) return C;
+    if constexpr (C >= 2) {
+        if (zscan_threads<K, C / 2>(g.nz) <= 1024) return C / 2;
+    }
+    if constexpr (C >= 4) {
+        if (zscan_threads<K, C / 4>(g.nz) <= 1024) return C / 4;
+    }
+    return 0;
+}
+
 template <typename T>
 hipError_t launch_zsolve(const GridDev& g, const SpecDev<T>& s, hipStream_t st) {
     constexpr int W = TileW<T>::value;
-    constexpr int WZ = ZCols<T>::value;
-    constexpr int LPW = 64 / WZ;
-    auto lanes = [&](int K) {
-        int lc = (g.nz + K - 1) / K;
-        return (lc + LPW - 1) / LPW * LPW;
-    };
-    const int nblk = s.nkxb * g.ny * (W / WZ);
-    const int nxh = g.nx / 2 + 1;
-    constexpr int K = ZRows<T>::value;
-    if (WZ * lanes(K) <= 1024) {
-        hipLaunchKernelGGL((k_zsolve_scan<T, K>), dim3(nblk), dim3(WZ * lanes(K)), 0, st, s.b, g.nz, g.ny, nxh, g.dz,
-                           g.o, g.lamx, g.lamy);
-        return hipGetLastError();
+    constexpr int K = ZRows<T>::value, C = ZCols<T>::value;
+    const int wz = zscan_cols<T>(g);
+    if (wz > 0 && !s.etab) return hipErrorInvalidValue;
+    if (wz == C) return zscan_launch<T, K, C>(g, s, st);
+    if constexpr (C >= 2) {
+        if (wz == C / 2) return zscan_launch<T, K, C / 2>(g, s, st);
+    }
+    if constexpr (C >= 4) {
+        if (wz == C / 4) return zscan_launch<T, K, C / 4>(g, s, st);
     }
     // taller columns: one lane per column, pivots kept in the scratch buffer
     const size_t ncol = (size_t)s.nkxb * g.ny * W;
     const int nblk_seq = (int)((ncol + 255) / 256);
     hipLaunchKernelGGL((k_zsolve_seq<T>), dim3(nblk_seq), dim3(256), 0, st, s.b, s.piv, g.nz, g.ny, s.nkxb,
                        g.nx / 2 + 1, g.dz, g.o, g.lamx, g.lamy);
+    return hipGetLastError();
+}
+
+template <typename T>
+bool zsolve_tiled(const GridDev& g) {
+    return zscan_cols<T>(g) > 0;
+}
+
+template <typename T>
+size_t zexcess_elems(const GridDev& g, int nkxb) {
+    constexpr int K = ZRows<T>::value;
+    if (!zsolve_tiled<T>(g)) return 0;
+    return (size_t)nkxb * g.ny * ((g.nz + K - 1) / K) * TileW<T>::value;
+}
+
+template <typename T>
+hipError_t launch_zexcess(const GridDev& g, int nkxb, T* etab, hipStream_t st) {
+    constexpr int K = ZRows<T>::value;
+    const size_t ncol = (size_t)nkxb * g.ny * TileW<T>::value;
+    const int nblk = (int)((ncol + 255) / 256);
+    hipLaunchKernelGGL((k_zexcess<T, K>), dim3(nblk), dim3(256), 0, st, etab, g.nz, g.ny, nkxb, g.nx / 2 + 1, g.dz,
+                       g.o, g.lamx, g.lamy);
     return hipGetLastError();
 }
 
@@ -460,6 +486,12 @@ hipError_t launch_zsolve00(const GridDev& g, const SpecDev<T>& s, double* defect
 
 template hipError_t launch_zsolve<double>(const GridDev&, const SpecDev<double>&, hipStream_t);
 template hipError_t launch_zsolve<float>(const GridDev&, const SpecDev<float>&, hipStream_t);
+template bool zsolve_tiled<double>(const GridDev&);
+template bool zsolve_tiled<float>(const GridDev&);
+template size_t zexcess_elems<double>(const GridDev&, int);
+template size_t zexcess_elems<float>(const GridDev&, int);
+template hipError_t launch_zexcess<double>(const GridDev&, int, double*, hipStream_t);
+template hipError_t launch_zexcess<float>(const GridDev&, int, float*, hipStream_t);
 template hipError_t launch_zsolve00<double>(const GridDev&, const SpecDev<double>&, double*, hipStream_t);
 template hipError_t launch_zsolve00<float>(const GridDev&, const SpecDev<float>&, double*, hipStream_t);
 

@@ -110,7 +110,7 @@ def test_stage_lengths_y(n, prec, tol):
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 1e-5)])
-@pytest.mark.parametrize("nz", [2, 3, 63, 64, 65, 192, 384, 511, 512, 1024])
+@pytest.mark.parametrize("nz", [2, 3, 63, 64, 65, 192, 384, 511, 512, 513, 1024, 1025, 2048])
 def test_stage_z_heights(nz, prec, tol):
     banner(f"z height {nz} {prec}")
     test_stage_z_solve((16, 4, nz), prec, tol)
@@ -118,7 +118,7 @@ def test_stage_z_heights(nz, prec, tol):
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 1e-5)])
 def test_stage_z_solve_tall(prec, tol):
-    """Columns taller than one block's tile (lane-per-column fallback)."""
+    """Columns taller than a full-width block holds (narrower blocks)."""
     test_stage_z_solve((8, 6, 600), prec, tol)
 
 
