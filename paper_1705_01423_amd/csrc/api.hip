@@ -275,12 +275,22 @@ double* sub_field(ps_plan_t p, int q) {
     return (double*)((char*)p->sub_buf + per * q);
 }
 
+// A face velocity whose divergence (D u*) * scale is the right-hand side, formed inside the
+// x transform instead of being stored.
+struct DivSrc {
+    const double* u;
+    const double* v;
+    const double* w;
+    double scale;
+};
+
 // One spectral solve with the plan's kernels at precision T:
 // out = S(in) (mode 0) or out += S(in) - mu (mode 1), scale_in / scale_out per plane (optional).
 template <typename T>
 ps_status spectral_solve(ps_plan_t p, const double* in, double* out, int mode, const double* mu_dev,
                          double mu_scale, const double* zin, const double* zout, bool want_wsum,
-                         bool want_norms, hipStream_t st, const double* resid_x = nullptr) {
+                         bool want_norms, hipStream_t st, const double* resid_x = nullptr,
+                         const DivSrc* div = nullptr) {
     // resid_x != NULL: the transformed input is the refinement residual (in - mean) - L resid_x,
     // formed inside the x transform; its norms go to R_R2 / R_F2.
     const GridDev& g = p->gd;
@@ -301,6 +311,10 @@ ps_status spectral_solve(ps_plan_t p, const double* in, double* out, int mode, c
             PS_HIP(launch_xfwd<T>(g, sc, in, nullptr, p->partial + (size_t)2 * bpp * z0, st, resid_x,
                                   p->small + R_WSUM, inv_den(p)),
                    "x forward FFT (residual)");
+        else if (div)
+            PS_HIP(launch_xfwd_div<T>(g, sc, div->u, div->v, div->w, div->scale,
+                                      want_wsum ? p->partial + (size_t)bpp * z0 : nullptr, st),
+                   "x forward FFT (divergence)");
         else
             PS_HIP(launch_xfwd<T>(g, sc, in, zin, want_wsum ? p->partial + (size_t)bpp * z0 : nullptr, st),
                    "x forward FFT");
@@ -335,15 +349,17 @@ ps_status read_small(ps_plan_t p, hipStream_t st) {
 ps_status check_finite(ps_plan_t p, const double* f, hipStream_t st);
 
 // Full solve at the plan's precision.  in -> out; zin/zout optional per-plane scalings
+// div != NULL (FP64 plans only, no finiteness check): the right-hand side is the divergence
+// of div's velocity, formed in the x transform; `in` is then unused.
 ps_status solve_impl(ps_plan_t p, const double* in, double* out, const double* zin, const double* zout,
-                     hipStream_t st, ps_info* info) {
+                     hipStream_t st, ps_info* info, const DivSrc* div = nullptr) {
     ps_info loc{};
     loc.rel_residual = -1.0;
     const bool strict = (p->flags & PS_FLAG_STRICT_COMPAT) != 0;
     if (p->flags & PS_FLAG_CHECK_FINITE) PS_CHECK(check_finite(p, in, st));
     ps_status result = PS_OK;
     if (p->prec == PS_FP64) {
-        PS_CHECK(spectral_solve<double>(p, in, out, 0, nullptr, 0.0, zin, zout, false, false, st));
+        PS_CHECK(spectral_solve<double>(p, in, out, 0, nullptr, 0.0, zin, zout, false, false, st, nullptr, div));
         loc.iterations = 1;
         if (info || strict) {
             PS_CHECK(read_small(p, st));
@@ -609,9 +625,17 @@ ps_status project(ps_plan_t p, double* u, double* v, double* w, double* pr, doub
     if (!(s > 0) || !std::isfinite(s)) return fail(PS_EINVAL, "s must be positive");
     if (!(c >= 0) || !std::isfinite(c)) return fail(PS_EINVAL, "c must be non-negative");
     hipStream_t st = (hipStream_t)stream;
-    PS_HIP(launch_divergence(p->gd, u, v, w, p->fbuf, 1.0 / s, st), "divergence");
     double* phi = phi_out ? phi_out : p->phibuf;
-    ps_status r = solve_impl(p, p->fbuf, phi, nullptr, nullptr, st, info);
+    ps_status r;
+    if (p->prec == PS_FP64 && !(p->flags & PS_FLAG_CHECK_FINITE)) {
+        // the divergence is formed inside the x transform and never stored
+        const DivSrc d{u, v, w, 1.0 / s};
+        r = solve_impl(p, nullptr, phi, nullptr, nullptr, st, info, &d);
+    } else {
+        // the refinement's residual (and the finiteness check) need the right-hand side stored
+        PS_HIP(launch_divergence(p->gd, u, v, w, p->fbuf, 1.0 / s, st), "divergence");
+        r = solve_impl(p, p->fbuf, phi, nullptr, nullptr, st, info);
+    }
     if (r != PS_OK && r != PS_ENOTCONVERGED) return r;
     PS_HIP(launch_project_update(p->gd, u, v, w, pr, phi, s, c, st), "projection update");
     return r;

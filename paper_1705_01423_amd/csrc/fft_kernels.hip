@@ -85,16 +85,26 @@ struct YShape {
 };
 
 // ---------------------------------------------------------------------------
-// Residual of the flux-form Laplacian evaluated while loading (refinement step):
-// input = (f - mu) - L x, with L x read from the FP64 iterate x around each point.
+// What the x transform's loader reads (XL_* below):
+//  XL_PLAIN: the field f (optionally scaled per plane).
+//  XL_RESID: the refinement residual (f - mu) - L x of the flux-form Laplacian, with
+//            L x read from the FP64 iterate x around each point.
+//  XL_DIV:   the divergence D u* / s of a face velocity (u at x-faces, v at y-faces,
+//            w at z-faces with nz + 1 planes), so that the projection never stores f.
+enum { XL_PLAIN = 0, XL_RESID = 1, XL_DIV = 2 };
 struct ResidIn {
     const double* x;      // current iterate (whole box; the f pointer is offset to the launch's first plane)
     const double* mu;     // mu[0] * mu_scale = weighted mean of f
     double mu_scale;
     int z0;               // first plane of this launch (for the z neighbours)
+    // XL_DIV: velocity components offset to the launch's first plane, and 1/s
+    const double* u;
+    const double* v;
+    const double* w;
+    double div_scale;
 };
 
-template <typename T, int M, bool RESID>
+template <typename T, int M, int LM>
 __global__ void __launch_bounds__((XShape<T, M>::THREADS))
 k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny, int nkxb,
        const cx<T>* __restrict__ tw, const cx<T>* __restrict__ ptw, const double* __restrict__ scale_z,
@@ -109,8 +119,8 @@ k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny,
     const int t = tid - rl * NT;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);   // neighbouring rows on one XCD
     int row0 = blk * R;
-    if constexpr (RESID) {
-        // The residual stencil reads the iterate's rows at y +- 1 and z +- 1.  Blocks walk
+    if constexpr (LM != XL_PLAIN) {
+        // The residual and divergence stencils read rows at y +- 1 and z +- 1.  Blocks walk
         // tiles of kYT row groups in y, then z, then the next tile, so that the rows a block
         // needs were loaded a few blocks earlier on the same XCD (L2 hits, not refetches).
         constexpr int kYT = 8;
@@ -132,13 +142,15 @@ k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny,
     const int zg = rin.z0 + zl;
     const int yr = row - zl * ny;
     const size_t plane = (size_t)ny * (2 * M);
+    constexpr bool RESID = LM == XL_RESID;
     const double* xrow = RESID ? rin.x + (size_t)zg * plane + (size_t)yr * (2 * M) : nullptr;
     const double* xjm = RESID ? rin.x + (size_t)zg * plane + (size_t)(yr == 0 ? ny - 1 : yr - 1) * (2 * M) : nullptr;
     const double* xjp = RESID ? rin.x + (size_t)zg * plane + (size_t)(yr + 1 == ny ? 0 : yr + 1) * (2 * M) : nullptr;
     const double mu = RESID ? rin.mu[0] * rin.mu_scale : 0.0;
     auto ld = [&](int e) -> cx<T> {
         if (!valid) return cx<T>{(T)0, (T)0};
-        double2 v = ld_stream2<PS_NT_XF>(frow + 2 * e);
+        double2 v = {0.0, 0.0};
+        if constexpr (LM != XL_DIV) v = ld_stream2<PS_NT_XF>(frow + 2 * e);
         if constexpr (RESID) {
             const int n = 2 * M;
             const double2 c = *reinterpret_cast<const double2*>(xrow + 2 * e);
@@ -165,6 +177,21 @@ k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny,
             v.y = f1 - l1;
             acc0 += v.x * v.x + v.y * v.y;
             acc1 += f0 * f0 + f1 * f1;
+        } else if constexpr (LM == XL_DIV) {
+            // f = (D u*) / s at the cells (2e, 2e + 1) of row (z, y): periodic x and y, w at z-faces
+            const int n = 2 * M;
+            const size_t rb = (size_t)row * n;   // row offset within the launch's planes
+            const double2 uc = ld_stream2<PS_NT_XF>(rin.u + rb + 2 * e);
+            const double ur = rin.u[rb + (2 * e + 2 == n ? 0 : 2 * e + 2)];
+            const double2 vc = ld_stream2<PS_NT_XF>(rin.v + rb + 2 * e);
+            const double2 vp = *reinterpret_cast<const double2*>(rin.v + (rb - (size_t)yr * n) +
+                                                                 (size_t)(yr + 1 == ny ? 0 : yr + 1) * n + 2 * e);
+            const double2 wc = *reinterpret_cast<const double2*>(rin.w + rb + 2 * e);
+            const double2 wp = *reinterpret_cast<const double2*>(rin.w + rb + plane + 2 * e);
+            const double dzk = dz[zl];
+            v.x = rin.div_scale * ((uc.y - uc.x) / g.dx + (vp.x - vc.x) / g.dy + (wp.x - wc.x) / dzk);
+            v.y = rin.div_scale * ((ur - uc.y) / g.dx + (vp.y - vc.y) / g.dy + (wp.y - wc.y) / dzk);
+            acc0 += v.x + v.y;
         } else {
             v.x *= zs;
             v.y *= zs;
@@ -387,25 +414,35 @@ bool fft_length_supported(int n) {
 
 template <typename T, int M>
 static hipError_t xfwd_launch_t(const GridDev& g, const SpecDev<T>& s, const double* f, const double* scale_z,
-                                double* partial, const ResidIn* rin, hipStream_t st) {
+                                double* partial, const ResidIn* rin, int mode, hipStream_t st) {
     using X = XShape<T, M>;
     const int nzl = s.nzc > 0 ? s.nzc : g.nz;
     const size_t zoff = (size_t)s.z0 * g.nx * g.ny;
     const int nrows = g.ny * nzl;
     const int nblk = (nrows + X::R - 1) / X::R;
-    if (rin) {
+    if (mode == XL_RESID) {
         // the residual form is used by the refinement, which runs its solves in FP32
         if constexpr (std::is_same<T, float>::value) {
             ResidIn r = *rin;
             r.z0 = s.z0;
-            hipLaunchKernelGGL((k_xfwd<T, M, true>), dim3(nblk), dim3(X::THREADS), X::LDS, st, f + zoff, s.a, nrows,
-                               g.ny, s.nkxb, s.twx, s.ptw, nullptr, g.dz + s.z0, partial, r, g);
+            hipLaunchKernelGGL((k_xfwd<T, M, XL_RESID>), dim3(nblk), dim3(X::THREADS), X::LDS, st, f + zoff, s.a,
+                               nrows, g.ny, s.nkxb, s.twx, s.ptw, nullptr, g.dz + s.z0, partial, r, g);
             return hipGetLastError();
         }
         return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL((k_xfwd<T, M, false>), dim3(nblk), dim3(X::THREADS), X::LDS, st, f + zoff, s.a, nrows, g.ny,
-                       s.nkxb, s.twx, s.ptw, scale_z ? scale_z + s.z0 : nullptr, g.dz + s.z0, partial, ResidIn{}, g);
+    if (mode == XL_DIV) {
+        ResidIn r = *rin;
+        r.u += zoff;
+        r.v += zoff;
+        r.w += zoff;
+        hipLaunchKernelGGL((k_xfwd<T, M, XL_DIV>), dim3(nblk), dim3(X::THREADS), X::LDS, st, nullptr, s.a, nrows, g.ny,
+                           s.nkxb, s.twx, s.ptw, nullptr, g.dz + s.z0, partial, r, g);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL((k_xfwd<T, M, XL_PLAIN>), dim3(nblk), dim3(X::THREADS), X::LDS, st, f + zoff, s.a, nrows,
+                       g.ny, s.nkxb, s.twx, s.ptw, scale_z ? scale_z + s.z0 : nullptr, g.dz + s.z0, partial,
+                       ResidIn{}, g);
     return hipGetLastError();
 }
 
@@ -442,12 +479,27 @@ template <typename T>
 hipError_t launch_xfwd(const GridDev& g, const SpecDev<T>& s, const double* f, const double* scale_z,
                        double* partial, hipStream_t st, const double* resid_x, const double* resid_mu,
                        double mu_scale) {
-    ResidIn rin{resid_x, resid_mu, mu_scale, 0};
-    const ResidIn* rp = resid_x ? &rin : nullptr;
+    ResidIn rin{resid_x, resid_mu, mu_scale, 0, nullptr, nullptr, nullptr, 0.0};
+    const int mode = resid_x ? XL_RESID : XL_PLAIN;
     switch (g.nx / 2) {
 #define PS_CASE(L) \
     case L:        \
-        return xfwd_launch_t<T, L>(g, s, f, scale_z, partial, rp, st);
+        return xfwd_launch_t<T, L>(g, s, f, scale_z, partial, &rin, mode, st);
+        PS_FFT_LENGTHS(PS_CASE)
+#undef PS_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t launch_xfwd_div(const GridDev& g, const SpecDev<T>& s, const double* u, const double* v, const double* w,
+                           double div_scale, double* partial, hipStream_t st) {
+    ResidIn rin{nullptr, nullptr, 0.0, 0, u, v, w, div_scale};
+    switch (g.nx / 2) {
+#define PS_CASE(L) \
+    case L:        \
+        return xfwd_launch_t<T, L>(g, s, nullptr, nullptr, partial, &rin, XL_DIV, st);
         PS_FFT_LENGTHS(PS_CASE)
 #undef PS_CASE
         default:
@@ -521,6 +573,8 @@ int xinv_blocks(const GridDev& g) {
 #define PS_INST(T)                                                                                           \
     template hipError_t launch_xfwd<T>(const GridDev&, const SpecDev<T>&, const double*, const double*,     \
                                        double*, hipStream_t, const double*, const double*, double);         \
+    template hipError_t launch_xfwd_div<T>(const GridDev&, const SpecDev<T>&, const double*, const double*, \
+                                           const double*, double, double*, hipStream_t);                    \
     template hipError_t launch_xinv<T>(const GridDev&, const SpecDev<T>&, double*, double, int,             \
                                        const double*, double, const double*, double*, hipStream_t);         \
     template hipError_t launch_yfwd<T>(const GridDev&, const SpecDev<T>&, hipStream_t);                    \

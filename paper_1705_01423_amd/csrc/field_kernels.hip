@@ -16,13 +16,9 @@ static inline int nblocks(size_t n, int t) { return (int)((n + t - 1) / t); }
 __global__ void __launch_bounds__(256)
 k_divergence(const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w,
              double* __restrict__ f, GridDev g, double scale) {
-    const size_t n = (size_t)g.nx * g.ny * g.nz;
-    const size_t id = (size_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (id >= n) return;
-    const int i = (int)(id % g.nx);
-    const size_t jk = id / g.nx;
-    const int j = (int)(jk % g.ny);
-    const int k = (int)(jk / g.ny);
+    int i, j, k;
+    if (!stencil_cell(g, i, j, k)) return;
+    const size_t id = ((size_t)k * g.ny + j) * g.nx + i;
     const size_t plane = (size_t)g.nx * g.ny;
     const int ip = (i + 1 == g.nx) ? 0 : i + 1;
     const int jp = (j + 1 == g.ny) ? 0 : j + 1;
@@ -38,13 +34,9 @@ k_divergence(const double* __restrict__ u, const double* __restrict__ v, const d
 __global__ void __launch_bounds__(256)
 k_project_update(double* __restrict__ u, double* __restrict__ v, double* __restrict__ w, double* __restrict__ p,
                  const double* __restrict__ phi, GridDev g, double s, double c) {
-    const size_t n = (size_t)g.nx * g.ny * g.nz;
-    const size_t id = (size_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (id >= n) return;
-    const int i = (int)(id % g.nx);
-    const size_t jk = id / g.nx;
-    const int j = (int)(jk % g.ny);
-    const int k = (int)(jk / g.ny);
+    int i, j, k;
+    if (!stencil_cell(g, i, j, k)) return;
+    const size_t id = ((size_t)k * g.ny + j) * g.nx + i;
     const size_t plane = (size_t)g.nx * g.ny;
     const int im = (i == 0) ? g.nx - 1 : i - 1;
     const int jm = (j == 0) ? g.ny - 1 : j - 1;
@@ -62,45 +54,6 @@ k_project_update(double* __restrict__ u, double* __restrict__ v, double* __restr
     }
     if (k + 1 < g.nz) fp = (phi[id + plane] - pc) * g.o[k + 1];
     if (p) p[id] += pc - c * ((fp - fm) / g.dz[k]);
-}
-
-// r = (f - mu) - L x (flux form); partial[blk] = sum r^2
-__global__ void __launch_bounds__(256)
-k_residual(const double* __restrict__ f, const double* __restrict__ mu, double mu_scale,
-           const double* __restrict__ x, double* __restrict__ r, GridDev g, double* __restrict__ partial) {
-    const size_t n = (size_t)g.nx * g.ny * g.nz;
-    const size_t id = (size_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    double rr = 0.0, ff = 0.0;
-    if (id < n) {
-        const int i = (int)(id % g.nx);
-        const size_t jk = id / g.nx;
-        const int j = (int)(jk % g.ny);
-        const int k = (int)(jk / g.ny);
-        const size_t plane = (size_t)g.nx * g.ny;
-        const size_t rowb = (size_t)k * plane + (size_t)j * g.nx;
-        const int im = (i == 0) ? g.nx - 1 : i - 1;
-        const int ip = (i + 1 == g.nx) ? 0 : i + 1;
-        const int jm = (j == 0) ? g.ny - 1 : j - 1;
-        const int jp = (j + 1 == g.ny) ? 0 : j + 1;
-        const double xc = x[id];
-        const double idx2 = 1.0 / (g.dx * g.dx), idy2 = 1.0 / (g.dy * g.dy);
-        const double lx = ((x[rowb + ip] - xc) - (xc - x[rowb + im])) * idx2;
-        const double ly = ((x[(size_t)k * plane + (size_t)jp * g.nx + i] - xc) -
-                           (xc - x[(size_t)k * plane + (size_t)jm * g.nx + i])) * idy2;
-        // o = 1/dzc at interior faces, 0 at the walls (zero flux)
-        const double fzp = (k + 1 < g.nz) ? (x[id + plane] - xc) * g.o[k + 1] : 0.0;
-        const double fzm = (k > 0) ? (xc - x[id - plane]) * g.o[k] : 0.0;
-        const double lz = (fzp - fzm) * g.idz[k];
-        const double fc = f[id] - mu[0] * mu_scale;
-        const double rv = fc - (lx + ly + lz);
-        r[id] = rv;
-        rr = rv * rv;
-        ff = fc * fc;
-    }
-    if (partial) {
-        double vv[2] = {rr, ff};
-        block_sum_store<2>(vv, partial + 2 * blockIdx.x);
-    }
 }
 
 // out[blockIdx.x * ncomp + c] = sum of partial[b * ncomp + c] over the block's contiguous
@@ -135,23 +88,29 @@ __global__ void k_scale_planes(const double* __restrict__ in, double* __restrict
 // fac = [l (n), invd (n), c (n)] with the LU recurrences of the Thomas method.
 // kind 0 (centre): n = nz rows, wall half a cell beyond the end centres.
 // kind 1 (face):   n = nz - 1 interior faces.
-__global__ void k_cn_factor(GridDev g, int kind, double beta, double* __restrict__ fac) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// The off-diagonal coupling coefficients are formed in parallel into LDS (nz <= 2048),
+// then one thread runs the LU recurrence.
+__global__ void __launch_bounds__(256) k_cn_factor(GridDev g, int kind, double beta, double* __restrict__ fac) {
+    __shared__ double am_s[2048], ap_s[2048];
     const int n = kind == 0 ? g.nz : g.nz - 1;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) {
+        if (kind == 0) {
+            am_s[r] = 1.0 / (g.dzw[r] * g.dz[r]);
+            ap_s[r] = 1.0 / (g.dzw[r + 1] * g.dz[r]);
+        } else {
+            const int k = r + 1;
+            am_s[r] = 1.0 / (g.dz[k - 1] * g.dzc[k]);
+            ap_s[r] = 1.0 / (g.dz[k] * g.dzc[k]);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double* l = fac;
     double* invd = fac + n;
     double* cs = fac + 2 * n;
     double dprev = 1.0, cprev = 0.0;
     for (int r = 0; r < n; ++r) {
-        double am, ap;
-        if (kind == 0) {
-            am = 1.0 / (g.dzw[r] * g.dz[r]);
-            ap = 1.0 / (g.dzw[r + 1] * g.dz[r]);
-        } else {
-            const int k = r + 1;
-            am = 1.0 / (g.dz[k - 1] * g.dzc[k]);
-            ap = 1.0 / (g.dz[k] * g.dzc[k]);
-        }
+        const double am = am_s[r], ap = ap_s[r];
         const double diag = 1.0 + beta * (am + ap);
         const double sub = (r == 0) ? 0.0 : -beta * am;
         const double sup = (r == n - 1) ? 0.0 : -beta * ap;
@@ -193,6 +152,149 @@ k_cn_solve(GridDev g, int kind, const double* __restrict__ fac, double* __restri
     }
 }
 
+// Tiled CN solve: a block holds 64 consecutive columns (one per lane) and all n rows,
+// wave w owning rows [w KZ, w KZ + KZ).  With the shared LU factors the forward sweep
+// y_r = x_r - l_r y_{r-1} and the backward sweep d_r = invd_r (y_r - c_r d_{r+1}) are
+// affine maps whose slopes do not depend on the column, so each wave runs its chunk
+// from a zero entry value, the chunk results are combined across waves through LDS, and
+// each wave adds (running product of slopes) x (true entry value).  Every value is read
+// and written once.
+//   CN_ADD: out += C^-1 in       CN_SET: out = C^-1 in (in may alias out)
+//   CN_T:   out = V C^-1 V^-1 in (V = dz for centre fields, dzc for interior faces);
+//           CN_SET / CN_T zero the two wall rows of face fields.
+enum { CN_ADD = 0, CN_SET = 1, CN_T = 2 };
+template <int KZ, int MODE>
+__global__ void __launch_bounds__(1024)
+k_cn_tiled(GridDev g, int kind, const double* __restrict__ fac, const double* in, double* out) {
+    __shared__ double bs[16][64];
+    __shared__ double as[16];
+    const size_t plane = (size_t)g.nx * g.ny;
+    const int n = kind == 0 ? g.nz : g.nz - 1;
+    const int ko = kind == 0 ? 0 : 1;
+    const double* l = fac;
+    const double* invd = fac + n;
+    const double* cs = fac + 2 * n;
+    const double* wv = kind == 0 ? g.dz : g.dzc;
+    // the wave index is uniform, so the per-row factors are scalar loads
+    const int lane = threadIdx.x & 63, nwave = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const size_t col = (size_t)xcd_remap(blockIdx.x, gridDim.x) * 64 + lane;
+    const bool valid = col < plane;
+    const size_t base = (size_t)ko * plane + col;
+    const int r0 = wave * KZ;
+    double x[KZ];
+#pragma unroll
+    for (int i = 0; i < KZ; ++i) {
+        const int r = r0 + i;
+        x[i] = (valid && r < n) ? in[base + (size_t)r * plane] : 0.0;
+        if (MODE == CN_T && r < n) x[i] /= wv[r + ko];
+    }
+    // forward sweep from a zero entry value
+    double b = 0.0, a = 1.0;
+#pragma unroll
+    for (int i = 0; i < KZ; ++i) {
+        const int r = r0 + i;
+        if (r < n) {
+            b = x[i] - l[r] * b;   // l[0] = 0
+            a *= -l[r];
+            x[i] = b;
+        }
+    }
+    bs[wave][lane] = b;
+    if (lane == 0) as[wave] = a;
+    __syncthreads();
+    double yin = 0.0;
+    for (int v = 0; v < wave; ++v) yin = as[v] * yin + bs[v][lane];
+    double pr = 1.0;
+#pragma unroll
+    for (int i = 0; i < KZ; ++i) {
+        const int r = r0 + i;
+        if (r < n) {
+            pr *= -l[r];
+            x[i] += pr * yin;
+        }
+    }
+    __syncthreads();
+    // backward sweep from a zero entry value (cs[n-1] = 0)
+    b = 0.0;
+    a = 1.0;
+#pragma unroll
+    for (int i = KZ - 1; i >= 0; --i) {
+        const int r = r0 + i;
+        if (r < n) {
+            b = (x[i] - cs[r] * b) * invd[r];
+            a *= -cs[r] * invd[r];
+            x[i] = b;
+        }
+    }
+    bs[wave][lane] = b;
+    if (lane == 0) as[wave] = a;
+    __syncthreads();
+    double din = 0.0;
+    for (int v = nwave - 1; v > wave; --v) din = as[v] * din + bs[v][lane];
+    pr = 1.0;
+#pragma unroll
+    for (int i = KZ - 1; i >= 0; --i) {
+        const int r = r0 + i;
+        if (r < n) {
+            pr *= -cs[r] * invd[r];
+            x[i] += pr * din;
+        }
+    }
+    if (!valid) return;
+#pragma unroll
+    for (int i = 0; i < KZ; ++i) {
+        const int r = r0 + i;
+        if (r < n) {
+            double* o = out + base + (size_t)r * plane;
+            if (MODE == CN_ADD)
+                *o += x[i];
+            else if (MODE == CN_SET)
+                *o = x[i];
+            else
+                *o = x[i] * wv[r + ko];
+        }
+    }
+    if (MODE != CN_ADD && kind == 1 && wave == 0) {
+        out[col] = 0.0;
+        out[(size_t)g.nz * plane + col] = 0.0;
+    }
+}
+
+// Launch the tiled CN solve when the rows fit 16 waves of at most 32 rows each;
+// returns false (nothing launched) otherwise.
+template <int MODE>
+static bool cn_tiled_launch(const GridDev& g, int kind, const double* fac, const double* in, double* out,
+                            hipStream_t st, hipError_t* err) {
+    const int n = kind == 0 ? g.nz : g.nz - 1;
+    const size_t plane = (size_t)g.nx * g.ny;
+    const int nblk = (int)((plane + 63) / 64);
+    int kz = 0;
+    for (int c : {4, 8, 16, 32})
+        if ((n + c - 1) / c <= 16) {
+            kz = c;
+            break;
+        }
+    if (kz == 0) return false;
+    const int threads = 64 * ((n + kz - 1) / kz);
+    switch (kz) {
+        case 4:
+            hipLaunchKernelGGL((k_cn_tiled<4, MODE>), dim3(nblk), dim3(threads), 0, st, g, kind, fac, in, out);
+            break;
+        case 8:
+            hipLaunchKernelGGL((k_cn_tiled<8, MODE>), dim3(nblk), dim3(threads), 0, st, g, kind, fac, in, out);
+            break;
+        case 16:
+            hipLaunchKernelGGL((k_cn_tiled<16, MODE>), dim3(nblk), dim3(threads), 0, st, g, kind, fac, in, out);
+            break;
+        default:
+            hipLaunchKernelGGL((k_cn_tiled<32, MODE>), dim3(nblk), dim3(threads), 0, st, g, kind, fac, in, out);
+            break;
+    }
+    *err = hipGetLastError();
+    return true;
+}
+
 // ---- CFL (Listing 1) ------------------------------------------------------
 __global__ void __launch_bounds__(256)
 k_cfl(const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w, GridDev g,
@@ -226,13 +328,9 @@ k_cfl(const double* __restrict__ u, const double* __restrict__ v, const double* 
 __global__ void __launch_bounds__(256)
 k_adj_rhs(const double* __restrict__ gu, const double* __restrict__ gv, const double* __restrict__ gw,
           const double* __restrict__ gp, double* __restrict__ f, GridDev g, double inv_s, double c) {
-    const size_t n = (size_t)g.nx * g.ny * g.nz;
-    const size_t id = (size_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (id >= n) return;
-    const int i = (int)(id % g.nx);
-    const size_t jk = id / g.nx;
-    const int j = (int)(jk % g.ny);
-    const int k = (int)(jk / g.ny);
+    int i, j, k;
+    if (!stencil_cell(g, i, j, k)) return;
+    const size_t id = ((size_t)k * g.ny + j) * g.nx + i;
     const size_t plane = (size_t)g.nx * g.ny;
     const int ip = (i + 1 == g.nx) ? 0 : i + 1;
     const int jp = (j + 1 == g.ny) ? 0 : j + 1;
@@ -256,13 +354,9 @@ __global__ void __launch_bounds__(256)
 k_adj_update(const double* __restrict__ gu, const double* __restrict__ gv, const double* __restrict__ gw,
              const double* __restrict__ phi, double* __restrict__ ou, double* __restrict__ ov,
              double* __restrict__ ow, GridDev g) {
-    const size_t n = (size_t)g.nx * g.ny * g.nz;
-    const size_t id = (size_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (id >= n) return;
-    const int i = (int)(id % g.nx);
-    const size_t jk = id / g.nx;
-    const int j = (int)(jk % g.ny);
-    const int k = (int)(jk / g.ny);
+    int i, j, k;
+    if (!stencil_cell(g, i, j, k)) return;
+    const size_t id = ((size_t)k * g.ny + j) * g.nx + i;
     const size_t plane = (size_t)g.nx * g.ny;
     const int im = (i == 0) ? g.nx - 1 : i - 1;
     const int jm = (j == 0) ? g.ny - 1 : j - 1;
@@ -278,37 +372,26 @@ k_adj_update(const double* __restrict__ gu, const double* __restrict__ gv, const
 
 hipError_t launch_adj_rhs(const GridDev& g, const double* gu, const double* gv, const double* gw, const double* gp,
                           double* f, double inv_s, double c, hipStream_t st) {
-    const size_t n = (size_t)g.nx * g.ny * g.nz;
-    hipLaunchKernelGGL(k_adj_rhs, dim3(nblocks(n, 256)), dim3(256), 0, st, gu, gv, gw, gp, f, g, inv_s, c);
+    hipLaunchKernelGGL(k_adj_rhs, dim3(stencil_blocks(g)), dim3(kStencilBlock), 0, st, gu, gv, gw, gp, f, g, inv_s, c);
     return hipGetLastError();
 }
 
 hipError_t launch_adj_update(const GridDev& g, const double* gu, const double* gv, const double* gw,
                              const double* phi, double* ou, double* ov, double* ow, hipStream_t st) {
-    const size_t n = (size_t)g.nx * g.ny * g.nz;
-    hipLaunchKernelGGL(k_adj_update, dim3(nblocks(n, 256)), dim3(256), 0, st, gu, gv, gw, phi, ou, ov, ow, g);
+    hipLaunchKernelGGL(k_adj_update, dim3(stencil_blocks(g)), dim3(kStencilBlock), 0, st, gu, gv, gw, phi, ou, ov, ow, g);
     return hipGetLastError();
 }
 
 // ---- launchers --------------------------------------------------------------
 hipError_t launch_divergence(const GridDev& g, const double* u, const double* v, const double* w, double* f,
                              double scale, hipStream_t st) {
-    const size_t n = (size_t)g.nx * g.ny * g.nz;
-    hipLaunchKernelGGL(k_divergence, dim3(nblocks(n, 256)), dim3(256), 0, st, u, v, w, f, g, scale);
+    hipLaunchKernelGGL(k_divergence, dim3(stencil_blocks(g)), dim3(kStencilBlock), 0, st, u, v, w, f, g, scale);
     return hipGetLastError();
 }
 
 hipError_t launch_project_update(const GridDev& g, double* u, double* v, double* w, double* p, const double* phi,
                                  double s, double c, hipStream_t st) {
-    const size_t n = (size_t)g.nx * g.ny * g.nz;
-    hipLaunchKernelGGL(k_project_update, dim3(nblocks(n, 256)), dim3(256), 0, st, u, v, w, p, phi, g, s, c);
-    return hipGetLastError();
-}
-
-hipError_t launch_residual(const GridDev& g, const double* f, const double* mu, double mu_scale, const double* x,
-                           double* r, double* partial, hipStream_t st) {
-    const size_t n = (size_t)g.nx * g.ny * g.nz;
-    hipLaunchKernelGGL(k_residual, dim3(nblocks(n, 256)), dim3(256), 0, st, f, mu, mu_scale, x, r, g, partial);
+    hipLaunchKernelGGL(k_project_update, dim3(stencil_blocks(g)), dim3(kStencilBlock), 0, st, u, v, w, p, phi, g, s, c);
     return hipGetLastError();
 }
 
@@ -354,11 +437,22 @@ hipError_t launch_scale_planes(const GridDev& g, const double* in, double* out, 
 }
 
 hipError_t launch_cn_factor(const GridDev& g, int kind, double beta, double* fac, hipStream_t st) {
-    hipLaunchKernelGGL(k_cn_factor, dim3(1), dim3(64), 0, st, g, kind, beta, fac);
+    hipLaunchKernelGGL(k_cn_factor, dim3(1), dim3(256), 0, st, g, kind, beta, fac);
     return hipGetLastError();
 }
 
+bool launch_cn_tiled_add(const GridDev& g, int kind, const double* fac, const double* rhs, double* q,
+                         hipStream_t st, hipError_t* err) {
+    return cn_tiled_launch<CN_ADD>(g, kind, fac, rhs, q, st, err);
+}
+bool launch_cn_tiled_t(const GridDev& g, int kind, const double* fac, const double* in, double* out,
+                       hipStream_t st, hipError_t* err) {
+    return cn_tiled_launch<CN_T>(g, kind, fac, in, out, st, err);
+}
+
 hipError_t launch_cn_solve(const GridDev& g, int kind, const double* fac, double* x, hipStream_t st) {
+    hipError_t e;
+    if (cn_tiled_launch<CN_SET>(g, kind, fac, x, x, st, &e)) return e;
     const size_t plane = (size_t)g.nx * g.ny;
     hipLaunchKernelGGL(k_cn_solve, dim3(nblocks(plane, 256)), dim3(256), 0, st, g, kind, fac, x);
     return hipGetLastError();

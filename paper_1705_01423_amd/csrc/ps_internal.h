@@ -116,6 +116,31 @@ struct GridDev {
     const double* idz;   // nz, 1/dz
 };
 
+// Stencil kernels: one thread per cell; a block covers kStencilBlock consecutive x of
+// one (y, z) row.  Blocks walk a tile of kStencilTY rows in y, then z, then the next
+// tile, so that the z +- 1 (and y +- 1) neighbour rows a block reads were loaded a few
+// blocks earlier on the same XCD and are still in its L2.
+constexpr int kStencilBlock = 256;
+constexpr int kStencilTY = 8;
+inline int stencil_blocks(const GridDev& g) {
+    const int nxs = (g.nx + kStencilBlock - 1) / kStencilBlock;
+    const int nyt = (g.ny + kStencilTY - 1) / kStencilTY;
+    return nxs * kStencilTY * g.nz * nyt;
+}
+// Cell (i, j, k) of this thread; false for the padding threads of ragged rows / tiles.
+__device__ __forceinline__ bool stencil_cell(const GridDev& g, int& i, int& j, int& k) {
+    int r = xcd_remap(blockIdx.x, gridDim.x);
+    const int nxs = (g.nx + kStencilBlock - 1) / kStencilBlock;
+    const int xs = r % nxs;
+    r /= nxs;
+    const int jin = r % kStencilTY;
+    r /= kStencilTY;
+    k = r % g.nz;
+    j = (r / g.nz) * kStencilTY + jin;
+    i = xs * kStencilBlock + (int)threadIdx.x;
+    return i < g.nx && j < g.ny;
+}
+
 // Per-precision spectral machinery: twiddle tables and buffers.
 template <typename T>
 struct SpecDev {
@@ -142,6 +167,11 @@ template <typename T>
 hipError_t launch_xfwd(const GridDev& g, const SpecDev<T>& s, const double* f, const double* scale_z,
                        double* partial, hipStream_t st, const double* resid_x = nullptr,
                        const double* resid_mu = nullptr, double mu_scale = 0.0);
+// The x transform of the divergence (D u*) * div_scale of a face velocity (u, v: nz planes,
+// w: nz + 1 planes), formed while loading; partial (optional) receives sum dz f per block.
+template <typename T>
+hipError_t launch_xfwd_div(const GridDev& g, const SpecDev<T>& s, const double* u, const double* v, const double* w,
+                           double div_scale, double* partial, hipStream_t st);
 template <typename T>
 hipError_t launch_yfwd(const GridDev& g, const SpecDev<T>& s, hipStream_t st);
 template <typename T>
@@ -181,9 +211,6 @@ hipError_t launch_divergence(const GridDev& g, const double* u, const double* v,
                              double* f, double scale, hipStream_t st);
 hipError_t launch_project_update(const GridDev& g, double* u, double* v, double* w, double* p,
                                  const double* phi, double s, double c, hipStream_t st);
-// r = (f - mu[0] * mu_scale) - L x; partial (optional): per-block {sum r^2, sum (f - mu)^2}
-hipError_t launch_residual(const GridDev& g, const double* f, const double* mu, double mu_scale, const double* x,
-                           double* r, double* partial, hipStream_t st);
 // flag[0] |= 1 when some value of p[0..n) is not finite
 hipError_t launch_nonfinite(const double* p, size_t n, unsigned* flag, hipStream_t st);
 hipError_t launch_adj_rhs(const GridDev& g, const double* gu, const double* gv, const double* gw, const double* gp,
@@ -196,6 +223,12 @@ hipError_t launch_fill(double* p, size_t n, double v, hipStream_t st);
 hipError_t launch_scale_planes(const GridDev& g, const double* in, double* out, const double* zs, int nplanes,
                                size_t plane, hipStream_t st);
 hipError_t launch_cn_factor(const GridDev& g, int kind, double beta, double* fac, hipStream_t st);
+// Tiled CN solves (columns of up to 512 rows): q += C^-1 rhs, and out = V C^-1 V^-1 in.
+// Return false, launching nothing, when the columns are too tall; *err gets the launch status.
+bool launch_cn_tiled_add(const GridDev& g, int kind, const double* fac, const double* rhs, double* q,
+                         hipStream_t st, hipError_t* err);
+bool launch_cn_tiled_t(const GridDev& g, int kind, const double* fac, const double* in, double* out,
+                       hipStream_t st, hipError_t* err);
 hipError_t launch_cn_solve(const GridDev& g, int kind, const double* fac, double* x, hipStream_t st);
 hipError_t launch_cfl(const GridDev& g, const double* u, const double* v, const double* w, double* out,
                       hipStream_t st);

@@ -38,13 +38,9 @@ __device__ __forceinline__ double sq(double a) { return a * a; }
 // One thread per cell (k, j, i): rhs of u, v at the cell's x/y faces, and of w, T at
 // its bottom z-face k (interior faces only; wall rows are zeroed).
 __global__ void __launch_bounds__(256) k_explicit(SubstepArgs a, GridDev g) {
-    const size_t n = (size_t)g.nx * g.ny * g.nz;
-    const size_t id = (size_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (id >= n) return;
-    const int i = (int)(id % g.nx);
-    const size_t jk = id / g.nx;
-    const int j = (int)(jk % g.ny);
-    const int k = (int)(jk / g.ny);
+    int i, j, k;
+    if (!stencil_cell(g, i, j, k)) return;
+    const size_t id = ((size_t)k * g.ny + j) * g.nx + i;
     const Ix X{g.nx, g.ny, g.nz, (size_t)g.nx * g.ny};
     const int im = wrapm(i, g.nx), ip = wrapp(i, g.nx);
     const int jm = wrapm(j, g.ny), jp = wrapp(j, g.ny);
@@ -234,13 +230,9 @@ k_cn_solve_t(GridDev g, int kind, const double* __restrict__ fac, const double* 
 // each face carries Lambda_f = kappa_c / h_c - kappa_{c+1} / h_{c+1}; a flux
 // F = U Q sends Lambda U dQ and Lambda Q dU to the points averaged into Q and U.
 __global__ void __launch_bounds__(256) k_explicit_adj(SubstepAdjArgs a, GridDev g) {
-    const size_t n = (size_t)g.nx * g.ny * g.nz;
-    const size_t id = (size_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (id >= n) return;
-    const int i = (int)(id % g.nx);
-    const size_t jk = id / g.nx;
-    const int j = (int)(jk % g.ny);
-    const int k = (int)(jk / g.ny);
+    int i, j, k;
+    if (!stencil_cell(g, i, j, k)) return;
+    const size_t id = ((size_t)k * g.ny + j) * g.nx + i;
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     const Ix X{nx, ny, nz, (size_t)nx * ny};
     const int im = wrapm(i, nx), ip = wrapp(i, nx);
@@ -447,25 +439,27 @@ __global__ void __launch_bounds__(256) k_explicit_adj(SubstepAdjArgs a, GridDev 
 
 hipError_t launch_cn_solve_t(const GridDev& g, int kind, const double* fac, const double* in, double* out,
                              hipStream_t st) {
+    hipError_t e;
+    if (launch_cn_tiled_t(g, kind, fac, in, out, st, &e)) return e;
     const size_t plane = (size_t)g.nx * g.ny;
     hipLaunchKernelGGL(k_cn_solve_t, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, st, g, kind, fac, in, out);
     return hipGetLastError();
 }
 
 hipError_t launch_explicit_adj(const GridDev& g, const SubstepAdjArgs& a, hipStream_t st) {
-    const size_t n = (size_t)g.nx * g.ny * g.nz;
-    hipLaunchKernelGGL(k_explicit_adj, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, g);
+    hipLaunchKernelGGL(k_explicit_adj, dim3(stencil_blocks(g)), dim3(kStencilBlock), 0, st, a, g);
     return hipGetLastError();
 }
 
 hipError_t launch_explicit(const GridDev& g, const SubstepArgs& a, hipStream_t st) {
-    const size_t n = (size_t)g.nx * g.ny * g.nz;
-    hipLaunchKernelGGL(k_explicit, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, g);
+    hipLaunchKernelGGL(k_explicit, dim3(stencil_blocks(g)), dim3(kStencilBlock), 0, st, a, g);
     return hipGetLastError();
 }
 
 hipError_t launch_cn_solve_add(const GridDev& g, int kind, const double* fac, double* rhs, double* q,
                                hipStream_t st) {
+    hipError_t e;
+    if (launch_cn_tiled_add(g, kind, fac, rhs, q, st, &e)) return e;
     const size_t plane = (size_t)g.nx * g.ny;
     hipLaunchKernelGGL(k_cn_solve_add, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, st, g, kind, fac, rhs, q);
     return hipGetLastError();

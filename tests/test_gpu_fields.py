@@ -41,6 +41,30 @@ def test_project_parity(s, c):
     assert d1 < 1e-12 * d0
 
 
+@pytest.mark.parametrize("shape", [(48, 32, 24), (24, 6, 10), (96, 24, 40)])
+def test_project_fused_divergence(shape):
+    """FP64 projections form D u*/s inside the x transform; with the finiteness check the
+    divergence is stored first by its own kernel.  Same arithmetic, so bitwise-equal results
+    (blocks walk y tiles then z when ny allows, plain row order otherwise)."""
+    nx, ny, nz = shape
+    banner(f"project fused divergence {shape}")
+    g, fused = grids(nx, ny, nz, 2.0, 2.0)
+    _, stored = grids(nx, ny, nz, 2.0, 2.0, flags=2)   # PS_FLAG_CHECK_FINITE
+    u, v, w = _modes(nx, ny, nz, 2.0, 2.0)
+    p = torch.as_tensor(np.random.default_rng(4).standard_normal(fused.centre_shape))
+    out = []
+    for plan in (fused, stored):
+        ud, vd, wd, pd = _cuda(u, v, w, p)
+        phi = torch.empty_like(pd)
+        plan.project(ud, vd, wd, pd, phi, 0.7, 0.01)
+        out.append((ud, vd, wd, pd, phi))
+    for a, b in zip(*out):
+        assert torch.equal(a, b)
+    ref = poisson.project(u, v, w, p, g, 0.7, 0.01)
+    for a, b in zip(out[0], ref):
+        assert rel(a, b) < 1e-12
+
+
 def test_project_refined():
     banner("project fp32_refined")
     g, plan = grids(64, 48, 40, 2.0, 2.0, precision="fp32_refined")
@@ -53,10 +77,12 @@ def test_project_refined():
         assert rel(a, b) < 1e-11, info
 
 
+@pytest.mark.parametrize("nz", [2, 3, 33, 64, 65, 200, 512, 513, 600])
 @pytest.mark.parametrize("kind", [0, 1])
-def test_cn_solve(kind):
-    banner(f"cn kind={kind}")
-    g, plan = grids(24, 16, 33)
+def test_cn_solve(kind, nz):
+    """Tiled solve (up to 16 waves of at most 32 rows) and the lane-per-column sweep beyond."""
+    banner(f"cn kind={kind} nz={nz}")
+    g, plan = grids(24, 16, nz)
     shape = plan.centre_shape if kind == 0 else plan.face_shape
     rhs = torch.as_tensor(np.random.default_rng(2).standard_normal(shape))
     beta = 2.5e-4
@@ -174,6 +200,47 @@ def test_substep_parity(l, prec, tol):
         assert rel(a, b) < tol, name
     for a, b in zip(hout, ref_h):
         assert rel(a, b) < 1e-13
+
+
+@pytest.mark.parametrize("shape", [(384, 12, 6), (48, 24, 20), (96, 6, 9)])
+def test_substep_shapes(shape):
+    """Rows longer than one stencil block (ragged x segments) and ragged y tiles."""
+    nx, ny, nz = shape
+    banner(f"substep shape {shape}")
+    g, plan = grids(nx, ny, nz)
+    state = _rb(nx, ny, nz, seed=21)
+    dt, nu, ka = 2e-2, 2e-2, 1.5e-2
+    ref_state, ref_h = ss.substep(state, g, 1, dt, nu, ka)
+    dstate = _cuda(*state)
+    hout = [torch.empty_like(x) for x in dstate[:4]]
+    plan.substep(1, dt, nu, ka, *dstate, h_out=hout)
+    for name, a, b in zip("uvwTp", dstate, ref_state):
+        assert rel(a, b) < 1e-12, name
+    for a, b in zip(hout, ref_h):
+        assert rel(a, b) < 1e-13
+
+
+@pytest.mark.parametrize("shape", [(12, 12, 8), (384, 6, 5)])
+def test_substep_adjoint_shapes(shape):
+    nx, ny, nz = shape
+    banner(f"substep adjoint shape {shape}")
+    g, plan = grids(nx, ny, nz, precision="fp64")
+    state = _rb(nx, ny, nz, seed=23, unoise=0.1)
+    dt, nu, ka = 2e-2, 1e-2, 8e-3
+    rng = np.random.default_rng(24)
+    cot = [torch.as_tensor(rng.standard_normal(x.shape)) for x in state]
+    for c in (cot[2], cot[3]):
+        c[0] = 0
+        c[-1] = 0
+    xs = [a.clone().requires_grad_(True) for a in state]
+    out, _ = ss.substep(xs, g, 1, dt, nu, ka, differentiable=True)
+    loss = sum((a * b).sum() for a, b in zip(out, cot))
+    ref = torch.autograd.grad(loss, xs)
+    got = plan.substep_adjoint(dt, nu, ka, *_cuda(*state), _cuda(*cot))
+    for name, a, b in zip("uvwTp", got, ref):
+        if name in "wT":
+            a, b = a[1:-1], b[1:-1]
+        assert rel(a, b) < 1e-11, name
 
 
 def test_substep_increment_parity():
