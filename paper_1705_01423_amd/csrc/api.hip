@@ -295,47 +295,54 @@ ps_status spectral_solve(ps_plan_t p, const double* in, double* out, int mode, c
     // formed inside the x transform; its norms go to R_R2 / R_F2.
     const GridDev& g = p->gd;
     SpecDev<T> s = spec_of<T>(p);
-    const int nbx = xfwd_blocks<T>(g);
     const double scale = 1.0 / ((double)p->nx * (double)p->ny);
     // Plane chunks: the x and y stages run chunk by chunk through the first planes of
-    // buffer a, so that this small intermediate can stay in the last-level cache.
-    const int P = (p->chunk > 0 && p->chunk < g.nz && nbx % g.nz == 0) ? p->chunk : g.nz;
-    const int bpp = nbx / g.nz;   // x-stage blocks per plane (when chunking)
-    for (int z0 = 0; z0 < g.nz; z0 += P) {
+    // buffer a, so that this small intermediate can stay in the last-level cache.  Each
+    // chunk's x-stage blocks write their partial sums after the previous chunks'.
+    const int P = (p->chunk > 0 && p->chunk < g.nz) ? p->chunk : g.nz;
+    auto chunk_of = [&](int z0, GridDev& gc) {
         SpecDev<T> sc = s;
+        gc = g;
         if (P < g.nz) {
             sc.z0 = z0;
             sc.nzc = std::min(P, g.nz - z0);
+            gc.nz = sc.nzc;
         }
+        return sc;
+    };
+    int nbx = 0;   // x-forward blocks so far
+    for (int z0 = 0; z0 < g.nz; z0 += P) {
+        GridDev gc;
+        const SpecDev<T> sc = chunk_of(z0, gc);
         if (resid_x)
-            PS_HIP(launch_xfwd<T>(g, sc, in, nullptr, p->partial + (size_t)2 * bpp * z0, st, resid_x,
-                                  p->small + R_WSUM, inv_den(p)),
+            PS_HIP(launch_xfwd<T>(g, sc, in, nullptr, p->partial + (size_t)2 * nbx, st, resid_x, p->small + R_WSUM,
+                                  inv_den(p)),
                    "x forward FFT (residual)");
         else if (div)
             PS_HIP(launch_xfwd_div<T>(g, sc, div->u, div->v, div->w, div->scale,
-                                      want_wsum ? p->partial + (size_t)bpp * z0 : nullptr, st),
+                                      want_wsum ? p->partial + (size_t)nbx : nullptr, st),
                    "x forward FFT (divergence)");
         else
-            PS_HIP(launch_xfwd<T>(g, sc, in, zin, want_wsum ? p->partial + (size_t)bpp * z0 : nullptr, st),
+            PS_HIP(launch_xfwd<T>(g, sc, in, zin, want_wsum ? p->partial + (size_t)nbx : nullptr, st),
                    "x forward FFT");
+        nbx += xfwd_blocks<T>(gc);
         PS_HIP(launch_yfwd<T>(g, sc, st), "y forward FFT");
     }
     if (resid_x) PS_HIP(launch_reduce2(p->partial, nbx, 2, p->red_scratch, p->small + R_R2, st), "reduce");
     if (want_wsum) PS_HIP(launch_reduce2(p->partial, nbx, 1, p->red_scratch, p->small + R_WSUM, st), "reduce");
     PS_HIP(launch_zsolve<T>(g, s, st), "z solve");
     PS_HIP(launch_zsolve00<T>(g, s, p->small + R_DEFECT, st), "z solve (0,0)");
+    int nbi = 0;   // x-inverse blocks so far
     for (int z0 = 0; z0 < g.nz; z0 += P) {
-        SpecDev<T> sc = s;
-        if (P < g.nz) {
-            sc.z0 = z0;
-            sc.nzc = std::min(P, g.nz - z0);
-        }
+        GridDev gc;
+        const SpecDev<T> sc = chunk_of(z0, gc);
         PS_HIP(launch_yinv<T>(g, sc, st), "y inverse FFT");
         PS_HIP(launch_xinv<T>(g, sc, out, scale, mode, mu_dev, mu_scale, zout,
-                              want_norms ? p->partial + (size_t)3 * bpp * z0 : nullptr, st),
+                              want_norms ? p->partial + (size_t)3 * nbi : nullptr, st),
                "x inverse FFT");
+        nbi += xinv_blocks<T>(gc);
     }
-    if (want_norms) PS_HIP(launch_reduce2(p->partial, nbx, 3, p->red_scratch, p->small + R_D2, st), "reduce");
+    if (want_norms) PS_HIP(launch_reduce2(p->partial, nbi, 3, p->red_scratch, p->small + R_D2, st), "reduce");
     return PS_OK;
 }
 
@@ -544,6 +551,8 @@ ps_status poisson_plan_create(ps_plan_t* out, int nx, int ny, int nz, double lx,
     }
     int nbx = prec == PS_FP64 ? xfwd_blocks<double>(p->gd) : xfwd_blocks<float>(p->gd);
     int nbr = (int)((p->npts + 255) / 256);
+    // plane chunks may each end with a partly filled x-stage block: one more per plane at most
+    nbx += nz;
     p->nblk_max = nbx > nbr ? nbx : nbr;
     if (const char* ev = getenv("PS_CHUNK_PLANES")) p->chunk = atoi(ev);
     p->ws_bytes = workspace_layout(p, false);

@@ -41,6 +41,10 @@ constexpr int kYEmax = PS_Y_EMAX;
 #ifndef PS_X_THREADS
 #define PS_X_THREADS 64
 #endif
+// the inverse x transform reads strided tiles: two rows per block make each read 256 B
+#ifndef PS_X_THREADS_INV
+#define PS_X_THREADS_INV 128
+#endif
 #ifndef PS_X_LDS
 #define PS_X_LDS 72000
 #endif
@@ -56,13 +60,14 @@ constexpr int kYEmax = PS_Y_EMAX;
 
 // Rows of one block: LDS row = lds_len(M) slots (odd for M >= 16, so that rows
 // start in different banks).
-template <typename T, int M>
+template <typename T, int M, bool INV = false>
 struct XShape {
     static constexpr int EM = XEmax<T>::value;
     using Sh = FftShape<M, EM>;
     static constexpr int NT = Sh::NT;
     static constexpr int LROW = lds_len(M);
-    static constexpr int R0 = PS_X_THREADS / NT > 0 ? PS_X_THREADS / NT : 1;
+    static constexpr int TH = INV ? PS_X_THREADS_INV : PS_X_THREADS;
+    static constexpr int R0 = TH / NT > 0 ? TH / NT : 1;
     static constexpr int RL0 = PS_X_LDS / (LROW * (int)sizeof(cx<T>));
     static constexpr int RL = RL0 > 0 ? RL0 : 1;
     static constexpr int R = R0 < RL ? R0 : RL;
@@ -249,12 +254,12 @@ k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny,
 
 // ---------------------------------------------------------------------------
 template <typename T, int M>
-__global__ void __launch_bounds__((XShape<T, M>::THREADS))
+__global__ void __launch_bounds__((XShape<T, M, true>::THREADS))
 k_xinv(const cx<T>* __restrict__ in, double* __restrict__ out, int nrows, int ny, int nkxb,
        const cx<T>* __restrict__ tw, const cx<T>* __restrict__ ptw, double scale, int mode,
        const double* __restrict__ mu, double mu_scale, const double* __restrict__ scale_z,
        const double* __restrict__ dz, double* __restrict__ partial) {
-    using X = XShape<T, M>;
+    using X = XShape<T, M, true>;
     constexpr int NT = X::NT, R = X::R, LROW = X::LROW;
     constexpr int W = TileW<T>::value;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -450,7 +455,7 @@ template <typename T, int M>
 static hipError_t xinv_launch_t(const GridDev& g, const SpecDev<T>& s, double* out, double scale, int mode,
                                 const double* mu, double mu_scale, const double* scale_z, double* partial,
                                 hipStream_t st) {
-    using X = XShape<T, M>;
+    using X = XShape<T, M, true>;
     const int nzl = s.nzc > 0 ? s.nzc : g.nz;
     const size_t zoff = (size_t)s.z0 * g.nx * g.ny;
     const int nrows = g.ny * nzl;
@@ -565,9 +570,22 @@ int xfwd_blocks(const GridDev& g) {
     }
 }
 
+template <typename T, int M>
+static int xiblocks_t(const GridDev& g) {
+    return (g.ny * g.nz + XShape<T, M, true>::R - 1) / XShape<T, M, true>::R;
+}
+
 template <typename T>
 int xinv_blocks(const GridDev& g) {
-    return xfwd_blocks<T>(g);
+    switch (g.nx / 2) {
+#define PS_CASE(L) \
+    case L:        \
+        return xiblocks_t<T, L>(g);
+        PS_FFT_LENGTHS(PS_CASE)
+#undef PS_CASE
+        default:
+            return 0;
+    }
 }
 
 #define PS_INST(T)                                                                                           \

@@ -126,6 +126,9 @@ __device__ __forceinline__ Aff<T> shfl_down_aff(const Aff<T>& m, int d) {
 // lane groups), at most 1024 threads: tall columns run in narrower blocks (WZ/2,
 // WZ/4), and only columns too tall for those use the lane-per-column sweep (never
 // with the default shapes, which tile every nz <= 2048).
+#ifndef PS_Z_LDS_COEF
+#define PS_Z_LDS_COEF 0
+#endif
 #ifndef PS_Z_ROWS64
 #define PS_Z_ROWS64 8
 #endif
@@ -147,8 +150,13 @@ struct ZCols {
     static constexpr int value = sizeof(T) == 8 ? PS_Z_COLS64 : PS_Z_COLS32;
 };
 
+#ifdef PS_Z_WAVES_PER_EU
+#define PS_Z_ATTR __attribute__((amdgpu_waves_per_eu(PS_Z_WAVES_PER_EU)))
+#else
+#define PS_Z_ATTR
+#endif
 template <typename T, int K, int WZ, int MAXT>
-__global__ void __launch_bounds__(MAXT)
+__global__ void __launch_bounds__(MAXT) PS_Z_ATTR
 k_zsolve_scan(cx<T>* __restrict__ b, const T* __restrict__ etab, int nz, int ny, int nxh,
               const double* __restrict__ dz, const double* __restrict__ o, const double* __restrict__ lamx,
               const double* __restrict__ lamy) {
@@ -157,6 +165,15 @@ k_zsolve_scan(cx<T>* __restrict__ b, const T* __restrict__ etab, int nz, int ny,
     constexpr int NSUB = W / WZ;
     constexpr int LPW = 64 / WZ;          // lanes of one column inside a wave
     __shared__ T xs[16 * WZ * 4];         // per-wave totals
+#if PS_Z_LDS_COEF
+    // o in LDS: re-read where used instead of being held in registers across the scans
+    __shared__ double os_[2049];
+    for (int q = threadIdx.x; q <= nz; q += blockDim.x) os_[q] = o[q];
+    __syncthreads();
+    const double* oc = os_;
+#else
+    const double* oc = o;
+#endif
     const int tid = threadIdx.x;
     const int c = tid % WZ;
     const int l = tid / WZ;
@@ -201,18 +218,18 @@ k_zsolve_scan(cx<T>* __restrict__ b, const T* __restrict__ etab, int nz, int ny,
             if (k == 0) {
                 e = s;
             } else {
-                const T ok = (T)o[k];
+                const T ok = (T)oc[k];
                 const T mm = (i == 0) ? ok / (ok + eprev) : ok * rp[i - 1];
                 if (i == 0) m0 = mm;
                 e = s + mm * eprev;
             }
-            rp[i] = (T)1 / ((T)o[k + 1] + e);
+            rp[i] = (T)1 / ((T)oc[k + 1] + e);
             eprev = e;
             const T g = -(T)dz[k];
             v[i] = {g * v[i].x, g * v[i].y};   // g_k = -dz_k F_k
         }
     }
-    auto mult = [&](int i, int k) -> T { return i == 0 ? m0 : (T)o[k] * rp[i - 1]; };
+    auto mult = [&](int i, int k) -> T { return i == 0 ? m0 : (T)oc[k] * rp[i - 1]; };
 
     // ---- (B) forward sweep ------------------------------------------------------
     Aff<T> fa = {(T)1, {(T)0, (T)0}};
@@ -263,7 +280,7 @@ k_zsolve_scan(cx<T>* __restrict__ b, const T* __restrict__ etab, int nz, int ny,
     for (int i = K - 1; i >= 0; --i) {
         const int k = k0 + i;
         if (k < nz) {
-            const T ak = (T)o[k + 1] * rp[i];
+            const T ak = (T)oc[k + 1] * rp[i];
             ba = {ak * ba.a, {ak * ba.b.x + rp[i] * v[i].x, ak * ba.b.y + rp[i] * v[i].y}};
         }
     }
@@ -293,7 +310,7 @@ k_zsolve_scan(cx<T>* __restrict__ b, const T* __restrict__ etab, int nz, int ny,
     for (int i = K - 1; i >= 0; --i) {
         const int k = k0 + i;
         if (k < nz) {
-            const T ak = (T)o[k + 1] * rp[i];
+            const T ak = (T)oc[k + 1] * rp[i];
             x = {rp[i] * v[i].x + ak * x.x, rp[i] * v[i].y + ak * x.y};
             v[i] = x;
         }

@@ -134,7 +134,8 @@ def test_solve_fp64_parity(shape):
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32_refined", 1e-11)])
-@pytest.mark.parametrize("shape,chunk", [((64, 64, 64), 8), ((48, 96, 33), 16), ((24, 48, 16), 5)])
+@pytest.mark.parametrize("shape,chunk", [((64, 64, 64), 8), ((48, 96, 33), 16), ((24, 48, 16), 5),
+                                         ((16, 3, 10), 3), ((96, 6, 7), 2)])
 def test_solve_plane_chunks(shape, chunk, prec, tol, monkeypatch):
     """x/y stages run in plane chunks (last chunk partial) give the same solve."""
     banner(f"chunked solve {shape} chunk={chunk} {prec}")
