@@ -343,6 +343,16 @@ def other_workloads(args):
                                       "adjoint_over_forward": round(adj / fwd, 3),
                                       "poisson_iterations": infos[-1]["iterations"],
                                       "gpoints_per_s": round(npts / fwd / 1e6, 3)}
+    plan.close()
+    # the same substep with the FP64 solve (one pass instead of three FP32 ones)
+    plan = Plan(cfg.nx, cfg.ny, cfg.nz, cfg.lx, cfg.ly, zf, precision="fp64")
+    step()
+    fwd64 = _event_ms(step, 3) - reset_ms
+    plan.substep_adjoint(dt, nu, ka, *saved, cot)
+    adj64 = _event_ms(lambda: plan.substep_adjoint(dt, nu, ka, *saved, cot), 3)
+    res["rk3_substep_768x768x512_fp64_poisson"] = {"forward_ms": round(fwd64, 3), "adjoint_ms": round(adj64, 3),
+                                                   "gpoints_per_s": round(npts / fwd64 / 1e6, 3)}
+    plan.close()
     return res
 
 

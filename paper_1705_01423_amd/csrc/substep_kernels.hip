@@ -19,146 +19,247 @@ namespace ps {
 
 namespace {
 
-struct Ix {
-    int nx, ny, nz;
-    size_t plane;
-    __device__ __forceinline__ size_t at(int k, int j, int i) const {
-        return (size_t)k * plane + (size_t)j * nx + i;
-    }
-};
-
-__device__ __forceinline__ int wrapm(int i, int n) { return i == 0 ? n - 1 : i - 1; }
-__device__ __forceinline__ int wrapp(int i, int n) { return i + 1 == n ? 0 : i + 1; }
 __device__ __forceinline__ double sq(double a) { return a * a; }
 
 }  // namespace
 
 
 
-// One thread per cell (k, j, i): rhs of u, v at the cell's x/y faces, and of w, T at
-// its bottom z-face k (interior faces only; wall rows are zeroed).
-__global__ void __launch_bounds__(256) k_explicit(SubstepArgs a, GridDev g) {
-    int i, j, k;
-    if (!stencil_cell(g, i, j, k)) return;
-    const size_t id = ((size_t)k * g.ny + j) * g.nx + i;
-    const Ix X{g.nx, g.ny, g.nz, (size_t)g.nx * g.ny};
-    const int im = wrapm(i, g.nx), ip = wrapp(i, g.nx);
-    const int jm = wrapm(j, g.ny), jp = wrapp(j, g.ny);
+// ---------------------------------------------------------------------------
+// z-marching stencil blocks.  A block owns a TX x TY tile of (x, y) columns and a
+// segment of ZSEG planes; it keeps three consecutive z-planes (k-1, k, k+1) of its
+// NF stencil fields in LDS, each as a (TY + 2) x (TX + 2) tile with a one-cell
+// periodic halo, and walks up the segment loading one new plane per step.  Every
+// field value is read from memory about once (plus the halo and two planes per
+// segment), and neighbour reads are LDS reads.
+template <int NF, int TX, int TY>
+struct Ring {
+    static constexpr int HX = TX + 2, HY = TY + 2, PL = HX * HY;
+    double* s;   // [3][NF][PL]
+    int tx, ty;
+    __device__ __forceinline__ static int slot(int kk) { return (kk + 3) % 3; }
+    // field f at (k + dk, j + dj, i + di) of this thread's cell
+    __device__ __forceinline__ double operator()(int k, int f, int dk, int dj, int di) const {
+        return s[(slot(k + dk) * NF + f) * PL + (ty + 1 + dj) * HX + (tx + 1 + di)];
+    }
+    // Plane kk of every field, staged through registers so that the loads of a later
+    // plane are in flight while the current one is computed: fetch() issues the loads
+    // (zeros where a field has no such plane: centre fields have planes 0..nz-1, face
+    // fields 0..nz), put() stores them into the plane's LDS slot.
+    static constexpr int NQ = (PL + TX * TY - 1) / (TX * TY);
+    struct Stage {
+        double v[NQ][NF];
+    };
+    __device__ __forceinline__ void fetch(int kk, const double* const (&F)[NF], const bool (&face)[NF],
+                                          const GridDev& g, int i0, int j0, Stage& st) const {
+        const size_t plane = (size_t)g.nx * g.ny;
+#pragma unroll
+        for (int qi = 0; qi < NQ; ++qi) {
+            const int q = (int)threadIdx.x + qi * TX * TY;
+            const int hy = q / HX, hx = q - hy * HX;
+            int gj = j0 - 1 + hy, gi = i0 - 1 + hx;
+            gj = gj < 0 ? gj + g.ny : gj % g.ny;
+            gi = gi < 0 ? gi + g.nx : gi % g.nx;
+            const size_t off = (size_t)(kk < 0 ? 0 : kk) * plane + (size_t)gj * g.nx + gi;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                const bool ok = q < PL && kk >= 0 && (kk < g.nz || (face[f] && kk == g.nz));
+                double v = 0.0;
+                if (ok) v = F[f][off];
+                st.v[qi][f] = v;
+            }
+        }
+    }
+    __device__ __forceinline__ void put(int kk, const Stage& st) {
+        const int sl = slot(kk);
+#pragma unroll
+        for (int qi = 0; qi < NQ; ++qi) {
+            const int q = (int)threadIdx.x + qi * TX * TY;
+            if (q < PL) {
+#pragma unroll
+                for (int f = 0; f < NF; ++f) s[(sl * NF + f) * PL + q] = st.v[qi][f];
+            }
+        }
+    }
+};
+
+constexpr int kExTX = 64, kExTY = 4, kExZSEG = 64;
+
+// Block -> (x tile, y tile, z segment), x tile fastest so that neighbouring y tiles
+// (which share halo rows) run together on one XCD.
+struct ExTile {
+    int i0, j0, kb, ke;
+};
+template <int TX, int TY, int ZSEG>
+__device__ __forceinline__ ExTile ex_tile(const GridDev& g) {
+    const int nxt = (g.nx + TX - 1) / TX, nyt = (g.ny + TY - 1) / TY;
+    int r = xcd_remap(blockIdx.x, gridDim.x);
+    const int xt = r % nxt;
+    r /= nxt;
+    const int yt = r % nyt;
+    const int zs = r / nyt;
+    ExTile t;
+    t.i0 = xt * TX;
+    t.j0 = yt * TY;
+    t.kb = zs * ZSEG;
+    t.ke = min(g.nz, t.kb + ZSEG);
+    return t;
+}
+template <int TX, int TY, int ZSEG>
+inline int ex_blocks(const GridDev& g) {
+    return ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) * ((g.nz + ZSEG - 1) / ZSEG);
+}
+
+// Right-hand sides of u, v at the cell's x/y faces and of w, T at its bottom z-face k
+// (interior faces; wall rows are zeroed).
+__global__ void __launch_bounds__(kExTX * kExTY) k_explicit(SubstepArgs a, GridDev g) {
+    constexpr int TX = kExTX, TY = kExTY, NF = 5;
+    enum { FU, FV, FW, FT, FP };
+    __shared__ double lds[3 * NF * (TX + 2) * (TY + 2)];
+    const ExTile tile = ex_tile<TX, TY, kExZSEG>(g);
+    Ring<NF, TX, TY> R{lds, (int)threadIdx.x % TX, (int)threadIdx.x / TX};
+    const int i = tile.i0 + R.tx, j = tile.j0 + R.ty;
+    const bool valid = i < g.nx && j < g.ny;
+    const double* const F[NF] = {a.u, a.v, a.w, a.t, a.p};
+    const bool face[NF] = {false, false, true, true, false};
+    const size_t plane = (size_t)g.nx * g.ny;
     const double idx = 1.0 / g.dx, idy = 1.0 / g.dy;
     const double idx2 = idx * idx, idy2 = idy * idy;
     const int nz = g.nz;
-    const double *u = a.u, *v = a.v, *w = a.w, *t = a.t, *p = a.p;
-
-    // ---- u at (x-face i, y-centre j, z-centre k) ----
-    {
-        const double uc = u[id], uim = u[X.at(k, j, im)], uip = u[X.at(k, j, ip)];
-        const double ujm = u[X.at(k, jm, i)], ujp = u[X.at(k, jp, i)];
-        const double ax = (sq(0.5 * (uc + uip)) - sq(0.5 * (uim + uc))) * idx;
-        const double fyb = 0.5 * (v[X.at(k, j, i)] + v[X.at(k, j, im)]) * (0.5 * (uc + ujm));
-        const double fyt = 0.5 * (v[X.at(k, jp, i)] + v[X.at(k, jp, im)]) * (0.5 * (ujp + uc));
-        const double ay = (fyt - fyb) * idy;
-        double fzb = 0.0, fzt = 0.0, ukm = 0.0, ukp = 0.0;
-        if (k > 0) {
-            ukm = u[X.at(k - 1, j, i)];
-            fzb = 0.5 * (w[X.at(k, j, i)] + w[X.at(k, j, im)]) * (0.5 * (ukm + uc));
+    typename Ring<NF, TX, TY>::Stage st;
+    R.fetch(tile.kb - 1, F, face, g, tile.i0, tile.j0, st);
+    R.put(tile.kb - 1, st);
+    R.fetch(tile.kb, F, face, g, tile.i0, tile.j0, st);
+    R.put(tile.kb, st);
+    R.fetch(tile.kb + 1, F, face, g, tile.i0, tile.j0, st);
+    for (int k = tile.kb; k < tile.ke; ++k) {
+        R.put(k + 1, st);
+        __syncthreads();
+        const size_t id = (size_t)k * plane + (size_t)j * g.nx + i;
+        // previous-substep H of this cell, loaded before the next plane's prefetch
+        double hp[4] = {0.0, 0.0, 0.0, 0.0};
+        if (valid && a.rho != 0.0) {
+            hp[0] = a.hpu[id];
+            hp[1] = a.hpv[id];
+            hp[2] = a.hpw[id];
+            hp[3] = a.hpt[id];
         }
-        if (k + 1 < nz) {
-            ukp = u[X.at(k + 1, j, i)];
-            fzt = 0.5 * (w[X.at(k + 1, j, i)] + w[X.at(k + 1, j, im)]) * (0.5 * (uc + ukp));
+        if (k + 2 <= tile.ke) R.fetch(k + 2, F, face, g, tile.i0, tile.j0, st);
+        if (valid) {
+            auto L = [&](int f, int dk, int dj, int di) { return R(k, f, dk, dj, di); };
+            // ---- u at (x-face i, y-centre j, z-centre k) ----
+            {
+                const double uc = L(FU, 0, 0, 0), uim = L(FU, 0, 0, -1), uip = L(FU, 0, 0, 1);
+                const double ujm = L(FU, 0, -1, 0), ujp = L(FU, 0, 1, 0);
+                const double ax = (sq(0.5 * (uc + uip)) - sq(0.5 * (uim + uc))) * idx;
+                const double fyb = 0.5 * (L(FV, 0, 0, 0) + L(FV, 0, 0, -1)) * (0.5 * (uc + ujm));
+                const double fyt = 0.5 * (L(FV, 0, 1, 0) + L(FV, 0, 1, -1)) * (0.5 * (ujp + uc));
+                const double ay = (fyt - fyb) * idy;
+                double fzb = 0.0, fzt = 0.0, ukm = 0.0, ukp = 0.0;
+                if (k > 0) {
+                    ukm = L(FU, -1, 0, 0);
+                    fzb = 0.5 * (L(FW, 0, 0, 0) + L(FW, 0, 0, -1)) * (0.5 * (ukm + uc));
+                }
+                if (k + 1 < nz) {
+                    ukp = L(FU, 1, 0, 0);
+                    fzt = 0.5 * (L(FW, 1, 0, 0) + L(FW, 1, 0, -1)) * (0.5 * (uc + ukp));
+                }
+                const double az = (fzt - fzb) / g.dz[k];
+                const double h = -(ax + ay + az) + a.nu * ((uip - 2.0 * uc + uim) * idx2 + (ujp - 2.0 * uc + ujm) * idy2);
+                const double fb = (k > 0) ? (uc - ukm) / g.dzw[k] : uc / g.dzw[0];
+                const double ft = (k + 1 < nz) ? (ukp - uc) / g.dzw[k + 1] : -uc / g.dzw[nz];
+                const double dzz = (ft - fb) / g.dz[k];
+                const double gp = (L(FP, 0, 0, 0) - L(FP, 0, 0, -1)) * idx;
+                double r = a.gam * h - a.alp * gp + a.alp * (a.nu * dzz);
+                if (a.rho != 0.0) r += a.rho * hp[0];
+                a.ru[id] = a.dt * r;
+                if (a.hu) a.hu[id] = h;
+            }
+            // ---- v at (x-centre i, y-face j, z-centre k) ----
+            {
+                const double vc = L(FV, 0, 0, 0), vjm = L(FV, 0, -1, 0), vjp = L(FV, 0, 1, 0);
+                const double vim = L(FV, 0, 0, -1), vip = L(FV, 0, 0, 1);
+                const double ay = (sq(0.5 * (vc + vjp)) - sq(0.5 * (vjm + vc))) * idy;
+                const double fxl = 0.5 * (L(FU, 0, 0, 0) + L(FU, 0, -1, 0)) * (0.5 * (vc + vim));
+                const double fxr = 0.5 * (L(FU, 0, 0, 1) + L(FU, 0, -1, 1)) * (0.5 * (vip + vc));
+                const double ax = (fxr - fxl) * idx;
+                double fzb = 0.0, fzt = 0.0, vkm = 0.0, vkp = 0.0;
+                if (k > 0) {
+                    vkm = L(FV, -1, 0, 0);
+                    fzb = 0.5 * (L(FW, 0, 0, 0) + L(FW, 0, -1, 0)) * (0.5 * (vkm + vc));
+                }
+                if (k + 1 < nz) {
+                    vkp = L(FV, 1, 0, 0);
+                    fzt = 0.5 * (L(FW, 1, 0, 0) + L(FW, 1, -1, 0)) * (0.5 * (vc + vkp));
+                }
+                const double az = (fzt - fzb) / g.dz[k];
+                const double h = -(ax + ay + az) + a.nu * ((vip - 2.0 * vc + vim) * idx2 + (vjp - 2.0 * vc + vjm) * idy2);
+                const double fb = (k > 0) ? (vc - vkm) / g.dzw[k] : vc / g.dzw[0];
+                const double ft = (k + 1 < nz) ? (vkp - vc) / g.dzw[k + 1] : -vc / g.dzw[nz];
+                const double dzz = (ft - fb) / g.dz[k];
+                const double gp = (L(FP, 0, 0, 0) - L(FP, 0, -1, 0)) * idy;
+                double r = a.gam * h - a.alp * gp + a.alp * (a.nu * dzz);
+                if (a.rho != 0.0) r += a.rho * hp[1];
+                a.rv[id] = a.dt * r;
+                if (a.hv) a.hv[id] = h;
+            }
+            // ---- w and T at (x-centre i, y-centre j, z-face k), interior faces ----
+            if (k == 0) {
+                a.rw[id] = 0.0;
+                a.rt[id] = 0.0;
+                if (a.hw) a.hw[id] = 0.0;
+                if (a.ht) a.ht[id] = 0.0;
+            } else {
+                const double dzm = g.dz[k - 1], dzp = g.dz[k], den = 1.0 / (2.0 * g.dzc[k]);
+                // volume-weighted horizontal transport on the side faces
+                const double uwl = (dzm * L(FU, -1, 0, 0) + dzp * L(FU, 0, 0, 0)) * den;
+                const double uwr = (dzm * L(FU, -1, 0, 1) + dzp * L(FU, 0, 0, 1)) * den;
+                const double vwb = (dzm * L(FV, -1, 0, 0) + dzp * L(FV, 0, 0, 0)) * den;
+                const double vwt = (dzm * L(FV, -1, 1, 0) + dzp * L(FV, 0, 1, 0)) * den;
+                const double wc = L(FW, 0, 0, 0), wim = L(FW, 0, 0, -1), wip = L(FW, 0, 0, 1);
+                const double wjm = L(FW, 0, -1, 0), wjp = L(FW, 0, 1, 0);
+                const double wkm = L(FW, -1, 0, 0), wkp = L(FW, 1, 0, 0);
+                const double tc = L(FT, 0, 0, 0), tim = L(FT, 0, 0, -1), tip = L(FT, 0, 0, 1);
+                const double tjm = L(FT, 0, -1, 0), tjp = L(FT, 0, 1, 0);
+                const double tkm = L(FT, -1, 0, 0), tkp = L(FT, 1, 0, 0);
+                const double idzc = 1.0 / g.dzc[k];
+                const double wtop = 0.5 * (wc + wkp), wbot = 0.5 * (wkm + wc);   // at centres k, k-1
+                // w
+                {
+                    const double ax = (uwr * (0.5 * (wc + wip)) - uwl * (0.5 * (wim + wc))) * idx;
+                    const double ay = (vwt * (0.5 * (wc + wjp)) - vwb * (0.5 * (wjm + wc))) * idy;
+                    const double az = (sq(wtop) - sq(wbot)) * idzc;
+                    const double h = -(ax + ay + az) +
+                                     a.nu * ((wip - 2.0 * wc + wim) * idx2 + (wjp - 2.0 * wc + wjm) * idy2) + tc;
+                    const double dzz = ((wkp - wc) / dzp - (wc - wkm) / dzm) * idzc;
+                    const double gp = (L(FP, 0, 0, 0) - L(FP, -1, 0, 0)) * idzc;
+                    double r = a.gam * h - a.alp * gp + a.alp * (a.nu * dzz);
+                    if (a.rho != 0.0) r += a.rho * hp[2];
+                    a.rw[id] = a.dt * r;
+                    if (a.hw) a.hw[id] = h;
+                }
+                // T
+                {
+                    const double ax = (uwr * (0.5 * (tc + tip)) - uwl * (0.5 * (tim + tc))) * idx;
+                    const double ay = (vwt * (0.5 * (tc + tjp)) - vwb * (0.5 * (tjm + tc))) * idy;
+                    const double az = (wtop * (0.5 * (tc + tkp)) - wbot * (0.5 * (tkm + tc))) * idzc;
+                    const double h = -(ax + ay + az) + a.ka * ((tip - 2.0 * tc + tim) * idx2 + (tjp - 2.0 * tc + tjm) * idy2);
+                    const double dzz = ((tkp - tc) / dzp - (tc - tkm) / dzm) * idzc;
+                    double r = a.gam * h + a.alp * (a.ka * dzz);
+                    if (a.rho != 0.0) r += a.rho * hp[3];
+                    a.rt[id] = a.dt * r;
+                    if (a.ht) a.ht[id] = h;
+                }
+            }
+            if (k + 1 == nz) {
+                const size_t top = id + plane;
+                a.rw[top] = 0.0;
+                a.rt[top] = 0.0;
+                if (a.hw) a.hw[top] = 0.0;
+                if (a.ht) a.ht[top] = 0.0;
+            }
         }
-        const double az = (fzt - fzb) / g.dz[k];
-        const double h = -(ax + ay + az) + a.nu * ((uip - 2.0 * uc + uim) * idx2 + (ujp - 2.0 * uc + ujm) * idy2);
-        const double fb = (k > 0) ? (uc - ukm) / g.dzw[k] : uc / g.dzw[0];
-        const double ft = (k + 1 < nz) ? (ukp - uc) / g.dzw[k + 1] : -uc / g.dzw[nz];
-        const double dzz = (ft - fb) / g.dz[k];
-        const double gp = (p[id] - p[X.at(k, j, im)]) * idx;
-        double r = a.gam * h - a.alp * gp + a.alp * (a.nu * dzz);
-        if (a.rho != 0.0) r += a.rho * a.hpu[id];
-        a.ru[id] = a.dt * r;
-        if (a.hu) a.hu[id] = h;
-    }
-    // ---- v at (x-centre i, y-face j, z-centre k) ----
-    {
-        const double vc = v[id], vjm = v[X.at(k, jm, i)], vjp = v[X.at(k, jp, i)];
-        const double vim = v[X.at(k, j, im)], vip = v[X.at(k, j, ip)];
-        const double ay = (sq(0.5 * (vc + vjp)) - sq(0.5 * (vjm + vc))) * idy;
-        const double fxl = 0.5 * (u[X.at(k, j, i)] + u[X.at(k, jm, i)]) * (0.5 * (vc + vim));
-        const double fxr = 0.5 * (u[X.at(k, j, ip)] + u[X.at(k, jm, ip)]) * (0.5 * (vip + vc));
-        const double ax = (fxr - fxl) * idx;
-        double fzb = 0.0, fzt = 0.0, vkm = 0.0, vkp = 0.0;
-        if (k > 0) {
-            vkm = v[X.at(k - 1, j, i)];
-            fzb = 0.5 * (w[X.at(k, j, i)] + w[X.at(k, jm, i)]) * (0.5 * (vkm + vc));
-        }
-        if (k + 1 < nz) {
-            vkp = v[X.at(k + 1, j, i)];
-            fzt = 0.5 * (w[X.at(k + 1, j, i)] + w[X.at(k + 1, jm, i)]) * (0.5 * (vc + vkp));
-        }
-        const double az = (fzt - fzb) / g.dz[k];
-        const double h = -(ax + ay + az) + a.nu * ((vip - 2.0 * vc + vim) * idx2 + (vjp - 2.0 * vc + vjm) * idy2);
-        const double fb = (k > 0) ? (vc - vkm) / g.dzw[k] : vc / g.dzw[0];
-        const double ft = (k + 1 < nz) ? (vkp - vc) / g.dzw[k + 1] : -vc / g.dzw[nz];
-        const double dzz = (ft - fb) / g.dz[k];
-        const double gp = (p[id] - p[X.at(k, jm, i)]) * idy;
-        double r = a.gam * h - a.alp * gp + a.alp * (a.nu * dzz);
-        if (a.rho != 0.0) r += a.rho * a.hpv[id];
-        a.rv[id] = a.dt * r;
-        if (a.hv) a.hv[id] = h;
-    }
-    // ---- w and T at (x-centre i, y-centre j, z-face k), interior faces ----
-    if (k == 0) {
-        a.rw[id] = 0.0;
-        a.rt[id] = 0.0;
-        if (a.hw) a.hw[id] = 0.0;
-        if (a.ht) a.ht[id] = 0.0;
-    } else {
-        const double dzm = g.dz[k - 1], dzp = g.dz[k], den = 1.0 / (2.0 * g.dzc[k]);
-        // volume-weighted horizontal transport on the side faces
-        const double uwl = (dzm * u[X.at(k - 1, j, i)] + dzp * u[X.at(k, j, i)]) * den;
-        const double uwr = (dzm * u[X.at(k - 1, j, ip)] + dzp * u[X.at(k, j, ip)]) * den;
-        const double vwb = (dzm * v[X.at(k - 1, j, i)] + dzp * v[X.at(k, j, i)]) * den;
-        const double vwt = (dzm * v[X.at(k - 1, jp, i)] + dzp * v[X.at(k, jp, i)]) * den;
-        const double wc = w[id], wim = w[X.at(k, j, im)], wip = w[X.at(k, j, ip)];
-        const double wjm = w[X.at(k, jm, i)], wjp = w[X.at(k, jp, i)];
-        const double wkm = w[X.at(k - 1, j, i)], wkp = w[X.at(k + 1, j, i)];
-        const double tc = t[id], tim = t[X.at(k, j, im)], tip = t[X.at(k, j, ip)];
-        const double tjm = t[X.at(k, jm, i)], tjp = t[X.at(k, jp, i)];
-        const double tkm = t[X.at(k - 1, j, i)], tkp = t[X.at(k + 1, j, i)];
-        const double idzc = 1.0 / g.dzc[k];
-        const double wtop = 0.5 * (wc + wkp), wbot = 0.5 * (wkm + wc);   // at centres k, k-1
-        // w
-        {
-            const double ax = (uwr * (0.5 * (wc + wip)) - uwl * (0.5 * (wim + wc))) * idx;
-            const double ay = (vwt * (0.5 * (wc + wjp)) - vwb * (0.5 * (wjm + wc))) * idy;
-            const double az = (sq(wtop) - sq(wbot)) * idzc;
-            const double h = -(ax + ay + az) +
-                             a.nu * ((wip - 2.0 * wc + wim) * idx2 + (wjp - 2.0 * wc + wjm) * idy2) + tc;
-            const double dzz = ((wkp - wc) / dzp - (wc - wkm) / dzm) * idzc;
-            const double gp = (p[id] - p[X.at(k - 1, j, i)]) * idzc;
-            double r = a.gam * h - a.alp * gp + a.alp * (a.nu * dzz);
-            if (a.rho != 0.0) r += a.rho * a.hpw[id];
-            a.rw[id] = a.dt * r;
-            if (a.hw) a.hw[id] = h;
-        }
-        // T
-        {
-            const double ax = (uwr * (0.5 * (tc + tip)) - uwl * (0.5 * (tim + tc))) * idx;
-            const double ay = (vwt * (0.5 * (tc + tjp)) - vwb * (0.5 * (tjm + tc))) * idy;
-            const double az = (wtop * (0.5 * (tc + tkp)) - wbot * (0.5 * (tkm + tc))) * idzc;
-            const double h = -(ax + ay + az) + a.ka * ((tip - 2.0 * tc + tim) * idx2 + (tjp - 2.0 * tc + tjm) * idy2);
-            const double dzz = ((tkp - tc) / dzp - (tc - tkm) / dzm) * idzc;
-            double r = a.gam * h + a.alp * (a.ka * dzz);
-            if (a.rho != 0.0) r += a.rho * a.hpt[id];
-            a.rt[id] = a.dt * r;
-            if (a.ht) a.ht[id] = h;
-        }
-    }
-    if (k + 1 == nz) {
-        const size_t top = id + X.plane;
-        a.rw[top] = 0.0;
-        a.rt[top] = 0.0;
-        if (a.hw) a.hw[top] = 0.0;
-        if (a.ht) a.ht[top] = 0.0;
+        __syncthreads();
     }
 }
 
@@ -229,211 +330,259 @@ k_cn_solve_t(GridDev g, int kind, const double* __restrict__ fac, const double* 
 // point.  For a control-volume equation sum_faces +-F_f / h with cotangent kappa,
 // each face carries Lambda_f = kappa_c / h_c - kappa_{c+1} / h_{c+1}; a flux
 // F = U Q sends Lambda U dQ and Lambda Q dU to the points averaged into Q and U.
-__global__ void __launch_bounds__(256) k_explicit_adj(SubstepAdjArgs a, GridDev g) {
-    int i, j, k;
-    if (!stencil_cell(g, i, j, k)) return;
-    const size_t id = ((size_t)k * g.ny + j) * g.nx + i;
-    const int nx = g.nx, ny = g.ny, nz = g.nz;
-    const Ix X{nx, ny, nz, (size_t)nx * ny};
-    const int im = wrapm(i, nx), ip = wrapp(i, nx);
-    const int jm = wrapm(j, ny), jp = wrapp(j, ny);
+// z-marching blocks as in k_explicit, with the state and the right-hand-side
+// cotangents in the LDS ring.
+constexpr int kAdTX = 64, kAdTY = 4, kAdZSEG = 64;
+// Prefetching the next plane through registers costs the adjoint its occupancy
+// (its gathers already hold many values), so it loads each plane when needed.
+#ifndef PS_ADJ_PIPE
+#define PS_ADJ_PIPE 0
+#endif
+__global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a, GridDev g) {
+    constexpr int TX = kAdTX, TY = kAdTY, NF = 8;
+    enum { FU, FV, FW, FT, FLU, FLV, FLW, FLT };
+    __shared__ double lds[3 * NF * (TX + 2) * (TY + 2)];
+    const ExTile tile = ex_tile<TX, TY, kAdZSEG>(g);
+    Ring<NF, TX, TY> R{lds, (int)threadIdx.x % TX, (int)threadIdx.x / TX};
+    const int i = tile.i0 + R.tx, j = tile.j0 + R.ty;
+    const bool valid = i < g.nx && j < g.ny;
+    const double* const F[NF] = {a.u, a.v, a.w, a.t, a.lu, a.lv, a.lw, a.lt};
+    const bool face[NF] = {false, false, true, true, false, false, true, true};
+    const int nz = g.nz;
+    const size_t plane = (size_t)g.nx * g.ny;
     const double idx = 1.0 / g.dx, idy = 1.0 / g.dy;
     const double idx2 = idx * idx, idy2 = idy * idy;
     const double cadv = -a.dt * a.gam;   // kappa = cadv * lambda (A enters the rhs as -dt gamma A)
-    const double *u = a.u, *v = a.v, *w = a.w, *t = a.t;
-    auto U = [&](int kk, int jj, int ii) { return u[X.at(kk, jj, ii)]; };
-    auto V = [&](int kk, int jj, int ii) { return v[X.at(kk, jj, ii)]; };
-    auto Wf = [&](int kk, int jj, int ii) { return w[X.at(kk, jj, ii)]; };
-    auto Tf = [&](int kk, int jj, int ii) { return t[X.at(kk, jj, ii)]; };
-    auto KU = [&](int kk, int jj, int ii) { return cadv * a.lu[X.at(kk, jj, ii)]; };
-    auto KV = [&](int kk, int jj, int ii) { return cadv * a.lv[X.at(kk, jj, ii)]; };
-    // kappa of interior z-face equations (zero on the wall rows)
-    auto KW = [&](int kk, int jj, int ii) { return (kk >= 1 && kk <= nz - 1) ? cadv * a.lw[X.at(kk, jj, ii)] : 0.0; };
-    auto KT = [&](int kk, int jj, int ii) { return (kk >= 1 && kk <= nz - 1) ? cadv * a.lt[X.at(kk, jj, ii)] : 0.0; };
-    auto idzc = [&](int kk) { return (kk >= 1 && kk <= nz - 1) ? 1.0 / g.dzc[kk] : 0.0; };
-    // volume-weighted transport at (x-face ii or y-face jj, z-face kk)
-    auto UW = [&](int kk, int jj, int ii) {
-        return (g.dz[kk - 1] * U(kk - 1, jj, ii) + g.dz[kk] * U(kk, jj, ii)) / (2.0 * g.dzc[kk]);
-    };
-    auto VW = [&](int kk, int jj, int ii) {
-        return (g.dz[kk - 1] * V(kk - 1, jj, ii) + g.dz[kk] * V(kk, jj, ii)) / (2.0 * g.dzc[kk]);
-    };
+    typename Ring<NF, TX, TY>::Stage st;
+    R.fetch(tile.kb - 1, F, face, g, tile.i0, tile.j0, st);
+    R.put(tile.kb - 1, st);
+    R.fetch(tile.kb, F, face, g, tile.i0, tile.j0, st);
+    R.put(tile.kb, st);
+#if PS_ADJ_PIPE
+    R.fetch(tile.kb + 1, F, face, g, tile.i0, tile.j0, st);
+#endif
+    for (int k = tile.kb; k < tile.ke; ++k) {
+#if !PS_ADJ_PIPE
+        R.fetch(k + 1, F, face, g, tile.i0, tile.j0, st);
+#endif
+        R.put(k + 1, st);
+        __syncthreads();
+        const size_t id = (size_t)k * plane + (size_t)j * g.nx + i;
+        // direct cotangents of this cell, loaded before the next plane's prefetch
+        double dd[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        if (valid) {
+            dd[0] = a.du[id];
+            dd[1] = a.dv[id];
+            dd[2] = a.dw[id];
+            dd[3] = a.dt_[id];
+            dd[4] = a.dp[id];
+        }
+#if PS_ADJ_PIPE
+        if (k + 2 <= tile.ke) R.fetch(k + 2, F, face, g, tile.i0, tile.j0, st);
+#endif
+        if (valid) {
+            // fields at absolute plane kk (k - 1 <= kk <= k + 1) and horizontal offsets (dj, di)
+            auto U = [&](int kk, int dj, int di) { return R(k, FU, kk - k, dj, di); };
+            auto V = [&](int kk, int dj, int di) { return R(k, FV, kk - k, dj, di); };
+            auto Wf = [&](int kk, int dj, int di) { return R(k, FW, kk - k, dj, di); };
+            auto Tf = [&](int kk, int dj, int di) { return R(k, FT, kk - k, dj, di); };
+            auto LU = [&](int kk, int dj, int di) { return R(k, FLU, kk - k, dj, di); };
+            auto LV = [&](int kk, int dj, int di) { return R(k, FLV, kk - k, dj, di); };
+            auto LW = [&](int kk, int dj, int di) { return R(k, FLW, kk - k, dj, di); };
+            auto LT = [&](int kk, int dj, int di) { return R(k, FLT, kk - k, dj, di); };
+            auto KU = [&](int kk, int dj, int di) { return cadv * LU(kk, dj, di); };
+            auto KV = [&](int kk, int dj, int di) { return cadv * LV(kk, dj, di); };
+            // kappa of interior z-face equations (zero on the wall rows)
+            auto KW = [&](int kk, int dj, int di) { return (kk >= 1 && kk <= nz - 1) ? cadv * LW(kk, dj, di) : 0.0; };
+            auto KT = [&](int kk, int dj, int di) { return (kk >= 1 && kk <= nz - 1) ? cadv * LT(kk, dj, di) : 0.0; };
+            auto idzc = [&](int kk) { return (kk >= 1 && kk <= nz - 1) ? 1.0 / g.dzc[kk] : 0.0; };
+            // volume-weighted transport at (x-face or y-face, z-face kk)
+            auto UW = [&](int kk, int dj, int di) {
+                return (g.dz[kk - 1] * U(kk - 1, dj, di) + g.dz[kk] * U(kk, dj, di)) / (2.0 * g.dzc[kk]);
+            };
+            auto VW = [&](int kk, int dj, int di) {
+                return (g.dz[kk - 1] * V(kk - 1, dj, di) + g.dz[kk] * V(kk, dj, di)) / (2.0 * g.dzc[kk]);
+            };
 
-    // ================= g_u at (k, j, i) =================
-    {
-        double s = 0.0;
-        // u-eq, x faces at centres i, i-1: F = U^2
-        {
-            const double L0 = (KU(k, j, i) - KU(k, j, ip)) * idx, U0 = 0.5 * (U(k, j, i) + U(k, j, ip));
-            const double L1 = (KU(k, j, im) - KU(k, j, i)) * idx, U1 = 0.5 * (U(k, j, im) + U(k, j, i));
-            s += L0 * U0 + L1 * U1;
+            // ================= g_u at (k, j, i) =================
+            {
+                double s = 0.0;
+                // u-eq, x faces at centres i, i-1: F = U^2
+                {
+                    const double L0 = (KU(k, 0, 0) - KU(k, 0, 1)) * idx, U0 = 0.5 * (U(k, 0, 0) + U(k, 0, 1));
+                    const double L1 = (KU(k, 0, -1) - KU(k, 0, 0)) * idx, U1 = 0.5 * (U(k, 0, -1) + U(k, 0, 0));
+                    s += L0 * U0 + L1 * U1;
+                }
+                // u-eq, y faces j, j+1 (x-face i): Q = avg u
+                {
+                    const double Lj = (KU(k, -1, 0) - KU(k, 0, 0)) * idy;
+                    const double Lp = (KU(k, 0, 0) - KU(k, 1, 0)) * idy;
+                    const double Vj = 0.5 * (V(k, 0, 0) + V(k, 0, -1));
+                    const double Vp = 0.5 * (V(k, 1, 0) + V(k, 1, -1));
+                    s += 0.5 * (Lj * Vj + Lp * Vp);
+                }
+                // u-eq, z faces k, k+1 (interior): Q = avg u
+                if (k >= 1) {
+                    const double L = KU(k - 1, 0, 0) / g.dz[k - 1] - KU(k, 0, 0) / g.dz[k];
+                    s += 0.5 * L * 0.5 * (Wf(k, 0, 0) + Wf(k, 0, -1));
+                }
+                if (k + 1 <= nz - 1) {
+                    const double L = KU(k, 0, 0) / g.dz[k] - KU(k + 1, 0, 0) / g.dz[k + 1];
+                    s += 0.5 * L * 0.5 * (Wf(k + 1, 0, 0) + Wf(k + 1, 0, -1));
+                }
+                // v-eq, x faces at (x-face i, y-faces j and j+1): U = avg of u over y
+                {
+                    const double L0 = (KV(k, 0, -1) - KV(k, 0, 0)) * idx, Q0 = 0.5 * (V(k, 0, -1) + V(k, 0, 0));
+                    const double L1 = (KV(k, 1, -1) - KV(k, 1, 0)) * idx, Q1 = 0.5 * (V(k, 1, -1) + V(k, 1, 0));
+                    s += 0.5 * (L0 * Q0 + L1 * Q1);
+                }
+                // w- and T-eq, x faces at (x-face i, z-faces k and k+1): volume-weighted u
+                for (int kf = k; kf <= k + 1; ++kf) {
+                    if (kf < 1 || kf > nz - 1) continue;
+                    const double wt = g.dz[k] / (2.0 * g.dzc[kf]);
+                    const double Lw = (KW(kf, 0, -1) - KW(kf, 0, 0)) * idx, Qw = 0.5 * (Wf(kf, 0, -1) + Wf(kf, 0, 0));
+                    const double Lt = (KT(kf, 0, -1) - KT(kf, 0, 0)) * idx, Qt = 0.5 * (Tf(kf, 0, -1) + Tf(kf, 0, 0));
+                    s += wt * (Lw * Qw + Lt * Qt);
+                }
+                // linear terms: horizontal diffusion (symmetric) and Dzz^T = dz Dzz dz^-1
+                const double lc = LU(k, 0, 0);
+                double lin = a.gam * a.nu *
+                             ((LU(k, 0, 1) - 2.0 * lc + LU(k, 0, -1)) * idx2 +
+                              (LU(k, 1, 0) - 2.0 * lc + LU(k, -1, 0)) * idy2);
+                {
+                    const double mc = lc / g.dz[k];
+                    const double fb = (k > 0) ? (mc - LU(k - 1, 0, 0) / g.dz[k - 1]) / g.dzw[k] : mc / g.dzw[0];
+                    const double ft = (k + 1 < nz) ? (LU(k + 1, 0, 0) / g.dz[k + 1] - mc) / g.dzw[k + 1] : -mc / g.dzw[nz];
+                    lin += a.alp * a.nu * (ft - fb);
+                }
+                a.gu[id] = dd[0] + s + a.dt * lin;
+            }
+            // ================= g_v at (k, j, i) =================
+            {
+                double s = 0.0;
+                {
+                    const double L0 = (KV(k, 0, 0) - KV(k, 1, 0)) * idy, U0 = 0.5 * (V(k, 0, 0) + V(k, 1, 0));
+                    const double L1 = (KV(k, -1, 0) - KV(k, 0, 0)) * idy, U1 = 0.5 * (V(k, -1, 0) + V(k, 0, 0));
+                    s += L0 * U0 + L1 * U1;
+                }
+                {
+                    const double Li = (KV(k, 0, -1) - KV(k, 0, 0)) * idx;
+                    const double Lp = (KV(k, 0, 0) - KV(k, 0, 1)) * idx;
+                    const double Ui = 0.5 * (U(k, 0, 0) + U(k, -1, 0));
+                    const double Up = 0.5 * (U(k, 0, 1) + U(k, -1, 1));
+                    s += 0.5 * (Li * Ui + Lp * Up);
+                }
+                if (k >= 1) {
+                    const double L = KV(k - 1, 0, 0) / g.dz[k - 1] - KV(k, 0, 0) / g.dz[k];
+                    s += 0.5 * L * 0.5 * (Wf(k, 0, 0) + Wf(k, -1, 0));
+                }
+                if (k + 1 <= nz - 1) {
+                    const double L = KV(k, 0, 0) / g.dz[k] - KV(k + 1, 0, 0) / g.dz[k + 1];
+                    s += 0.5 * L * 0.5 * (Wf(k + 1, 0, 0) + Wf(k + 1, -1, 0));
+                }
+                // u-eq, y faces at (x-faces i and i+1, y-face j): V = avg of v over x
+                {
+                    const double L0 = (KU(k, -1, 0) - KU(k, 0, 0)) * idy, Q0 = 0.5 * (U(k, -1, 0) + U(k, 0, 0));
+                    const double L1 = (KU(k, -1, 1) - KU(k, 0, 1)) * idy, Q1 = 0.5 * (U(k, -1, 1) + U(k, 0, 1));
+                    s += 0.5 * (L0 * Q0 + L1 * Q1);
+                }
+                for (int kf = k; kf <= k + 1; ++kf) {
+                    if (kf < 1 || kf > nz - 1) continue;
+                    const double wt = g.dz[k] / (2.0 * g.dzc[kf]);
+                    const double Lw = (KW(kf, -1, 0) - KW(kf, 0, 0)) * idy, Qw = 0.5 * (Wf(kf, -1, 0) + Wf(kf, 0, 0));
+                    const double Lt = (KT(kf, -1, 0) - KT(kf, 0, 0)) * idy, Qt = 0.5 * (Tf(kf, -1, 0) + Tf(kf, 0, 0));
+                    s += wt * (Lw * Qw + Lt * Qt);
+                }
+                const double lc = LV(k, 0, 0);
+                double lin = a.gam * a.nu *
+                             ((LV(k, 0, 1) - 2.0 * lc + LV(k, 0, -1)) * idx2 +
+                              (LV(k, 1, 0) - 2.0 * lc + LV(k, -1, 0)) * idy2);
+                {
+                    const double mc = lc / g.dz[k];
+                    const double fb = (k > 0) ? (mc - LV(k - 1, 0, 0) / g.dz[k - 1]) / g.dzw[k] : mc / g.dzw[0];
+                    const double ft = (k + 1 < nz) ? (LV(k + 1, 0, 0) / g.dz[k + 1] - mc) / g.dzw[k + 1] : -mc / g.dzw[nz];
+                    lin += a.alp * a.nu * (ft - fb);
+                }
+                a.gv[id] = dd[1] + s + a.dt * lin;
+            }
+            // ================= g_p at (k, j, i):  -dt alpha G^T lambda =================
+            {
+                double gt = (LU(k, 0, 0) - LU(k, 0, 1)) * idx + (LV(k, 0, 0) - LV(k, 1, 0)) * idy;
+                if (k >= 1) gt += LW(k, 0, 0) / g.dzc[k];
+                if (k + 1 <= nz - 1) gt -= LW(k + 1, 0, 0) / g.dzc[k + 1];
+                a.gp[id] = dd[4] - a.dt * a.alp * gt;
+            }
+            // ================= g_w, g_T at z-face k (interior) =================
+            if (k == 0) {
+                a.gw[id] = 0.0;
+                a.gt[id] = 0.0;
+            } else {
+                double sw = 0.0, st = 0.0;
+                // w-eq z faces at centres k and k-1: F = U^2, U = avg w
+                {
+                    const double L0 = KW(k, 0, 0) * idzc(k) - KW(k + 1, 0, 0) * idzc(k + 1);
+                    const double L1 = KW(k - 1, 0, 0) * idzc(k - 1) - KW(k, 0, 0) * idzc(k);
+                    sw += L0 * 0.5 * (Wf(k, 0, 0) + Wf(k + 1, 0, 0)) + L1 * 0.5 * (Wf(k - 1, 0, 0) + Wf(k, 0, 0));
+                }
+                // T-eq z faces at centres k and k-1: U = avg w, Q = avg T
+                {
+                    const double L0 = KT(k, 0, 0) * idzc(k) - KT(k + 1, 0, 0) * idzc(k + 1);
+                    const double L1 = KT(k - 1, 0, 0) * idzc(k - 1) - KT(k, 0, 0) * idzc(k);
+                    sw += 0.5 * (L0 * 0.5 * (Tf(k, 0, 0) + Tf(k + 1, 0, 0)) + L1 * 0.5 * (Tf(k - 1, 0, 0) + Tf(k, 0, 0)));
+                    st += 0.5 * (L0 * 0.5 * (Wf(k, 0, 0) + Wf(k + 1, 0, 0)) + L1 * 0.5 * (Wf(k - 1, 0, 0) + Wf(k, 0, 0)));
+                }
+                // w- and T-eq x faces i, i+1 (transport UW) and y faces j, j+1 (transport VW)
+                {
+                    const double Lw0 = (KW(k, 0, -1) - KW(k, 0, 0)) * idx, Lw1 = (KW(k, 0, 0) - KW(k, 0, 1)) * idx;
+                    const double Lt0 = (KT(k, 0, -1) - KT(k, 0, 0)) * idx, Lt1 = (KT(k, 0, 0) - KT(k, 0, 1)) * idx;
+                    const double U0 = UW(k, 0, 0), U1 = UW(k, 0, 1);
+                    sw += 0.5 * (Lw0 * U0 + Lw1 * U1);
+                    st += 0.5 * (Lt0 * U0 + Lt1 * U1);
+                    const double Mw0 = (KW(k, -1, 0) - KW(k, 0, 0)) * idy, Mw1 = (KW(k, 0, 0) - KW(k, 1, 0)) * idy;
+                    const double Mt0 = (KT(k, -1, 0) - KT(k, 0, 0)) * idy, Mt1 = (KT(k, 0, 0) - KT(k, 1, 0)) * idy;
+                    const double V0 = VW(k, 0, 0), V1 = VW(k, 1, 0);
+                    sw += 0.5 * (Mw0 * V0 + Mw1 * V1);
+                    st += 0.5 * (Mt0 * V0 + Mt1 * V1);
+                }
+                // u-eq z faces at (x-faces i, i+1; z-face k): W = avg of w over x, Q = avg of u over z
+                {
+                    const double L0 = KU(k - 1, 0, 0) / g.dz[k - 1] - KU(k, 0, 0) / g.dz[k];
+                    const double L1 = KU(k - 1, 0, 1) / g.dz[k - 1] - KU(k, 0, 1) / g.dz[k];
+                    sw += 0.5 * (L0 * 0.5 * (U(k - 1, 0, 0) + U(k, 0, 0)) + L1 * 0.5 * (U(k - 1, 0, 1) + U(k, 0, 1)));
+                }
+                // v-eq z faces at (y-faces j, j+1; z-face k)
+                {
+                    const double L0 = KV(k - 1, 0, 0) / g.dz[k - 1] - KV(k, 0, 0) / g.dz[k];
+                    const double L1 = KV(k - 1, 1, 0) / g.dz[k - 1] - KV(k, 1, 0) / g.dz[k];
+                    sw += 0.5 * (L0 * 0.5 * (V(k - 1, 0, 0) + V(k, 0, 0)) + L1 * 0.5 * (V(k - 1, 1, 0) + V(k, 1, 0)));
+                }
+                // linear terms
+                const double lwc = LW(k, 0, 0), ltc = LT(k, 0, 0);
+                double linw = a.gam * a.nu *
+                              ((LW(k, 0, 1) - 2.0 * lwc + LW(k, 0, -1)) * idx2 +
+                               (LW(k, 1, 0) - 2.0 * lwc + LW(k, -1, 0)) * idy2);
+                double lint = a.gam * a.ka *
+                              ((LT(k, 0, 1) - 2.0 * ltc + LT(k, 0, -1)) * idx2 +
+                               (LT(k, 1, 0) - 2.0 * ltc + LT(k, -1, 0)) * idy2);
+                {
+                    // Dzz^T on faces = dzc Dzz dzc^-1 (wall rows of lambda are zero)
+                    const double mw = lwc * idzc(k), mwm = LW(k - 1, 0, 0) * idzc(k - 1),
+                                 mwp = LW(k + 1, 0, 0) * idzc(k + 1);
+                    const double mt = ltc * idzc(k), mtm = LT(k - 1, 0, 0) * idzc(k - 1),
+                                 mtp = LT(k + 1, 0, 0) * idzc(k + 1);
+                    linw += a.alp * a.nu * ((mwp - mw) / g.dz[k] - (mw - mwm) / g.dz[k - 1]);
+                    lint += a.alp * a.ka * ((mtp - mt) / g.dz[k] - (mt - mtm) / g.dz[k - 1]);
+                }
+                a.gw[id] = dd[2] + sw + a.dt * linw;
+                a.gt[id] = dd[3] + st + a.dt * lint + a.dt * a.gam * lwc;   // buoyancy +T in the w equation
+            }
+            if (k + 1 == nz) {
+                a.gw[id + plane] = 0.0;
+                a.gt[id + plane] = 0.0;
+            }
+
         }
-        // u-eq, y faces j, j+1 (x-face i): Q = avg u
-        {
-            const double Lj = (KU(k, jm, i) - KU(k, j, i)) * idy;
-            const double Lp = (KU(k, j, i) - KU(k, jp, i)) * idy;
-            const double Vj = 0.5 * (V(k, j, i) + V(k, j, im));
-            const double Vp = 0.5 * (V(k, jp, i) + V(k, jp, im));
-            s += 0.5 * (Lj * Vj + Lp * Vp);
-        }
-        // u-eq, z faces k, k+1 (interior): Q = avg u
-        if (k >= 1) {
-            const double L = KU(k - 1, j, i) / g.dz[k - 1] - KU(k, j, i) / g.dz[k];
-            s += 0.5 * L * 0.5 * (Wf(k, j, i) + Wf(k, j, im));
-        }
-        if (k + 1 <= nz - 1) {
-            const double L = KU(k, j, i) / g.dz[k] - KU(k + 1, j, i) / g.dz[k + 1];
-            s += 0.5 * L * 0.5 * (Wf(k + 1, j, i) + Wf(k + 1, j, im));
-        }
-        // v-eq, x faces at (x-face i, y-faces j and j+1): U = avg of u over y
-        {
-            const double L0 = (KV(k, j, im) - KV(k, j, i)) * idx, Q0 = 0.5 * (V(k, j, im) + V(k, j, i));
-            const double L1 = (KV(k, jp, im) - KV(k, jp, i)) * idx, Q1 = 0.5 * (V(k, jp, im) + V(k, jp, i));
-            s += 0.5 * (L0 * Q0 + L1 * Q1);
-        }
-        // w- and T-eq, x faces at (x-face i, z-faces k and k+1): volume-weighted u
-        for (int kf = k; kf <= k + 1; ++kf) {
-            if (kf < 1 || kf > nz - 1) continue;
-            const double wt = g.dz[k] / (2.0 * g.dzc[kf]);
-            const double Lw = (KW(kf, j, im) - KW(kf, j, i)) * idx, Qw = 0.5 * (Wf(kf, j, im) + Wf(kf, j, i));
-            const double Lt = (KT(kf, j, im) - KT(kf, j, i)) * idx, Qt = 0.5 * (Tf(kf, j, im) + Tf(kf, j, i));
-            s += wt * (Lw * Qw + Lt * Qt);
-        }
-        // linear terms: horizontal diffusion (symmetric) and Dzz^T = dz Dzz dz^-1
-        const double lc = a.lu[id];
-        double lin = a.gam * a.nu *
-                     ((a.lu[X.at(k, j, ip)] - 2.0 * lc + a.lu[X.at(k, j, im)]) * idx2 +
-                      (a.lu[X.at(k, jp, i)] - 2.0 * lc + a.lu[X.at(k, jm, i)]) * idy2);
-        {
-            const double mc = lc / g.dz[k];
-            const double fb = (k > 0) ? (mc - a.lu[X.at(k - 1, j, i)] / g.dz[k - 1]) / g.dzw[k] : mc / g.dzw[0];
-            const double ft = (k + 1 < nz) ? (a.lu[X.at(k + 1, j, i)] / g.dz[k + 1] - mc) / g.dzw[k + 1] : -mc / g.dzw[nz];
-            lin += a.alp * a.nu * (ft - fb);
-        }
-        a.gu[id] = a.du[id] + s + a.dt * lin;
-    }
-    // ================= g_v at (k, j, i) =================
-    {
-        double s = 0.0;
-        {
-            const double L0 = (KV(k, j, i) - KV(k, jp, i)) * idy, U0 = 0.5 * (V(k, j, i) + V(k, jp, i));
-            const double L1 = (KV(k, jm, i) - KV(k, j, i)) * idy, U1 = 0.5 * (V(k, jm, i) + V(k, j, i));
-            s += L0 * U0 + L1 * U1;
-        }
-        {
-            const double Li = (KV(k, j, im) - KV(k, j, i)) * idx;
-            const double Lp = (KV(k, j, i) - KV(k, j, ip)) * idx;
-            const double Ui = 0.5 * (U(k, j, i) + U(k, jm, i));
-            const double Up = 0.5 * (U(k, j, ip) + U(k, jm, ip));
-            s += 0.5 * (Li * Ui + Lp * Up);
-        }
-        if (k >= 1) {
-            const double L = KV(k - 1, j, i) / g.dz[k - 1] - KV(k, j, i) / g.dz[k];
-            s += 0.5 * L * 0.5 * (Wf(k, j, i) + Wf(k, jm, i));
-        }
-        if (k + 1 <= nz - 1) {
-            const double L = KV(k, j, i) / g.dz[k] - KV(k + 1, j, i) / g.dz[k + 1];
-            s += 0.5 * L * 0.5 * (Wf(k + 1, j, i) + Wf(k + 1, jm, i));
-        }
-        // u-eq, y faces at (x-faces i and i+1, y-face j): V = avg of v over x
-        {
-            const double L0 = (KU(k, jm, i) - KU(k, j, i)) * idy, Q0 = 0.5 * (U(k, jm, i) + U(k, j, i));
-            const double L1 = (KU(k, jm, ip) - KU(k, j, ip)) * idy, Q1 = 0.5 * (U(k, jm, ip) + U(k, j, ip));
-            s += 0.5 * (L0 * Q0 + L1 * Q1);
-        }
-        for (int kf = k; kf <= k + 1; ++kf) {
-            if (kf < 1 || kf > nz - 1) continue;
-            const double wt = g.dz[k] / (2.0 * g.dzc[kf]);
-            const double Lw = (KW(kf, jm, i) - KW(kf, j, i)) * idy, Qw = 0.5 * (Wf(kf, jm, i) + Wf(kf, j, i));
-            const double Lt = (KT(kf, jm, i) - KT(kf, j, i)) * idy, Qt = 0.5 * (Tf(kf, jm, i) + Tf(kf, j, i));
-            s += wt * (Lw * Qw + Lt * Qt);
-        }
-        const double lc = a.lv[id];
-        double lin = a.gam * a.nu *
-                     ((a.lv[X.at(k, j, ip)] - 2.0 * lc + a.lv[X.at(k, j, im)]) * idx2 +
-                      (a.lv[X.at(k, jp, i)] - 2.0 * lc + a.lv[X.at(k, jm, i)]) * idy2);
-        {
-            const double mc = lc / g.dz[k];
-            const double fb = (k > 0) ? (mc - a.lv[X.at(k - 1, j, i)] / g.dz[k - 1]) / g.dzw[k] : mc / g.dzw[0];
-            const double ft = (k + 1 < nz) ? (a.lv[X.at(k + 1, j, i)] / g.dz[k + 1] - mc) / g.dzw[k + 1] : -mc / g.dzw[nz];
-            lin += a.alp * a.nu * (ft - fb);
-        }
-        a.gv[id] = a.dv[id] + s + a.dt * lin;
-    }
-    // ================= g_p at (k, j, i):  -dt alpha G^T lambda =================
-    {
-        double gt = (a.lu[id] - a.lu[X.at(k, j, ip)]) * idx + (a.lv[id] - a.lv[X.at(k, jp, i)]) * idy;
-        if (k >= 1) gt += a.lw[id] / g.dzc[k];
-        if (k + 1 <= nz - 1) gt -= a.lw[X.at(k + 1, j, i)] / g.dzc[k + 1];
-        a.gp[id] = a.dp[id] - a.dt * a.alp * gt;
-    }
-    // ================= g_w, g_T at z-face k (interior) =================
-    if (k == 0) {
-        a.gw[id] = 0.0;
-        a.gt[id] = 0.0;
-    } else {
-        double sw = 0.0, st = 0.0;
-        // w-eq z faces at centres k and k-1: F = U^2, U = avg w
-        {
-            const double L0 = KW(k, j, i) * idzc(k) - KW(k + 1, j, i) * idzc(k + 1);
-            const double L1 = KW(k - 1, j, i) * idzc(k - 1) - KW(k, j, i) * idzc(k);
-            sw += L0 * 0.5 * (Wf(k, j, i) + Wf(k + 1, j, i)) + L1 * 0.5 * (Wf(k - 1, j, i) + Wf(k, j, i));
-        }
-        // T-eq z faces at centres k and k-1: U = avg w, Q = avg T
-        {
-            const double L0 = KT(k, j, i) * idzc(k) - KT(k + 1, j, i) * idzc(k + 1);
-            const double L1 = KT(k - 1, j, i) * idzc(k - 1) - KT(k, j, i) * idzc(k);
-            sw += 0.5 * (L0 * 0.5 * (Tf(k, j, i) + Tf(k + 1, j, i)) + L1 * 0.5 * (Tf(k - 1, j, i) + Tf(k, j, i)));
-            st += 0.5 * (L0 * 0.5 * (Wf(k, j, i) + Wf(k + 1, j, i)) + L1 * 0.5 * (Wf(k - 1, j, i) + Wf(k, j, i)));
-        }
-        // w- and T-eq x faces i, i+1 (transport UW) and y faces j, j+1 (transport VW)
-        {
-            const double Lw0 = (KW(k, j, im) - KW(k, j, i)) * idx, Lw1 = (KW(k, j, i) - KW(k, j, ip)) * idx;
-            const double Lt0 = (KT(k, j, im) - KT(k, j, i)) * idx, Lt1 = (KT(k, j, i) - KT(k, j, ip)) * idx;
-            const double U0 = UW(k, j, i), U1 = UW(k, j, ip);
-            sw += 0.5 * (Lw0 * U0 + Lw1 * U1);
-            st += 0.5 * (Lt0 * U0 + Lt1 * U1);
-            const double Mw0 = (KW(k, jm, i) - KW(k, j, i)) * idy, Mw1 = (KW(k, j, i) - KW(k, jp, i)) * idy;
-            const double Mt0 = (KT(k, jm, i) - KT(k, j, i)) * idy, Mt1 = (KT(k, j, i) - KT(k, jp, i)) * idy;
-            const double V0 = VW(k, j, i), V1 = VW(k, jp, i);
-            sw += 0.5 * (Mw0 * V0 + Mw1 * V1);
-            st += 0.5 * (Mt0 * V0 + Mt1 * V1);
-        }
-        // u-eq z faces at (x-faces i, i+1; z-face k): W = avg of w over x, Q = avg of u over z
-        {
-            const double L0 = KU(k - 1, j, i) / g.dz[k - 1] - KU(k, j, i) / g.dz[k];
-            const double L1 = KU(k - 1, j, ip) / g.dz[k - 1] - KU(k, j, ip) / g.dz[k];
-            sw += 0.5 * (L0 * 0.5 * (U(k - 1, j, i) + U(k, j, i)) + L1 * 0.5 * (U(k - 1, j, ip) + U(k, j, ip)));
-        }
-        // v-eq z faces at (y-faces j, j+1; z-face k)
-        {
-            const double L0 = KV(k - 1, j, i) / g.dz[k - 1] - KV(k, j, i) / g.dz[k];
-            const double L1 = KV(k - 1, jp, i) / g.dz[k - 1] - KV(k, jp, i) / g.dz[k];
-            sw += 0.5 * (L0 * 0.5 * (V(k - 1, j, i) + V(k, j, i)) + L1 * 0.5 * (V(k - 1, jp, i) + V(k, jp, i)));
-        }
-        // linear terms
-        const double lwc = a.lw[id], ltc = a.lt[id];
-        double linw = a.gam * a.nu *
-                      ((a.lw[X.at(k, j, ip)] - 2.0 * lwc + a.lw[X.at(k, j, im)]) * idx2 +
-                       (a.lw[X.at(k, jp, i)] - 2.0 * lwc + a.lw[X.at(k, jm, i)]) * idy2);
-        double lint = a.gam * a.ka *
-                      ((a.lt[X.at(k, j, ip)] - 2.0 * ltc + a.lt[X.at(k, j, im)]) * idx2 +
-                       (a.lt[X.at(k, jp, i)] - 2.0 * ltc + a.lt[X.at(k, jm, i)]) * idy2);
-        {
-            // Dzz^T on faces = dzc Dzz dzc^-1 (wall rows of lambda are zero)
-            const double mw = lwc * idzc(k), mwm = a.lw[X.at(k - 1, j, i)] * idzc(k - 1),
-                         mwp = a.lw[X.at(k + 1, j, i)] * idzc(k + 1);
-            const double mt = ltc * idzc(k), mtm = a.lt[X.at(k - 1, j, i)] * idzc(k - 1),
-                         mtp = a.lt[X.at(k + 1, j, i)] * idzc(k + 1);
-            linw += a.alp * a.nu * ((mwp - mw) / g.dz[k] - (mw - mwm) / g.dz[k - 1]);
-            lint += a.alp * a.ka * ((mtp - mt) / g.dz[k] - (mt - mtm) / g.dz[k - 1]);
-        }
-        a.gw[id] = a.dw[id] + sw + a.dt * linw;
-        a.gt[id] = a.dt_[id] + st + a.dt * lint + a.dt * a.gam * lwc;   // buoyancy +T in the w equation
-    }
-    if (k + 1 == nz) {
-        a.gw[id + X.plane] = 0.0;
-        a.gt[id + X.plane] = 0.0;
+        __syncthreads();
     }
 }
 
@@ -447,12 +596,12 @@ hipError_t launch_cn_solve_t(const GridDev& g, int kind, const double* fac, cons
 }
 
 hipError_t launch_explicit_adj(const GridDev& g, const SubstepAdjArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL(k_explicit_adj, dim3(stencil_blocks(g)), dim3(kStencilBlock), 0, st, a, g);
+    hipLaunchKernelGGL(k_explicit_adj, dim3(ex_blocks<kAdTX, kAdTY, kAdZSEG>(g)), dim3(kAdTX * kAdTY), 0, st, a, g);
     return hipGetLastError();
 }
 
 hipError_t launch_explicit(const GridDev& g, const SubstepArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL(k_explicit, dim3(stencil_blocks(g)), dim3(kStencilBlock), 0, st, a, g);
+    hipLaunchKernelGGL(k_explicit, dim3(ex_blocks<kExTX, kExTY, kExZSEG>(g)), dim3(kExTX * kExTY), 0, st, a, g);
     return hipGetLastError();
 }
 
