@@ -352,6 +352,21 @@ def other_workloads(args):
     adj64 = _event_ms(lambda: plan.substep_adjoint(dt, nu, ka, *saved, cot), 3)
     res["rk3_substep_768x768x512_fp64_poisson"] = {"forward_ms": round(fwd64, 3), "adjoint_ms": round(adj64, 3),
                                                    "gpoints_per_s": round(npts / fwd64 / 1e6, 3)}
+    # one full RK3 step (three substeps, Courant-limited dt) and the heat-flux statistics
+    used = []
+
+    def full_step():
+        reset()
+        used.append(plan.step(nu, ka, *st, dt=0.0, cfl=1.3)[0])
+
+    full_step()
+    step_ms = _event_ms(full_step, 3) - reset_ms
+    hf_ms = _event_ms(lambda: plan.heat_flux(st[2], st[3], ka), 5)
+    mean_t, flux = plan.heat_flux(st[2], st[3], ka)
+    nu_prof = (flux / ka).cpu()
+    res["rk3_step_768x768x512_fp64_poisson"] = {"ms": round(step_ms, 3), "dt": used[-1],
+                                                "heat_flux_ms": round(hf_ms, 3),
+                                                "nusselt_wall_mean": round(float(0.5 * (nu_prof[0] + nu_prof[-1])), 6)}
     plan.close()
     return res
 

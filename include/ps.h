@@ -204,8 +204,9 @@ ps_status ps_cfl(ps_plan_t plan, const double* u, const double* v, const double*
  * gamma = (8/15, 5/12, 3/4), rho = (0, -17/60, -5/12), alpha = gamma + rho.
  * state: u, v, w, t, p, updated in place.  h_prev: the previous substep's H
  * (four fields u, v, w, t; ignored for l = 1, may then be NULL).  h_out:
- * receives this substep's H (may be NULL).  The Poisson solve runs at the
- * plan's precision.
+ * receives this substep's H (may be NULL); h_prev and h_out may be the same
+ * buffers (each point's H is read before it is overwritten).  The Poisson
+ * solve runs at the plan's precision.
  */
 ps_status rk3_substep(ps_plan_t plan, int l, double dt, double nu, double kappa,
                       double* u, double* v, double* w, double* t, double* p,
@@ -224,6 +225,35 @@ ps_status rk3_substep_adjoint(ps_plan_t plan, double dt, double nu, double kappa
                               const double* t, const double* p,
                               const double* const* g_out, double* const* g_in,
                               void* stream, ps_info* info);
+
+/*
+ * rk3_step - one full time step of the low-storage RK3 scheme (Sec. 2.1): the
+ * substeps l = 1, 2, 3 of rk3_substep with the same dt, each handing its H to
+ * the next through plan-owned temporaries.  dt > 0 is taken as given; dt <= 0
+ * selects the Courant-limited step of Listing 1, dt = min(dt_max, cfl_target /
+ * ps_cfl(u, v, w)), which reads the Courant number back to the host (one
+ * synchronisation).  State as rk3_substep, updated in place.  *dt_used (host,
+ * may be NULL) receives the step taken; info (may be NULL) sums the Poisson
+ * solves of the three substeps.
+ */
+ps_status rk3_step(ps_plan_t plan, double dt, double cfl_target, double dt_max, double nu, double kappa,
+                   double* u, double* v, double* w, double* t, double* p, double* dt_used, void* stream,
+                   ps_info* info);
+
+/*
+ * ps_heat_flux - wall-normal statistics of a convection state (the Nusselt
+ * number of Sec. 4): plane means of T on the nz + 1 z-faces,
+ *   mean_t[k] = <T>_k,
+ * and the total vertical heat flux through the nz cell-centre planes,
+ *   flux[k] = < wbar Tbar >_k - kappa (<T>_{k+1} - <T>_k) / dz_k,
+ * wbar, Tbar the averages of the two z-faces bounding cell k, < > the x-y
+ * plane average.  For unit height and wall temperatures 1 and 0 the Nusselt
+ * profile is flux / kappa.  mean_t (nz + 1) and flux (nz): device arrays.
+ * Plane sums run in a fixed order (deterministic for a given box).  Uses the
+ * plan's scratch: order it with the plan's other calls.
+ */
+ps_status ps_heat_flux(ps_plan_t plan, const double* w, const double* t, double kappa, double* mean_t,
+                       double* flux, void* stream);
 
 /*
  * ps_debug_stage - run one stage of poisson_solve on the plan's own layout

@@ -44,6 +44,9 @@ SIGNATURES = {
                             POINTER(PsInfo)]),
     "rk3_substep_adjoint": (c_int, [_P, c_double, c_double, c_double, _D, _D, _D, _D, _D, _PP, _PP, c_void_p,
                                     POINTER(PsInfo)]),
+    "rk3_step": (c_int, [_P, c_double, c_double, c_double, c_double, c_double, _D, _D, _D, _D, _D,
+                         POINTER(c_double), c_void_p, POINTER(PsInfo)]),
+    "ps_heat_flux": (c_int, [_P, _D, _D, c_double, _D, _D, c_void_p]),
     "ps_debug_stage": (c_int, [_P, c_int, _D, _D, c_void_p]),
     "ps_spectral_layout": (c_int, [_P, POINTER(c_int), POINTER(c_int)]),
     "ps_spectral_elems": (c_size_t, [_P]),

@@ -143,6 +143,26 @@ class Plan:
                                     _ptr(p, "p", self.centre_shape), hp, ho, _stream(), ctypes.byref(info)))
         return info.as_dict()
 
+    def step(self, nu, kappa, u, v, w, t, p, dt=0.0, cfl=1.3, dt_max=float("inf")):
+        """One full RK3 step (three substeps); dt <= 0 takes the Courant-limited step
+        min(dt_max, cfl / Courant number).  Returns (dt taken, info)."""
+        used = ctypes.c_double()
+        info = PsInfo()
+        check(self._lib.rk3_step(self._h, float(dt), float(cfl), float(dt_max), float(nu), float(kappa),
+                                 _ptr(u, "u", self.centre_shape), _ptr(v, "v", self.centre_shape),
+                                 _ptr(w, "w", self.face_shape), _ptr(t, "t", self.face_shape),
+                                 _ptr(p, "p", self.centre_shape), ctypes.byref(used), _stream(),
+                                 ctypes.byref(info)))
+        return used.value, info.as_dict()
+
+    def heat_flux(self, w, t, kappa):
+        """(mean T on the nz + 1 faces, vertical heat flux on the nz centre planes), device tensors."""
+        mean_t = torch.empty(self.nz + 1, dtype=torch.float64, device=w.device)
+        flux = torch.empty(self.nz, dtype=torch.float64, device=w.device)
+        check(self._lib.ps_heat_flux(self._h, _ptr(w, "w", self.face_shape), _ptr(t, "t", self.face_shape),
+                                     float(kappa), _ptr(mean_t, "mean_t"), _ptr(flux, "flux"), _stream()))
+        return mean_t, flux
+
     def substep_adjoint(self, dt, nu, kappa, u, v, w, t, p, g_out):
         g_in = [torch.empty_like(x) for x in (u, v, w, t, p)]
         go = (ctypes.c_void_p * 5)(*[_ptr(x, "g_out").value for x in g_out])

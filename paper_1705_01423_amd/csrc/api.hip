@@ -767,6 +767,62 @@ ps_status rk3_substep(ps_plan_t p, int l, double dt, double nu, double kappa, do
     return project(p, u, v, w, pr, nullptr, alp * dt, bnu, stream, info);
 }
 
+ps_status rk3_step(ps_plan_t p, double dt, double cfl_target, double dt_max, double nu, double kappa, double* u,
+                   double* v, double* w, double* t, double* pr, double* dt_used, void* stream, ps_info* info) {
+    PS_CHECK(check_plan(p));
+    PS_CHECK(check_ptr(u, "u"));
+    PS_CHECK(check_ptr(v, "v"));
+    PS_CHECK(check_ptr(w, "w"));
+    PS_CHECK(check_ptr(t, "t"));
+    PS_CHECK(check_ptr(pr, "p"));
+    if (!(nu >= 0) || !(kappa >= 0) || !std::isfinite(nu) || !std::isfinite(kappa))
+        return fail(PS_EINVAL, "nu and kappa must be non-negative");
+    hipStream_t st = (hipStream_t)stream;
+    if (!(dt > 0)) {
+        if (!(cfl_target > 0) || !std::isfinite(cfl_target)) return fail(PS_EINVAL, "cfl_target must be positive");
+        if (!(dt_max > 0)) return fail(PS_EINVAL, "dt_max must be positive");
+        // Courant number of the current state, read back once
+        PS_HIP(launch_cfl(p->gd, u, v, w, p->small + R_CFL, st), "cfl");
+        PS_CHECK(read_small(p, st));
+        const double c = p->h_res[R_CFL];
+        if (!std::isfinite(c)) return fail(PS_ENONFINITE, "Courant number is not finite");
+        dt = std::min(dt_max, cfl_target / std::max(c, 1e-8));
+    }
+    if (!std::isfinite(dt)) return fail(PS_EINVAL, "dt must be finite");
+    PS_CHECK(ensure_substep_buffers(p));
+    // H^l of substep l is read by substep l + 1 and overwritten in place (each point's
+    // explicit terms are read before they are written, by the same thread)
+    double* h[4] = {sub_field(p, 4), sub_field(p, 5), sub_field(p, 6), sub_field(p, 7)};
+    const double* hc[4] = {h[0], h[1], h[2], h[3]};
+    ps_info acc{};
+    for (int l = 1; l <= 3; ++l) {
+        ps_info li{};
+        const ps_status r = rk3_substep(p, l, dt, nu, kappa, u, v, w, t, pr, l > 1 ? hc : nullptr, h, stream,
+                                        info ? &li : nullptr);
+        if (r != PS_OK && r != PS_ENOTCONVERGED) return r;
+        acc.iterations += li.iterations;
+        acc.rel_update = std::max(acc.rel_update, li.rel_update);
+        acc.rel_residual = std::max(acc.rel_residual, li.rel_residual);
+        acc.compat_defect = li.compat_defect;
+        acc.gauge_shift = li.gauge_shift;
+    }
+    if (dt_used) *dt_used = dt;
+    if (info) *info = acc;
+    return PS_OK;
+}
+
+ps_status ps_heat_flux(ps_plan_t p, const double* w, const double* t, double kappa, double* mean_t, double* flux,
+                       void* stream) {
+    PS_CHECK(check_plan(p));
+    PS_CHECK(check_ptr(w, "w"));
+    PS_CHECK(check_ptr(t, "t"));
+    if (!mean_t || !flux || ((uintptr_t)mean_t) % 8 || ((uintptr_t)flux) % 8)
+        return fail(PS_EINVAL, "mean_t and flux must be aligned device pointers");
+    if (!(kappa >= 0) || !std::isfinite(kappa)) return fail(PS_EINVAL, "kappa must be non-negative");
+    PS_HIP(launch_heat_flux(p->gd, w, t, kappa, p->partial, mean_t, flux, (hipStream_t)stream), "heat flux");
+    return PS_OK;
+}
+
 ps_status rk3_substep_adjoint(ps_plan_t p, double dt, double nu, double kappa, const double* u, const double* v,
                               const double* w, const double* t, const double* pr, const double* const* g_out,
                               double* const* g_in, void* stream, ps_info* info) {

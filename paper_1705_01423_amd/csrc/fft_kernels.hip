@@ -31,9 +31,16 @@ namespace ps {
 #ifndef PS_Y_EMAX
 #define PS_Y_EMAX 16
 #endif
-template <typename T>
+#ifndef PS_X_EMAX64_INV
+#define PS_X_EMAX64_INV PS_X_EMAX64
+#endif
+#ifndef PS_X_EMAX32_INV
+#define PS_X_EMAX32_INV PS_X_EMAX32
+#endif
+template <typename T, bool INV = false>
 struct XEmax {
-    static constexpr int value = sizeof(T) == 8 ? PS_X_EMAX64 : PS_X_EMAX32;
+    static constexpr int value =
+        sizeof(T) == 8 ? (INV ? PS_X_EMAX64_INV : PS_X_EMAX64) : (INV ? PS_X_EMAX32_INV : PS_X_EMAX32);
 };
 constexpr int kYEmax = PS_Y_EMAX;
 
@@ -62,7 +69,7 @@ constexpr int kYEmax = PS_Y_EMAX;
 // start in different banks).
 template <typename T, int M, bool INV = false>
 struct XShape {
-    static constexpr int EM = XEmax<T>::value;
+    static constexpr int EM = XEmax<T, INV>::value;
     using Sh = FftShape<M, EM>;
     static constexpr int NT = Sh::NT;
     static constexpr int LROW = lds_len(M);

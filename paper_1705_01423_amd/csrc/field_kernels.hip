@@ -320,6 +320,37 @@ k_cfl(const double* __restrict__ u, const double* __restrict__ v, const double* 
     if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(q));
 }
 
+// ---- wall-normal statistics ------------------------------------------------
+// Block k sums plane k of T (k = 0..nz) and, for k < nz, the plane of
+// wbar Tbar = (w_k + w_{k+1}) (T_k + T_{k+1}) / 4 over cell-centre plane k.
+__global__ void __launch_bounds__(1024)
+k_plane_sums(const double* __restrict__ w, const double* __restrict__ t, GridDev g, double* __restrict__ sums) {
+    const int k = blockIdx.x;
+    const size_t plane = (size_t)g.nx * g.ny;
+    const double* tk = t + (size_t)k * plane;
+    double v[2] = {0.0, 0.0};
+    for (size_t q = threadIdx.x; q < plane; q += blockDim.x) {
+        const double tc = tk[q];
+        v[0] += tc;
+        if (k < g.nz) {
+            const double wb = 0.5 * (w[(size_t)k * plane + q] + w[(size_t)(k + 1) * plane + q]);
+            v[1] += wb * (0.5 * (tc + tk[q + plane]));
+        }
+    }
+    block_sum_store<2>(v, sums + 2 * k);
+}
+
+// mean_t[k] = sum_T[k] / (nx ny); flux[k] = sum_wT[k] / (nx ny) - kappa (mean_t[k+1] - mean_t[k]) / dz_k
+__global__ void k_heat_flux(const double* __restrict__ sums, GridDev g, double kappa, double* __restrict__ mean_t,
+                            double* __restrict__ flux) {
+    const double inv = 1.0 / ((double)g.nx * (double)g.ny);
+    for (int k = threadIdx.x; k <= g.nz; k += blockDim.x) {
+        const double tm = sums[2 * k] * inv;
+        mean_t[k] = tm;
+        if (k < g.nz) flux[k] = sums[2 * k + 1] * inv - kappa * (sums[2 * (k + 1)] * inv - tm) / g.dz[k];
+    }
+}
+
 // ---- projection adjoint -----------------------------------------------------
 // With Vf = dz on u, v and dzc on interior w, and Vc = dz:
 //   g_u* = g_u - Vf G S [ D Vf^-1 g_u + (1/s) (I - c Dzz) Vc^-1 g_p ].
@@ -433,6 +464,15 @@ hipError_t launch_scale_planes(const GridDev& g, const double* in, double* out, 
     (void)g;
     const size_t n = (size_t)nplanes * plane;
     hipLaunchKernelGGL(k_scale_planes, dim3(nblocks(n, 256)), dim3(256), 0, st, in, out, zs, plane, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_heat_flux(const GridDev& g, const double* w, const double* t, double kappa, double* sums,
+                            double* mean_t, double* flux, hipStream_t st) {
+    hipLaunchKernelGGL(k_plane_sums, dim3(g.nz + 1), dim3(1024), 0, st, w, t, g, sums);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_heat_flux, dim3(1), dim3(256), 0, st, sums, g, kappa, mean_t, flux);
     return hipGetLastError();
 }
 

@@ -230,6 +230,10 @@ bool launch_cn_tiled_add(const GridDev& g, int kind, const double* fac, const do
 bool launch_cn_tiled_t(const GridDev& g, int kind, const double* fac, const double* in, double* out,
                        hipStream_t st, hipError_t* err);
 hipError_t launch_cn_solve(const GridDev& g, int kind, const double* fac, double* x, hipStream_t st);
+// Plane means of T (nz + 1 faces) and total vertical heat flux through the nz centre planes;
+// sums: 2 (nz + 1) doubles of scratch.
+hipError_t launch_heat_flux(const GridDev& g, const double* w, const double* t, double kappa, double* sums,
+                            double* mean_t, double* flux, hipStream_t st);
 hipError_t launch_cfl(const GridDev& g, const double* u, const double* v, const double* w, double* out,
                       hipStream_t st);
 

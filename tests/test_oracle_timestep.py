@@ -1,0 +1,96 @@
+"""Pins of the oracle's full RK3 step and wall-normal statistics (paper Sec. 2.1, Listing 1, Sec. 4)."""
+import math
+
+import numpy as np
+import torch
+
+from oracle import Grid
+from oracle import substep as ss
+from oracle import timestep as ts
+from paper_1705_01423_amd.synth import zfaces
+
+F64 = torch.float64
+
+
+def _grid(nx, ny, nz, lx=1.0, ly=1.0, alpha=3.0):
+    return Grid(nx, ny, nz, lx, ly, zfaces(nz, alpha))
+
+
+def _conduction(g):
+    t = (1 - g.zf)[:, None, None].expand(g.nz + 1, g.ny, g.nx).clone()
+    z = torch.zeros(g.nz, g.ny, g.nx, dtype=F64)
+    zw = torch.zeros(g.nz + 1, g.ny, g.nx, dtype=F64)
+    return z, z.clone(), zw, t, z.clone()
+
+
+def test_step_keeps_conduction_state():
+    """Three substeps of the conduction state: no motion, T unchanged (buoyancy is hydrostatic)."""
+    g = _grid(8, 6, 10)
+    u, v, w, t, p = _conduction(g)
+    un, vn, wn, tn, _ = ts.rk3_step((u, v, w, t, p), g, 2e-3, 1e-3, 1e-3)
+    assert float(un.abs().max()) == 0.0 and float(vn.abs().max()) == 0.0
+    assert float(wn.abs().max()) < 1e-14
+    assert float((tn - t).abs().max()) < 1e-15
+
+
+def test_step_rk3_amplification():
+    """A horizontal mode v = eps cos(theta x_i) carried by a uniform u = U (nu = 0): the central
+    advection operator has the eigenvalue mu = -i U sin(theta dx) / dx, and one full step of the
+    low-storage scheme multiplies the mode by 1 + z + z^2/2 + z^3/6, z = mu dt.  This pins the
+    hand-over of H between the substeps (rho terms) and the coefficients together."""
+    nx, ny, nz, lx = 16, 4, 6, 2.0
+    g = _grid(nx, ny, nz, lx=lx)
+    U, eps, m, dt = 0.7, 1e-3, 3, 0.05
+    dx = lx / nx
+    theta = 2 * math.pi * m / lx
+    xc = (torch.arange(nx, dtype=F64) + 0.5) * dx
+    u, v, w, t, p = _conduction(g)
+    u = torch.full_like(u, U)
+    v = (eps * torch.cos(theta * xc))[None, None, :].expand(nz, ny, nx).clone()
+    un, vn, wn, tn, _ = ts.rk3_step((u, v, w, t, p), g, dt, 0.0, 0.0)
+    z = -1j * U * math.sin(theta * dx) / dx * dt
+    amp = 1 + z + z * z / 2 + z ** 3 / 6
+    expect = eps * (amp * torch.exp(1j * theta * xc.to(torch.complex128))).real
+    assert float((vn[0, 0] - expect).abs().max()) < 1e-15
+    assert float((vn - vn[0:1, 0:1]).abs().max()) < 1e-16
+    assert float((un - U).abs().max()) < 1e-15
+    assert float(wn.abs().max()) < 1e-14
+    assert float((tn - t).abs().max()) < 1e-15
+
+
+def test_cfl_dt():
+    g = _grid(8, 6, 5)
+    rng = np.random.default_rng(2)
+    u, v = (torch.as_tensor(rng.standard_normal((5, 6, 8))) for _ in range(2))
+    w = torch.as_tensor(rng.standard_normal((6, 6, 8)))
+    c = ss.cfl(u, v, w, g)
+    assert ts.cfl_dt(u, v, w, g, 1.3) == 1.3 / c
+    assert ts.cfl_dt(u, v, w, g, 1.3, dt_max=1e-9) == 1e-9
+
+
+def test_heat_flux_conduction():
+    """Linear conduction profile: <T> = 1 - z on every face, flux = kappa (Nu = 1) everywhere."""
+    g = _grid(8, 6, 12)
+    _, _, w, t, _ = _conduction(g)
+    kappa = 3e-3
+    tm, f = ts.heat_flux(w, t, g, kappa)
+    assert torch.allclose(tm, 1 - g.zf, rtol=0, atol=1e-16)
+    assert torch.allclose(f / kappa, torch.ones(g.nz, dtype=F64), rtol=0, atol=1e-13)
+
+
+def test_heat_flux_modes():
+    """w = a_k cos(theta x), T = b_k cos(theta x) + c_k: the plane average of cos^2 over the
+    periodic grid is exactly 1/2, so <wbar Tbar>_k = abar_k bbar_k / 2 and <T>_k = c_k."""
+    nx, ny, nz = 12, 4, 7
+    g = _grid(nx, ny, nz)
+    rng = np.random.default_rng(3)
+    a, b, c = (torch.as_tensor(rng.standard_normal(nz + 1)) for _ in range(3))
+    xc = (torch.arange(nx, dtype=F64) + 0.5) / nx
+    cosx = torch.cos(2 * math.pi * 2 * xc)[None, None, :]
+    w = a[:, None, None] * cosx.expand(nz + 1, ny, nx)
+    t = b[:, None, None] * cosx.expand(nz + 1, ny, nx) + c[:, None, None]
+    kappa = 0.0
+    tm, f = ts.heat_flux(w, t, g, kappa)
+    assert torch.allclose(tm, c, rtol=0, atol=1e-15)
+    ab, bb = 0.5 * (a[:-1] + a[1:]), 0.5 * (b[:-1] + b[1:])
+    assert torch.allclose(f, 0.5 * ab * bb, rtol=0, atol=1e-15)
