@@ -797,8 +797,9 @@ ps_status rk3_step(ps_plan_t p, double dt, double cfl_target, double dt_max, dou
     ps_info acc{};
     for (int l = 1; l <= 3; ++l) {
         ps_info li{};
-        const ps_status r = rk3_substep(p, l, dt, nu, kappa, u, v, w, t, pr, l > 1 ? hc : nullptr, h, stream,
-                                        info ? &li : nullptr);
+        // the last substep's H is not needed by anyone
+        const ps_status r = rk3_substep(p, l, dt, nu, kappa, u, v, w, t, pr, l > 1 ? hc : nullptr,
+                                        l < 3 ? h : nullptr, stream, info ? &li : nullptr);
         if (r != PS_OK && r != PS_ENOTCONVERGED) return r;
         acc.iterations += li.iterations;
         acc.rel_update = std::max(acc.rel_update, li.rel_update);

@@ -5,6 +5,8 @@
 // Threads map to (x fastest) grid points, so every warp-wide access along x is
 // contiguous; neighbours in y and z come from other rows and are served by the
 // caches.
+#include <algorithm>
+
 #include "ps_internal.h"
 #include "reduce.h"
 
@@ -296,28 +298,36 @@ static bool cn_tiled_launch(const GridDev& g, int kind, const double* fac, const
 }
 
 // ---- CFL (Listing 1) ------------------------------------------------------
+// A fixed grid of blocks strides over the cells; each block reduces its maximum and
+// posts it with one atomic max (non-negative doubles order like their bit patterns).
+constexpr int kCflBlocks = 2048;
 __global__ void __launch_bounds__(256)
 k_cfl(const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w, GridDev g,
       unsigned long long* __restrict__ out) {
+    __shared__ double wmax[4];
     const size_t n = (size_t)g.nx * g.ny * g.nz;
-    const size_t id = (size_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const size_t plane = (size_t)g.nx * g.ny;
     double q = 0.0;
-    if (id < n) {
+    for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < n; id += (size_t)gridDim.x * blockDim.x) {
         const int i = (int)(id % g.nx);
         const size_t jk = id / g.nx;
         const int j = (int)(jk % g.ny);
         const int k = (int)(jk / g.ny);
-        const size_t plane = (size_t)g.nx * g.ny;
         const int ip = (i + 1 == g.nx) ? 0 : i + 1;
         const int jp = (j + 1 == g.ny) ? 0 : j + 1;
-        q = fabs(w[id] + w[id + plane]) / g.dz[k] +
-            fabs(v[id] + v[(size_t)k * plane + (size_t)jp * g.nx + i]) / g.dy +
-            fabs(u[id] + u[(size_t)k * plane + (size_t)j * g.nx + ip]) / g.dx;
-        q *= 0.5;
+        double c = fabs(w[id] + w[id + plane]) / g.dz[k] +
+                   fabs(v[id] + v[(size_t)k * plane + (size_t)jp * g.nx + i]) / g.dy +
+                   fabs(u[id] + u[(size_t)k * plane + (size_t)j * g.nx + ip]) / g.dx;
+        q = fmax(q, 0.5 * c);
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) q = fmax(q, __shfl_xor(q, off, 64));
-    if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(q));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = q;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int wv = 1; wv < (int)(blockDim.x >> 6); ++wv) q = fmax(q, wmax[wv]);
+        atomicMax(out, (unsigned long long)__double_as_longlong(q));
+    }
 }
 
 // ---- wall-normal statistics ------------------------------------------------
@@ -503,8 +513,8 @@ hipError_t launch_cfl(const GridDev& g, const double* u, const double* v, const 
     const size_t n = (size_t)g.nx * g.ny * g.nz;
     hipError_t e = launch_fill(out, 1, 1e-8, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_cfl, dim3(nblocks(n, 256)), dim3(256), 0, st, u, v, w, g,
-                       reinterpret_cast<unsigned long long*>(out));
+    const int nb = (int)std::min<size_t>((size_t)kCflBlocks, (n + 255) / 256);
+    hipLaunchKernelGGL(k_cfl, dim3(nb), dim3(256), 0, st, u, v, w, g, reinterpret_cast<unsigned long long*>(out));
     return hipGetLastError();
 }
 
