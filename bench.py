@@ -70,11 +70,16 @@ def main():
     ap.add_argument("--no-refined", action="store_true")
     ap.add_argument("--stage-reps", type=int, default=10)
     ap.add_argument("--no-extra", action="store_true", help="skip the projection/adjoint/substep legs")
+    ap.add_argument("--only-extra", action="store_true",
+                    help="run only the projection/adjoint/substep legs and print their JSON (profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this library runs one box on one GPU; runs on more than one GPU are not supported",
               file=sys.stderr)
         sys.exit(2)
+    if args.only_extra:
+        print(json.dumps(other_workloads(args)), flush=True)
+        return
 
     import numpy as np
     import torch
