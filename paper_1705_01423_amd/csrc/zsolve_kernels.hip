@@ -14,6 +14,8 @@
 // its right-hand side is made compatible (dz-weighted mean removed), then it
 // is integrated directly - wall-normal fluxes Q_{k+1} = Q_k + dz_k F_k, then
 // P_k = P_{k-1} + dzc_k Q_k - and re-gauged to zero dz-weighted mean.
+#include <algorithm>
+
 #include "ps_internal.h"
 
 namespace ps {
@@ -150,58 +152,28 @@ struct ZCols {
     static constexpr int value = sizeof(T) == 8 ? PS_Z_COLS64 : PS_Z_COLS32;
 };
 
-#ifdef PS_Z_WAVES_PER_EU
-#define PS_Z_ATTR __attribute__((amdgpu_waves_per_eu(PS_Z_WAVES_PER_EU)))
-#else
-#define PS_Z_ATTR
-#endif
-template <typename T, int K, int WZ, int MAXT>
-__global__ void __launch_bounds__(MAXT) PS_Z_ATTR
-k_zsolve_scan(cx<T>* __restrict__ b, const T* __restrict__ etab, int nz, int ny, int nxh,
-              const double* __restrict__ dz, const double* __restrict__ o, const double* __restrict__ lamx,
-              const double* __restrict__ lamy) {
-    constexpr int W = TileW<T>::value;
-    static_assert(W % WZ == 0, "columns per block must divide the tile width");   // WZ: a sub-tile
-    constexpr int NSUB = W / WZ;
-    constexpr int LPW = 64 / WZ;          // lanes of one column inside a wave
-    __shared__ T xs[16 * WZ * 4];         // per-wave totals
-#if PS_Z_LDS_COEF
-    // o in LDS: re-read where used instead of being held in registers across the scans
-    __shared__ double os_[2049];
-    for (int q = threadIdx.x; q <= nz; q += blockDim.x) os_[q] = o[q];
-    __syncthreads();
-    const double* oc = os_;
-#else
-    const double* oc = o;
-#endif
-    const int tid = threadIdx.x;
-    const int c = tid % WZ;
-    const int l = tid / WZ;
-    const int wave = tid >> 6;
-    const int nwave = blockDim.x >> 6;
-    const int lw = l % LPW;
-    const int bid = xcd_remap(blockIdx.x, gridDim.x);
-    const int csub = bid % NSUB;
-    const int tile_id = bid / NSUB;
-    const int ky = tile_id % ny;
-    const int kxb = tile_id / ny;
-    const int kx = kxb * W + csub * WZ + c;
-    const bool store = kx < nxh && !(kx == 0 && ky == 0);
-    const T lam = store ? (T)(lamx[kx] + lamy[ky]) : (T)1;
-    cx<T>* tile = b + (size_t)tile_id * nz * W + csub * WZ + c;
-    const int k0 = l * K;
-    const int nchunk = (nz + K - 1) / K;
-
-    cx<T> v[K];
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
-        const int k = k0 + i;
-        v[i] = (k < nz) ? ld_stream<PS_NT_Z>(tile + (size_t)k * W) : cx<T>{(T)0, (T)0};
+// Barrier of the scans: __syncthreads, or (RAW) an LDS-only barrier (this wave's LDS
+// accesses complete, then s_barrier) that leaves outstanding global->LDS copies in flight.
+template <bool RAW>
+__device__ __forceinline__ void zbar() {
+    if constexpr (RAW) {
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0); vmcnt and expcnt left at their maxima
+        __builtin_amdgcn_s_barrier();
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    } else {
+        __syncthreads();
     }
-    // ---- (A) excess entering the chunk: e_{k0-1} -----------------------------------
-    T eprev = (T)0;
-    if (l < nchunk) eprev = etab[((size_t)tile_id * nchunk + l) * W + csub * WZ + c];
+}
 
+// Pivots, forward sweep and back substitution of one block's columns: lane (l, c) holds
+// rows [k0, k0 + K) of column c in v (the right-hand side in, the solution out) and the
+// excess eprev = e_{k0-1} entering its chunk.
+template <typename T, int K, int WZ, bool RAW>
+__device__ __forceinline__ void zscan_solve(cx<T> (&v)[K], T eprev, T lam, int k0, int nz, int c, int wave,
+                                            int nwave, int lw, T* xs, const double* __restrict__ dz,
+                                            const double* __restrict__ oc) {
+    constexpr int LPW = 64 / WZ;
     // ---- pivots: rp_k = 1 / p_k; the chunk's first multiplier m0 = o_k0 / p_{k0-1} --------
     // Only rp and the scaled right-hand side stay in registers; the multipliers
     // m_k = o_k rp_{k-1} and the back-substitution coefficients o_{k+1} rp_k are re-formed
@@ -255,7 +227,7 @@ k_zsolve_scan(cx<T>* __restrict__ b, const T* __restrict__ etab, int nz, int ny,
     }
     Aff<T> fex = shfl_up_aff(finc, WZ);
     if (lw == 0) fex = {(T)1, {(T)0, (T)0}};
-    __syncthreads();
+    zbar<RAW>();
     Aff<T> fpw = {(T)1, {(T)0, (T)0}};
     for (int w2 = 0; w2 < wave; ++w2) {
         const T* q = xs + (w2 * WZ + c) * 4;
@@ -272,7 +244,7 @@ k_zsolve_scan(cx<T>* __restrict__ b, const T* __restrict__ etab, int nz, int ny,
             v[i] = y;
         }
     }
-    __syncthreads();
+    zbar<RAW>();
 
     // ---- (C) back substitution -------------------------------------------------
     Aff<T> ba = {(T)1, {(T)0, (T)0}};
@@ -298,7 +270,7 @@ k_zsolve_scan(cx<T>* __restrict__ b, const T* __restrict__ etab, int nz, int ny,
     }
     Aff<T> bex = shfl_down_aff(binc, WZ);
     if (lw == LPW - 1) bex = {(T)1, {(T)0, (T)0}};
-    __syncthreads();
+    zbar<RAW>();
     Aff<T> bpw = {(T)1, {(T)0, (T)0}};
     for (int w2 = nwave - 1; w2 > wave; --w2) {
         const T* q = xs + (w2 * WZ + c) * 4;
@@ -315,11 +287,146 @@ k_zsolve_scan(cx<T>* __restrict__ b, const T* __restrict__ etab, int nz, int ny,
             v[i] = x;
         }
     }
+}
+
+#ifdef PS_Z_WAVES_PER_EU
+#define PS_Z_ATTR __attribute__((amdgpu_waves_per_eu(PS_Z_WAVES_PER_EU)))
+#else
+#define PS_Z_ATTR
+#endif
+template <typename T, int K, int WZ, int MAXT>
+__global__ void __launch_bounds__(MAXT) PS_Z_ATTR
+k_zsolve_scan(cx<T>* __restrict__ b, const T* __restrict__ etab, int nz, int ny, int nxh,
+              const double* __restrict__ dz, const double* __restrict__ o, const double* __restrict__ lamx,
+              const double* __restrict__ lamy) {
+    constexpr int W = TileW<T>::value;
+    static_assert(W % WZ == 0, "columns per block must divide the tile width");   // WZ: a sub-tile
+    constexpr int NSUB = W / WZ;
+    constexpr int LPW = 64 / WZ;          // lanes of one column inside a wave
+    __shared__ T xs[16 * WZ * 4];         // per-wave totals
+#if PS_Z_LDS_COEF
+    // o in LDS: re-read where used instead of being held in registers across the scans
+    __shared__ double os_[2049];
+    for (int q = threadIdx.x; q <= nz; q += blockDim.x) os_[q] = o[q];
+    __syncthreads();
+    const double* oc = os_;
+#else
+    const double* oc = o;
+#endif
+    const int tid = threadIdx.x;
+    const int c = tid % WZ;
+    const int l = tid / WZ;
+    const int wave = tid >> 6;
+    const int nwave = blockDim.x >> 6;
+    const int lw = l % LPW;
+    const int bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int csub = bid % NSUB;
+    const int tile_id = bid / NSUB;
+    const int ky = tile_id % ny;
+    const int kxb = tile_id / ny;
+    const int kx = kxb * W + csub * WZ + c;
+    const bool store = kx < nxh && !(kx == 0 && ky == 0);
+    const T lam = store ? (T)(lamx[kx] + lamy[ky]) : (T)1;
+    cx<T>* tile = b + (size_t)tile_id * nz * W + csub * WZ + c;
+    const int k0 = l * K;
+    const int nchunk = (nz + K - 1) / K;
+
+    cx<T> v[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int k = k0 + i;
+        v[i] = (k < nz) ? ld_stream<PS_NT_Z>(tile + (size_t)k * W) : cx<T>{(T)0, (T)0};
+    }
+    // ---- (A) excess entering the chunk: e_{k0-1} -----------------------------------
+    T eprev = (T)0;
+    if (l < nchunk) eprev = etab[((size_t)tile_id * nchunk + l) * W + csub * WZ + c];
+
+    zscan_solve<T, K, WZ, false>(v, eprev, lam, k0, nz, c, wave, nwave, lw, xs, dz, oc);
     if (store) {
 #pragma unroll
         for (int i = 0; i < K; ++i) {
             const int k = k0 + i;
             if (k < nz) st_stream<PS_NT_Z>(tile + (size_t)k * W, v[i]);
+        }
+    }
+}
+
+// Streamed z solve: a fixed grid of full-tile blocks walks the tiles; while a block
+// solves tile t from registers, the next tile (nz x W contiguous values) streams into
+// the other half of a double LDS buffer by global->LDS copies (1 KB per wave
+// instruction), so every CU keeps a tile of loads in flight through the solve.  The
+// scans' barriers are LDS-only so that they do not wait for those copies.
+// Measured at 1024^2 x 512: FP32 z solve 1.36 -> 1.05 ms; in FP64 the solve work of
+// one block per CU is the limit (1.93 -> 1.98 ms), so the register-tile kernel stays.
+#ifndef PS_Z_PIPE32
+#define PS_Z_PIPE32 1
+#endif
+#ifndef PS_Z_PIPE64
+#define PS_Z_PIPE64 0
+#endif
+typedef __attribute__((address_space(3))) unsigned char lds_u8;
+constexpr int kZPipeMaxNz = 512;
+
+template <typename T, int K, int MAXT>
+__global__ void __launch_bounds__(MAXT)
+k_zsolve_pipe(cx<T>* __restrict__ b, const T* __restrict__ etab, int nz, int ny, int nxh, int ntiles,
+              const double* __restrict__ dz, const double* __restrict__ o, const double* __restrict__ lamx,
+              const double* __restrict__ lamy) {
+    constexpr int W = TileW<T>::value, WZ = W, LPW = 64 / WZ;
+    extern __shared__ __align__(16) unsigned char zsm[];
+    __shared__ T xs[16 * WZ * 4];
+    // grid metrics in LDS (nz <= kZPipeMaxNz): the solve then issues no global loads of its
+    // own, which would have to wait behind the copies of the next tile
+    __shared__ double zdz[kZPipeMaxNz], zo[kZPipeMaxNz + 1];
+    cx<T>* buf = reinterpret_cast<cx<T>*>(zsm);   // [2][nz * W]
+    for (int q = threadIdx.x; q <= nz; q += blockDim.x) {
+        zo[q] = o[q];
+        if (q < nz) zdz[q] = dz[q];
+    }
+    const int tid = threadIdx.x;
+    const int c = tid % WZ, l = tid / WZ, lane = tid & 63, lw = l % LPW;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nwave = blockDim.x >> 6;
+    const int k0 = l * K, nchunk = (nz + K - 1) / K;
+    const size_t telems = (size_t)nz * W;
+    const int nkb = (int)(telems * sizeof(cx<T>) / 1024);   // 1 KB copies per tile (nz * W * sizeof % 1024 == 0)
+    auto copy_tile = [&](int t, int sel) {
+        const unsigned char* src = reinterpret_cast<const unsigned char*>(b + (size_t)t * telems);
+        lds_u8* dst = (lds_u8*)(reinterpret_cast<unsigned char*>(buf + sel * telems));   // LDS address
+        for (int q = wave; q < nkb; q += nwave)
+            __builtin_amdgcn_global_load_lds(src + (size_t)q * 1024 + lane * 16, dst + q * 1024, 16, 0, 0);
+    };
+    int t = blockIdx.x;
+    if (t < ntiles) copy_tile(t, 0);
+    for (int it = 0; t < ntiles; ++it, t += gridDim.x) {
+        const int sel = it & 1;
+        __builtin_amdgcn_s_waitcnt(0);   // this wave's copies (and stores) are done
+        __syncthreads();                 // ... and every other wave's
+        const int ky = t % ny, kxb = t / ny, kx = kxb * W + c;
+        const bool store = kx < nxh && !(kx == 0 && ky == 0);
+        const T lam = store ? (T)(lamx[kx] + lamy[ky]) : (T)1;
+        T eprev = (T)0;
+        if (l < nchunk) eprev = etab[((size_t)t * nchunk + l) * W + c];
+        cx<T> v[K];
+        const cx<T>* cur = buf + sel * telems;
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const int k = k0 + i;
+            v[i] = (k < nz) ? cur[(size_t)k * W + c] : cx<T>{(T)0, (T)0};
+        }
+        // this tile's global loads complete before the copies are issued (the counter
+        // that tracks them is in order)
+        asm volatile("" ::"v"(lam), "v"(eprev));
+        // the next tile streams into the other buffer while this one is solved
+        if (t + (int)gridDim.x < ntiles) copy_tile(t + gridDim.x, sel ^ 1);
+        zscan_solve<T, K, WZ, true>(v, eprev, lam, k0, nz, c, wave, nwave, lw, xs, zdz, zo);
+        if (store) {
+            cx<T>* tile = b + (size_t)t * telems + c;
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                const int k = k0 + i;
+                if (k < nz) tile[(size_t)k * W] = v[i];
+            }
         }
     }
 }
@@ -452,12 +559,50 @@ int zscan_cols(const GridDev& g) {
     return 0;
 }
 
+// Streamed variant: full tiles, whole KB copies, two tiles in LDS (<= 128 KB), <= 1024 threads.
+template <typename T>
+static hipError_t zpipe_launch(const GridDev& g, const SpecDev<T>& s, hipStream_t st, bool* launched) {
+    constexpr int W = TileW<T>::value, K = ZRows<T>::value;
+    *launched = false;
+    const size_t tbytes = (size_t)g.nz * W * sizeof(cx<T>);
+    const int threads = zscan_threads<K, W>(g.nz);
+    constexpr bool enabled = sizeof(T) == 4 ? PS_Z_PIPE32 : PS_Z_PIPE64;
+    if (!enabled || g.nz > kZPipeMaxNz || tbytes % 1024 != 0 || 2 * tbytes > 131072 || threads > 1024 || !s.etab)
+        return hipSuccess;
+    static int ncu = 0;
+    if (ncu == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+            ncu = 256;
+    }
+    const int ntiles = s.nkxb * g.ny;
+    const int nblk = std::min(ntiles, ncu);
+    const int nxh = g.nx / 2 + 1;
+#define PS_ZPIPE(MAXT)                                                                                           \
+    hipLaunchKernelGGL((k_zsolve_pipe<T, K, MAXT>), dim3(nblk), dim3(threads), 2 * tbytes, st, s.b, s.etab, g.nz, \
+                       g.ny, nxh, ntiles, g.dz, g.o, g.lamx, g.lamy)
+    if (threads <= 256)
+        PS_ZPIPE(256);
+    else if (threads <= 512)
+        PS_ZPIPE(512);
+    else
+        PS_ZPIPE(1024);
+#undef PS_ZPIPE
+    *launched = true;
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_zsolve(const GridDev& g, const SpecDev<T>& s, hipStream_t st) {
     constexpr int W = TileW<T>::value;
     constexpr int K = ZRows<T>::value, C = ZCols<T>::value;
     const int wz = zscan_cols<T>(g);
     if (wz > 0 && !s.etab) return hipErrorInvalidValue;
+    {
+        bool launched = false;
+        const hipError_t e = zpipe_launch<T>(g, s, st, &launched);
+        if (launched || e != hipSuccess) return e;
+    }
     if (wz == C) return zscan_launch<T, K, C>(g, s, st);
     if constexpr (C >= 2) {
         if (wz == C / 2) return zscan_launch<T, K, C / 2>(g, s, st);
