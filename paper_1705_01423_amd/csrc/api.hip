@@ -62,10 +62,10 @@ struct ps_plan_s {
     size_t plane;         // nx * ny
     double sum_dz;
     // host metrics
-    std::vector<double> dz, dzc, o, dzw, lamx, lamy, inv_dz;
+    std::vector<double> dz, dzc, o, dzw, lamx, lamy, inv_dz, inv_dzw;
     // device tables (one allocation)
     void* d_tables = nullptr;
-    double *d_dz, *d_dzc, *d_o, *d_dzw, *d_lamx, *d_lamy, *d_inv_dz;
+    double *d_dz, *d_dzc, *d_o, *d_dzw, *d_lamx, *d_lamy, *d_inv_dz, *d_inv_dzw;
     cx<double>*d_twx64, *d_ptw64, *d_twy64;
     cx<float>*d_twx32, *d_ptw32, *d_twy32;
     void* d_etab = nullptr;   // z-solve excess table (tiled solves), in the plan's precision
@@ -186,7 +186,7 @@ ps_status upload_tables(ps_plan_t p) {
     fill_twiddles(twx, M, M);
     fill_twiddles(ptw, p->nx, M + 1);
     fill_twiddles(twy, p->ny, p->ny);
-    const size_t nd = (size_t)p->nz + 3 * (size_t)(p->nz + 1) + nxh + p->ny + p->nz;
+    const size_t nd = (size_t)p->nz + 4 * (size_t)(p->nz + 1) + nxh + p->ny + p->nz;
     size_t bytes = align256(nd * sizeof(double)) + align256((size_t)(M + M + 1 + p->ny) * sizeof(cx<double>)) +
                    align256((size_t)(M + M + 1 + p->ny) * sizeof(cx<float>));
     PS_HIP(hipMalloc(&p->d_tables, bytes), "hipMalloc(tables)");
@@ -200,7 +200,7 @@ ps_status upload_tables(ps_plan_t p) {
         return at;
     };
     size_t a_dz = putd(p->dz), a_dzc = putd(p->dzc), a_o = putd(p->o), a_dzw = putd(p->dzw);
-    size_t a_lx = putd(p->lamx), a_ly = putd(p->lamy), a_idz = putd(p->inv_dz);
+    size_t a_lx = putd(p->lamx), a_ly = putd(p->lamy), a_idz = putd(p->inv_dz), a_idzw = putd(p->inv_dzw);
     char* dbase = (char*)p->d_tables;
     p->d_dz = (double*)dbase + a_dz;
     p->d_dzc = (double*)dbase + a_dzc;
@@ -209,6 +209,7 @@ ps_status upload_tables(ps_plan_t p) {
     p->d_lamx = (double*)dbase + a_lx;
     p->d_lamy = (double*)dbase + a_ly;
     p->d_inv_dz = (double*)dbase + a_idz;
+    p->d_inv_dzw = (double*)dbase + a_idzw;
     size_t off64 = align256(nd * sizeof(double));
     cx<double>* h64 = (cx<double>*)(host.data() + off64);
     memcpy(h64, twx.data(), M * sizeof(cx<double>));
@@ -486,6 +487,8 @@ ps_status poisson_plan_create(ps_plan_t* out, int nx, int ny, int nz, double lx,
     }
     p->dzw[0] = 0.5 * p->dz[0];
     p->dzw[nz] = 0.5 * p->dz[nz - 1];
+    p->inv_dzw.resize(nz + 1);
+    for (int k = 0; k <= nz; ++k) p->inv_dzw[k] = 1.0 / p->dzw[k];
     p->inv_dz.resize(nz);
     double sdz = 0.0;
     for (int k = 0; k < nz; ++k) {
@@ -530,6 +533,7 @@ ps_status poisson_plan_create(ps_plan_t* out, int nx, int ny, int nz, double lx,
         g.lamx = p->d_lamx;
         g.lamy = p->d_lamy;
         g.idz = p->d_inv_dz;
+        g.idzw = p->d_inv_dzw;
     }
     {
         // per-plan z-solve excess table (formed once, on the null stream)

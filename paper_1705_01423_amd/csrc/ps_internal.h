@@ -114,6 +114,7 @@ struct GridDev {
     const double* lamx;  // nx/2+1
     const double* lamy;  // ny
     const double* idz;   // nz, 1/dz
+    const double* idzw;  // nz+1, 1/dzw
 };
 
 // Stencil kernels: one thread per cell; a block covers kStencilBlock consecutive x of

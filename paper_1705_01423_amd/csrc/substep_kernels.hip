@@ -164,11 +164,11 @@ __global__ void __launch_bounds__(kExTX * kExTY) k_explicit(SubstepArgs a, GridD
                     ukp = L(FU, 1, 0, 0);
                     fzt = 0.5 * (L(FW, 1, 0, 0) + L(FW, 1, 0, -1)) * (0.5 * (uc + ukp));
                 }
-                const double az = (fzt - fzb) / g.dz[k];
+                const double az = (fzt - fzb) * g.idz[k];
                 const double h = -(ax + ay + az) + a.nu * ((uip - 2.0 * uc + uim) * idx2 + (ujp - 2.0 * uc + ujm) * idy2);
-                const double fb = (k > 0) ? (uc - ukm) / g.dzw[k] : uc / g.dzw[0];
-                const double ft = (k + 1 < nz) ? (ukp - uc) / g.dzw[k + 1] : -uc / g.dzw[nz];
-                const double dzz = (ft - fb) / g.dz[k];
+                const double fb = (k > 0) ? (uc - ukm) * g.idzw[k] : uc * g.idzw[0];
+                const double ft = (k + 1 < nz) ? (ukp - uc) * g.idzw[k + 1] : -uc * g.idzw[nz];
+                const double dzz = (ft - fb) * g.idz[k];
                 const double gp = (L(FP, 0, 0, 0) - L(FP, 0, 0, -1)) * idx;
                 double r = a.gam * h - a.alp * gp + a.alp * (a.nu * dzz);
                 if (a.rho != 0.0) r += a.rho * hp[0];
@@ -192,11 +192,11 @@ __global__ void __launch_bounds__(kExTX * kExTY) k_explicit(SubstepArgs a, GridD
                     vkp = L(FV, 1, 0, 0);
                     fzt = 0.5 * (L(FW, 1, 0, 0) + L(FW, 1, -1, 0)) * (0.5 * (vc + vkp));
                 }
-                const double az = (fzt - fzb) / g.dz[k];
+                const double az = (fzt - fzb) * g.idz[k];
                 const double h = -(ax + ay + az) + a.nu * ((vip - 2.0 * vc + vim) * idx2 + (vjp - 2.0 * vc + vjm) * idy2);
-                const double fb = (k > 0) ? (vc - vkm) / g.dzw[k] : vc / g.dzw[0];
-                const double ft = (k + 1 < nz) ? (vkp - vc) / g.dzw[k + 1] : -vc / g.dzw[nz];
-                const double dzz = (ft - fb) / g.dz[k];
+                const double fb = (k > 0) ? (vc - vkm) * g.idzw[k] : vc * g.idzw[0];
+                const double ft = (k + 1 < nz) ? (vkp - vc) * g.idzw[k + 1] : -vc * g.idzw[nz];
+                const double dzz = (ft - fb) * g.idz[k];
                 const double gp = (L(FP, 0, 0, 0) - L(FP, 0, -1, 0)) * idy;
                 double r = a.gam * h - a.alp * gp + a.alp * (a.nu * dzz);
                 if (a.rho != 0.0) r += a.rho * hp[1];
@@ -210,7 +210,7 @@ __global__ void __launch_bounds__(kExTX * kExTY) k_explicit(SubstepArgs a, GridD
                 if (a.hw) a.hw[id] = 0.0;
                 if (a.ht) a.ht[id] = 0.0;
             } else {
-                const double dzm = g.dz[k - 1], dzp = g.dz[k], den = 1.0 / (2.0 * g.dzc[k]);
+                const double dzm = g.dz[k - 1], dzp = g.dz[k], den = 0.5 * g.o[k];   // o = 1/dzc (interior face)
                 // volume-weighted horizontal transport on the side faces
                 const double uwl = (dzm * L(FU, -1, 0, 0) + dzp * L(FU, 0, 0, 0)) * den;
                 const double uwr = (dzm * L(FU, -1, 0, 1) + dzp * L(FU, 0, 0, 1)) * den;
@@ -222,7 +222,7 @@ __global__ void __launch_bounds__(kExTX * kExTY) k_explicit(SubstepArgs a, GridD
                 const double tc = L(FT, 0, 0, 0), tim = L(FT, 0, 0, -1), tip = L(FT, 0, 0, 1);
                 const double tjm = L(FT, 0, -1, 0), tjp = L(FT, 0, 1, 0);
                 const double tkm = L(FT, -1, 0, 0), tkp = L(FT, 1, 0, 0);
-                const double idzc = 1.0 / g.dzc[k];
+                const double idzc = g.o[k];
                 const double wtop = 0.5 * (wc + wkp), wbot = 0.5 * (wkm + wc);   // at centres k, k-1
                 // w
                 {
@@ -231,7 +231,7 @@ __global__ void __launch_bounds__(kExTX * kExTY) k_explicit(SubstepArgs a, GridD
                     const double az = (sq(wtop) - sq(wbot)) * idzc;
                     const double h = -(ax + ay + az) +
                                      a.nu * ((wip - 2.0 * wc + wim) * idx2 + (wjp - 2.0 * wc + wjm) * idy2) + tc;
-                    const double dzz = ((wkp - wc) / dzp - (wc - wkm) / dzm) * idzc;
+                    const double dzz = ((wkp - wc) * g.idz[k] - (wc - wkm) * g.idz[k - 1]) * idzc;
                     const double gp = (L(FP, 0, 0, 0) - L(FP, -1, 0, 0)) * idzc;
                     double r = a.gam * h - a.alp * gp + a.alp * (a.nu * dzz);
                     if (a.rho != 0.0) r += a.rho * hp[2];
@@ -244,7 +244,7 @@ __global__ void __launch_bounds__(kExTX * kExTY) k_explicit(SubstepArgs a, GridD
                     const double ay = (vwt * (0.5 * (tc + tjp)) - vwb * (0.5 * (tjm + tc))) * idy;
                     const double az = (wtop * (0.5 * (tc + tkp)) - wbot * (0.5 * (tkm + tc))) * idzc;
                     const double h = -(ax + ay + az) + a.ka * ((tip - 2.0 * tc + tim) * idx2 + (tjp - 2.0 * tc + tjm) * idy2);
-                    const double dzz = ((tkp - tc) / dzp - (tc - tkm) / dzm) * idzc;
+                    const double dzz = ((tkp - tc) * g.idz[k] - (tc - tkm) * g.idz[k - 1]) * idzc;
                     double r = a.gam * h + a.alp * (a.ka * dzz);
                     if (a.rho != 0.0) r += a.rho * hp[3];
                     a.rt[id] = a.dt * r;
@@ -395,13 +395,13 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
             // kappa of interior z-face equations (zero on the wall rows)
             auto KW = [&](int kk, int dj, int di) { return (kk >= 1 && kk <= nz - 1) ? cadv * LW(kk, dj, di) : 0.0; };
             auto KT = [&](int kk, int dj, int di) { return (kk >= 1 && kk <= nz - 1) ? cadv * LT(kk, dj, di) : 0.0; };
-            auto idzc = [&](int kk) { return (kk >= 1 && kk <= nz - 1) ? 1.0 / g.dzc[kk] : 0.0; };
+            auto idzc = [&](int kk) { return g.o[kk]; };   // 1/dzc at interior faces, 0 at the walls
             // volume-weighted transport at (x-face or y-face, z-face kk)
             auto UW = [&](int kk, int dj, int di) {
-                return (g.dz[kk - 1] * U(kk - 1, dj, di) + g.dz[kk] * U(kk, dj, di)) / (2.0 * g.dzc[kk]);
+                return (g.dz[kk - 1] * U(kk - 1, dj, di) + g.dz[kk] * U(kk, dj, di)) * (0.5 * g.o[kk]);
             };
             auto VW = [&](int kk, int dj, int di) {
-                return (g.dz[kk - 1] * V(kk - 1, dj, di) + g.dz[kk] * V(kk, dj, di)) / (2.0 * g.dzc[kk]);
+                return (g.dz[kk - 1] * V(kk - 1, dj, di) + g.dz[kk] * V(kk, dj, di)) * (0.5 * g.o[kk]);
             };
 
             // ================= g_u at (k, j, i) =================
@@ -423,11 +423,11 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
                 }
                 // u-eq, z faces k, k+1 (interior): Q = avg u
                 if (k >= 1) {
-                    const double L = KU(k - 1, 0, 0) / g.dz[k - 1] - KU(k, 0, 0) / g.dz[k];
+                    const double L = KU(k - 1, 0, 0) * g.idz[k - 1] - KU(k, 0, 0) * g.idz[k];
                     s += 0.5 * L * 0.5 * (Wf(k, 0, 0) + Wf(k, 0, -1));
                 }
                 if (k + 1 <= nz - 1) {
-                    const double L = KU(k, 0, 0) / g.dz[k] - KU(k + 1, 0, 0) / g.dz[k + 1];
+                    const double L = KU(k, 0, 0) * g.idz[k] - KU(k + 1, 0, 0) * g.idz[k + 1];
                     s += 0.5 * L * 0.5 * (Wf(k + 1, 0, 0) + Wf(k + 1, 0, -1));
                 }
                 // v-eq, x faces at (x-face i, y-faces j and j+1): U = avg of u over y
@@ -439,7 +439,7 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
                 // w- and T-eq, x faces at (x-face i, z-faces k and k+1): volume-weighted u
                 for (int kf = k; kf <= k + 1; ++kf) {
                     if (kf < 1 || kf > nz - 1) continue;
-                    const double wt = g.dz[k] / (2.0 * g.dzc[kf]);
+                    const double wt = g.dz[k] * (0.5 * g.o[kf]);
                     const double Lw = (KW(kf, 0, -1) - KW(kf, 0, 0)) * idx, Qw = 0.5 * (Wf(kf, 0, -1) + Wf(kf, 0, 0));
                     const double Lt = (KT(kf, 0, -1) - KT(kf, 0, 0)) * idx, Qt = 0.5 * (Tf(kf, 0, -1) + Tf(kf, 0, 0));
                     s += wt * (Lw * Qw + Lt * Qt);
@@ -450,9 +450,9 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
                              ((LU(k, 0, 1) - 2.0 * lc + LU(k, 0, -1)) * idx2 +
                               (LU(k, 1, 0) - 2.0 * lc + LU(k, -1, 0)) * idy2);
                 {
-                    const double mc = lc / g.dz[k];
-                    const double fb = (k > 0) ? (mc - LU(k - 1, 0, 0) / g.dz[k - 1]) / g.dzw[k] : mc / g.dzw[0];
-                    const double ft = (k + 1 < nz) ? (LU(k + 1, 0, 0) / g.dz[k + 1] - mc) / g.dzw[k + 1] : -mc / g.dzw[nz];
+                    const double mc = lc * g.idz[k];
+                    const double fb = (k > 0) ? (mc - LU(k - 1, 0, 0) * g.idz[k - 1]) * g.idzw[k] : mc * g.idzw[0];
+                    const double ft = (k + 1 < nz) ? (LU(k + 1, 0, 0) * g.idz[k + 1] - mc) * g.idzw[k + 1] : -mc * g.idzw[nz];
                     lin += a.alp * a.nu * (ft - fb);
                 }
                 a.gu[id] = dd[0] + s + a.dt * lin;
@@ -473,11 +473,11 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
                     s += 0.5 * (Li * Ui + Lp * Up);
                 }
                 if (k >= 1) {
-                    const double L = KV(k - 1, 0, 0) / g.dz[k - 1] - KV(k, 0, 0) / g.dz[k];
+                    const double L = KV(k - 1, 0, 0) * g.idz[k - 1] - KV(k, 0, 0) * g.idz[k];
                     s += 0.5 * L * 0.5 * (Wf(k, 0, 0) + Wf(k, -1, 0));
                 }
                 if (k + 1 <= nz - 1) {
-                    const double L = KV(k, 0, 0) / g.dz[k] - KV(k + 1, 0, 0) / g.dz[k + 1];
+                    const double L = KV(k, 0, 0) * g.idz[k] - KV(k + 1, 0, 0) * g.idz[k + 1];
                     s += 0.5 * L * 0.5 * (Wf(k + 1, 0, 0) + Wf(k + 1, -1, 0));
                 }
                 // u-eq, y faces at (x-faces i and i+1, y-face j): V = avg of v over x
@@ -488,7 +488,7 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
                 }
                 for (int kf = k; kf <= k + 1; ++kf) {
                     if (kf < 1 || kf > nz - 1) continue;
-                    const double wt = g.dz[k] / (2.0 * g.dzc[kf]);
+                    const double wt = g.dz[k] * (0.5 * g.o[kf]);
                     const double Lw = (KW(kf, -1, 0) - KW(kf, 0, 0)) * idy, Qw = 0.5 * (Wf(kf, -1, 0) + Wf(kf, 0, 0));
                     const double Lt = (KT(kf, -1, 0) - KT(kf, 0, 0)) * idy, Qt = 0.5 * (Tf(kf, -1, 0) + Tf(kf, 0, 0));
                     s += wt * (Lw * Qw + Lt * Qt);
@@ -498,9 +498,9 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
                              ((LV(k, 0, 1) - 2.0 * lc + LV(k, 0, -1)) * idx2 +
                               (LV(k, 1, 0) - 2.0 * lc + LV(k, -1, 0)) * idy2);
                 {
-                    const double mc = lc / g.dz[k];
-                    const double fb = (k > 0) ? (mc - LV(k - 1, 0, 0) / g.dz[k - 1]) / g.dzw[k] : mc / g.dzw[0];
-                    const double ft = (k + 1 < nz) ? (LV(k + 1, 0, 0) / g.dz[k + 1] - mc) / g.dzw[k + 1] : -mc / g.dzw[nz];
+                    const double mc = lc * g.idz[k];
+                    const double fb = (k > 0) ? (mc - LV(k - 1, 0, 0) * g.idz[k - 1]) * g.idzw[k] : mc * g.idzw[0];
+                    const double ft = (k + 1 < nz) ? (LV(k + 1, 0, 0) * g.idz[k + 1] - mc) * g.idzw[k + 1] : -mc * g.idzw[nz];
                     lin += a.alp * a.nu * (ft - fb);
                 }
                 a.gv[id] = dd[1] + s + a.dt * lin;
@@ -508,8 +508,8 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
             // ================= g_p at (k, j, i):  -dt alpha G^T lambda =================
             {
                 double gt = (LU(k, 0, 0) - LU(k, 0, 1)) * idx + (LV(k, 0, 0) - LV(k, 1, 0)) * idy;
-                if (k >= 1) gt += LW(k, 0, 0) / g.dzc[k];
-                if (k + 1 <= nz - 1) gt -= LW(k + 1, 0, 0) / g.dzc[k + 1];
+                if (k >= 1) gt += LW(k, 0, 0) * g.o[k];
+                if (k + 1 <= nz - 1) gt -= LW(k + 1, 0, 0) * g.o[k + 1];
                 a.gp[id] = dd[4] - a.dt * a.alp * gt;
             }
             // ================= g_w, g_T at z-face k (interior) =================
@@ -546,14 +546,14 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
                 }
                 // u-eq z faces at (x-faces i, i+1; z-face k): W = avg of w over x, Q = avg of u over z
                 {
-                    const double L0 = KU(k - 1, 0, 0) / g.dz[k - 1] - KU(k, 0, 0) / g.dz[k];
-                    const double L1 = KU(k - 1, 0, 1) / g.dz[k - 1] - KU(k, 0, 1) / g.dz[k];
+                    const double L0 = KU(k - 1, 0, 0) * g.idz[k - 1] - KU(k, 0, 0) * g.idz[k];
+                    const double L1 = KU(k - 1, 0, 1) * g.idz[k - 1] - KU(k, 0, 1) * g.idz[k];
                     sw += 0.5 * (L0 * 0.5 * (U(k - 1, 0, 0) + U(k, 0, 0)) + L1 * 0.5 * (U(k - 1, 0, 1) + U(k, 0, 1)));
                 }
                 // v-eq z faces at (y-faces j, j+1; z-face k)
                 {
-                    const double L0 = KV(k - 1, 0, 0) / g.dz[k - 1] - KV(k, 0, 0) / g.dz[k];
-                    const double L1 = KV(k - 1, 1, 0) / g.dz[k - 1] - KV(k, 1, 0) / g.dz[k];
+                    const double L0 = KV(k - 1, 0, 0) * g.idz[k - 1] - KV(k, 0, 0) * g.idz[k];
+                    const double L1 = KV(k - 1, 1, 0) * g.idz[k - 1] - KV(k, 1, 0) * g.idz[k];
                     sw += 0.5 * (L0 * 0.5 * (V(k - 1, 0, 0) + V(k, 0, 0)) + L1 * 0.5 * (V(k - 1, 1, 0) + V(k, 1, 0)));
                 }
                 // linear terms
@@ -570,8 +570,8 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
                                  mwp = LW(k + 1, 0, 0) * idzc(k + 1);
                     const double mt = ltc * idzc(k), mtm = LT(k - 1, 0, 0) * idzc(k - 1),
                                  mtp = LT(k + 1, 0, 0) * idzc(k + 1);
-                    linw += a.alp * a.nu * ((mwp - mw) / g.dz[k] - (mw - mwm) / g.dz[k - 1]);
-                    lint += a.alp * a.ka * ((mtp - mt) / g.dz[k] - (mt - mtm) / g.dz[k - 1]);
+                    linw += a.alp * a.nu * ((mwp - mw) * g.idz[k] - (mw - mwm) * g.idz[k - 1]);
+                    lint += a.alp * a.ka * ((mtp - mt) * g.idz[k] - (mt - mtm) * g.idz[k - 1]);
                 }
                 a.gw[id] = dd[2] + sw + a.dt * linw;
                 a.gt[id] = dd[3] + st + a.dt * lint + a.dt * a.gam * lwc;   // buoyancy +T in the w equation

@@ -356,18 +356,27 @@ k_zsolve_scan(cx<T>* __restrict__ b, const T* __restrict__ etab, int nz, int ny,
 // the other half of a double LDS buffer by global->LDS copies (1 KB per wave
 // instruction), so every CU keeps a tile of loads in flight through the solve.  The
 // scans' barriers are LDS-only so that they do not wait for those copies.
-// Measured at 1024^2 x 512: FP32 z solve 1.36 -> 1.05 ms; in FP64 the solve work of
-// one block per CU is the limit (1.93 -> 1.98 ms), so the register-tile kernel stays.
+// Measured at 1024^2 x 512: FP32 z solve 1.36 -> 1.03 ms; in FP64 the solve work of
+// the streaming blocks is the limit (1.92 ms register-tile kernel against 1.98 ms with a
+// double buffer and 2.14 ms with one buffer and two blocks per CU), so it is not used there.
 #ifndef PS_Z_PIPE32
 #define PS_Z_PIPE32 1
 #endif
 #ifndef PS_Z_PIPE64
 #define PS_Z_PIPE64 0
 #endif
+// tiles held in LDS per block: 2 (double buffer, one block per CU at nz = 512) or 1
+// (refilled once the tile is in registers, two blocks per CU)
+#ifndef PS_Z_PIPE_NBUF64
+#define PS_Z_PIPE_NBUF64 1
+#endif
+#ifndef PS_Z_PIPE_NBUF32
+#define PS_Z_PIPE_NBUF32 2
+#endif
 typedef __attribute__((address_space(3))) unsigned char lds_u8;
 constexpr int kZPipeMaxNz = 512;
 
-template <typename T, int K, int MAXT>
+template <typename T, int K, int MAXT, int NBUF>
 __global__ void __launch_bounds__(MAXT)
 k_zsolve_pipe(cx<T>* __restrict__ b, const T* __restrict__ etab, int nz, int ny, int nxh, int ntiles,
               const double* __restrict__ dz, const double* __restrict__ o, const double* __restrict__ lamx,
@@ -378,7 +387,7 @@ k_zsolve_pipe(cx<T>* __restrict__ b, const T* __restrict__ etab, int nz, int ny,
     // grid metrics in LDS (nz <= kZPipeMaxNz): the solve then issues no global loads of its
     // own, which would have to wait behind the copies of the next tile
     __shared__ double zdz[kZPipeMaxNz], zo[kZPipeMaxNz + 1];
-    cx<T>* buf = reinterpret_cast<cx<T>*>(zsm);   // [2][nz * W]
+    cx<T>* buf = reinterpret_cast<cx<T>*>(zsm);   // [NBUF][nz * W]
     for (int q = threadIdx.x; q <= nz; q += blockDim.x) {
         zo[q] = o[q];
         if (q < nz) zdz[q] = dz[q];
@@ -399,7 +408,7 @@ k_zsolve_pipe(cx<T>* __restrict__ b, const T* __restrict__ etab, int nz, int ny,
     int t = blockIdx.x;
     if (t < ntiles) copy_tile(t, 0);
     for (int it = 0; t < ntiles; ++it, t += gridDim.x) {
-        const int sel = it & 1;
+        const int sel = NBUF == 2 ? (it & 1) : 0;
         __builtin_amdgcn_s_waitcnt(0);   // this wave's copies (and stores) are done
         __syncthreads();                 // ... and every other wave's
         const int ky = t % ny, kxb = t / ny, kx = kxb * W + c;
@@ -417,8 +426,10 @@ k_zsolve_pipe(cx<T>* __restrict__ b, const T* __restrict__ etab, int nz, int ny,
         // this tile's global loads complete before the copies are issued (the counter
         // that tracks them is in order)
         asm volatile("" ::"v"(lam), "v"(eprev));
-        // the next tile streams into the other buffer while this one is solved
-        if (t + (int)gridDim.x < ntiles) copy_tile(t + gridDim.x, sel ^ 1);
+        // one buffer: every wave has its values in registers before the buffer is refilled
+        if (NBUF == 1) __syncthreads();
+        // the next tile streams into the (other) buffer while this one is solved
+        if (t + (int)gridDim.x < ntiles) copy_tile(t + gridDim.x, NBUF == 2 ? sel ^ 1 : 0);
         zscan_solve<T, K, WZ, true>(v, eprev, lam, k0, nz, c, wave, nwave, lw, xs, zdz, zo);
         if (store) {
             cx<T>* tile = b + (size_t)t * telems + c;
@@ -567,7 +578,8 @@ static hipError_t zpipe_launch(const GridDev& g, const SpecDev<T>& s, hipStream_
     const size_t tbytes = (size_t)g.nz * W * sizeof(cx<T>);
     const int threads = zscan_threads<K, W>(g.nz);
     constexpr bool enabled = sizeof(T) == 4 ? PS_Z_PIPE32 : PS_Z_PIPE64;
-    if (!enabled || g.nz > kZPipeMaxNz || tbytes % 1024 != 0 || 2 * tbytes > 131072 || threads > 1024 || !s.etab)
+    constexpr int NBUF = sizeof(T) == 4 ? PS_Z_PIPE_NBUF32 : PS_Z_PIPE_NBUF64;
+    if (!enabled || g.nz > kZPipeMaxNz || tbytes % 1024 != 0 || NBUF * tbytes > 131072 || threads > 1024 || !s.etab)
         return hipSuccess;
     static int ncu = 0;
     if (ncu == 0) {
@@ -576,10 +588,10 @@ static hipError_t zpipe_launch(const GridDev& g, const SpecDev<T>& s, hipStream_
             ncu = 256;
     }
     const int ntiles = s.nkxb * g.ny;
-    const int nblk = std::min(ntiles, ncu);
+    const int nblk = std::min(ntiles, ncu * (NBUF == 1 ? 2 : 1));
     const int nxh = g.nx / 2 + 1;
 #define PS_ZPIPE(MAXT)                                                                                           \
-    hipLaunchKernelGGL((k_zsolve_pipe<T, K, MAXT>), dim3(nblk), dim3(threads), 2 * tbytes, st, s.b, s.etab, g.nz, \
+    hipLaunchKernelGGL((k_zsolve_pipe<T, K, MAXT, NBUF>), dim3(nblk), dim3(threads), NBUF * tbytes, st, s.b, s.etab, g.nz, \
                        g.ny, nxh, ntiles, g.dz, g.o, g.lamx, g.lamy)
     if (threads <= 256)
         PS_ZPIPE(256);
