@@ -200,9 +200,10 @@ k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny,
                                                                  (size_t)(yr + 1 == ny ? 0 : yr + 1) * n + 2 * e);
             const double2 wc = *reinterpret_cast<const double2*>(rin.w + rb + 2 * e);
             const double2 wp = *reinterpret_cast<const double2*>(rin.w + rb + plane + 2 * e);
-            const double dzk = dz[zl];
-            v.x = rin.div_scale * ((uc.y - uc.x) / g.dx + (vp.x - vc.x) / g.dy + (wp.x - wc.x) / dzk);
-            v.y = rin.div_scale * ((ur - uc.y) / g.dx + (vp.y - vc.y) / g.dy + (wp.y - wc.y) / dzk);
+            // the same arithmetic as the stored-divergence kernel (reciprocal multiplies)
+            const double idx = 1.0 / g.dx, idy = 1.0 / g.dy, idzk = g.idz[zg];
+            v.x = rin.div_scale * ((uc.y - uc.x) * idx + (vp.x - vc.x) * idy + (wp.x - wc.x) * idzk);
+            v.y = rin.div_scale * ((ur - uc.y) * idx + (vp.y - vc.y) * idy + (wp.y - wc.y) * idzk);
             acc0 += v.x + v.y;
         } else {
             v.x *= zs;
@@ -445,6 +446,7 @@ static hipError_t xfwd_launch_t(const GridDev& g, const SpecDev<T>& s, const dou
     }
     if (mode == XL_DIV) {
         ResidIn r = *rin;
+        r.z0 = s.z0;
         r.u += zoff;
         r.v += zoff;
         r.w += zoff;

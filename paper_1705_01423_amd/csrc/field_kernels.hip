@@ -25,9 +25,10 @@ k_divergence(const double* __restrict__ u, const double* __restrict__ v, const d
     const int ip = (i + 1 == g.nx) ? 0 : i + 1;
     const int jp = (j + 1 == g.ny) ? 0 : j + 1;
     const size_t rowb = (size_t)k * plane + (size_t)j * g.nx;
-    const double du = (u[rowb + ip] - u[id]) / g.dx;
-    const double dv = (v[(size_t)k * plane + (size_t)jp * g.nx + i] - v[id]) / g.dy;
-    const double dw = (w[id + plane] - w[id]) / g.dz[k];
+    const double idx = 1.0 / g.dx, idy = 1.0 / g.dy;
+    const double du = (u[rowb + ip] - u[id]) * idx;
+    const double dv = (v[(size_t)k * plane + (size_t)jp * g.nx + i] - v[id]) * idy;
+    const double dw = (w[id + plane] - w[id]) * g.idz[k];
     f[id] = scale * (du + dv + dw);
 }
 
@@ -45,17 +46,17 @@ k_project_update(double* __restrict__ u, double* __restrict__ v, double* __restr
     const double pc = phi[id];
     const double pim = phi[(size_t)k * plane + (size_t)j * g.nx + im];
     const double pjm = phi[(size_t)k * plane + (size_t)jm * g.nx + i];
-    u[id] -= s * ((pc - pim) / g.dx);
-    v[id] -= s * ((pc - pjm) / g.dy);
+    u[id] -= s * ((pc - pim) * (1.0 / g.dx));
+    v[id] -= s * ((pc - pjm) * (1.0 / g.dy));
     double fm = 0.0, fp = 0.0;
     if (k > 0) {
         const double pkm = phi[id - plane];
-        const double gw = (pc - pkm) / g.dzc[k];
+        const double gw = (pc - pkm) * g.o[k];   // o = 1/dzc at interior faces
         w[id] -= s * gw;
         fm = (pc - pkm) * g.o[k];
     }
     if (k + 1 < g.nz) fp = (phi[id + plane] - pc) * g.o[k + 1];
-    if (p) p[id] += pc - c * ((fp - fm) / g.dz[k]);
+    if (p) p[id] += pc - c * ((fp - fm) * g.idz[k]);
 }
 
 // out[blockIdx.x * ncomp + c] = sum of partial[b * ncomp + c] over the block's contiguous

@@ -152,6 +152,22 @@ struct ZCols {
     static constexpr int value = sizeof(T) == 8 ? PS_Z_COLS64 : PS_Z_COLS32;
 };
 
+// 1/x for the positive, normal pivots of the excess elimination: the hardware
+// reciprocal refined by Newton steps (two in FP64, one in FP32; within an ulp of the
+// quotient) in place of the full IEEE division, which sits on the dependent chain of
+// the pivots.
+__device__ __forceinline__ double pivot_rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float pivot_rcp(float x) {
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
 // Barrier of the scans: __syncthreads, or (RAW) an LDS-only barrier (this wave's LDS
 // accesses complete, then s_barrier) that leaves outstanding global->LDS copies in flight.
 template <bool RAW>
@@ -191,11 +207,11 @@ __device__ __forceinline__ void zscan_solve(cx<T> (&v)[K], T eprev, T lam, int k
                 e = s;
             } else {
                 const T ok = (T)oc[k];
-                const T mm = (i == 0) ? ok / (ok + eprev) : ok * rp[i - 1];
+                const T mm = (i == 0) ? ok * pivot_rcp(ok + eprev) : ok * rp[i - 1];
                 if (i == 0) m0 = mm;
                 e = s + mm * eprev;
             }
-            rp[i] = (T)1 / ((T)oc[k + 1] + e);
+            rp[i] = pivot_rcp((T)oc[k + 1] + e);
             eprev = e;
             const T g = -(T)dz[k];
             v[i] = {g * v[i].x, g * v[i].y};   // g_k = -dz_k F_k
