@@ -68,3 +68,16 @@ def test_null_plan_rejected():
     st = lib.poisson_solve(None, ctypes.c_void_p(16), ctypes.c_void_p(32), None, None)
     assert st == _lib.PS_EINVAL
     assert lib.poisson_plan_destroy(None) == _lib.PS_OK
+
+
+def test_null_plan_rejected_by_every_entry_point():
+    """Every field entry point validates the plan before touching the device."""
+    lib = _lib.load()
+    d = ctypes.c_void_p(256)
+    st = lib.rk3_step(None, 0.0, 1.3, 1.0, 1e-3, 1e-3, d, d, d, d, d, None, None, None)
+    assert st == _lib.PS_EINVAL
+    assert lib.ps_heat_flux(None, d, d, 1e-3, d, d, None) == _lib.PS_EINVAL
+    assert lib.project(None, d, d, d, d, None, 1.0, 0.0, None, None) == _lib.PS_EINVAL
+    assert lib.cn_solve(None, 0, 1e-3, d, None) == _lib.PS_EINVAL
+    assert lib.ps_cfl(None, d, d, d, d, None) == _lib.PS_EINVAL
+    assert "plan" in lib.ps_last_error().decode()

@@ -202,7 +202,7 @@ def test_substep_parity(l, prec, tol):
         assert rel(a, b) < 1e-13
 
 
-@pytest.mark.parametrize("shape", [(384, 12, 6), (48, 24, 20), (96, 6, 9)])
+@pytest.mark.parametrize("shape", [(384, 12, 6), (48, 24, 20), (96, 6, 9), (4, 2, 2), (8, 3, 3)])
 def test_substep_shapes(shape):
     """Rows longer than one stencil block (ragged x segments) and ragged y tiles."""
     nx, ny, nz = shape
@@ -220,7 +220,7 @@ def test_substep_shapes(shape):
         assert rel(a, b) < 1e-13
 
 
-@pytest.mark.parametrize("shape", [(12, 12, 8), (384, 6, 5)])
+@pytest.mark.parametrize("shape", [(12, 12, 8), (384, 6, 5), (4, 2, 3)])
 def test_substep_adjoint_shapes(shape):
     nx, ny, nz = shape
     banner(f"substep adjoint shape {shape}")

@@ -22,7 +22,7 @@ def _rb(nx, ny, nz, seed=31, unoise=0.05, lx=1.0, ly=1.0):
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32_refined", 1e-10)])
-@pytest.mark.parametrize("shape", [(16, 12, 10), (96, 24, 20)])
+@pytest.mark.parametrize("shape", [(16, 12, 10), (96, 24, 20), (4, 2, 2)])
 def test_step_parity(shape, prec, tol):
     nx, ny, nz = shape
     banner(f"rk3 step {shape} {prec}")
@@ -90,6 +90,23 @@ def test_heat_flux_parity(shape):
     mt, f = plan.heat_flux(w.to("cuda"), t.to("cuda"), kappa)
     assert float((mt.cpu() - rt).abs().max()) < 1e-14
     assert rel(f, rf) < 1e-12
+
+
+def test_step_sequence():
+    """Five Courant-limited steps in a row: the time step follows the evolving state."""
+    nx, ny, nz = 24, 16, 12
+    g, plan = grids(nx, ny, nz)
+    state = _rb(nx, ny, nz, unoise=0.3, seed=41)
+    nu, ka = 1e-2, 1e-2
+    ref = list(state)
+    dstate = [a.clone().to("cuda") for a in state]
+    for n in range(5):
+        dt = ts.cfl_dt(ref[0], ref[1], ref[2], g, 1.2)
+        ref = list(ts.rk3_step(ref, g, dt, nu, ka))
+        used, _ = plan.step(nu, ka, *dstate, dt=0.0, cfl=1.2)
+        assert abs(used - dt) <= 1e-12 * dt, n
+    for name, a, b in zip("uvwTp", dstate, ref):
+        assert rel(a, b) < 1e-11, name
 
 
 def test_heat_flux_conduction():
