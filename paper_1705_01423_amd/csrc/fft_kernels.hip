@@ -26,7 +26,7 @@ namespace ps {
 #define PS_X_EMAX64 8
 #endif
 #ifndef PS_X_EMAX32
-#define PS_X_EMAX32 16
+#define PS_X_EMAX32 8
 #endif
 #ifndef PS_Y_EMAX
 #define PS_Y_EMAX 16
@@ -55,8 +55,10 @@ constexpr int kYEmax = PS_Y_EMAX;
 #ifndef PS_X_LDS
 #define PS_X_LDS 72000
 #endif
+// up to 1024 threads: FP32 tiles (16 columns) then run whole per block; FP64 tiles are
+// limited to 8 columns (512 threads) by the LDS budget either way
 #ifndef PS_Y_THREADS
-#define PS_Y_THREADS 512
+#define PS_Y_THREADS 1024
 #endif
 #ifndef PS_Y_LDS
 #define PS_Y_LDS 140000
