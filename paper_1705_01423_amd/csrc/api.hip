@@ -74,6 +74,7 @@ struct ps_plan_s {
     size_t ws_bytes = 0;
     bool ws_owned = false;
     int w_tile, nkxb;
+    int ncu = 0;          // compute units of the device
     size_t spec_elems;
     // carved pointers
     void* spec_a;
@@ -127,6 +128,7 @@ SpecDev<double> spec_of<double>(ps_plan_t p) {
     s.b = (cx<double>*)p->spec_b;
     s.piv = (double*)p->piv;
     s.etab = (const double*)p->d_etab;
+    s.ncu = p->ncu;
     return s;
 }
 
@@ -142,6 +144,7 @@ SpecDev<float> spec_of<float>(ps_plan_t p) {
     s.b = (cx<float>*)p->spec_b;
     s.piv = (float*)p->piv;
     s.etab = (const float*)p->d_etab;
+    s.ncu = p->ncu;
     return s;
 }
 
@@ -511,6 +514,8 @@ ps_status poisson_plan_create(ps_plan_t* out, int nx, int ny, int nz, double lx,
         delete p;
         return fail(PS_EDEVICE, "no HIP device");
     }
+    if (hipDeviceGetAttribute(&p->ncu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess)
+        p->ncu = 0;
     ps_status s = upload_tables(p);
     if (s != PS_OK) {
         poisson_plan_destroy(p);

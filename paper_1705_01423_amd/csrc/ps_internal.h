@@ -156,6 +156,7 @@ struct SpecDev {
     const T* etab = nullptr;  // pivot excess entering each lane chunk of the tiled z solve
     // Plane range of the x / y stages: planes [z0, z0 + nzc) (nzc = 0: all).  Buffer a
     // is then indexed relative to z0 (it may hold just those planes); b stays absolute.
+    int ncu = 0;              // compute units of the plan's device (persistent launches)
     int z0 = 0;
     int nzc = 0;
 };

@@ -597,12 +597,7 @@ static hipError_t zpipe_launch(const GridDev& g, const SpecDev<T>& s, hipStream_
     constexpr int NBUF = sizeof(T) == 4 ? PS_Z_PIPE_NBUF32 : PS_Z_PIPE_NBUF64;
     if (!enabled || g.nz > kZPipeMaxNz || tbytes % 1024 != 0 || NBUF * tbytes > 131072 || threads > 1024 || !s.etab)
         return hipSuccess;
-    static int ncu = 0;
-    if (ncu == 0) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
-            ncu = 256;
-    }
+    const int ncu = s.ncu > 0 ? s.ncu : 256;
     const int ntiles = s.nkxb * g.ny;
     const int nblk = std::min(ntiles, ncu * (NBUF == 1 ? 2 : 1));
     const int nxh = g.nx / 2 + 1;
