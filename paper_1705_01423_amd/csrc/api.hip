@@ -2,6 +2,7 @@
 // Kernels live in fft_kernels.hip, zsolve_kernels.hip, field_kernels.hip and
 // substep_kernels.hip; this file validates arguments and sequences launches.
 #include <algorithm>
+#include <utility>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -334,8 +335,18 @@ ps_status spectral_solve(ps_plan_t p, const double* in, double* out, int mode, c
     }
     if (resid_x) PS_HIP(launch_reduce2(p->partial, nbx, 2, p->red_scratch, p->small + R_R2, st), "reduce");
     if (want_wsum) PS_HIP(launch_reduce2(p->partial, nbx, 1, p->red_scratch, p->small + R_WSUM, st), "reduce");
-    PS_HIP(launch_zsolve<T>(g, s, st), "z solve");
-    PS_HIP(launch_zsolve00<T>(g, s, p->small + R_DEFECT, st), "z solve (0,0)");
+    // Without plane chunks buffer a holds a whole spectrum: the z solve may then write
+    // into it (b layout), and the inverse stages run with the two buffers' roles swapped.
+    if (P == g.nz && zsolve_out_of_place<T>(g)) {
+        SpecDev<T> sz = s;
+        sz.bz = s.a;
+        PS_HIP(launch_zsolve<T>(g, sz, st), "z solve");
+        PS_HIP(launch_zsolve00<T>(g, sz, p->small + R_DEFECT, st), "z solve (0,0)");
+        std::swap(s.a, s.b);
+    } else {
+        PS_HIP(launch_zsolve<T>(g, s, st), "z solve");
+        PS_HIP(launch_zsolve00<T>(g, s, p->small + R_DEFECT, st), "z solve (0,0)");
+    }
     int nbi = 0;   // x-inverse blocks so far
     for (int z0 = 0; z0 < g.nz; z0 += P) {
         GridDev gc;

@@ -154,6 +154,7 @@ struct SpecDev {
     cx<T>* b;                 // [nkxb][ny][nz][W]
     T* piv;                   // z-solve pivots, same layout as b (real); tall columns only
     const T* etab = nullptr;  // pivot excess entering each lane chunk of the tiled z solve
+    cx<T>* bz = nullptr;      // z solve output in the b layout (nullptr: in place in b)
     // Plane range of the x / y stages: planes [z0, z0 + nzc) (nzc = 0: all).  Buffer a
     // is then indexed relative to z0 (it may hold just those planes); b stays absolute.
     int ncu = 0;              // compute units of the plan's device (persistent launches)
@@ -192,6 +193,9 @@ int xinv_blocks(const GridDev& g);
 // z solves on buffer b (all columns except (0,0)), then the (0,0) column.
 template <typename T>
 hipError_t launch_zsolve(const GridDev& g, const SpecDev<T>& s, hipStream_t st);
+// whether launch_zsolve can write its result to SpecDev::bz instead of in place
+template <typename T>
+bool zsolve_out_of_place(const GridDev& g);
 // The tiled z solve (columns of up to 1024 rows) starts each lane's chunk of rows from the
 // pivot excess of the row above it.  The excesses depend only on the grid and the
 // wavenumbers, so they are formed once per plan (sequential FP64 recurrence per column) into
