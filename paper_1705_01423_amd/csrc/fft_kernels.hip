@@ -118,8 +118,18 @@ struct ResidIn {
     double div_scale;
 };
 
+// Minimum waves per SIMD of the x transforms (register caps; 1: none).
+#ifndef PS_XF_WPE
+#define PS_XF_WPE 1
+#endif
+#ifndef PS_XR_WPE
+#define PS_XR_WPE 1
+#endif
+#ifndef PS_XI_WPE
+#define PS_XI_WPE 1
+#endif
 template <typename T, int M, int LM>
-__global__ void __launch_bounds__((XShape<T, M>::THREADS))
+__global__ void __launch_bounds__((XShape<T, M>::THREADS), (LM == XL_RESID ? PS_XR_WPE : PS_XF_WPE))
 k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny, int nkxb,
        const cx<T>* __restrict__ tw, const cx<T>* __restrict__ ptw, const double* __restrict__ scale_z,
        const double* __restrict__ dz, double* __restrict__ partial, ResidIn rin, GridDev g) {
@@ -145,14 +155,18 @@ k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny,
             row0 = zz * ny + (yt * kYT + yi) * R;
         }
     }
-    const int row = row0 + rl;
-    const bool valid = row < nrows;
+    const int row_u = row0 + rl;
+    const bool valid = row_u < nrows;
+    // Rows past the end (a partial last block) read the last row and contribute zeros:
+    // every load is unconditional, so a thread's loads are all in flight together
+    // (a load under a branch would be waited for before the next one is issued).
+    const int row = valid ? row_u : nrows - 1;
     const double* frow = f + (size_t)row * (2 * M);
-    const double zs = (valid && scale_z) ? scale_z[row / ny] : 1.0;
+    const double zs = scale_z ? scale_z[row / ny] : 1.0;
     cx<T>* lrow = smem + rl * LROW;
     double acc0 = 0.0, acc1 = 0.0;
     // residual mode: row (z, y) of the whole box and its neighbours
-    const int zl = valid ? row / ny : 0;
+    const int zl = row / ny;
     const int zg = rin.z0 + zl;
     const int yr = row - zl * ny;
     const size_t plane = (size_t)ny * (2 * M);
@@ -162,35 +176,42 @@ k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny,
     const double* xjp = RESID ? rin.x + (size_t)zg * plane + (size_t)(yr + 1 == ny ? 0 : yr + 1) * (2 * M) : nullptr;
     const double mu = RESID ? rin.mu[0] * rin.mu_scale : 0.0;
     auto ld = [&](int e) -> cx<T> {
-        if (!valid) return cx<T>{(T)0, (T)0};
         double2 v = {0.0, 0.0};
         if constexpr (LM != XL_DIV) v = ld_stream2<PS_NT_XF>(frow + 2 * e);
         if constexpr (RESID) {
             const int n = 2 * M;
             const double2 c = *reinterpret_cast<const double2*>(xrow + 2 * e);
-            const double xl = xrow[e == 0 ? n - 1 : 2 * e - 1];
-            const double xr = xrow[2 * e + 2 == n ? 0 : 2 * e + 2];
+            // periodic x neighbours and the z neighbours (the row itself stands in for a
+            // missing one; its term is dropped), addressed by index arithmetic so that every
+            // load is unconditional
+            const int il = 2 * e - 1 + (int)(e == 0) * n;
+            const int ir = 2 * e + 2 - (int)(2 * e + 2 == n) * n;
+            const double xl = xrow[il];
+            const double xr = xrow[ir];
             const double2 a = *reinterpret_cast<const double2*>(xjm + 2 * e);
             const double2 b = *reinterpret_cast<const double2*>(xjp + 2 * e);
+            const bool up = zg + 1 < g.nz, dn = zg > 0;
+            const double2 qu = *reinterpret_cast<const double2*>(xrow + (size_t)up * plane + 2 * e);
+            const double2 qd = *reinterpret_cast<const double2*>(xrow - (size_t)dn * plane + 2 * e);
+            // a missing neighbour's coefficient is zero (its difference is zero too), so the
+            // sums are those of the present terms alone
+            const double ou = up ? g.o[zg + 1] : 0.0, od = dn ? g.o[zg] : 0.0, iz = g.idz[zg];
             const double idx2 = 1.0 / (g.dx * g.dx), idy2 = 1.0 / (g.dy * g.dy);
             double lz0 = 0.0, lz1 = 0.0;
-            if (zg + 1 < g.nz) {
-                const double2 q = *reinterpret_cast<const double2*>(xrow + plane + 2 * e);
-                lz0 += (q.x - c.x) * g.o[zg + 1];
-                lz1 += (q.y - c.y) * g.o[zg + 1];
-            }
-            if (zg > 0) {
-                const double2 q = *reinterpret_cast<const double2*>(xrow - plane + 2 * e);
-                lz0 -= (c.x - q.x) * g.o[zg];
-                lz1 -= (c.y - q.y) * g.o[zg];
-            }
-            const double l0 = ((c.y - c.x) - (c.x - xl)) * idx2 + ((b.x - c.x) - (c.x - a.x)) * idy2 + lz0 * g.idz[zg];
-            const double l1 = ((xr - c.y) - (c.y - c.x)) * idx2 + ((b.y - c.y) - (c.y - a.y)) * idy2 + lz1 * g.idz[zg];
+            lz0 += (qu.x - c.x) * ou;
+            lz1 += (qu.y - c.y) * ou;
+            lz0 -= (c.x - qd.x) * od;
+            lz1 -= (c.y - qd.y) * od;
+            const double l0 = ((c.y - c.x) - (c.x - xl)) * idx2 + ((b.x - c.x) - (c.x - a.x)) * idy2 + lz0 * iz;
+            const double l1 = ((xr - c.y) - (c.y - c.x)) * idx2 + ((b.y - c.y) - (c.y - a.y)) * idy2 + lz1 * iz;
             const double f0 = v.x - mu, f1 = v.y - mu;
-            v.x = f0 - l0;
-            v.y = f1 - l1;
+            v.x = valid ? f0 - l0 : 0.0;
+            v.y = valid ? f1 - l1 : 0.0;
             acc0 += v.x * v.x + v.y * v.y;
-            acc1 += f0 * f0 + f1 * f1;
+            acc1 += valid ? f0 * f0 + f1 * f1 : 0.0;
+            // each element's value is formed here, in order: otherwise the loads of every
+            // element's stencil are hoisted together and held in registers (one wave per SIMD)
+            asm volatile("" : "+v"(v.x), "+v"(v.y));
         } else if constexpr (LM == XL_DIV) {
             // f = (D u*) / s at the cells (2e, 2e + 1) of row (z, y): periodic x and y, w at z-faces
             const int n = 2 * M;
@@ -206,10 +227,12 @@ k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny,
             const double idx = 1.0 / g.dx, idy = 1.0 / g.dy, idzk = g.idz[zg];
             v.x = rin.div_scale * ((uc.y - uc.x) * idx + (vp.x - vc.x) * idy + (wp.x - wc.x) * idzk);
             v.y = rin.div_scale * ((ur - uc.y) * idx + (vp.y - vc.y) * idy + (wp.y - wc.y) * idzk);
+            v.x = valid ? v.x : 0.0;   // selects, not branches: the loads stay unconditional
+            v.y = valid ? v.y : 0.0;
             acc0 += v.x + v.y;
         } else {
-            v.x *= zs;
-            v.y *= zs;
+            v.x = valid ? v.x * zs : 0.0;
+            v.y = valid ? v.y * zs : 0.0;
             acc0 += v.x + v.y;
         }
         return cx<T>{(T)v.x, (T)v.y};
@@ -217,56 +240,58 @@ k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny,
     auto st = [&](int e, cx<T> val) { lrow[lds_pad(e)] = val; };
     fft_run<T, M, X::EM, -1>(t, lrow, 1, tw, ld, st);
     __syncthreads();
-    const int ntot = nkxb * R * W;
+    // r2c unpack of the R rows into (kx tile, row) order: nkxb = (M + W) / W tiles of W
+    // (kx > M are padding).  Fully unrolled, with the twiddle loads unconditional
+    // (clamped index), so that they are all in flight together.
+    constexpr int NTOT = ((M + W) / W) * R * W;
+    constexpr int NIT = (NTOT + X::THREADS - 1) / X::THREADS;
     const int z0 = row0 / ny, y0 = row0 - z0 * ny;
-    for (int q = tid; q < ntot; q += X::THREADS) {
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int q = tid + it * X::THREADS;
         const int w = q % W;
         const int r2 = (q / W) % R;
         const int kxb = q / (W * R);
         const int row2 = row0 + r2;
-        if (row2 >= nrows) continue;
         const int kx = kxb * W + w;
         const cx<T>* zr = smem + r2 * LROW;
-        cx<T> xv;
-        if (kx == 0) {
-            cx<T> z0 = zr[0];
-            xv = {z0.x + z0.y, (T)0};
-        } else if (kx == M) {
-            cx<T> z0 = zr[0];
-            xv = {z0.x - z0.y, (T)0};
-        } else if (kx > M) {
-            xv = {(T)0, (T)0};
-        } else {
-            cx<T> a = zr[lds_pad(kx)];
-            cx<T> b = conjg(zr[lds_pad(M - kx)]);
-            cx<T> fe = scal(a + b, (T)0.5);
-            cx<T> d = a - b;
-            cx<T> fo = {(T)0.5 * d.y, -(T)0.5 * d.x};
-            xv = fe + cmul(ptw[kx], fo);
-        }
+        const int kg = min(max(kx, 1), M - 1);   // general case index, clamped into range
+        const cx<T> tw_k = ptw[kg];
+        const cx<T> a = zr[lds_pad(kg)];
+        const cx<T> b = conjg(zr[lds_pad(M - kg)]);
+        const cx<T> zz = zr[0];
+        const cx<T> fe = scal(a + b, (T)0.5);
+        const cx<T> d = a - b;
+        const cx<T> fo = {(T)0.5 * d.y, -(T)0.5 * d.x};
+        cx<T> xv = fe + cmul(tw_k, fo);
+        if (kx == 0) xv = {zz.x + zz.y, (T)0};
+        if (kx == M) xv = {zz.x - zz.y, (T)0};
+        if (kx > M) xv = {(T)0, (T)0};
         int z = z0, y = y0 + r2;
         if (y >= ny) {   // the block's rows cross into the next plane(s)
             z += y / ny;
             y -= (y / ny) * ny;
         }
-        st_stream<PS_NT_XF>(out + (((size_t)z * nkxb + kxb) * ny + y) * W + w, xv);
+        if (q < NTOT && row2 < nrows && kxb < nkxb)
+            st_stream<PS_NT_XF>(out + (((size_t)z * nkxb + kxb) * ny + y) * W + w, xv);
     }
     if (partial) {
         if constexpr (RESID) {
             double v[2] = {acc0, acc1};   // sum r^2, sum (f - mu)^2
             block_sum_store<2>(v, partial + 2 * blockIdx.x);
         } else {
-            double v[1] = {valid ? acc0 * dz[row / ny] : 0.0};   // sum dz f
+            double v[1] = {acc0 * dz[row / ny]};   // sum dz f (zero for rows past the end)
             block_sum_store<1>(v, partial + blockIdx.x);
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-template <typename T, int M>
-__global__ void __launch_bounds__((XShape<T, M, true>::THREADS))
+// MODE 0: out = scale * c2r(in).  MODE 1 (accumulate): out += scale * c2r(in) - mu.
+template <typename T, int M, int MODE>
+__global__ void __launch_bounds__((XShape<T, M, true>::THREADS), PS_XI_WPE)
 k_xinv(const cx<T>* __restrict__ in, double* __restrict__ out, int nrows, int ny, int nkxb,
-       const cx<T>* __restrict__ tw, const cx<T>* __restrict__ ptw, double scale, int mode,
+       const cx<T>* __restrict__ tw, const cx<T>* __restrict__ ptw, double scale,
        const double* __restrict__ mu, double mu_scale, const double* __restrict__ scale_z,
        const double* __restrict__ dz, double* __restrict__ partial) {
     using X = XShape<T, M, true>;
@@ -289,17 +314,16 @@ k_xinv(const cx<T>* __restrict__ in, double* __restrict__ out, int nrows, int ny
         const int w = q % W;
         const int r2 = (q / W) % R;
         const int kxb = q / (W * R);
-        const int row2 = row0 + r2;
-        const int kx = kxb * W + w;
-        buf[it] = cx<T>{(T)0, (T)0};
-        if (q < NTOT && row2 < nrows && kx <= M) {
-            int z = z0, y = y0 + r2;
-            if (y >= ny) {   // the block's rows cross into the next plane(s)
-                z += y / ny;
-                y -= (y / ny) * ny;
-            }
-            buf[it] = ld_stream<PS_NT_XI>(in + (((size_t)z * nkxb + kxb) * ny + y) * W + w);
+        // unconditional loads (clamped row and tile; padding columns kx > M are read and
+        // dropped), so that all of a thread's loads are in flight together
+        const int row2 = min(row0 + r2, nrows - 1);
+        const int kxc = min(kxb, nkxb - 1);
+        int z = z0, y = y0 + (row2 - row0);
+        if (y >= ny) {   // the block's rows cross into the next plane(s)
+            z += y / ny;
+            y -= (y / ny) * ny;
         }
+        buf[it] = ld_stream<PS_NT_XI>(in + (((size_t)z * nkxb + kxc) * ny + y) * W + w);
     }
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
@@ -315,11 +339,11 @@ k_xinv(const cx<T>* __restrict__ in, double* __restrict__ out, int nrows, int ny
     __syncthreads();
     const int rl = tid / NT;
     const int t = tid - rl * NT;
-    const int row = blockIdx.x * R + rl;
-    const bool valid = row < nrows;
+    const int row_u = blockIdx.x * R + rl;
+    const bool valid = row_u < nrows;
+    const int row = valid ? row_u : nrows - 1;   // rows past the end compute, store nothing
     cx<T>* lrow = smem + rl * LROW;
     auto ld = [&](int e) -> cx<T> {
-        if (!valid) return cx<T>{(T)0, (T)0};
         cx<T> xa, xb;
         if (e == 0) {
             xa = {lrow[0].x, (T)0};
@@ -334,19 +358,34 @@ k_xinv(const cx<T>* __restrict__ in, double* __restrict__ out, int nrows, int ny
         return cx<T>{a.x - bb.y, a.y + bb.x};
     };
     double* orow = out + (size_t)row * (2 * M);
-    const double sc = scale * ((valid && scale_z) ? scale_z[row / ny] : 1.0);
-    const double m0 = (mode == 1) ? mu[0] * mu_scale : 0.0;
+    const double sc = scale * (scale_z ? scale_z[row / ny] : 1.0);
+    const double m0 = MODE == 1 ? mu[0] * mu_scale : 0.0;
     double s_d2 = 0.0, s_o2 = 0.0, s_o = 0.0;
+    // MODE 1: the values being accumulated into, loaded before the transform (all in
+    // flight together) in the order in which the transform hands out its results:
+    // element t + b NT + m Ls of the last radix-r pass, b outer, m inner.
+    using Sh = FftShape<M, X::EM>;
+    constexpr int E = Sh::E, NP = Sh::NP, RL = Sh::P.r[NP - 1], LS = plan_ls(Sh::P, NP - 1);
+    double2 acc_old[MODE == 1 ? E : 1];
+    if constexpr (MODE == 1) {
+#pragma unroll
+        for (int b = 0; b < E / RL; ++b) {
+#pragma unroll
+            for (int m = 0; m < RL; ++m)
+                acc_old[b * RL + m] = *reinterpret_cast<const double2*>(orow + 2 * (t + b * Sh::NT + m * LS));
+        }
+    }
+    int sidx = 0;
     auto st = [&](int e, cx<T> val) {
-        if (!valid) return;
         double2 r = {(double)val.x * sc, (double)val.y * sc};
         double2 o;
-        if (mode == 1) {
-            double2 old = *reinterpret_cast<const double2*>(orow + 2 * e);
+        if constexpr (MODE == 1) {
+            const double2 old = acc_old[sidx++];
             o = {old.x + r.x - m0, old.y + r.y - m0};
         } else {
             o = r;
         }
+        if (!valid) return;
         st_stream2<PS_NT_XI>(orow + 2 * e, o);
         s_d2 += r.x * r.x + r.y * r.y;
         s_o2 += o.x * o.x + o.y * o.y;
@@ -354,7 +393,7 @@ k_xinv(const cx<T>* __restrict__ in, double* __restrict__ out, int nrows, int ny
     };
     fft_run<T, M, X::EM, +1>(t, lrow, 1, tw, ld, st);
     if (partial) {
-        const double dzr = valid ? dz[row / ny] : 0.0;
+        const double dzr = valid ? dz[row / ny] : 0.0;   // (row clamped: the load is in range)
         double v[3] = {s_d2, s_o2, s_o * dzr};
         block_sum_store<3>(v, partial + 3 * blockIdx.x);
     }
@@ -471,9 +510,14 @@ static hipError_t xinv_launch_t(const GridDev& g, const SpecDev<T>& s, double* o
     const size_t zoff = (size_t)s.z0 * g.nx * g.ny;
     const int nrows = g.ny * nzl;
     const int nblk = (nrows + X::R - 1) / X::R;
-    hipLaunchKernelGGL((k_xinv<T, M>), dim3(nblk), dim3(X::THREADS), X::LDS, st, s.a, out + zoff, nrows, g.ny,
-                       s.nkxb, s.twx, s.ptw, scale, mode, mu, mu_scale, scale_z ? scale_z + s.z0 : nullptr,
-                       g.dz + s.z0, partial);
+    if (mode == 1)
+        hipLaunchKernelGGL((k_xinv<T, M, 1>), dim3(nblk), dim3(X::THREADS), X::LDS, st, s.a, out + zoff, nrows,
+                           g.ny, s.nkxb, s.twx, s.ptw, scale, mu, mu_scale, scale_z ? scale_z + s.z0 : nullptr,
+                           g.dz + s.z0, partial);
+    else
+        hipLaunchKernelGGL((k_xinv<T, M, 0>), dim3(nblk), dim3(X::THREADS), X::LDS, st, s.a, out + zoff, nrows,
+                           g.ny, s.nkxb, s.twx, s.ptw, scale, mu, mu_scale, scale_z ? scale_z + s.z0 : nullptr,
+                           g.dz + s.z0, partial);
     return hipGetLastError();
 }
 
