@@ -43,20 +43,24 @@ k_project_update(double* __restrict__ u, double* __restrict__ v, double* __restr
     const size_t plane = (size_t)g.nx * g.ny;
     const int im = (i == 0) ? g.nx - 1 : i - 1;
     const int jm = (j == 0) ? g.ny - 1 : j - 1;
+    // Every load is unconditional (a missing z neighbour reads the cell itself, p absent
+    // reads phi) so that they are all in flight together; absent terms are selected away.
+    const bool lo = k > 0, hi = k + 1 < g.nz;
     const double pc = phi[id];
     const double pim = phi[(size_t)k * plane + (size_t)j * g.nx + im];
     const double pjm = phi[(size_t)k * plane + (size_t)jm * g.nx + i];
-    u[id] -= s * ((pc - pim) * (1.0 / g.dx));
-    v[id] -= s * ((pc - pjm) * (1.0 / g.dy));
-    double fm = 0.0, fp = 0.0;
-    if (k > 0) {
-        const double pkm = phi[id - plane];
-        const double gw = (pc - pkm) * g.o[k];   // o = 1/dzc at interior faces
-        w[id] -= s * gw;
-        fm = (pc - pkm) * g.o[k];
-    }
-    if (k + 1 < g.nz) fp = (phi[id + plane] - pc) * g.o[k + 1];
-    if (p) p[id] += pc - c * ((fp - fm) * g.idz[k]);
+    const double pkm = phi[lo ? id - plane : id];
+    const double pkp = phi[hi ? id + plane : id];
+    const double uo = u[id], vo = v[id], wo = w[id];
+    const double po = (p ? p : phi)[id];
+    u[id] = uo - s * ((pc - pim) * (1.0 / g.dx));
+    v[id] = vo - s * ((pc - pjm) * (1.0 / g.dy));
+    // fm: the z gradient at face k (o = 1/dzc at interior faces); the bottom wall face keeps
+    // its value (w - s * 0)
+    const double fm = lo ? (pc - pkm) * g.o[k] : 0.0;
+    const double fp = hi ? (pkp - pc) * g.o[k + 1] : 0.0;
+    w[id] = wo - s * fm;
+    if (p) p[id] = po + (pc - c * ((fp - fm) * g.idz[k]));
 }
 
 // out[blockIdx.x * ncomp + c] = sum of partial[b * ncomp + c] over the block's contiguous
@@ -184,13 +188,19 @@ k_cn_tiled(GridDev g, int kind, const double* __restrict__ fac, const double* in
     const size_t col = (size_t)xcd_remap(blockIdx.x, gridDim.x) * 64 + lane;
     const bool valid = col < plane;
     const size_t base = (size_t)ko * plane + col;
+    const size_t basec = (size_t)ko * plane + (valid ? col : 0);   // in range for every lane
     const int r0 = wave * KZ;
     double x[KZ];
+    // unconditional loads (clamped row and column) of which every lane's are in flight
+    // together; values of rows r >= n and of lanes past the plane are never used
 #pragma unroll
-    for (int i = 0; i < KZ; ++i) {
-        const int r = r0 + i;
-        x[i] = (valid && r < n) ? in[base + (size_t)r * plane] : 0.0;
-        if (MODE == CN_T && r < n) x[i] /= wv[r + ko];
+    for (int i = 0; i < KZ; ++i) x[i] = in[basec + (size_t)min(r0 + i, n - 1) * plane];
+#pragma unroll
+    for (int i = 0; i < KZ; ++i) anchor(x[i]);
+    if constexpr (MODE == CN_T) {
+#pragma unroll
+        for (int i = 0; i < KZ; ++i)
+            if (r0 + i < n) x[i] /= wv[r0 + i + ko];
     }
     // forward sweep from a zero entry value
     double b = 0.0, a = 1.0;
@@ -245,17 +255,34 @@ k_cn_tiled(GridDev g, int kind, const double* __restrict__ fac, const double* in
         }
     }
     if (!valid) return;
+    if constexpr (MODE == CN_ADD) {
+        // the values added to, read in groups of 8 rows ahead of their stores (one wait
+        // per group rather than one per row)
+        constexpr int G = KZ < 8 ? KZ : 8;
 #pragma unroll
-    for (int i = 0; i < KZ; ++i) {
-        const int r = r0 + i;
-        if (r < n) {
-            double* o = out + base + (size_t)r * plane;
-            if (MODE == CN_ADD)
-                *o += x[i];
-            else if (MODE == CN_SET)
-                *o = x[i];
-            else
-                *o = x[i] * wv[r + ko];
+        for (int i0 = 0; i0 < KZ; i0 += G) {
+            double ov[G];
+#pragma unroll
+            for (int i = 0; i < G; ++i) ov[i] = out[base + (size_t)min(r0 + i0 + i, n - 1) * plane];
+#pragma unroll
+            for (int i = 0; i < G; ++i) anchor(ov[i]);
+#pragma unroll
+            for (int i = 0; i < G; ++i) {
+                const int r = r0 + i0 + i;
+                if (r < n) out[base + (size_t)r * plane] = ov[i] + x[i0 + i];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < KZ; ++i) {
+            const int r = r0 + i;
+            if (r < n) {
+                double* o = out + base + (size_t)r * plane;
+                if (MODE == CN_SET)
+                    *o = x[i];
+                else
+                    *o = x[i] * wv[r + ko];
+            }
         }
     }
     if (MODE != CN_ADD && kind == 1 && wave == 0) {
@@ -376,17 +403,24 @@ k_adj_rhs(const double* __restrict__ gu, const double* __restrict__ gv, const do
     const size_t plane = (size_t)g.nx * g.ny;
     const int ip = (i + 1 == g.nx) ? 0 : i + 1;
     const int jp = (j + 1 == g.ny) ? 0 : j + 1;
+    // unconditional loads (a missing z neighbour reads the cell itself, gp absent reads
+    // gu), absent terms selected away: all loads in flight together
+    const bool lo = k > 0, hi = k + 1 < g.nz;
     const double idz = 1.0 / g.dz[k];
-    const double du = (gu[(size_t)k * plane + (size_t)j * g.nx + ip] - gu[id]) * idz / g.dx;
-    const double dv = (gv[(size_t)k * plane + (size_t)jp * g.nx + i] - gv[id]) * idz / g.dy;
-    const double wt = (k + 1 < g.nz) ? gw[id + plane] / g.dzc[k + 1] : 0.0;
-    const double wb = (k > 0) ? gw[id] / g.dzc[k] : 0.0;
+    const double gu0 = gu[id], gu1 = gu[(size_t)k * plane + (size_t)j * g.nx + ip];
+    const double gv0 = gv[id], gv1 = gv[(size_t)k * plane + (size_t)jp * g.nx + i];
+    const double gwt = gw[id + plane], gwb = gw[id];
+    const double* hp = gp ? gp : gu;
+    const double h0 = hp[id], hu = hp[hi ? id + plane : id], hd = hp[lo ? id - plane : id];
+    const double du = (gu1 - gu0) * idz / g.dx;
+    const double dv = (gv1 - gv0) * idz / g.dy;
+    const double wt = hi ? gwt / g.dzc[k + 1] : 0.0;
+    const double wb = lo ? gwb / g.dzc[k] : 0.0;
     double val = du + dv + (wt - wb) / g.dz[k];
     if (gp) {
-        const double hc = gp[id] * idz;
-        double fp = 0.0, fm = 0.0;
-        if (k + 1 < g.nz) fp = (gp[id + plane] / g.dz[k + 1] - hc) * g.o[k + 1];
-        if (k > 0) fm = (hc - gp[id - plane] / g.dz[k - 1]) * g.o[k];
+        const double hc = h0 * idz;
+        const double fp = hi ? (hu / g.dz[k + 1] - hc) * g.o[k + 1] : 0.0;
+        const double fm = lo ? (hc - hd / g.dz[k - 1]) * g.o[k] : 0.0;
         val += inv_s * (hc - c * ((fp - fm) / g.dz[k]));
     }
     f[id] = val;
@@ -402,13 +436,15 @@ k_adj_update(const double* __restrict__ gu, const double* __restrict__ gv, const
     const size_t plane = (size_t)g.nx * g.ny;
     const int im = (i == 0) ? g.nx - 1 : i - 1;
     const int jm = (j == 0) ? g.ny - 1 : j - 1;
+    const bool lo = k > 0;
     const double pc = phi[id];
-    ou[id] = gu[id] - g.dz[k] * ((pc - phi[(size_t)k * plane + (size_t)j * g.nx + im]) / g.dx);
-    ov[id] = gv[id] - g.dz[k] * ((pc - phi[(size_t)k * plane + (size_t)jm * g.nx + i]) / g.dy);
-    if (k > 0)
-        ow[id] = gw[id] - (pc - phi[id - plane]);
-    else
-        ow[id] = 0.0;
+    const double pim = phi[(size_t)k * plane + (size_t)j * g.nx + im];
+    const double pjm = phi[(size_t)k * plane + (size_t)jm * g.nx + i];
+    const double pkm = phi[lo ? id - plane : id];
+    const double gu0 = gu[id], gv0 = gv[id], gw0 = gw[id];
+    ou[id] = gu0 - g.dz[k] * ((pc - pim) / g.dx);
+    ov[id] = gv0 - g.dz[k] * ((pc - pjm) / g.dy);
+    ow[id] = lo ? gw0 - (pc - pkm) : 0.0;
     if (k + 1 == g.nz) ow[id + plane] = 0.0;
 }
 

@@ -11,6 +11,13 @@
 
 namespace ps {
 
+// Marks a loaded value as used at this point (an empty asm reading its register).  Loads
+// whose values are only used under a (uniform) branch are otherwise sunk into it by the
+// compiler, and a load under a branch is waited for before anything after the branch:
+// anchoring keeps a group of loads together, in flight at once, with one wait.
+__device__ __forceinline__ void anchor(double v) { asm volatile("" ::"v"(v)); }
+
+
 // Spectral tile width: W consecutive kx columns are stored together so that
 // every row of a tile is one 128-byte segment (8 complex FP64 or 16 complex FP32).
 template <typename T>

@@ -532,16 +532,31 @@ k_zsolve00(const cx<T>* b, cx<T>* bo, int nz, int nxny, const double* __restrict
     const int lane = threadIdx.x;
     const int K = (nz + 63) / 64;
     const int k0 = lane * K;
-    double fv[KMAX];
+    double fv[KMAX], dzv[KMAX], dzcv[KMAX];
     double s_dzf = 0.0, s_dz = 0.0;
+    // all of the lane's loads first (clamped rows, anchored so that they stay together),
+    // then the sums over its existing rows
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) {
+        const int kc = min(k0 + i, nz - 1);
+        fv[i] = (double)b[(size_t)kc * W].x;
+        dzv[i] = dz[kc];
+        dzcv[i] = dzc[kc];
+    }
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) {
+        anchor(fv[i]);
+        anchor(dzv[i]);
+        anchor(dzcv[i]);
+    }
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) {
         const int k = k0 + i;
-        fv[i] = 0.0;
         if (i < K && k < nz) {
-            fv[i] = (double)b[(size_t)k * W].x;
-            s_dzf += dz[k] * fv[i];
-            s_dz += dz[k];
+            s_dzf += dzv[i] * fv[i];
+            s_dz += dzv[i];
+        } else {
+            fv[i] = 0.0;
         }
     }
     const double tot_dz = wave_sum(s_dz);
@@ -551,7 +566,7 @@ k_zsolve00(const cx<T>* b, cx<T>* bo, int nz, int nxny, const double* __restrict
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) {
         const int k = k0 + i;
-        if (i < K && k < nz) loc += dz[k] * (fv[i] - mean_plane);
+        if (i < K && k < nz) loc += dzv[i] * (fv[i] - mean_plane);
     }
     double qexcl = wave_scan_incl(loc) - loc;   // Q at face k0
     // potential increments: P_k = P_{k-1} + dzc_k Q_k for k >= 1, P_0 = 0
@@ -563,9 +578,9 @@ k_zsolve00(const cx<T>* b, cx<T>* bo, int nz, int nxny, const double* __restrict
         const int k = k0 + i;
         inc[i] = 0.0;
         if (i < K && k < nz) {
-            inc[i] = (k >= 1) ? dzc[k] * q : 0.0;
+            inc[i] = (k >= 1) ? dzcv[i] * q : 0.0;
             locp += inc[i];
-            q += dz[k] * (fv[i] - mean_plane);
+            q += dzv[i] * (fv[i] - mean_plane);
         }
     }
     double pexcl = wave_scan_incl(locp) - locp;
@@ -577,7 +592,7 @@ k_zsolve00(const cx<T>* b, cx<T>* bo, int nz, int nxny, const double* __restrict
         if (i < K && k < nz) {
             pv += inc[i];
             fv[i] = pv;
-            s_dzp += dz[k] * pv;
+            s_dzp += dzv[i] * pv;
         }
     }
     const double shift = wave_sum(s_dzp) / tot_dz;
