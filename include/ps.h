@@ -260,7 +260,10 @@ ps_status ps_heat_flux(ps_plan_t plan, const double* w, const double* t, double 
  * (test and measurement entry; same kernels as poisson_solve).
  *   stage 0: forward x FFT   f (nz x ny x nx FP64)     -> spectral buffer A
  *   stage 1: forward y FFT   spectral A                 -> spectral buffer B
- *   stage 2: z solves        spectral B, in place (incl. the (0,0) column)
+ *   stage 2: z solves        spectral B -> out (incl. the (0,0) column); the kernels
+ *            run as in poisson_solve: from B into A where the solve works out of place
+ *            (FP64 register-tile path), else in place in B.  With out NULL the result
+ *            stays in that buffer.
  *   stage 3: inverse y FFT   spectral B                 -> spectral A
  *   stage 4: inverse x FFT   spectral A                 -> phi (FP64)
  * in/out: device pointers; spectral buffers are complex (FP64 pairs for

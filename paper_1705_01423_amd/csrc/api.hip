@@ -955,14 +955,24 @@ ps_status ps_debug_stage(ps_plan_t p, int stage, const void* in, void* out, void
             PS_HIP(f64 ? launch_yfwd<double>(g, spec_of<double>(p), st) : launch_yfwd<float>(g, spec_of<float>(p), st),
                    "y forward FFT");
             return copy_out(p->spec_b);
-        case 2:
+        case 2: {
+            // as in poisson_solve: out of place from B into A where that path applies
             PS_CHECK(copy_in(p->spec_b));
-            PS_HIP(f64 ? launch_zsolve<double>(g, spec_of<double>(p), st) : launch_zsolve<float>(g, spec_of<float>(p), st),
-                   "z solve");
-            PS_HIP(f64 ? launch_zsolve00<double>(g, spec_of<double>(p), p->small + R_DEFECT, st)
-                       : launch_zsolve00<float>(g, spec_of<float>(p), p->small + R_DEFECT, st),
-                   "z solve (0,0)");
-            return copy_out(p->spec_b);
+            const bool whole = p->chunk <= 0 || p->chunk >= g.nz;
+            const bool oop = whole && (f64 ? zsolve_out_of_place<double>(g) : zsolve_out_of_place<float>(g));
+            if (f64) {
+                SpecDev<double> sz = spec_of<double>(p);
+                if (oop) sz.bz = sz.a;
+                PS_HIP(launch_zsolve<double>(g, sz, st), "z solve");
+                PS_HIP(launch_zsolve00<double>(g, sz, p->small + R_DEFECT, st), "z solve (0,0)");
+            } else {
+                SpecDev<float> sz = spec_of<float>(p);
+                if (oop) sz.bz = sz.a;
+                PS_HIP(launch_zsolve<float>(g, sz, st), "z solve");
+                PS_HIP(launch_zsolve00<float>(g, sz, p->small + R_DEFECT, st), "z solve (0,0)");
+            }
+            return copy_out(oop ? p->spec_a : p->spec_b);
+        }
         case 3:
             PS_CHECK(copy_in(p->spec_b));
             PS_HIP(f64 ? launch_yinv<double>(g, spec_of<double>(p), st) : launch_yinv<float>(g, spec_of<float>(p), st),
