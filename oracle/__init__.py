@@ -23,9 +23,8 @@ FFT), ``math.fsum`` (exactly rounded sums).  Adjoints are obtained with
 library's hand-written adjoints.
 
 Parity status of every function is listed in the module that defines it; the
-only functions without an independent pin are the advection interpolation
-beyond its energy invariant and the temperature update order of the substep
-("parity unpinned", see ``substep``).
+only reading without an independent pin is the temperature update order of the
+substep ("parity unpinned", see ``substep``).
 """
 from .grid import Grid  # noqa: F401
 from . import operators, poisson, cn  # noqa: F401

@@ -14,7 +14,9 @@ volume-weighted averages of the two neighbouring centre values,
 (dz_{k-1} u_{k-1} + dz_k u_k) / (2 dzc_k).  With these choices the transporting
 fluxes of every control volume are exactly divergence free whenever the
 pressure-cell divergence is, and advection then conserves discrete kinetic
-energy (pinned by tests/test_oracle_substep.py).
+energy (pinned by tests/test_oracle_cn_substep.py, together with second-order
+convergence of the explicit terms to the continuous operators on uniform and
+stretched grids).
 
 Time advancement (Sec. 2.1: low-storage RK3 with Crank-Nicolson for the
 wall-normal viscous term, pressure in "delta" form), substep l:
@@ -31,8 +33,8 @@ with gamma = (8/15, 5/12, 3/4), rho = (0, -17/60, -5/12), alpha = gamma + rho.
 CFL number (Listing 1 of the paper): the maximum over cells of
 0.5 (|w_k + w_{k+1}| / dz_k + |v_j + v_{j+1}| / dy + |u_i + u_{i+1}| / dx).
 
-Parity unpinned: the exact interpolation of the advection terms beyond the
-energy invariant, and the velocity used in the temperature advection.
+Parity unpinned: the velocity used in the temperature advection (the
+substep's input velocity, a reading of the paper).
 """
 from __future__ import annotations
 
