@@ -122,6 +122,9 @@ struct ResidIn {
 #ifndef PS_XF_WPE
 #define PS_XF_WPE 1
 #endif
+#ifndef PS_XR_GROUP
+#define PS_XR_GROUP 1
+#endif
 #ifndef PS_XR_WPE
 #define PS_XR_WPE 1
 #endif
@@ -175,6 +178,8 @@ k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny,
     const double* xjm = RESID ? rin.x + (size_t)zg * plane + (size_t)(yr == 0 ? ny - 1 : yr - 1) * (2 * M) : nullptr;
     const double* xjp = RESID ? rin.x + (size_t)zg * plane + (size_t)(yr + 1 == ny ? 0 : yr + 1) * (2 * M) : nullptr;
     const double mu = RESID ? rin.mu[0] * rin.mu_scale : 0.0;
+    int rgroup = 0;   // residual loader: elements formed so far (a compile-time count once unrolled)
+    double2 rpend[PS_XR_GROUP];
     auto ld = [&](int e) -> cx<T> {
         double2 v = {0.0, 0.0};
         if constexpr (LM != XL_DIV) v = ld_stream2<PS_NT_XF>(frow + 2 * e);
@@ -209,9 +214,14 @@ k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny,
             v.y = valid ? f1 - l1 : 0.0;
             acc0 += v.x * v.x + v.y * v.y;
             acc1 += valid ? f0 * f0 + f1 * f1 : 0.0;
-            // each element's value is formed here, in order: otherwise the loads of every
-            // element's stencil are hoisted together and held in registers (one wave per SIMD)
-            asm volatile("" : "+v"(v.x), "+v"(v.y));
+            // the values of every PS_XR_GROUP elements are formed at the group's end (an empty
+            // asm reads them): the loads of one group are in flight together; without it every
+            // element's stencil is hoisted at once and held in registers (one wave per SIMD)
+            rpend[rgroup % PS_XR_GROUP] = v;
+            if (++rgroup % PS_XR_GROUP == 0) {
+#pragma unroll
+                for (int q = 0; q < PS_XR_GROUP; ++q) asm volatile("" : "+v"(rpend[q].x), "+v"(rpend[q].y));
+            }
         } else if constexpr (LM == XL_DIV) {
             // f = (D u*) / s at the cells (2e, 2e + 1) of row (z, y): periodic x and y, w at z-faces
             const int n = 2 * M;
