@@ -19,7 +19,8 @@
  * y and z).
  *
  * Storage: every field is a device pointer to FP64 values, C order [z][y][x]
- * (x fastest), contiguous, 8-byte aligned, owned by the caller.
+ * (x fastest), contiguous, 16-byte aligned (checked: PS_EINVAL otherwise),
+ * owned by the caller.
  *   centre fields (p, phi, f, u, v):  nz x ny x nx
  *   z-face fields (w, T):             (nz+1) x ny x nx, wall rows 0 and nz stored
  * u sits on x-faces (x = i*dx), v on y-faces (y = j*dy), w and T on z-faces
