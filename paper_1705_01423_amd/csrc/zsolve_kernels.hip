@@ -439,7 +439,7 @@ constexpr int kZPipeMaxNz = 512;
 
 template <typename T, int K, int MAXT, int NBUF>
 __global__ void __launch_bounds__(MAXT)
-k_zsolve_pipe(cx<T>* __restrict__ b, const T* __restrict__ etab, int nz, int ny, int nxh, int ntiles,
+k_zsolve_pipe(const cx<T>* b, cx<T>* bo, const T* __restrict__ etab, int nz, int ny, int nxh, int ntiles,
               const double* __restrict__ dz, const double* __restrict__ o, const double* __restrict__ lamx,
               const double* __restrict__ lamy) {
     constexpr int W = TileW<T>::value, WZ = W, LPW = 64 / WZ;
@@ -473,8 +473,10 @@ k_zsolve_pipe(cx<T>* __restrict__ b, const T* __restrict__ etab, int nz, int ny,
         __builtin_amdgcn_s_waitcnt(0);   // this wave's copies (and stores) are done
         __syncthreads();                 // ... and every other wave's
         const int ky = t % ny, kxb = t / ny, kx = kxb * W + c;
-        const bool store = kx < nxh && !(kx == 0 && ky == 0);
-        const T lam = store ? (T)(lamx[kx] + lamy[ky]) : (T)1;
+        const bool real_col = kx < nxh && !(kx == 0 && ky == 0);
+        // out of place, padding columns are stored too (a finite dummy solution)
+        const bool store = real_col || (bo != b && !(kx == 0 && ky == 0));
+        const T lam = real_col ? (T)(lamx[kx] + lamy[ky]) : (T)1;
         T eprev = (T)0;
         if (l < nchunk) eprev = etab[((size_t)t * nchunk + l) * W + c];
         cx<T> v[K];
@@ -494,7 +496,7 @@ k_zsolve_pipe(cx<T>* __restrict__ b, const T* __restrict__ etab, int nz, int ny,
         zscan_solve<T, K, WZ, true, false, MAXT / 64>(v, eprev, lam, k0, nz, c, wave, nwave, lw, xs,
                                                       ZCoefLds<T>{zdz, zo, k0});
         if (store) {
-            cx<T>* tile = b + (size_t)t * telems + c;
+            cx<T>* tile = bo + (size_t)t * telems + c;
 #pragma unroll
             for (int i = 0; i < K; ++i) {
                 const int k = k0 + i;
@@ -680,8 +682,8 @@ static hipError_t zpipe_launch(const GridDev& g, const SpecDev<T>& s, hipStream_
     const int nblk = std::min(ntiles, ncu * (NBUF == 1 ? 2 : 1));
     const int nxh = g.nx / 2 + 1;
 #define PS_ZPIPE(MAXT)                                                                                           \
-    hipLaunchKernelGGL((k_zsolve_pipe<T, K, MAXT, NBUF>), dim3(nblk), dim3(threads), NBUF * tbytes, st, s.b, s.etab, g.nz, \
-                       g.ny, nxh, ntiles, g.dz, g.o, g.lamx, g.lamy)
+    hipLaunchKernelGGL((k_zsolve_pipe<T, K, MAXT, NBUF>), dim3(nblk), dim3(threads), NBUF * tbytes, st, s.b,       \
+                       s.bz ? s.bz : s.b, s.etab, g.nz, g.ny, nxh, ntiles, g.dz, g.o, g.lamx, g.lamy)
     if (threads <= 256)
         PS_ZPIPE(256);
     else if (threads <= 512)
@@ -694,13 +696,14 @@ static hipError_t zpipe_launch(const GridDev& g, const SpecDev<T>& s, hipStream_
 }
 
 // Out of place (reading b, writing another buffer) measured faster than in place:
-// 1024^2 x 512 FP64 solve 8.43 -> 8.27 ms.  Only through the register-tile kernels.
+// 1024^2 x 512 FP64 solve 8.43 -> 8.27 ms, FP32-refined solve 21.37 -> 20.82 ms.  Through
+// the register-tile and the streamed kernels (not the lane-per-column fallback).
 #ifndef PS_Z_OOP
 #define PS_Z_OOP 1
 #endif
 template <typename T>
 bool zsolve_out_of_place(const GridDev& g) {
-    return PS_Z_OOP && zscan_cols<T>(g) > 0 && !zpipe_applies<T>(g);
+    return PS_Z_OOP && zscan_cols<T>(g) > 0;
 }
 
 template <typename T>
