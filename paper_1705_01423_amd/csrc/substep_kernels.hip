@@ -99,7 +99,16 @@ struct Ring {
     }
 };
 
-constexpr int kExTX = 64, kExTY = 4, kExZSEG = 64;
+// Column tile of the forward kernel: 32 x 8 (halo 1.33 cells per cell, 40.8 KB of LDS,
+// three blocks per CU) measured 7.60 -> 6.9-7.1 ms against 64 x 4 at 768^2 x 512; 16 x 16:
+// 7.24 ms.  The adjoint's eight-field ring keeps 64 x 4 (32 x 8 measured the same).
+#ifndef PS_EX_TX
+#define PS_EX_TX 32
+#endif
+#ifndef PS_EX_TY
+#define PS_EX_TY 8
+#endif
+constexpr int kExTX = PS_EX_TX, kExTY = PS_EX_TY, kExZSEG = 64;
 
 // Block -> (x tile, y tile, z segment), x tile fastest so that neighbouring y tiles
 // (which share halo rows) run together on one XCD.
@@ -351,7 +360,13 @@ k_cn_solve_t(GridDev g, int kind, const double* __restrict__ fac, const double* 
 // F = U Q sends Lambda U dQ and Lambda Q dU to the points averaged into Q and U.
 // z-marching blocks as in k_explicit, with the state and the right-hand-side
 // cotangents in the LDS ring.
-constexpr int kAdTX = 64, kAdTY = 4, kAdZSEG = 64;
+#ifndef PS_AD_TX
+#define PS_AD_TX 64
+#endif
+#ifndef PS_AD_TY
+#define PS_AD_TY 4
+#endif
+constexpr int kAdTX = PS_AD_TX, kAdTY = PS_AD_TY, kAdZSEG = 64;
 // The next plane is prefetched through registers as in k_explicit (the LDS ring already
 // limits the adjoint to two waves per SIMD, so the staged values cost no occupancy):
 // 768^2 x 512, 18.6 -> 16.0 ms against loading each plane when needed.
