@@ -65,7 +65,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c3")
+    ap.add_argument("--config", default="couette1024x1024x512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-refined", action="store_true")
     ap.add_argument("--stage-reps", type=int, default=10)
@@ -281,7 +281,7 @@ def other_workloads(args):
 
     res = {}
     # ---- projection + pressure update, 512 x 512 x 384 ----
-    cfg = synth.CONFIGS["c2"]
+    cfg = synth.CONFIGS["slab512x512x384"]
     zf = synth.zfaces(cfg.nz, cfg.alpha)
     log("projection 512x512x384")
     u, v, w = (torch.as_tensor(a).to("cuda") for a in synth.mode_velocity(cfg))
@@ -305,7 +305,7 @@ def other_workloads(args):
     torch.cuda.empty_cache()
 
     # ---- adjoint / forward cost, 256 x 256 x 192 ----
-    cfg = synth.CONFIGS["c4"]
+    cfg = synth.CONFIGS["slab256x256x192"]
     zf = synth.zfaces(cfg.nz, cfg.alpha)
     log("projection adjoint 256x256x192")
     u, v, w = (torch.as_tensor(a).to("cuda") for a in synth.mode_velocity(cfg))
@@ -320,7 +320,7 @@ def other_workloads(args):
     torch.cuda.empty_cache()
 
     # ---- RK3 substep and its adjoint, 768 x 768 x 512, Ra = 1e8, Pr = 1 ----
-    cfg = synth.CONFIGS["c5"]
+    cfg = synth.CONFIGS["rb768x768x512"]
     zf = synth.zfaces(cfg.nz, cfg.alpha)
     log("rk3 substep 768x768x512")
     ra, pr = cfg.extra["ra"], cfg.extra["pr"]

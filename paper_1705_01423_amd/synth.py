@@ -61,11 +61,11 @@ class Config:
 # Rayleigh-Benard grids (Table 3); the 1024 x 1024 x 512 slab stands in for the
 # plane-Couette case.  Seeds are 1000 + index.
 CONFIGS = {
-    "c1": Config("c1", 64, 64, 64, 1.0, 1.0, 3.0, 1000),
-    "c2": Config("c2", 512, 512, 384, 2.0, 2.0, 3.0, 1001),
-    "c3": Config("c3", 1024, 1024, 512, 4.0, 4.0, 3.0, 1002, {"couette": True}),
-    "c4": Config("c4", 256, 256, 192, 2.0, 2.0, 3.0, 1003),
-    "c5": Config("c5", 768, 768, 512, 1.0, 1.0, 3.0, 1004, {"ra": 1e8, "pr": 1.0}),
+    "cube64": Config("cube64", 64, 64, 64, 1.0, 1.0, 3.0, 1000),
+    "slab512x512x384": Config("slab512x512x384", 512, 512, 384, 2.0, 2.0, 3.0, 1001),
+    "couette1024x1024x512": Config("couette1024x1024x512", 1024, 1024, 512, 4.0, 4.0, 3.0, 1002, {"couette": True}),
+    "slab256x256x192": Config("slab256x256x192", 256, 256, 192, 2.0, 2.0, 3.0, 1003),
+    "rb768x768x512": Config("rb768x768x512", 768, 768, 512, 1.0, 1.0, 3.0, 1004, {"ra": 1e8, "pr": 1.0}),
 }
 
 

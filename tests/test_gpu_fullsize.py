@@ -31,9 +31,9 @@ def _setup(name, precision="fp64"):
 
 
 @pytest.fixture(scope="module")
-def c3():
-    banner("c3 inputs + oracle solve")
-    cfg, zf, g = _setup("c3")
+def couette():
+    banner("couette inputs + oracle solve")
+    cfg, zf, g = _setup("couette1024x1024x512")
     u, v, w = synth.mode_velocity(cfg)
     f = op.divergence(torch.as_tensor(u), torch.as_tensor(v), torch.as_tensor(w), g)
     del u, v, w
@@ -42,13 +42,13 @@ def c3():
 
 
 @pytest.mark.timeout(900)
-def test_c3_solve_fp64(c3):
-    cfg, zf, g, f, ref, defect = c3
-    banner("c3 fp64 solve")
+def test_couette_solve_fp64(couette):
+    cfg, zf, g, f, ref, defect = couette
+    banner("couette fp64 solve")
     plan = Plan(cfg.nx, cfg.ny, cfg.nz, cfg.lx, cfg.ly, zf, precision="fp64")
     phi, info = plan.solve(f.to("cuda"))
     err = rel(phi, ref)
-    print(f"c3 fp64 rel-L2 {err:.3e}", flush=True)
+    print(f"couette fp64 rel-L2 {err:.3e}", flush=True)
     assert err < 1e-12
     assert abs(info["compat_defect"] - defect) < 1e-14
     # gauge: dz-weighted zero mean
@@ -58,21 +58,21 @@ def test_c3_solve_fp64(c3):
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("prec,plan_tol,tol", [("fp32_refined", 0.0, 1e-11), ("fp32_refined", 1e-11, 1e-11),
                                                ("fp32_refined", 1e-8, 1e-8), ("fp32", 0.0, 1e-5)])
-def test_c3_solve_fp32(c3, prec, plan_tol, tol):
+def test_couette_solve_fp32(couette, prec, plan_tol, tol):
     """The refinement's stop rule meets the requested relative error against the oracle."""
-    cfg, zf, g, f, ref, _ = c3
-    banner(f"c3 {prec} solve tol={plan_tol}")
+    cfg, zf, g, f, ref, _ = couette
+    banner(f"couette {prec} solve tol={plan_tol}")
     plan = Plan(cfg.nx, cfg.ny, cfg.nz, cfg.lx, cfg.ly, zf, precision=prec, tol=plan_tol)
     phi, info = plan.solve(f.to("cuda"))
     err = rel(phi, ref)
-    print(f"c3 {prec} rel-L2 {err:.3e} iterations {info['iterations']}", flush=True)
+    print(f"couette {prec} rel-L2 {err:.3e} iterations {info['iterations']}", flush=True)
     assert err < tol
 
 
 @pytest.mark.timeout(900)
-def test_c2_project():
-    banner("c2 projection")
-    cfg, zf, g = _setup("c2")
+def test_slab512_project():
+    banner("slab512 projection")
+    cfg, zf, g = _setup("slab512x512x384")
     u, v, w = (torch.as_tensor(a) for a in synth.mode_velocity(cfg))
     z = torch.zeros_like(u)
     ref = poisson.project(u, v, w, z, g)
@@ -82,7 +82,7 @@ def test_c2_project():
     plan.project(ud, vd, wd, pd, phi)
     for name, a, b in zip(("u", "v", "w", "p", "phi"), (ud, vd, wd, pd, phi), ref):
         err = rel(a, b)
-        print(f"c2 {name} rel-L2 {err:.3e}", flush=True)
+        print(f"slab512 {name} rel-L2 {err:.3e}", flush=True)
         assert err < 1e-12
     # Discrete divergence after projection: its floor is the rounding of L phi, about
     # eps |L| |phi| (|L| ~ 4/dz_min^2 ~ 7e8 on this grid), so it is compared with the
@@ -90,14 +90,14 @@ def test_c2_project():
     d0 = float(op.divergence(u, v, w, g).abs().max())
     d1 = float(op.divergence(ud.cpu(), vd.cpu(), wd.cpu(), g).abs().max())
     dref = float(op.divergence(ref[0], ref[1], ref[2], g).abs().max())
-    print(f"c2 max|div| before {d0:.3e} after {d1:.3e} (oracle {dref:.3e})", flush=True)
+    print(f"slab512 max|div| before {d0:.3e} after {d1:.3e} (oracle {dref:.3e})", flush=True)
     assert d1 < 4.0 * dref + 1e-14 * d0 and d1 < 1e-9 * d0
 
 
 @pytest.mark.timeout(900)
-def test_c4_project_parity():
-    banner("c4 projection parity")
-    cfg, zf, g = _setup("c4")
+def test_slab256_project_parity():
+    banner("slab256 projection parity")
+    cfg, zf, g = _setup("slab256x256x192")
     u, v, w = (torch.as_tensor(a) for a in synth.mode_velocity(cfg))
     ref = poisson.project(u, v, w, torch.zeros_like(u), g)
     plan = Plan(cfg.nx, cfg.ny, cfg.nz, cfg.lx, cfg.ly, zf, precision="fp64")
@@ -106,15 +106,15 @@ def test_c4_project_parity():
     plan.project(ud, vd, wd, None, phi)
     for name, a, b in zip(("u", "v", "w", "phi"), (ud, vd, wd, phi), (ref[0], ref[1], ref[2], ref[4])):
         err = rel(a, b)
-        print(f"c4 {name} rel-L2 {err:.3e}", flush=True)
+        print(f"slab256 {name} rel-L2 {err:.3e}", flush=True)
         assert err < 1e-12
 
 
 @pytest.mark.timeout(900)
-def test_c4_adjoint_finite_differences():
+def test_slab256_adjoint_finite_differences():
     """Loss sum(w . u_projected); hand-written adjoint vs central differences, h = 1e-6, 32 directions."""
-    banner("c4 adjoint FD")
-    cfg, zf, g = _setup("c4")
+    banner("slab256 adjoint FD")
+    cfg, zf, g = _setup("slab256x256x192")
     plan = Plan(cfg.nx, cfg.ny, cfg.nz, cfg.lx, cfg.ly, zf, precision="fp64")
     u, v, w = (torch.as_tensor(a).to("cuda") for a in synth.mode_velocity(cfg))
     om = [torch.as_tensor(a).to("cuda") for a in synth.face_weights(cfg)]
@@ -156,12 +156,12 @@ def test_c4_adjoint_finite_differences():
                 pm = ProjectFn.apply(*[a - b for a, b in zip((u, v, w), d)], plan)
                 fd1 = float(sum(((x - y) * o).sum() for x, y, o in zip(pp, pm, om)) / 2.0)
             assert abs(fd1 - an) <= 1e-9 * max(abs(an), gnorm), (trial, fd1, an)
-    print(f"c4 FD worst relative error {worst:.3e} (scale ||g|| = {gnorm:.3e})", flush=True)
+    print(f"slab256 FD worst relative error {worst:.3e} (scale ||g|| = {gnorm:.3e})", flush=True)
 
 
-def test_c4_dense_8cube():
+def test_slab256_dense_8cube():
     """8^3 sub-case of the 256^2 x 192 box: the adjoint equals the transpose of the oracle's dense Jacobian."""
-    banner("c4 dense 8^3")
+    banner("slab256 dense 8^3")
     n = 8
     zf = synth.zfaces(n, 3.0)
     g = Grid(n, n, n, 2.0, 2.0, zf)
@@ -192,8 +192,8 @@ def test_c4_dense_8cube():
 
 
 @pytest.fixture(scope="module")
-def c5():
-    cfg, zf, g = _setup("c5")
+def rb768():
+    cfg, zf, g = _setup("rb768x768x512")
     ra, pr = cfg.extra["ra"], cfg.extra["pr"]
     nu, ka = math.sqrt(pr / ra), 1.0 / math.sqrt(ra * pr)
     state = [torch.as_tensor(a) for a in synth.rb_state(cfg)]
@@ -202,9 +202,9 @@ def c5():
 
 
 @pytest.mark.timeout(1200)
-def test_c5_substep_forward(c5):
-    cfg, zf, g, state, dt, nu, ka = c5
-    banner(f"c5 substep forward dt={dt:.3e}")
+def test_rb768_substep_forward(rb768):
+    cfg, zf, g, state, dt, nu, ka = rb768
+    banner(f"rb768 substep forward dt={dt:.3e}")
     plan = Plan(cfg.nx, cfg.ny, cfg.nz, cfg.lx, cfg.ly, zf, precision="fp32_refined")
     dstate = [a.to("cuda") for a in state]
     cfl_gpu = float(plan.cfl(dstate[0], dstate[1], dstate[2]).item())
@@ -217,15 +217,15 @@ def test_c5_substep_forward(c5):
     for name, a, b, x0 in zip("uvwTp", out, ref, state):
         err = rel(a, b)
         inc = rel(a - x0, b - x0) if float((b - x0).norm()) > 0 else 0.0
-        print(f"c5 {name} rel-L2 {err:.3e} (increment {inc:.3e})", flush=True)
+        print(f"rb768 {name} rel-L2 {err:.3e} (increment {inc:.3e})", flush=True)
         assert err < 1e-10 and inc < 1e-9
 
 
 @pytest.mark.timeout(900)
-def test_c5_substep_adjoint_fd(c5):
+def test_rb768_substep_adjoint_fd(rb768):
     """Substep VJP at 768^2 x 512 vs central differences of the FP64 GPU forward, 4 directions."""
-    cfg, zf, g, state, dt, nu, ka = c5
-    banner("c5 substep adjoint FD")
+    cfg, zf, g, state, dt, nu, ka = rb768
+    banner("rb768 substep adjoint FD")
     fwd = Plan(cfg.nx, cfg.ny, cfg.nz, cfg.lx, cfg.ly, zf, precision="fp64")
     adj = Plan(cfg.nx, cfg.ny, cfg.nz, cfg.lx, cfg.ly, zf, precision="fp32_refined")
     dstate = [a.to("cuda") for a in state]
@@ -255,5 +255,5 @@ def test_c5_substep_adjoint_fd(c5):
         del sp, sm
         an = float(sum((gi * di).sum() for gi, di in zip(gin, d)))
         err = abs(fd - an) / max(abs(an), gnorm)
-        print(f"c5 FD trial {trial}: fd {fd:.9e} adjoint {an:.9e} rel {err:.2e}", flush=True)
+        print(f"rb768 FD trial {trial}: fd {fd:.9e} adjoint {an:.9e} rel {err:.2e}", flush=True)
         assert err <= 1e-6

@@ -179,9 +179,9 @@ def test_solve_fp32_paths(prec):
         assert info["iterations"] >= 2
 
 
-def test_c1_config_parity():
+def test_cube64_parity():
     """64^3 stretched box, RHS = divergence of i.i.d. N(0,1) face velocities (wall w = 0)."""
-    cfg = synth.CONFIGS["c1"]
+    cfg = synth.CONFIGS["cube64"]
     g, plan = grids(cfg.nx, cfg.ny, cfg.nz, cfg.lx, cfg.ly, cfg.alpha)
     u, v, w = synth.random_face_velocity(cfg)
     f = op.divergence(torch.as_tensor(u), torch.as_tensor(v), torch.as_tensor(w), g)
