@@ -91,10 +91,13 @@ def test_stage_z_solve(shape, prec, tol):
 
 
 LENGTHS = [64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048]
+# the short lengths the shapes above do not reach, and the longest a plan accepts (4096)
+EDGE_X = [12, 16, 32, 3072, 4096]
+EDGE_Y = [3, 4, 6, 16, 32, 3072, 4096]
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 3e-6)])
-@pytest.mark.parametrize("n", LENGTHS)
+@pytest.mark.parametrize("n", LENGTHS + EDGE_X)
 def test_stage_lengths_x(n, prec, tol):
     """Forward and inverse x transforms for every supported length used by the workloads."""
     banner(f"x length {n} {prec}")
@@ -103,7 +106,7 @@ def test_stage_lengths_x(n, prec, tol):
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 3e-6)])
-@pytest.mark.parametrize("n", LENGTHS)
+@pytest.mark.parametrize("n", LENGTHS + EDGE_Y)
 def test_stage_lengths_y(n, prec, tol):
     banner(f"y length {n} {prec}")
     test_stage_y_both((8, n, 3), prec, tol)
@@ -131,6 +134,18 @@ def test_solve_fp64_parity(shape):
     phi, info = plan.solve(f.to("cuda"))
     assert rel(phi, ref) < 1e-12
     assert abs(info["compat_defect"] - defect) < 1e-12
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32_refined", 1e-11)])
+@pytest.mark.parametrize("shape", [(4096, 6, 5), (8, 4096, 5), (3072, 3, 4), (6, 3072, 4), (8, 6, 2048)])
+def test_solve_max_extents(shape, prec, tol):
+    """Whole solve at the largest length a plan accepts along each axis (x, y: 4096; z: 2048)."""
+    banner(f"solve at max extent {shape} {prec}")
+    g, plan = grids(*shape, lx=1.5, ly=2.0, precision=prec)
+    f = _rng_field(plan.centre_shape, 9)
+    ref = poisson.solve(f, g)
+    phi, _ = plan.solve(f.to("cuda"))
+    assert rel(phi, ref) < tol
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32_refined", 1e-11)])
