@@ -110,6 +110,57 @@ def test_advection_conserves_energy():
     assert abs(float((g.vw() * t * at).sum())) < 1e-13 * float((g.vw() * (t * at).abs()).sum())
 
 
+def _wall_normal_modes(g):
+    """Eigenpairs of the wall-normal second differences (centre fields with zero wall values,
+    interior faces), least damped first."""
+    def dzz_inner(q):
+        full = torch.cat([torch.zeros(1, 1, 1, dtype=F64), q, torch.zeros(1, 1, 1, dtype=F64)], 0)
+        return op.dzz_face(full, g)[1:g.nz]
+
+    out = []
+    for fn, n in ((lambda q: op.dzz_centre_dirichlet(q, g), g.nz), (dzz_inner, g.nz - 1)):
+        lam, vec = np.linalg.eig(_dense(fn, (n, 1, 1)))
+        assert np.abs(lam.imag).max() == 0.0 and lam.real.max() < 0
+        order = np.argsort(-lam.real)
+        out.append((lam.real[order], vec.real[:, order]))
+    return out
+
+
+@pytest.mark.parametrize("l", [1, 2, 3])
+def test_substep_crank_nicolson_modes(l):
+    """Horizontally uniform u, v and T perturbations along eigenvectors of the wall-normal
+    second difference feel neither advection, horizontal diffusion nor a pressure gradient, so
+    a substep multiplies each by the trapezoidal (Crank-Nicolson) factor (1 + a/2) / (1 - a/2),
+    a = alpha_l dt D lambda (Sec. 2.1: only the wall-normal diffusive term is implicit)."""
+    g = _grid(4, 3, 12)
+    nu, kappa, dt, eps = 0.02, 0.013, 0.05, 1e-3
+    (lc, vc), (lf, vf) = _wall_normal_modes(g)
+    shape = (g.nz, g.ny, g.nx)
+    u = torch.as_tensor(eps * vc[:, 0])[:, None, None].expand(shape).clone()
+    v = torch.as_tensor(eps * vc[:, 2])[:, None, None].expand(shape).clone()
+    tmode = torch.zeros(g.nz + 1, dtype=F64)
+    tmode[1:g.nz] = torch.as_tensor(eps * vf[:, 1])
+    t = (1 - g.zf + tmode)[:, None, None].expand(g.nz + 1, g.ny, g.nx).clone()
+    w = torch.zeros(g.nz + 1, g.ny, g.nx, dtype=F64)
+    p = torch.zeros(shape, dtype=F64)
+    # the previous substep's explicit terms of this state: zero but for the buoyancy on w
+    hprev = ss.explicit_terms(u, v, w, t, g, nu, kappa) if l > 1 else None
+    (un, vn, wn, tn, _), _ = ss.substep((u, v, w, t, p), g, l, dt, nu, kappa, hprev=hprev)
+    alp = ss.GAMMA[l - 1] + ss.RHO[l - 1]
+
+    def factor(diff, lam):
+        a = alp * dt * diff * lam
+        return (1 + a / 2) / (1 - a / 2)
+
+    def rel(x, y):
+        return float((x - y).norm() / y.norm())
+
+    assert rel(un, factor(nu, lc[0]) * u) < 1e-12
+    assert rel(vn, factor(nu, lc[2]) * v) < 1e-12
+    assert rel(tn - (1 - g.zf)[:, None, None], factor(kappa, lf[1]) * (t - (1 - g.zf)[:, None, None])) < 1e-12
+    assert float(wn.abs().max()) < 1e-15
+
+
 def test_rest_state():
     """Conduction state: velocity stays zero, T unchanged, buoyancy goes into the pressure."""
     g = _grid(8, 6, 10)
