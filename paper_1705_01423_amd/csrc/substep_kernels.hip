@@ -99,8 +99,8 @@ struct Ring {
     }
 };
 
-// Column tile of the forward kernel: 32 x 8 (halo 1.33 cells per cell, 40.8 KB of LDS,
-// three blocks per CU) measured 7.60 -> 6.9-7.1 ms against 64 x 4 at 768^2 x 512; 16 x 16:
+// Column tile of the forward kernel: 32 x 8 (halo 1.33 cells per cell, 40.8 KB of LDS: four
+// blocks fit one CU's 160 KB) measured 7.60 -> 6.9-7.1 ms against 64 x 4 at 768^2 x 512; 16 x 16:
 // 7.24 ms.  The adjoint's eight-field ring keeps 64 x 4 (32 x 8 measured the same).
 #ifndef PS_EX_TX
 #define PS_EX_TX 32
