@@ -243,7 +243,7 @@ ps_status rk3_step(ps_plan_t plan, double dt, double cfl_target, double dt_max, 
 
 /*
  * ps_heat_flux - wall-normal statistics of a convection state (the Nusselt
- * number of Sec. 4): plane means of T on the nz + 1 z-faces,
+ * number reported in Sec. 5, Table 3): plane means of T on the nz + 1 z-faces,
  *   mean_t[k] = <T>_k,
  * and the total vertical heat flux through the nz cell-centre planes,
  *   flux[k] = < wbar Tbar >_k - kappa (<T>_{k+1} - <T>_k) / dz_k,

@@ -22,9 +22,9 @@ FFT), ``math.fsum`` (exactly rounded sums).  Adjoints are obtained with
 ``torch.autograd`` through these same functions, independently of the GPU
 library's hand-written adjoints.
 
-Parity status of every function is listed in the module that defines it; the
-only reading without an independent pin is the temperature update order of the
-substep ("parity unpinned", see ``substep``).
+Parity status of every function is listed in the module that defines it; every
+reading has an independent pin (the temperature update order of the substep
+by the third-order time convergence of Sec. 2.1, see ``substep``).
 """
 from .grid import Grid  # noqa: F401
 from . import operators, poisson, cn  # noqa: F401

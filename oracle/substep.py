@@ -26,15 +26,20 @@ wall-normal viscous term, pressure in "delta" form), substep l:
     L phi = D u* / (alpha_l dt),  u = u* - alpha_l dt G phi,
     p <- p + phi - (alpha_l dt nu / 2) Dzz phi
     T likewise with kappa and without pressure, using the substep's input
-    velocity in its advection.
+    velocity in its advection (the same stage as the momentum terms).
 
 with gamma = (8/15, 5/12, 3/4), rho = (0, -17/60, -5/12), alpha = gamma + rho.
 
 CFL number (Listing 1 of the paper): the maximum over cells of
 0.5 (|w_k + w_{k+1}| / dz_k + |v_j + v_{j+1}| / dy + |u_i + u_{i+1}| / dx).
 
-Parity unpinned: the velocity used in the temperature advection (the
-substep's input velocity, a reading of the paper).
+Which velocity advects the temperature inside a substep: Sec. 2.2 lists the
+temperature update after the velocity correction, which could be read as
+advecting T with the corrected velocity; Sec. 2.1 states a third-order time
+error for the scheme.  Only the substep's input velocity keeps that order (the
+corrected one gives about first order in T), so that is the reading taken.
+Pinned by tests/test_oracle_timestep.py::test_step_third_order_in_time, with
+the other reading planted as a mistake in tests/test_oracle_mutations.py.
 """
 from __future__ import annotations
 

@@ -1,5 +1,5 @@
 """A full RK3 time step, the CFL-limited time step and wall-normal statistics (paper Sec. 2.1,
-Listing 1, Sec. 4).  Test infrastructure: plain FP64 torch on the CPU.
+Listing 1; the Nusselt number reported in Sec. 5, Table 3).  Test infrastructure: plain FP64 torch on the CPU.
 
 * One time step is the three substeps l = 1, 2, 3 of the low-storage RK3 scheme with the
   same dt, each substep handing its explicit terms H^l to the next (rho_l H^{l-1}).

@@ -63,7 +63,7 @@ def _fails(pin):
 
 # (module, original text, planted mistake, pins expected to catch it)
 CASES = {
-    # Poisson solve, Sec. 3.2 / Eq. (4)
+    # Poisson solve, Sec. 2.2 (Eqs. (1)-(3) give the equations it serves)
     "z-solve: first-row excess from the wrong cell": (
         "poisson", "e = lam * dz[0]", "e = lam * dz[1]",
         [lambda: t_po.test_manufactured_stretched((16, 12, 10)), lambda: t_po.test_brute_force_dense((6, 12, 5))]),
@@ -139,10 +139,22 @@ CASES = {
     "u advection: y flux interpolated from the wrong neighbour": (
         "substep", "fy = (0.5 * (v + _xm(v))) * (0.5 * (u + _ym(u)))", "fy = (0.5 * (v + _xp(v))) * (0.5 * (u + _ym(u)))",
         [t_cn.test_advection_conserves_energy, lambda: t_cn.test_explicit_terms_second_order(0.0)]),
+    "temperature advected with the corrected velocity": (
+        "substep",
+        "    tn = t + cn.solve_face(rt, g, bka)\n    s = alp * dt\n"
+        "    un, vn, wn, pn, _ = poisson.project(us, vs, ws, p, g, s=s, c=bnu,\n"
+        "                                        differentiable=differentiable)\n",
+        "    s = alp * dt\n"
+        "    un, vn, wn, pn, _ = poisson.project(us, vs, ws, p, g, s=s, c=bnu,\n"
+        "                                        differentiable=differentiable)\n"
+        "    ht = _zero_walls(-adv_face(t, un, vn, wn, g) + kappa * (op.dxx(t, g) + op.dyy(t, g)), g)\n"
+        "    rt = _zero_walls(comb(ht, hpt, torch.zeros_like(t), kappa * op.dzz_face(t, g)), g)\n"
+        "    tn = t + cn.solve_face(rt, g, bka)\n",
+        [t_ts.test_step_third_order_in_time]),
     "CFL: y neighbour on the wrong side": (
         "substep", "+ torch.abs(v + _yp(v)) / g.dy", "+ torch.abs(v + _ym(v)) / g.dy",
         [t_cn.test_cfl_brute_force]),
-    # Full step and statistics, Sec. 2.1 and Sec. 4
+    # Full step and statistics, Sec. 2.1 and Sec. 5 (Table 3)
     "heat flux: conduction term with the wrong sign": (
         "timestep", "cond = kappa * (tm[1:] - tm[:-1]) / g.dz", "cond = kappa * (tm[:-1] - tm[1:]) / g.dz",
         [t_ts.test_heat_flux_conduction]),

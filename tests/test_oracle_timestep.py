@@ -1,4 +1,4 @@
-"""Pins of the oracle's full RK3 step and wall-normal statistics (paper Sec. 2.1, Listing 1, Sec. 4)."""
+"""Pins of the oracle's full RK3 step and wall-normal statistics (paper Sec. 2.1, Listing 1; the Nusselt number of Sec. 5, Table 3)."""
 import math
 
 import numpy as np
@@ -94,3 +94,48 @@ def test_heat_flux_modes():
     assert torch.allclose(tm, c, rtol=0, atol=1e-15)
     ab, bb = 0.5 * (a[:-1] + a[1:]), 0.5 * (b[:-1] + b[1:])
     assert torch.allclose(f, 0.5 * ab * bb, rtol=0, atol=1e-15)
+
+
+def _smooth_state(g):
+    """A smooth, discretely divergence-free velocity (a few modes, projected) with no-slip walls,
+    and a smooth temperature perturbation of the conduction profile."""
+    from oracle import poisson
+    tx, ty = 2 * math.pi / g.lx, 2 * math.pi / g.ly
+    xc = (torch.arange(g.nx, dtype=F64) + 0.5) * g.dx
+    xf = torch.arange(g.nx, dtype=F64) * g.dx
+    yc = (torch.arange(g.ny, dtype=F64) + 0.5) * g.dy
+    yf = torch.arange(g.ny, dtype=F64) * g.dy
+    sz, s2z = torch.sin(math.pi * g.zc), torch.sin(2 * math.pi * g.zc)
+    u = (0.8 * torch.sin(tx * xf)[None, None, :] * torch.cos(ty * yc)[None, :, None] + 0.3 * torch.cos(ty * yc)[None, :, None]) * sz[:, None, None]
+    v = 0.5 * torch.cos(tx * xc)[None, None, :] * torch.sin(ty * yf)[None, :, None] * s2z[:, None, None]
+    w = 0.6 * torch.cos(tx * xc)[None, None, :] * torch.cos(ty * yc)[None, :, None] * (torch.sin(math.pi * g.zf) ** 2)[:, None, None]
+    u = u.expand(g.nz, g.ny, g.nx).clone()
+    v = v.expand(g.nz, g.ny, g.nx).clone()
+    w = w.expand(g.nz + 1, g.ny, g.nx).clone()
+    p = torch.zeros(g.nz, g.ny, g.nx, dtype=F64)
+    u, v, w, _, _ = poisson.project(u, v, w, p, g)
+    t = ((1 - g.zf)[:, None, None] + 0.2 * torch.sin(tx * xc)[None, None, :] * torch.cos(ty * yc)[None, :, None]
+         * torch.sin(math.pi * g.zf)[:, None, None])
+    return u, v, w, t.expand(g.nz + 1, g.ny, g.nx).clone(), p
+
+
+def test_step_third_order_in_time():
+    """Sec. 2.1: the RK3 scheme advances the solution with a third-order time error.  Without
+    viscosity and diffusion (no Crank-Nicolson part), integrating a smooth state to t = 0.4 with
+    n = 16, 32, 64, 128 steps, the differences between successive runs must shrink by 2^3 = 8 per
+    halving of dt, for the velocity and for the temperature.  This also pins which velocity
+    advects the temperature inside a substep: the substep's input velocity (the same stage as the
+    momentum terms) keeps the third order; the velocity after the projection drops it to about
+    first order (ratios near 2)."""
+    g = _grid(12, 8, 12, alpha=2.0)
+    s0 = _smooth_state(g)
+    runs = []
+    for n in (16, 32, 64, 128):
+        s = s0
+        for _ in range(n):
+            s = ts.rk3_step(s, g, 0.4 / n, 0.0, 0.0)
+        runs.append(s)
+    for q, name in enumerate(("u", "v", "w", "T")):
+        d = [float((runs[i][q] - runs[i + 1][q]).abs().max()) for i in range(3)]
+        ratios = (d[0] / d[1], d[1] / d[2])
+        assert all(7.0 <= r <= 9.0 for r in ratios), (name, d, ratios)
