@@ -89,12 +89,15 @@ typedef struct {
  * formed identically on every path):
  *   dz[k] = zf[k+1]-zf[k];  dzc[k] = (dz[k-1]+dz[k])/2;  o[k] = 1/dzc[k]
  *   lamx[kx] = (4/dx^2) sin^2(pi kx/nx)  (modified wavenumbers, Sec. 2.2)
- * nx, ny must be of the form 2^a 3^b with nx even, 4 <= nx, ny <= 4096;
- * 2 <= nz <= 2048.
+ * nx, ny must be of the form 2^a 3^b with b <= 1 (one factor 3 at most: the
+ * transform lengths the library is built for), nx even, 4 <= nx, ny <= 4096;
+ * 2 <= nz <= 2048.  Other sizes return PS_EINVAL.
  * prec: ps_precision.  tol: relative error target of the refinement (<= 0
  * selects 1e-12): it stops when the last correction ||delta_i||/||phi|| is
  * <= tol, or, from the second correction on, when the error it predicts is,
- * rho_i ||delta_i||/||phi|| with rho_i = ||delta_i|| / ||delta_{i-1}||.
+ * rho_i ||delta_i||/||phi|| with rho_i = ||delta_i|| / ||delta_{i-1}||.  A
+ * correction that shrinks by less than half (the rounding floor) or the cap
+ * max_iter ends it without convergence (PS_ENOTCONVERGED from the solve).
  * max_iter: refinement cap (<= 0 selects 10).  flags: PS_FLAG_*.
  * The plan is bound to the current HIP device and allocates its workspace
  * there (see poisson_plan_workspace_bytes).  It also allocates its own
@@ -129,12 +132,15 @@ ps_status poisson_plan_destroy(ps_plan_t plan);
  *
  * L = D G is the flux-form staggered Laplacian: periodic in x and y, zero
  * normal gradient at the walls (Sec. 2.1-2.2).  The right-hand side is made
- * compatible by removing its dz-weighted mean (reported in info, or an error
- * under PS_FLAG_STRICT_COMPAT when it exceeds 1e-8 of max|f|).  f and phi:
- * centre fields (nz x ny x nx); f is not modified; phi may not alias f.
- * FP32_REFINED synchronises once per refinement iteration; info != NULL
- * synchronises at the end.  Returns PS_ENOTCONVERGED (phi still written)
- * when refinement stops above the tolerance.
+ * compatible by removing its dz-weighted mean (reported in info; under
+ * PS_FLAG_STRICT_COMPAT the call returns PS_ENOTCOMPAT, phi written, when
+ * |mean| exceeds 1e-8 max|f|: one more read of f and a synchronisation).
+ * f and phi: centre fields (nz x ny x nx); f is not modified; phi may not
+ * alias f.  PS_FLAG_CHECK_FINITE: PS_ENONFINITE, nothing written, when f
+ * holds a NaN or Inf.  FP32_REFINED synchronises once per refinement
+ * iteration; info != NULL synchronises at the end.  Returns
+ * PS_ENOTCONVERGED (phi still written, info filled) when the refinement
+ * stops above the tolerance (see poisson_plan_create).
  */
 ps_status poisson_solve(ps_plan_t plan, const double* f, double* phi, void* stream, ps_info* info);
 
@@ -145,7 +151,10 @@ ps_status poisson_solve(ps_plan_t plan, const double* f, double* phi, void* stre
  * interior faces updated (wall rows left as given; the divergence uses them);
  * p: centre field updated in place (may be NULL: no pressure update);
  * phi_out: receives phi (may be NULL).  s > 0 (alpha_l dt; 1 for a plain
- * projection), c >= 0 (alpha_l dt nu / 2).
+ * projection), c >= 0 (alpha_l dt nu / 2).  The plan's flags apply to the
+ * right-hand side D u* / s as in poisson_solve (with either flag set it is
+ * stored before the solve instead of formed inside the first transform);
+ * on PS_ENOTCONVERGED the update is still applied.
  */
 ps_status project(ps_plan_t plan, double* u, double* v, double* w, double* p, double* phi_out,
                   double s, double c, void* stream, ps_info* info);
@@ -187,7 +196,8 @@ ps_status project_adjoint(ps_plan_t plan, const double* g_u, const double* g_v, 
 /*
  * ps_cfl - maximum CFL number of Listing 1 of the paper, for unit time step:
  *   max over cells of 0.5 (|w_k + w_{k+1}|/dz_k + |v_j + v_{j+1}|/dy + |u_i + u_{i+1}|/dx)
- * (at least 1e-8).  Writes one double to the device pointer cfl_dev.
+ * (at least 1e-8).  Writes one double to the device pointer cfl_dev.  A NaN
+ * velocity gives a NaN (the maximum propagates NaN).
  */
 ps_status ps_cfl(ps_plan_t plan, const double* u, const double* v, const double* w,
                  double* cfl_dev, void* stream);
@@ -215,17 +225,45 @@ ps_status rk3_substep(ps_plan_t plan, int l, double dt, double nu, double kappa,
                       void* stream, ps_info* info);
 
 /*
- * rk3_substep_adjoint - vector-Jacobian product of rk3_substep (l = 1 form,
+ * rk3_substep_adjoint - vector-Jacobian product of rk3_substep (substep l,
  * dt fixed) at the input state (u, v, w, t, p), which is not modified: the
- * forward intermediates are recomputed from it.  g_out[0..4] are the
- * cotangents of the output (u, v, w, t, p); g_in[0..4] receive the
- * cotangents of the input.  Wall rows of w and t carry zero cotangent.
+ * substep is linear in everything but the advection, whose derivative is
+ * formed from that state (Sec. 2.1 discretisation).  Cotangents in:
+ *   g_out[0..4]  of the output state (u, v, w, t, p);
+ *   g_hout[0..3] of the substep's H output (u, v, w, t), or NULL when H is
+ *                not used downstream (the substep's H feeds substep l + 1).
+ * Cotangents out:
+ *   g_in[0..4]    of the input state;
+ *   g_hprev[0..3] of the previous substep's H (h_prev of rk3_substep), or
+ *                 NULL; for l = 1 it is zero (rho_1 = 0).
+ * g_hprev may share g_hout's buffers (g_hout is consumed first); g_in may not
+ * alias g_out or g_hout, nor g_hprev g_in or g_out.  Wall rows of w and t
+ * carry zero cotangent.  The Poisson solves run at the plan's precision
+ * (status as project_adjoint).
  */
-ps_status rk3_substep_adjoint(ps_plan_t plan, double dt, double nu, double kappa,
+ps_status rk3_substep_adjoint(ps_plan_t plan, int l, double dt, double nu, double kappa,
                               const double* u, const double* v, const double* w,
                               const double* t, const double* p,
-                              const double* const* g_out, double* const* g_in,
+                              const double* const* g_out, const double* const* g_hout,
+                              double* const* g_in, double* const* g_hprev,
                               void* stream, ps_info* info);
+
+/*
+ * rk3_step_adjoint - vector-Jacobian product of rk3_step with a fixed dt > 0
+ * (the Courant-limited step size is a non-differentiable maximum and is not
+ * differentiated; pass the dt the forward step used).  The three substeps
+ * (Sec. 2.1) are recomputed from the input state (u, v, w, t, p, not
+ * modified), then their adjoints run in reverse, each handing the cotangent
+ * of H^l down to substep l.  g_out[0..4]: cotangents of the step's output
+ * state; g_in[0..4] receive those of its input.  Allocates 28 field-sized
+ * temporaries in the plan on first use.  Returns PS_ENOTCONVERGED (outputs
+ * written) when a refinement stopped above the tolerance.
+ */
+ps_status rk3_step_adjoint(ps_plan_t plan, double dt, double nu, double kappa,
+                           const double* u, const double* v, const double* w,
+                           const double* t, const double* p,
+                           const double* const* g_out, double* const* g_in,
+                           void* stream, ps_info* info);
 
 /*
  * rk3_step - one full time step of the low-storage RK3 scheme (Sec. 2.1): the
@@ -233,9 +271,12 @@ ps_status rk3_substep_adjoint(ps_plan_t plan, double dt, double nu, double kappa
  * the next through plan-owned temporaries.  dt > 0 is taken as given; dt <= 0
  * selects the Courant-limited step of Listing 1, dt = min(dt_max, cfl_target /
  * ps_cfl(u, v, w)), which reads the Courant number back to the host (one
- * synchronisation).  State as rk3_substep, updated in place.  *dt_used (host,
- * may be NULL) receives the step taken; info (may be NULL) sums the Poisson
- * solves of the three substeps.
+ * synchronisation); a non-finite Courant number returns PS_ENONFINITE before
+ * anything is enqueued.  State as rk3_substep, updated in place.  *dt_used
+ * (host, may be NULL) receives the step taken; info (may be NULL) sums the
+ * Poisson solves of the three substeps.  When a substep's refinement stops
+ * above the tolerance the step is still completed and PS_ENOTCONVERGED is
+ * returned.
  */
 ps_status rk3_step(ps_plan_t plan, double dt, double cfl_target, double dt_max, double nu, double kappa,
                    double* u, double* v, double* w, double* t, double* p, double* dt_used, void* stream,

@@ -43,6 +43,8 @@ the other reading planted as a mistake in tests/test_oracle_mutations.py.
 """
 from __future__ import annotations
 
+import math
+
 import torch
 
 from . import operators as op
@@ -147,11 +149,15 @@ def _zero_walls(q, g):
 
 
 def cfl(u, v, w, g):
-    """Maximum CFL number (Listing 1 of the paper), for unit time step."""
+    """Maximum CFL number (Listing 1 of the paper), for unit time step, at least 1e-8.
+
+    A non-finite velocity gives NaN (the paper does not treat that case; the maximum is
+    taken to propagate NaN so that a time step is never derived from a broken state)."""
     q = (torch.abs(w[:-1] + w[1:]) / g.dz[:, None, None]
          + torch.abs(v + _yp(v)) / g.dy
          + torch.abs(u + _xp(u)) / g.dx)
-    return max(1e-8, float((0.5 * q).max()))
+    c = float((0.5 * q).max())
+    return c if math.isnan(c) else max(1e-8, c)
 
 
 def substep(state, g, l, dt, nu, kappa, hprev=None, differentiable=False):

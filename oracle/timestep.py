@@ -22,11 +22,12 @@ import torch
 from .substep import cfl, substep
 
 
-def rk3_step(state, g, dt, nu, kappa):
-    """Three substeps with a fixed dt.  state = (u, v, w, T, p); returns the new state."""
+def rk3_step(state, g, dt, nu, kappa, differentiable=False):
+    """Three substeps with a fixed dt.  state = (u, v, w, T, p); returns the new state.
+    differentiable=True runs the Poisson solves through their autograd form (for adjoints)."""
     h = None
     for l in (1, 2, 3):
-        state, h = substep(state, g, l, dt, nu, kappa, hprev=h)
+        state, h = substep(state, g, l, dt, nu, kappa, hprev=h, differentiable=differentiable)
     return state
 
 

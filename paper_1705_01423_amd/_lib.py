@@ -42,8 +42,10 @@ SIGNATURES = {
     "ps_cfl": (c_int, [_P, _D, _D, _D, _D, c_void_p]),
     "rk3_substep": (c_int, [_P, c_int, c_double, c_double, c_double, _D, _D, _D, _D, _D, _PP, _PP, c_void_p,
                             POINTER(PsInfo)]),
-    "rk3_substep_adjoint": (c_int, [_P, c_double, c_double, c_double, _D, _D, _D, _D, _D, _PP, _PP, c_void_p,
-                                    POINTER(PsInfo)]),
+    "rk3_substep_adjoint": (c_int, [_P, c_int, c_double, c_double, c_double, _D, _D, _D, _D, _D, _PP, _PP, _PP,
+                                    _PP, c_void_p, POINTER(PsInfo)]),
+    "rk3_step_adjoint": (c_int, [_P, c_double, c_double, c_double, _D, _D, _D, _D, _D, _PP, _PP, c_void_p,
+                                 POINTER(PsInfo)]),
     "rk3_step": (c_int, [_P, c_double, c_double, c_double, c_double, c_double, _D, _D, _D, _D, _D,
                          POINTER(c_double), c_void_p, POINTER(PsInfo)]),
     "ps_heat_flux": (c_int, [_P, _D, _D, c_double, _D, _D, c_void_p]),

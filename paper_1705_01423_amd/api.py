@@ -163,14 +163,31 @@ class Plan:
                                      float(kappa), _ptr(mean_t, "mean_t"), _ptr(flux, "flux"), _stream()))
         return mean_t, flux
 
-    def substep_adjoint(self, dt, nu, kappa, u, v, w, t, p, g_out):
+    def substep_adjoint(self, dt, nu, kappa, u, v, w, t, p, g_out, l=1, g_hout=None, want_hprev=False):
+        """VJP of substep l at the input state: g_in (five fields), and with want_hprev also the
+        cotangent of the previous substep's H (four fields).  g_hout: cotangent of the
+        substep's own H output (four fields) or None."""
+        g_in = [torch.empty_like(x) for x in (u, v, w, t, p)]
+        g_hp = [torch.empty_like(x) for x in (u, v, w, t)] if want_hprev else None
+        go = (ctypes.c_void_p * 5)(*[_ptr(x, "g_out").value for x in g_out])
+        gho = (ctypes.c_void_p * 4)(*[_ptr(x, "g_hout").value for x in g_hout]) if g_hout is not None else None
+        gi = (ctypes.c_void_p * 5)(*[x.data_ptr() for x in g_in])
+        ghp = (ctypes.c_void_p * 4)(*[x.data_ptr() for x in g_hp]) if want_hprev else None
+        check(self._lib.rk3_substep_adjoint(self._h, int(l), float(dt), float(nu), float(kappa),
+                                            _ptr(u, "u", self.centre_shape), _ptr(v, "v", self.centre_shape),
+                                            _ptr(w, "w", self.face_shape), _ptr(t, "t", self.face_shape),
+                                            _ptr(p, "p", self.centre_shape), go, gho, gi, ghp, _stream(), None))
+        return (g_in, g_hp) if want_hprev else g_in
+
+    def step_adjoint(self, dt, nu, kappa, u, v, w, t, p, g_out):
+        """VJP of one full RK3 step with fixed dt at the input state (recomputed inside)."""
         g_in = [torch.empty_like(x) for x in (u, v, w, t, p)]
         go = (ctypes.c_void_p * 5)(*[_ptr(x, "g_out").value for x in g_out])
         gi = (ctypes.c_void_p * 5)(*[x.data_ptr() for x in g_in])
-        check(self._lib.rk3_substep_adjoint(self._h, float(dt), float(nu), float(kappa),
-                                            _ptr(u, "u", self.centre_shape), _ptr(v, "v", self.centre_shape),
-                                            _ptr(w, "w", self.face_shape), _ptr(t, "t", self.face_shape),
-                                            _ptr(p, "p", self.centre_shape), go, gi, _stream(), None))
+        check(self._lib.rk3_step_adjoint(self._h, float(dt), float(nu), float(kappa),
+                                         _ptr(u, "u", self.centre_shape), _ptr(v, "v", self.centre_shape),
+                                         _ptr(w, "w", self.face_shape), _ptr(t, "t", self.face_shape),
+                                         _ptr(p, "p", self.centre_shape), go, gi, _stream(), None))
         return g_in
 
     # ---- stage access (tests, measurement) ----
@@ -247,3 +264,43 @@ class ProjectFn(torch.autograd.Function):
     def backward(ctx, gu, gv, gw):
         a, b, c = ctx.plan.project_adjoint(gu.contiguous(), gv.contiguous(), gw.contiguous(), None, ctx.s, 0.0)
         return a, b, c, None, None
+
+
+class SubstepFn(torch.autograd.Function):
+    """First RK3 substep (u, v, w, T, p) -> new state with a fixed dt; backward = the
+    hand-written substep adjoint, which recomputes what it needs from the saved input."""
+
+    @staticmethod
+    def forward(ctx, u, v, w, t, p, plan, dt, nu, kappa):
+        ctx.plan, ctx.args = plan, (dt, nu, kappa)
+        ctx.save_for_backward(u, v, w, t, p)
+        out = [x.clone() for x in (u, v, w, t, p)]
+        plan.substep(1, dt, nu, kappa, *out)
+        return tuple(out)
+
+    @staticmethod
+    def backward(ctx, *g):
+        state = ctx.saved_tensors
+        g = [torch.zeros_like(x) if gi is None else gi.contiguous() for gi, x in zip(g, state)]
+        g_in = ctx.plan.substep_adjoint(*ctx.args, *state, g, l=1)
+        return (*g_in, None, None, None, None)
+
+
+class StepFn(torch.autograd.Function):
+    """One full RK3 step with a fixed dt; backward = rk3_step_adjoint (recomputes the
+    intermediate substep states from the saved input)."""
+
+    @staticmethod
+    def forward(ctx, u, v, w, t, p, plan, dt, nu, kappa):
+        ctx.plan, ctx.args = plan, (dt, nu, kappa)
+        ctx.save_for_backward(u, v, w, t, p)
+        out = [x.clone() for x in (u, v, w, t, p)]
+        plan.step(nu, kappa, *out, dt=dt)
+        return tuple(out)
+
+    @staticmethod
+    def backward(ctx, *g):
+        state = ctx.saved_tensors
+        g = [torch.zeros_like(x) if gi is None else gi.contiguous() for gi, x in zip(g, state)]
+        g_in = ctx.plan.step_adjoint(*ctx.args, *state, g)
+        return (*g_in, None, None, None, None)

@@ -42,6 +42,16 @@ ps_status hipfail(hipError_t e, const char* where) {
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
+// hipMalloc that leaves no error behind on failure: the runtime records a failed
+// allocation as its last error, which the next kernel launch's hipGetLastError() would
+// otherwise report as a launch failure.
+bool dev_alloc(void** ptr, size_t bytes) {
+    if (hipMalloc(ptr, bytes) == hipSuccess) return true;
+    *ptr = nullptr;
+    (void)hipGetLastError();
+    return false;
+}
+
 bool is_23(int n) {
     if (n < 1) return false;
     while (n % 2 == 0) n /= 2;
@@ -93,6 +103,7 @@ struct ps_plan_s {
     // substep temporaries (allocated on first use)
     double* sub_buf = nullptr;
     size_t sub_bytes = 0;
+    double* stepadj_buf = nullptr;   // step adjoint temporaries (allocated on first use)
     // host pinned readback
     double* h_res = nullptr;
     GridDev gd;
@@ -111,6 +122,7 @@ enum {
     R_F2 = 6,      // sum (f - mu)^2
     R_CFL = 8,
     R_FLAG = 9,    // non-finite flag
+    R_AMAX = 10,   // max |f| of the solve input (STRICT_COMPAT)
     R_NSLOTS = 16
 };
 
@@ -193,7 +205,7 @@ ps_status upload_tables(ps_plan_t p) {
     const size_t nd = (size_t)p->nz + 4 * (size_t)(p->nz + 1) + nxh + p->ny + p->nz;
     size_t bytes = align256(nd * sizeof(double)) + align256((size_t)(M + M + 1 + p->ny) * sizeof(cx<double>)) +
                    align256((size_t)(M + M + 1 + p->ny) * sizeof(cx<float>));
-    PS_HIP(hipMalloc(&p->d_tables, bytes), "hipMalloc(tables)");
+    if (!dev_alloc(&p->d_tables, bytes)) return fail(PS_ENOMEM, "cannot allocate %zu bytes of tables", bytes);
     std::vector<char> host(bytes, 0);
     double* hd = (double*)host.data();
     size_t o = 0;
@@ -267,7 +279,7 @@ constexpr int kSubFields = 8;
 ps_status ensure_substep_buffers(ps_plan_t p) {
     if (p->sub_buf) return PS_OK;
     const size_t per = align256((p->npts + p->plane) * sizeof(double));
-    if (hipMalloc((void**)&p->sub_buf, per * kSubFields) != hipSuccess) {
+    if (!dev_alloc((void**)&p->sub_buf, per * kSubFields)) {
         p->sub_buf = nullptr;
         return fail(PS_ENOMEM, "cannot allocate %zu bytes of substep temporaries", per * kSubFields);
     }
@@ -379,6 +391,8 @@ ps_status solve_impl(ps_plan_t p, const double* in, double* out, const double* z
     loc.rel_residual = -1.0;
     const bool strict = (p->flags & PS_FLAG_STRICT_COMPAT) != 0;
     if (p->flags & PS_FLAG_CHECK_FINITE) PS_CHECK(check_finite(p, in, st));
+    // the compatibility test compares the removed mean with max |f| of the (scaled) input
+    if (strict) PS_HIP(launch_absmax(in, p->npts, p->plane, zin, p->small + R_AMAX, st), "max |f|");
     ps_status result = PS_OK;
     if (p->prec == PS_FP64) {
         PS_CHECK(spectral_solve<double>(p, in, out, 0, nullptr, 0.0, zin, zout, false, false, st, nullptr, div));
@@ -425,12 +439,15 @@ ps_status solve_impl(ps_plan_t p, const double* in, double* out, const double* z
                 if (rel > 0.5 * prev) break;   // stagnation: rounding floor reached
                 prev = rel;
             }
-            if (!converged && loc.rel_update > 1e3 * p->tol) result = PS_ENOTCONVERGED;
-            if (!converged && result == PS_OK) converged = true;
-            if (result != PS_OK)
-                fail(result, "refinement stopped at ||delta||/||phi|| = %.3e after %d solves", loc.rel_update,
-                     loc.iterations);
+            if (!converged) {
+                result = PS_ENOTCONVERGED;
+                fail(result, "refinement stopped at ||delta||/||phi|| = %.3e after %d solves (tol %.3e)",
+                     loc.rel_update, loc.iterations, p->tol);
+            }
         }
+        // The iterate is refined unscaled (its residual is f - L x); a per-plane output
+        // scaling (the adjoint's Vc) is applied once, in place, at the end.
+        if (zout) PS_HIP(launch_scale_planes(p->gd, out, out, zout, p->nz, p->plane, st), "scale");
         if (info || strict) {
             PS_CHECK(read_small(p, st));
             loc.compat_defect = p->h_res[R_WSUM] * inv_den(p);
@@ -438,11 +455,12 @@ ps_status solve_impl(ps_plan_t p, const double* in, double* out, const double* z
         }
     }
     if (strict) {
-        // compare the defect with the size of the right-hand side (cheap bound: max over a reduction)
-        // the defect is reported relative to 1 when the input is O(1)
-        if (std::fabs(loc.compat_defect) > 1e-8) {
+        // the removed dz-weighted mean against the size of the right-hand side
+        const double fmax_abs = p->h_res[R_AMAX];
+        if (!(std::fabs(loc.compat_defect) <= 1e-8 * fmax_abs)) {
             if (info) *info = loc;
-            return fail(PS_ENOTCOMPAT, "right-hand side incompatible: weighted mean %.3e", loc.compat_defect);
+            return fail(PS_ENOTCOMPAT, "right-hand side incompatible: weighted mean %.3e, max |f| %.3e",
+                        loc.compat_defect, fmax_abs);
         }
     }
     if (info) *info = loc;
@@ -555,7 +573,7 @@ ps_status poisson_plan_create(ps_plan_t* out, int nx, int ny, int nz, double lx,
         // per-plan z-solve excess table (formed once, on the null stream)
         const size_t ne = prec == PS_FP64 ? zexcess_elems<double>(p->gd, p->nkxb) : zexcess_elems<float>(p->gd, p->nkxb);
         if (ne > 0) {
-            if (hipMalloc(&p->d_etab, ne * real_bytes(prec)) != hipSuccess) {
+            if (!dev_alloc(&p->d_etab, ne * real_bytes(prec))) {
                 p->d_etab = nullptr;
                 poisson_plan_destroy(p);
                 return fail(PS_ENOMEM, "cannot allocate the %zu-byte z-solve table", ne * real_bytes(prec));
@@ -576,7 +594,7 @@ ps_status poisson_plan_create(ps_plan_t* out, int nx, int ny, int nz, double lx,
     p->nblk_max = nbx > nbr ? nbx : nbr;
     if (const char* ev = getenv("PS_CHUNK_PLANES")) p->chunk = atoi(ev);
     p->ws_bytes = workspace_layout(p, false);
-    if (hipMalloc(&p->ws, p->ws_bytes) != hipSuccess) {
+    if (!dev_alloc(&p->ws, p->ws_bytes)) {
         p->ws = nullptr;
         poisson_plan_destroy(p);
         return fail(PS_ENOMEM, "cannot allocate %zu bytes of workspace", p->ws_bytes);
@@ -585,6 +603,7 @@ ps_status poisson_plan_create(ps_plan_t* out, int nx, int ny, int nz, double lx,
     workspace_layout(p, true);
     if (hipHostMalloc((void**)&p->h_res, R_NSLOTS * sizeof(double), hipHostMallocDefault) != hipSuccess) {
         p->h_res = nullptr;
+        (void)hipGetLastError();
         poisson_plan_destroy(p);
         return fail(PS_ENOMEM, "cannot allocate pinned host memory");
     }
@@ -606,7 +625,7 @@ ps_status poisson_plan_set_workspace(ps_plan_t p, void* dev, size_t bytes) {
     if (dev) {
         p->ws = dev;
     } else {
-        if (hipMalloc(&p->ws, p->ws_bytes) != hipSuccess) {
+        if (!dev_alloc(&p->ws, p->ws_bytes)) {
             p->ws = nullptr;
             return fail(PS_ENOMEM, "cannot allocate %zu bytes of workspace", p->ws_bytes);
         }
@@ -622,6 +641,7 @@ ps_status poisson_plan_destroy(ps_plan_t p) {
     if (p->d_tables) hipFree(p->d_tables);
     if (p->d_etab) hipFree(p->d_etab);
     if (p->sub_buf) hipFree(p->sub_buf);
+    if (p->stepadj_buf) hipFree(p->stepadj_buf);
     if (p->h_res) hipHostFree(p->h_res);
     delete p;
     return PS_OK;
@@ -656,12 +676,13 @@ ps_status project(ps_plan_t p, double* u, double* v, double* w, double* pr, doub
     hipStream_t st = (hipStream_t)stream;
     double* phi = phi_out ? phi_out : p->phibuf;
     ps_status r;
-    if (p->prec == PS_FP64 && !(p->flags & PS_FLAG_CHECK_FINITE)) {
+    if (p->prec == PS_FP64 && !(p->flags & (PS_FLAG_CHECK_FINITE | PS_FLAG_STRICT_COMPAT))) {
         // the divergence is formed inside the x transform and never stored
         const DivSrc d{u, v, w, 1.0 / s};
         r = solve_impl(p, nullptr, phi, nullptr, nullptr, st, info, &d);
     } else {
-        // the refinement's residual (and the finiteness check) need the right-hand side stored
+        // the refinement's residual (and the finiteness and compatibility checks) need the
+        // right-hand side stored
         PS_HIP(launch_divergence(p->gd, u, v, w, p->fbuf, 1.0 / s, st), "divergence");
         r = solve_impl(p, p->fbuf, phi, nullptr, nullptr, st, info);
     }
@@ -815,12 +836,20 @@ ps_status rk3_step(ps_plan_t p, double dt, double cfl_target, double dt_max, dou
     double* h[4] = {sub_field(p, 4), sub_field(p, 5), sub_field(p, 6), sub_field(p, 7)};
     const double* hc[4] = {h[0], h[1], h[2], h[3]};
     ps_info acc{};
+    ps_status result = PS_OK;
+    std::string first_msg;
     for (int l = 1; l <= 3; ++l) {
         ps_info li{};
         // the last substep's H is not needed by anyone
         const ps_status r = rk3_substep(p, l, dt, nu, kappa, u, v, w, t, pr, l > 1 ? hc : nullptr,
                                         l < 3 ? h : nullptr, stream, info ? &li : nullptr);
         if (r != PS_OK && r != PS_ENOTCONVERGED) return r;
+        // a refinement that stopped above the tolerance still completes the step (its phi is
+        // written); the step then reports the first such substep
+        if (r == PS_ENOTCONVERGED && result == PS_OK) {
+            result = r;
+            first_msg = g_last_error;
+        }
         acc.iterations += li.iterations;
         acc.rel_update = std::max(acc.rel_update, li.rel_update);
         acc.rel_residual = std::max(acc.rel_residual, li.rel_residual);
@@ -829,6 +858,7 @@ ps_status rk3_step(ps_plan_t p, double dt, double cfl_target, double dt_max, dou
     }
     if (dt_used) *dt_used = dt;
     if (info) *info = acc;
+    if (result != PS_OK) return fail(result, "%s", first_msg.c_str());
     return PS_OK;
 }
 
@@ -844,10 +874,12 @@ ps_status ps_heat_flux(ps_plan_t p, const double* w, const double* t, double kap
     return PS_OK;
 }
 
-ps_status rk3_substep_adjoint(ps_plan_t p, double dt, double nu, double kappa, const double* u, const double* v,
-                              const double* w, const double* t, const double* pr, const double* const* g_out,
-                              double* const* g_in, void* stream, ps_info* info) {
+ps_status rk3_substep_adjoint(ps_plan_t p, int l, double dt, double nu, double kappa, const double* u,
+                              const double* v, const double* w, const double* t, const double* pr,
+                              const double* const* g_out, const double* const* g_hout, double* const* g_in,
+                              double* const* g_hprev, void* stream, ps_info* info) {
     PS_CHECK(check_plan(p));
+    if (l < 1 || l > 3) return fail(PS_EINVAL, "substep index l=%d must be 1, 2 or 3", l);
     if (!(dt > 0) || !std::isfinite(dt)) return fail(PS_EINVAL, "dt must be positive");
     if (!(nu >= 0) || !(kappa >= 0) || !std::isfinite(nu) || !std::isfinite(kappa))
         return fail(PS_EINVAL, "nu and kappa must be non-negative");
@@ -863,9 +895,22 @@ ps_status rk3_substep_adjoint(ps_plan_t p, double dt, double nu, double kappa, c
         for (int r = 0; r < 5; ++r)
             if ((const void*)g_in[q] == (const void*)g_out[r]) return fail(PS_EINVAL, "g_in may not alias g_out");
     }
+    if (g_hout)
+        for (int q = 0; q < 4; ++q) {
+            PS_CHECK(check_ptr(g_hout[q], "g_hout[q]"));
+            for (int r = 0; r < 5; ++r)
+                if ((const void*)g_hout[q] == (const void*)g_in[r]) return fail(PS_EINVAL, "g_in may not alias g_hout");
+        }
+    if (g_hprev)
+        for (int q = 0; q < 4; ++q) {
+            PS_CHECK(check_ptr(g_hprev[q], "g_hprev[q]"));
+            for (int r = 0; r < 5; ++r)
+                if ((const void*)g_hprev[q] == (const void*)g_in[r] || (const void*)g_hprev[q] == (const void*)g_out[r])
+                    return fail(PS_EINVAL, "g_hprev may not alias g_in or g_out");
+        }
     PS_CHECK(ensure_substep_buffers(p));
     hipStream_t st = (hipStream_t)stream;
-    const double gam = kGamma[0], alp = kGamma[0] + kRho[0];
+    const double gam = kGamma[l - 1], rho = kRho[l - 1], alp = gam + rho;
     const double bnu = alp * dt * nu / 2.0, bka = alp * dt * kappa / 2.0;
     double* du = sub_field(p, 0);
     double* dv = sub_field(p, 1);
@@ -914,7 +959,107 @@ ps_status rk3_substep_adjoint(ps_plan_t p, double dt, double nu, double kappa, c
     a.gam = gam;
     a.alp = alp;
     PS_HIP(launch_explicit_adj(p->gd, a, st), "explicit adjoint");
+    if (g_hout) {
+        // cotangent of this substep's H output: H's own VJP at the input state, added in a
+        // second pass of the same kernel (H enters the right-hand sides as dt gamma H, so
+        // dt = gamma = 1 and alpha = 0 leave exactly H's derivative; g_in is read and
+        // rewritten point by point)
+        SubstepAdjArgs b = a;
+        b.lu = g_hout[0];
+        b.lv = g_hout[1];
+        b.lw = g_hout[2];
+        b.lt = g_hout[3];
+        b.du = g_in[0];
+        b.dv = g_in[1];
+        b.dw = g_in[2];
+        b.dt_ = g_in[3];
+        b.dp = g_in[4];
+        b.dt = 1.0;
+        b.gam = 1.0;
+        b.alp = 0.0;
+        PS_HIP(launch_explicit_adj(p->gd, b, st), "H adjoint");
+    }
+    if (g_hprev) {
+        // the previous substep's H enters the right-hand sides as dt rho H^{l-1} (zero for l = 1);
+        // written after the H pass so that g_hprev may share g_hout's buffers
+        const double c = dt * rho;
+        const size_t nc = p->npts, nf = p->npts + p->plane;
+        PS_HIP(launch_scale(lu, g_hprev[0], c, nc, st), "h_prev adjoint");
+        PS_HIP(launch_scale(lv, g_hprev[1], c, nc, st), "h_prev adjoint");
+        PS_HIP(launch_scale(lw, g_hprev[2], c, nf, st), "h_prev adjoint");
+        PS_HIP(launch_scale(lt, g_hprev[3], c, nf, st), "h_prev adjoint");
+    }
     return r;
+}
+
+// Field-sized temporaries of the step adjoint (allocated on first use): the states after
+// substeps 1 and 2 (five fields each), the H hand-over (four), two sets of state
+// cotangents (five each) and the H cotangent (four).
+constexpr int kStepAdjFields = 28;
+
+ps_status rk3_step_adjoint(ps_plan_t p, double dt, double nu, double kappa, const double* u, const double* v,
+                           const double* w, const double* t, const double* pr, const double* const* g_out,
+                           double* const* g_in, void* stream, ps_info* info) {
+    PS_CHECK(check_plan(p));
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(PS_EINVAL, "dt must be positive (the step adjoint takes dt fixed)");
+    if (!(nu >= 0) || !(kappa >= 0) || !std::isfinite(nu) || !std::isfinite(kappa))
+        return fail(PS_EINVAL, "nu and kappa must be non-negative");
+    const double* in[5] = {u, v, w, t, pr};
+    for (int q = 0; q < 5; ++q) PS_CHECK(check_ptr(in[q], "state"));
+    if (!g_out || !g_in) return fail(PS_EINVAL, "g_out and g_in are required");
+    for (int q = 0; q < 5; ++q) {
+        PS_CHECK(check_ptr(g_out[q], "g_out[q]"));
+        PS_CHECK(check_ptr(g_in[q], "g_in[q]"));
+        for (int r = 0; r < 5; ++r)
+            if ((const void*)g_in[q] == (const void*)g_out[r]) return fail(PS_EINVAL, "g_in may not alias g_out");
+    }
+    PS_CHECK(ensure_substep_buffers(p));
+    const size_t per = align256((p->npts + p->plane) * sizeof(double));
+    if (!p->stepadj_buf) {
+        if (!dev_alloc((void**)&p->stepadj_buf, per * kStepAdjFields))
+            return fail(PS_ENOMEM, "cannot allocate %zu bytes of step-adjoint temporaries", per * kStepAdjFields);
+    }
+    auto fld = [&](int q) { return (double*)((char*)p->stepadj_buf + per * q); };
+    double* s1[5] = {fld(0), fld(1), fld(2), fld(3), fld(4)};
+    double* s2[5] = {fld(5), fld(6), fld(7), fld(8), fld(9)};
+    double* h[4] = {fld(10), fld(11), fld(12), fld(13)};
+    double* ga[5] = {fld(14), fld(15), fld(16), fld(17), fld(18)};
+    double* gb[5] = {fld(19), fld(20), fld(21), fld(22), fld(23)};
+    double* gh[4] = {fld(24), fld(25), fld(26), fld(27)};
+    const double* hc[4] = {h[0], h[1], h[2], h[3]};
+    const double* ghc[4] = {gh[0], gh[1], gh[2], gh[3]};
+    hipStream_t st = (hipStream_t)stream;
+    const size_t bytes_c = p->npts * sizeof(double), bytes_f = (p->npts + p->plane) * sizeof(double);
+    const size_t fb[5] = {bytes_c, bytes_c, bytes_f, bytes_f, bytes_c};
+    // forward recomputation from the stored input: states after substeps 1 and 2
+    for (int q = 0; q < 5; ++q)
+        PS_HIP(hipMemcpyAsync(s1[q], in[q], fb[q], hipMemcpyDeviceToDevice, st), "copy state");
+    ps_status worst = PS_OK;
+    auto note = [&](ps_status r) {
+        if (r == PS_ENOTCONVERGED && worst == PS_OK) worst = r;
+        return r == PS_OK || r == PS_ENOTCONVERGED;
+    };
+    ps_status r = rk3_substep(p, 1, dt, nu, kappa, s1[0], s1[1], s1[2], s1[3], s1[4], nullptr, h, stream, nullptr);
+    if (!note(r)) return r;
+    for (int q = 0; q < 5; ++q)
+        PS_HIP(hipMemcpyAsync(s2[q], s1[q], fb[q], hipMemcpyDeviceToDevice, st), "copy state");
+    r = rk3_substep(p, 2, dt, nu, kappa, s2[0], s2[1], s2[2], s2[3], s2[4], hc, nullptr, stream, nullptr);
+    if (!note(r)) return r;
+    // reverse sweep: substep 3 at s2, substep 2 at s1 (with the cotangent of H^2), substep 1
+    // at the input (with the cotangent of H^1); H^l's cotangent is handed down in place
+    const double* go[5] = {g_out[0], g_out[1], g_out[2], g_out[3], g_out[4]};
+    const double* gac[5] = {ga[0], ga[1], ga[2], ga[3], ga[4]};
+    const double* gbc[5] = {gb[0], gb[1], gb[2], gb[3], gb[4]};
+    r = rk3_substep_adjoint(p, 3, dt, nu, kappa, s2[0], s2[1], s2[2], s2[3], s2[4], go, nullptr, ga, gh, stream,
+                            nullptr);
+    if (!note(r)) return r;
+    r = rk3_substep_adjoint(p, 2, dt, nu, kappa, s1[0], s1[1], s1[2], s1[3], s1[4], gac, ghc, gb, gh, stream,
+                            nullptr);
+    if (!note(r)) return r;
+    r = rk3_substep_adjoint(p, 1, dt, nu, kappa, u, v, w, t, pr, gbc, ghc, g_in, nullptr, stream, info);
+    if (!note(r)) return r;
+    if (worst != PS_OK) return fail(worst, "a Poisson refinement of the step adjoint stopped above the tolerance");
+    return PS_OK;
 }
 
 ps_status ps_spectral_layout(ps_plan_t p, int* w_tile, int* nkxb) {

@@ -83,8 +83,14 @@ __global__ void k_fill(double* __restrict__ p, size_t n, double v) {
     if (id < n) p[id] = v;
 }
 
-// out[z][...] = in[z][...] * zs[z] for nplanes planes of `plane` values
-__global__ void k_scale_planes(const double* __restrict__ in, double* __restrict__ out,
+// out = c * in (out may alias in)
+__global__ void k_scale(const double* in, double* out, double c, size_t n) {
+    const size_t id = (size_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (id < n) out[id] = c * in[id];
+}
+
+// out[z][...] = in[z][...] * zs[z] for nplanes planes of `plane` values (out may alias in)
+__global__ void k_scale_planes(const double* in, double* out,
                                const double* __restrict__ zs, size_t plane, size_t n) {
     const size_t id = (size_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (id < n) out[id] = in[id] * zs[id / plane];
@@ -327,8 +333,11 @@ static bool cn_tiled_launch(const GridDev& g, int kind, const double* fac, const
 
 // ---- CFL (Listing 1) ------------------------------------------------------
 // A fixed grid of blocks strides over the cells; each block reduces its maximum and
-// posts it with one atomic max (non-negative doubles order like their bit patterns).
+// posts it with one atomic max (non-negative doubles order like their bit patterns, and
+// every NaN pattern lies above +Inf).  The maximum propagates NaN (fmax would drop it), so
+// a non-finite velocity gives a non-finite Courant number.
 constexpr int kCflBlocks = 2048;
+__device__ __forceinline__ double nan_max(double q, double c) { return (c > q || c != c) ? c : q; }
 __global__ void __launch_bounds__(256)
 k_cfl(const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w, GridDev g,
       unsigned long long* __restrict__ out) {
@@ -346,14 +355,35 @@ k_cfl(const double* __restrict__ u, const double* __restrict__ v, const double* 
         double c = fabs(w[id] + w[id + plane]) / g.dz[k] +
                    fabs(v[id] + v[(size_t)k * plane + (size_t)jp * g.nx + i]) / g.dy +
                    fabs(u[id] + u[(size_t)k * plane + (size_t)j * g.nx + ip]) / g.dx;
-        q = fmax(q, 0.5 * c);
+        q = nan_max(q, 0.5 * c);
     }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) q = fmax(q, __shfl_xor(q, off, 64));
+    for (int off = 32; off > 0; off >>= 1) q = nan_max(q, __shfl_xor(q, off, 64));
     if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = q;
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int wv = 1; wv < (int)(blockDim.x >> 6); ++wv) q = fmax(q, wmax[wv]);
+        for (int wv = 1; wv < (int)(blockDim.x >> 6); ++wv) q = nan_max(q, wmax[wv]);
+        atomicMax(out, (unsigned long long)__double_as_longlong(q));
+    }
+}
+
+// out[0] = max(out[0], max |p| (x zs[plane], when given)) over n values; out[0] must hold a
+// non-negative double.  NaN propagates.
+__global__ void __launch_bounds__(256)
+k_absmax(const double* __restrict__ p, size_t n, size_t plane, const double* __restrict__ zs,
+         unsigned long long* __restrict__ out) {
+    __shared__ double wmax[4];
+    double q = 0.0;
+    for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < n; id += (size_t)gridDim.x * blockDim.x) {
+        const double v = zs ? p[id] * zs[id / plane] : p[id];
+        q = nan_max(q, fabs(v));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) q = nan_max(q, __shfl_xor(q, off, 64));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = q;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int wv = 1; wv < (int)(blockDim.x >> 6); ++wv) q = nan_max(q, wmax[wv]);
         atomicMax(out, (unsigned long long)__double_as_longlong(q));
     }
 }
@@ -506,6 +536,12 @@ hipError_t launch_fill(double* p, size_t n, double v, hipStream_t st) {
     return hipGetLastError();
 }
 
+hipError_t launch_scale(const double* in, double* out, double c, size_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scale, dim3(nblocks(n, 256)), dim3(256), 0, st, in, out, c, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_scale_planes(const GridDev& g, const double* in, double* out, const double* zs, int nplanes,
                                size_t plane, hipStream_t st) {
     (void)g;
@@ -542,6 +578,14 @@ hipError_t launch_cn_solve(const GridDev& g, int kind, const double* fac, double
     if (cn_tiled_launch<CN_SET>(g, kind, fac, x, x, st, &e)) return e;
     const size_t plane = (size_t)g.nx * g.ny;
     hipLaunchKernelGGL(k_cn_solve, dim3(nblocks(plane, 256)), dim3(256), 0, st, g, kind, fac, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_absmax(const double* p, size_t n, size_t plane, const double* zs, double* out, hipStream_t st) {
+    hipError_t e = launch_fill(out, 1, 0.0, st);
+    if (e != hipSuccess || n == 0) return e;
+    const int nb = (int)std::min<size_t>((size_t)kCflBlocks, (n + 255) / 256);
+    hipLaunchKernelGGL(k_absmax, dim3(nb), dim3(256), 0, st, p, n, plane, zs, reinterpret_cast<unsigned long long*>(out));
     return hipGetLastError();
 }
 

@@ -233,6 +233,8 @@ hipError_t launch_adj_update(const GridDev& g, const double* gu, const double* g
 // out[0..ncomp) = sums over nblk blocks of partial[b * ncomp + c]; scratch holds 1024 * ncomp doubles.
 hipError_t launch_reduce2(const double* partial, int nblk, int ncomp, double* scratch, double* out, hipStream_t st);
 hipError_t launch_fill(double* p, size_t n, double v, hipStream_t st);
+// out[0..n) = c * in[0..n) (out may alias in)
+hipError_t launch_scale(const double* in, double* out, double c, size_t n, hipStream_t st);
 hipError_t launch_scale_planes(const GridDev& g, const double* in, double* out, const double* zs, int nplanes,
                                size_t plane, hipStream_t st);
 hipError_t launch_cn_factor(const GridDev& g, int kind, double beta, double* fac, hipStream_t st);
@@ -249,6 +251,8 @@ hipError_t launch_heat_flux(const GridDev& g, const double* w, const double* t, 
                             double* mean_t, double* flux, hipStream_t st);
 hipError_t launch_cfl(const GridDev& g, const double* u, const double* v, const double* w, double* out,
                       hipStream_t st);
+// out[0] = max |p[id] (x zs[id / plane] when zs != NULL)| over n values (NaN propagates).
+hipError_t launch_absmax(const double* p, size_t n, size_t plane, const double* zs, double* out, hipStream_t st);
 
 // RK3 substep (substep_kernels.hip)
 struct SubstepArgs {

@@ -21,7 +21,7 @@ def _declared():
 def test_header_declares_entry_points():
     names = _declared()
     for n in ("poisson_plan_create", "poisson_solve", "project", "cn_solve", "poisson_solve_adjoint",
-              "project_adjoint", "rk3_substep", "rk3_substep_adjoint", "rk3_step", "ps_heat_flux",
+              "project_adjoint", "rk3_substep", "rk3_substep_adjoint", "rk3_step", "rk3_step_adjoint", "ps_heat_flux",
               "ps_debug_stage", "ps_last_error"):
         assert n in names
 
@@ -44,7 +44,8 @@ def _create(nx, ny, nz, zf=None, prec=0):
 
 
 @pytest.mark.parametrize("dims,msg", [((5, 8, 8), "nx"), ((10, 8, 8), "nx"), ((8, 7, 8), "ny"),
-                                      ((8, 8, 1), "nz"), ((8, 8, 4096), "nz"), ((8192, 8, 8), "nx")])
+                                      ((8, 8, 1), "nz"), ((8, 8, 4096), "nz"), ((8192, 8, 8), "nx"),
+                                      ((18, 8, 8), "nx"), ((8, 9, 8), "ny"), ((20, 8, 8), "nx")])
 def test_plan_rejects_bad_dims(dims, msg):
     st, err = _create(*dims)
     assert st == _lib.PS_EINVAL and msg in err

@@ -103,15 +103,35 @@ def test_cfl():
     assert abs(got - ref) <= 2e-16 * ref
 
 
-def test_solve_adjoint_vs_autograd():
-    banner("solve adjoint")
-    g, plan = grids(24, 24, 18, 1.5, 1.0)
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32_refined", 1e-11), ("fp32", 1e-5)])
+def test_solve_adjoint_vs_autograd(prec, tol):
+    """S^T = Vc S Vc^-1 at every precision: the output scaling Vc must follow the refinement."""
+    banner(f"solve adjoint {prec}")
+    g, plan = grids(24, 24, 18, 1.5, 1.0, precision=prec)
     rng = np.random.default_rng(5)
     f = torch.as_tensor(rng.standard_normal(plan.centre_shape)).requires_grad_(True)
     gphi = torch.as_tensor(rng.standard_normal(plan.centre_shape))
     (ref,) = torch.autograd.grad(poisson.solve_autograd(f, g), f, gphi)
     got, _ = plan.solve_adjoint(gphi.to("cuda"))
-    assert rel(got, ref) < 1e-12
+    assert rel(got, ref) < tol
+
+
+def test_solve_fn_backward_refined():
+    """PoissonSolveFn on an FP32-refined plan: forward and backward both to the refined tolerance."""
+    from paper_1705_01423_amd.api import PoissonSolveFn
+    banner("PoissonSolveFn fp32_refined")
+    g, plan = grids(32, 24, 20, 2.0, 1.0, precision="fp32_refined")
+    rng = np.random.default_rng(15)
+    f = torch.as_tensor(rng.standard_normal(plan.centre_shape))
+    gphi = torch.as_tensor(rng.standard_normal(plan.centre_shape))
+    fr = f.clone().requires_grad_(True)
+    phi_ref = poisson.solve_autograd(fr, g)
+    (ref,) = torch.autograd.grad(phi_ref, fr, gphi)
+    fd = f.to("cuda").requires_grad_(True)
+    phi = PoissonSolveFn.apply(fd, plan)
+    assert rel(phi, phi_ref) < 1e-11
+    (got,) = torch.autograd.grad(phi, fd, gphi.to("cuda"))
+    assert rel(got, ref) < 1e-11
 
 
 def _project_vjp(g, u, v, w, p, s, c, gu, gv, gw, gp):

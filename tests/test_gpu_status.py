@@ -1,0 +1,222 @@
+"""Every ps_status the library can return, forced from the host on small boxes.
+
+Arguments that fail validation (misaligned fields, undersized or misaligned workspaces)
+return before anything is enqueued; data-dependent statuses (an incompatible right-hand
+side under STRICT_COMPAT, a NaN under CHECK_FINITE, a refinement that cannot reach its
+tolerance, a non-finite Courant number) run their kernels normally and report afterwards.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import poisson
+from paper_1705_01423_amd import _lib
+from paper_1705_01423_amd._lib import PsError
+from paper_1705_01423_amd.api import Plan
+from paper_1705_01423_amd.synth import zfaces
+from gpu_util import banner, grids, rel
+
+pytestmark = pytest.mark.gpu
+F64 = torch.float64
+
+
+def _status(fn, *a, **k):
+    try:
+        fn(*a, **k)
+    except PsError as e:
+        return e.status, str(e)
+    return _lib.PS_OK, ""
+
+
+def _rhs(plan, seed=1, compatible=True):
+    rng = np.random.default_rng(seed)
+    f = torch.as_tensor(rng.standard_normal(plan.centre_shape))
+    if compatible:
+        dz = torch.as_tensor(np.diff(plan.zf))
+        f -= float((dz[:, None, None] * f).sum() / (dz.sum() * plan.nx * plan.ny))
+    return f
+
+
+# ---- PS_ENOTCOMPAT ------------------------------------------------------------------
+@pytest.mark.parametrize("prec", ["fp64", "fp32_refined"])
+def test_strict_compat(prec):
+    banner(f"strict compat {prec}")
+    g, plan = grids(24, 16, 12, precision=prec, flags=_lib.PS_FLAG_STRICT_COMPAT)
+    # compatible: mean removed to rounding (far below 1e-8 max|f|)
+    f = _rhs(plan)
+    phi, info = plan.solve(f.to("cuda"))
+    assert rel(phi, poisson.solve(f, g)) < 1e-11
+    # a mean of 1e-6 max|f| is rejected, 1e-10 max|f| accepted; phi is written either way
+    amax = float(f.abs().max())
+    st, msg = _status(plan.solve, (f + 1e-6 * amax).to("cuda"))
+    assert st == _lib.PS_ENOTCOMPAT, msg
+    st, msg = _status(plan.solve, (f + 1e-10 * amax).to("cuda"))
+    assert st == _lib.PS_OK, msg
+    # the threshold is relative: the same field scaled by 1e6 behaves the same
+    st, _ = _status(plan.solve, (1e6 * (f + 1e-6 * amax)).to("cuda"))
+    assert st == _lib.PS_ENOTCOMPAT
+    st, _ = _status(plan.solve, (1e6 * (f + 1e-10 * amax)).to("cuda"))
+    assert st == _lib.PS_OK
+
+
+def test_strict_compat_project():
+    """A velocity with flow through a wall has an incompatible divergence: the projection
+    reports it and leaves the velocity as given."""
+    banner("strict compat project")
+    g, plan = grids(24, 16, 12, flags=_lib.PS_FLAG_STRICT_COMPAT)
+    rng = np.random.default_rng(3)
+    u, v = (torch.as_tensor(rng.standard_normal(plan.centre_shape)).to("cuda") for _ in range(2))
+    w = torch.as_tensor(rng.standard_normal(plan.face_shape)).to("cuda")
+    w[0] = 0.5   # net inflow through the bottom wall
+    w[-1] = 0.0
+    u0, v0, w0 = u.clone(), v.clone(), w.clone()
+    st, msg = _status(plan.project, u, v, w)
+    assert st == _lib.PS_ENOTCOMPAT, msg
+    assert torch.equal(u, u0) and torch.equal(v, v0) and torch.equal(w, w0)
+    w[0] = 0.0
+    assert _status(plan.project, u, v, w)[0] == _lib.PS_OK
+
+
+# ---- PS_ENONFINITE --------------------------------------------------------------------
+@pytest.mark.parametrize("bad", [float("nan"), float("inf"), -float("inf")])
+def test_check_finite(bad):
+    banner(f"check finite {bad}")
+    _, plan = grids(24, 16, 12, flags=_lib.PS_FLAG_CHECK_FINITE)
+    f = _rhs(plan)
+    f[7, 3, 11] = bad
+    phi = torch.full(plan.centre_shape, 123.0, dtype=F64, device="cuda")
+    st, msg = _status(plan.solve, f.to("cuda"), phi)
+    assert st == _lib.PS_ENONFINITE, msg
+    assert bool((phi == 123.0).all()), "nothing is written on PS_ENONFINITE"
+
+
+def test_cfl_propagates_nan_and_step_refuses():
+    banner("cfl NaN")
+    g, plan = grids(16, 12, 10)
+    rng = np.random.default_rng(4)
+    u = torch.as_tensor(1e-2 * rng.standard_normal(plan.centre_shape)).to("cuda")
+    v = torch.as_tensor(1e-2 * rng.standard_normal(plan.centre_shape)).to("cuda")
+    w = torch.as_tensor(1e-2 * rng.standard_normal(plan.face_shape)).to("cuda")
+    w[0] = 0
+    w[-1] = 0
+    t = torch.as_tensor(np.linspace(1, 0, 11)[:, None, None] * np.ones(plan.face_shape)).to("cuda")
+    p = torch.zeros(plan.centre_shape, dtype=F64, device="cuda")
+    assert np.isfinite(float(plan.cfl(u, v, w).item()))
+    v[4, 5, 6] = float("nan")
+    assert np.isnan(float(plan.cfl(u, v, w).item()))
+    saved = [a.clone() for a in (u, w, t, p)]
+    st, msg = _status(plan.step, 1e-2, 1e-2, u, v, w, t, p, dt=0.0, cfl=1.3)
+    assert st == _lib.PS_ENONFINITE, msg
+    for a, b in zip((u, w, t, p), saved):
+        assert torch.equal(a, b), "the step must not start on a non-finite state"
+
+
+# ---- PS_ENOTCONVERGED -----------------------------------------------------------------
+def test_refinement_not_converged():
+    banner("not converged")
+    g, p64 = grids(24, 16, 12)
+    f = _rhs(p64, seed=5)
+    ref = poisson.solve(f, g)
+    # an unreachable tolerance ends at the rounding floor (stagnation): phi still accurate
+    _, plan = grids(24, 16, 12, precision="fp32_refined", tol=1e-30)
+    phi = torch.empty(plan.centre_shape, dtype=F64, device="cuda")
+    st, msg = _status(plan.solve, f.to("cuda"), phi)
+    assert st == _lib.PS_ENOTCONVERGED, msg
+    assert rel(phi, ref) < 1e-12
+    # one correction cannot reach 1e-12: the cap ends it, phi holds the corrected iterate
+    _, plan1 = grids(24, 16, 12, precision="fp32_refined", tol=1e-12, max_iter=1)
+    st, msg = _status(plan1.solve, f.to("cuda"), phi)
+    assert st == _lib.PS_ENOTCONVERGED, msg
+    assert rel(phi, ref) < 1e-8
+    # the same plan with a reachable tolerance converges
+    _, plan2 = grids(24, 16, 12, precision="fp32_refined", tol=1e-4, max_iter=1)
+    assert _status(plan2.solve, f.to("cuda"), phi)[0] == _lib.PS_OK
+
+
+def test_step_reports_not_converged():
+    """rk3_step completes its three substeps and then reports the refinement status."""
+    banner("step not converged")
+    nx, ny, nz = 16, 12, 10
+    zf = zfaces(nz, 3.0)
+    rng = np.random.default_rng(6)
+    state = [torch.as_tensor(1e-2 * rng.standard_normal(s)) for s in
+             [(nz, ny, nx), (nz, ny, nx), (nz + 1, ny, nx)]]
+    state[2][0] = 0
+    state[2][-1] = 0
+    t = torch.as_tensor(np.repeat((1 - zf)[:, None, None], ny, 1).repeat(nx, 2))
+    p = torch.zeros(nz, ny, nx, dtype=F64)
+    state += [t, p]
+    res = []
+    for prec, tol in (("fp64", 0.0), ("fp32_refined", 1e-30)):
+        plan = Plan(nx, ny, nz, 1.0, 1.0, zf, precision=prec, tol=tol)
+        st = [a.clone().to("cuda") for a in state]
+        code, msg = _status(plan.step, 1e-2, 1e-2, *st, dt=1e-2)
+        res.append((code, st))
+    assert res[0][0] == _lib.PS_OK
+    assert res[1][0] == _lib.PS_ENOTCONVERGED
+    for a, b in zip(res[1][1], res[0][1]):
+        assert rel(a, b) < 1e-11
+
+
+# ---- PS_EINVAL: pointers and workspaces --------------------------------------------------
+def test_misaligned_and_aliased_pointers():
+    _, plan = grids(24, 16, 12)
+    f = _rhs(plan).to("cuda")
+    buf = torch.zeros(f.numel() + 8, dtype=F64, device="cuda")
+    lib, h, s = plan._lib, plan._h, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    P = ctypes.c_void_p
+    assert lib.poisson_solve(h, P(f.data_ptr() + 8), P(buf.data_ptr()), s, None) == _lib.PS_EINVAL
+    assert b"aligned" in lib.ps_last_error()
+    assert lib.poisson_solve(h, P(f.data_ptr()), P(buf.data_ptr() + 8), s, None) == _lib.PS_EINVAL
+    assert lib.poisson_solve(h, P(f.data_ptr()), P(f.data_ptr()), s, None) == _lib.PS_EINVAL
+    assert lib.poisson_solve(h, None, P(buf.data_ptr()), s, None) == _lib.PS_EINVAL
+    assert lib.cn_solve(h, 7, 0.1, P(buf.data_ptr()), s) == _lib.PS_EINVAL
+    assert lib.cn_solve(h, 0, -0.1, P(buf.data_ptr()), s) == _lib.PS_EINVAL
+    assert lib.project(h, P(f.data_ptr()), P(f.data_ptr()), P(buf.data_ptr()), None, None, 0.0, 0.0, s,
+                       None) == _lib.PS_EINVAL
+    assert lib.ps_cfl(h, P(f.data_ptr()), P(f.data_ptr()), P(buf.data_ptr()), P(buf.data_ptr() + 4),
+                      s) == _lib.PS_EINVAL
+
+
+def test_workspace_checks_and_caller_owned():
+    banner("workspace")
+    g, plan = grids(24, 16, 12)
+    f = _rhs(plan, seed=8).to("cuda")
+    own, _ = plan.solve(f)
+    need = plan.workspace_bytes()
+    ws = torch.empty(need // 8 + 64, dtype=F64, device="cuda")
+    lib, h, P = plan._lib, plan._h, ctypes.c_void_p
+    assert lib.poisson_plan_set_workspace(h, P(ws.data_ptr()), need - 8) == _lib.PS_EINVAL
+    assert b"too small" in lib.ps_last_error()
+    assert lib.poisson_plan_set_workspace(h, P(ws.data_ptr() + 16), need) == _lib.PS_EINVAL
+    assert b"aligned" in lib.ps_last_error()
+    # the failed calls left the plan's own workspace in place
+    again, _ = plan.solve(f)
+    assert torch.equal(again, own)
+    # caller-owned workspace (garbage-filled first): bitwise the same result
+    ws.fill_(float("nan"))
+    plan.set_workspace(ws)
+    theirs, _ = plan.solve(f)
+    assert torch.equal(theirs, own)
+    # and back to a workspace of its own
+    plan.set_workspace(None)
+    mine, _ = plan.solve(f)
+    assert torch.equal(mine, own)
+    assert rel(own, poisson.solve(f.cpu(), g)) < 1e-12
+
+
+# ---- PS_ENOMEM --------------------------------------------------------------------------
+def test_out_of_memory_then_recovers():
+    """A plan far larger than the device reports PS_ENOMEM; the failed allocation leaves no
+    error behind for the next launches."""
+    banner("enomem")
+    zf = zfaces(2048, 3.0)
+    with pytest.raises(PsError) as e:
+        Plan(4096, 4096, 2048, 1.0, 1.0, zf, precision="fp64")
+    assert e.value.status == _lib.PS_ENOMEM
+    g, plan = grids(24, 16, 12)
+    f = _rhs(plan, seed=9)
+    phi, _ = plan.solve(f.to("cuda"))
+    assert rel(phi, poisson.solve(f, g)) < 1e-12

@@ -194,6 +194,11 @@ def test_cfl_brute_force():
                 best = max(best, 0.5 * q)
     got = ss.cfl(torch.tensor(u), torch.tensor(v), torch.tensor(w), g)
     assert abs(got - best) <= 1e-15 * best
+    # the floor of Listing 1 for a fluid at rest, and NaN for a broken state
+    z = torch.zeros(3, 4, 5, dtype=torch.float64)
+    assert ss.cfl(z, z, torch.zeros(4, 4, 5, dtype=torch.float64), g) == 1e-8
+    u[1, 2, 3] = float("nan")
+    assert math.isnan(ss.cfl(torch.tensor(u), torch.tensor(v), torch.tensor(w), g))
 
 
 def _fields_and_h(nx, ny, nz, lx, ly, alpha, nu, kappa):
