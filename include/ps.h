@@ -145,6 +145,23 @@ ps_status poisson_plan_destroy(ps_plan_t plan);
 ps_status poisson_solve(ps_plan_t plan, const double* f, double* phi, void* stream, ps_info* info);
 
 /*
+ * poisson_solve_static - poisson_solve without the plan's workspace and without
+ * any allocation: for callers that cannot allocate device memory during the
+ * call (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  The spectral buffers and reduction scratch come from
+ * one statically allocated device array of 256 MiB (268435456 bytes) that the
+ * library holds on every GPU it runs on until the process ends; the call
+ * returns PS_EINVAL, enqueuing nothing, when the plan needs more than that
+ * (poisson_plan_workspace_bytes() > 268435456, e.g. beyond about 256 x 256 x
+ * 192 in FP64).  Same results as poisson_solve (the same kernels), same
+ * arguments and synchronisation rules; the plan's device must be current.
+ * Every call on a GPU shares that GPU's array and leaves its contents behind
+ * (no result depends on them): calls that overlap on one GPU, on any streams
+ * or plans, race and must be serialised by the caller.
+ */
+ps_status poisson_solve_static(ps_plan_t plan, const double* f, double* phi, void* stream, ps_info* info);
+
+/*
  * project - projection and pressure update (Sec. 2.1, end of Sec. 2.2):
  *     L phi = D u* / s,   u <- u* - s G phi,   p <- p + phi - c Dzz phi
  * u, v: centre-z fields (nz x ny x nx), updated in place; w: z-face field,

@@ -35,6 +35,7 @@ SIGNATURES = {
     "poisson_plan_set_workspace": (c_int, [_P, c_void_p, c_size_t]),
     "poisson_plan_destroy": (c_int, [_P]),
     "poisson_solve": (c_int, [_P, _D, _D, c_void_p, POINTER(PsInfo)]),
+    "poisson_solve_static": (c_int, [_P, _D, _D, c_void_p, POINTER(PsInfo)]),
     "project": (c_int, [_P, _D, _D, _D, _D, _D, c_double, c_double, c_void_p, POINTER(PsInfo)]),
     "cn_solve": (c_int, [_P, c_int, c_double, _D, c_void_p]),
     "poisson_solve_adjoint": (c_int, [_P, _D, _D, c_void_p, POINTER(PsInfo)]),

@@ -93,6 +93,15 @@ class Plan:
                                       _stream(), ctypes.byref(info)))
         return out, info.as_dict()
 
+    def solve_static(self, f, out=None):
+        """poisson_solve_static: the same solve with the library's static device scratch
+        instead of the plan's workspace (allocates nothing)."""
+        out = torch.empty_like(f) if out is None else out
+        info = PsInfo()
+        check(self._lib.poisson_solve_static(self._h, _ptr(f, "f", self.centre_shape),
+                                             _ptr(out, "phi", self.centre_shape), _stream(), ctypes.byref(info)))
+        return out, info.as_dict()
+
     def solve_nosync(self, f, out):
         """poisson_solve without an info record (asynchronous for FP64)."""
         return check(self._lib.poisson_solve(self._h, _ptr(f, "f"), _ptr(out, "phi"), _stream(), None))

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -467,6 +468,42 @@ ps_status solve_impl(ps_plan_t p, const double* in, double* out, const double* z
     return result;
 }
 
+// ---- statically allocated scratch (allocation-free entry point) ----------------
+// A file-scope device array of kStaticScratchBytes that poisson_solve_static uses as the
+// plan's workspace.  Every GPU the library runs on holds its own copy from module load
+// to process end.  Host code never names the array except to look up its device address
+// (once per device, with that device current); kernels receive that address.
+constexpr size_t kStaticScratchBytes = size_t(256) << 20;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+ps_status static_scratch(int device, void** out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device < 0 || device >= kMaxDevices) return fail(PS_EDEVICE, "device %d out of range", device);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        PS_HIP(hipGetDevice(&cur), "hipGetDevice");
+        if (cur != device) PS_HIP(hipSetDevice(device), "hipSetDevice");
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return fail(PS_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        }
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return PS_OK;
+}
+
 }  // namespace
 
 // ============================================================================
@@ -661,6 +698,27 @@ ps_status poisson_solve_adjoint(ps_plan_t p, const double* g_phi, double* g_rhs,
     PS_CHECK(check_ptr(g_rhs, "g_rhs"));
     if ((const void*)g_phi == (const void*)g_rhs) return fail(PS_EINVAL, "g_rhs may not alias g_phi");
     return solve_impl(p, g_phi, g_rhs, p->d_inv_dz, p->d_dz, (hipStream_t)stream, info);
+}
+
+ps_status poisson_solve_static(ps_plan_t p, const double* f, double* phi, void* stream, ps_info* info) {
+    PS_CHECK(check_plan(p));
+    PS_CHECK(check_ptr(f, "f"));
+    PS_CHECK(check_ptr(phi, "phi"));
+    if ((const void*)f == (const void*)phi) return fail(PS_EINVAL, "phi may not alias f");
+    if (p->ws_bytes > kStaticScratchBytes)
+        return fail(PS_EINVAL, "box needs %zu bytes of scratch, more than the %zu of the static array", p->ws_bytes,
+                    kStaticScratchBytes);
+    void* sp = nullptr;
+    PS_CHECK(static_scratch(p->device, &sp));
+    // run the solve with the plan's buffers carved out of the static array, then restore
+    // the plan's own (the kernels already enqueued hold the static addresses)
+    void* own = p->ws;
+    p->ws = sp;
+    workspace_layout(p, true);
+    const ps_status r = solve_impl(p, f, phi, nullptr, nullptr, (hipStream_t)stream, info);
+    p->ws = own;
+    workspace_layout(p, true);
+    return r;
 }
 
 ps_status project(ps_plan_t p, double* u, double* v, double* w, double* pr, double* phi_out, double s, double c,

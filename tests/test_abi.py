@@ -21,7 +21,8 @@ def _declared():
 def test_header_declares_entry_points():
     names = _declared()
     for n in ("poisson_plan_create", "poisson_solve", "project", "cn_solve", "poisson_solve_adjoint",
-              "project_adjoint", "rk3_substep", "rk3_substep_adjoint", "rk3_step", "rk3_step_adjoint", "ps_heat_flux",
+              "project_adjoint", "rk3_substep", "rk3_substep_adjoint", "rk3_step", "rk3_step_adjoint",
+              "poisson_solve_static", "ps_heat_flux",
               "ps_debug_stage", "ps_last_error"):
         assert n in names
 
