@@ -16,6 +16,11 @@ the paper (Verzicco-Orlandi staggered finite differences, AFiD; Sec. 2.1-2.2):
                   pressure update.
 * ``cn``        - wall-normal Crank-Nicolson solves.
 * ``substep``   - explicit terms, CFL number and one RK3 substep.
+* ``timestep``  - the full RK3 step, the Courant-limited time step, wall-normal
+                  statistics.
+* ``multires``  - the multiple-resolution temperature grid (Sec. 6): velocity
+                  prolongation, temperature restriction, the temperature step
+                  on its own grid and the coupled step.
 
 Library primitives used as steps: ``torch.fft.rfft2 / irfft2`` (the 2-D real
 FFT), ``math.fsum`` (exactly rounded sums).  Adjoints are obtained with

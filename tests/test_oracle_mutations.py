@@ -15,11 +15,12 @@ import pytest
 import oracle
 import test_oracle_adjoint as t_adj
 import test_oracle_cn_substep as t_cn
+import test_oracle_multires as t_mr
 import test_oracle_poisson as t_po
 import test_oracle_timestep as t_ts
 
 ORACLE_DIR = pathlib.Path(oracle.__file__).parent
-PIN_MODULES = (t_adj, t_cn, t_po, t_ts)
+PIN_MODULES = (t_adj, t_cn, t_mr, t_po, t_ts)
 
 
 def _mutant(name, old, new):
@@ -154,6 +155,33 @@ CASES = {
     "CFL: y neighbour on the wrong side": (
         "substep", "+ torch.abs(v + _yp(v)) / g.dy", "+ torch.abs(v + _ym(v)) / g.dy",
         [t_cn.test_cfl_brute_force]),
+    # Multiple-resolution temperature grid, Sec. 6
+    "prolongation: local divergence correction dropped": (
+        "multires", "M = -G @ np.linalg.pinv(L) if ncell > 1", "M = 0.0 * G @ np.linalg.pinv(L) if ncell > 1",
+        [lambda: t_mr.test_prolonged_velocity_is_divergence_free((2, 2, 2)),
+         t_mr.test_uniform_temperature_stays_uniform]),
+    "prolongation: transverse slope with the wrong sign": (
+        "multires", "uf[k * rz + m, b::ry, ::rx] = u[k] + syu[k] * ey[b]",
+        "uf[k * rz + m, b::ry, ::rx] = u[k] - syu[k] * ey[b]",
+        [lambda: t_mr.test_prolongation_second_order(0.0, (2, 2, 2))]),
+    "prolongation: zero-gradient wall in place of the no-slip value": (
+        "multires", "qm = torch.cat([zero, q[:-1]], dim=0)", "qm = torch.cat([q[:1], q[:-1]], dim=0)",
+        [lambda: t_mr.test_prolongation_second_order(1.5, (2, 2, 2))]),
+    "prolongation: sub-face offsets not centred on the coarse face": (
+        "multires", "return torch.tensor([((b + 0.5) / r - 0.5) * h for b in range(r)], dtype=F64)",
+        "return torch.tensor([(b / r - 0.5) * h for b in range(r)], dtype=F64)",
+        [lambda: t_mr.test_coarse_face_fluxes_are_kept((2, 2, 2)),
+         lambda: t_mr.test_prolongation_second_order(0.0, (3, 2, 3))]),
+    "restriction: one sub-column instead of the column mean": (
+        "multires", "return at_faces.reshape(n, g.ny, ry, g.nx, rx).mean(dim=(2, 4))",
+        "return at_faces.reshape(n, g.ny, ry, g.nx, rx)[..., 0].mean(dim=2)",
+        [t_mr.test_restriction_keeps_plane_means_and_converges]),
+    "temperature step: every stage advected with the end-of-step velocity": (
+        "multires", "th = (s + STAGE_START[l - 1]) / nsub", "th = (s + 1.0) / nsub",
+        [t_mr.test_temperature_step_third_order_in_substep]),
+    "temperature substep: diffusion weighted by gamma instead of alpha": (
+        "multires", "rt = gam * h + alp * (kappa * op.dzz_face(t, gf))", "rt = gam * h + gam * (kappa * op.dzz_face(t, gf))",
+        [lambda: t_mr.test_temperature_substep_is_the_single_grid_one(2)]),
     # Full step and statistics, Sec. 2.1 and Sec. 5 (Table 3)
     "heat flux: conduction term with the wrong sign": (
         "timestep", "cond = kappa * (tm[1:] - tm[:-1]) / g.dz", "cond = kappa * (tm[:-1] - tm[1:]) / g.dz",
