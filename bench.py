@@ -379,7 +379,63 @@ def other_workloads(args):
                                                 "heat_flux_ms": round(hf_ms, 3),
                                                 "nusselt_wall_mean": round(float(0.5 * (nu_prof[0] + nu_prof[-1])), 6)}
     plan.close()
+    del st, saved, cot
+    torch.cuda.empty_cache()
+
+    # ---- multiple-resolution step: momentum 384 x 384 x 256, temperature 768 x 768 x 512 ----
+    res.update(multires_workload())
     return res
+
+
+def multires_workload(nsub=2):
+    """One coupled step with the momentum on the 384^2 x 256 grid and the temperature on a grid
+    refined twice in every direction (768^2 x 512 points), nsub temperature steps per step."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_1705_01423_amd import synth
+    from paper_1705_01423_amd.api import MultiRes, Plan
+
+    cfg = synth.CONFIGS["rb384x384x256"]
+    log("multiple-resolution step 384x384x256 / 768x768x512")
+    zf = synth.zfaces(cfg.nz, cfg.alpha)
+    ra, pr = cfg.extra["ra"], cfg.extra["pr"]
+    nu, ka = math.sqrt(pr / ra), 1.0 / math.sqrt(ra * pr)
+    u, v, w, _, p = (torch.as_tensor(a).to("cuda") for a in synth.rb_state(cfg))
+    plan = Plan(cfg.nx, cfg.ny, cfg.nz, cfg.lx, cfg.ly, zf, precision="fp64")
+    m = MultiRes(plan, 2, 2, 2, nsub=nsub)
+    zff = np.concatenate([[zf[k] + (q / 2) * (zf[k + 1] - zf[k]) for k in range(cfg.nz) for q in range(2)], [zf[-1]]])
+    tf = torch.as_tensor(synth.rb_temperature(cfg, zff, m.nxf, m.nyf)).to("cuda")
+    saved = [a.clone() for a in (u, v, w, p, tf)]
+    st = [a.clone() for a in saved]
+    dt = 1.3 / float(plan.cfl(u, v, w).item())
+
+    def reset():
+        for a, b in zip(st, saved):
+            a.copy_(b)
+
+    def step():
+        reset()
+        m.step(nu, ka, *st, dt=dt)
+
+    step()
+    reset_ms = _event_ms(reset, 3)
+    step_ms = _event_ms(step, 3) - reset_ms
+    vel = m.prolong_velocity(*saved[:3])
+    prol_ms = _event_ms(lambda: m.prolong_velocity(*saved[:3], out=vel), 5)
+    tt = saved[4].clone()
+    t_ms = _event_ms(lambda: m.temperature_step(dt, ka, vel, vel, tt), 3)
+    nf = m.nxf * m.nyf * m.nzf
+    out = {"rk3_step_mr_384x384x256_T768x768x512": {
+        "ms": round(step_ms, 3), "dt": dt, "nsub": nsub, "prolongation_ms": round(prol_ms, 3),
+        "prolongation_gbs": round(27.0 * nf / (prol_ms * 1e-3) / 1e9, 1),
+        "temperature_step_ms": round(t_ms, 3)}}
+    m.close()
+    plan.close()
+    torch.cuda.empty_cache()
+    return out
 
 
 if __name__ == "__main__":

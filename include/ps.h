@@ -315,6 +315,75 @@ ps_status ps_heat_flux(ps_plan_t plan, const double* w, const double* t, double 
                        double* flux, void* stream);
 
 /*
+ * Multiple-resolution temperature grid (Sec. 6: the temperature on a grid of
+ * higher resolution than the momentum, with its own refined time step).
+ *
+ * The temperature grid refines the plan's grid by integer factors (rx, ry,
+ * rz), every momentum cell split into rx ry rz equal sub-cells: nxf = rx nx,
+ * nyf = ry ny, nzf = rz nz, fine wall-normal faces zf'[rz k + m] = zf[k] +
+ * (m / rz) dz[k].  The temperature tf is a fine z-face field, (nzf + 1) x
+ * nyf x nxf, wall rows stored (fixed there).  Fine velocities: uf, vf
+ * nzf x nyf x nxf, wf (nzf + 1) x nyf x nxf, at the fine faces.
+ */
+typedef struct ps_mr_s* ps_mr_t;
+
+/*
+ * mr_create - temperature grid on top of a plan (which must outlive it).
+ * rx, ry, rz: 1 or 2 each (the factors the prolongation kernels are built
+ * for; nzf <= 2048).  nsub (1..64): RK3 steps of the temperature per
+ * momentum step.  Allocates the fine grid's tables and eight fine fields
+ * (two velocity time levels, right-hand side, H) plus one coarse face field.
+ */
+ps_status mr_create(ps_mr_t* out, ps_plan_t plan, int rx, int ry, int rz, int nsub);
+ps_status mr_destroy(ps_mr_t mr);
+ps_status mr_shape(ps_mr_t mr, int* nxf, int* nyf, int* nzf);
+
+/*
+ * mr_prolong_velocity - momentum-grid face velocity (u, v, w) -> fine face
+ * velocity (uf, vf, wf), second-order accurate and with every fine cell's
+ * divergence equal to that of its momentum cell (so a divergence-free
+ * velocity stays divergence free; the temperature advection needs it):
+ * linear profiles across each coarse face with slopes from the neighbouring
+ * faces (coarse fluxes kept; the no-slip wall value 0 as the outer point in
+ * z), linear interpolation along the normal inside each cell, then the
+ * smallest correction G psi, psi = -(L_loc)^+ r, of the cell's interior
+ * fine faces (r: sub-cell divergences; L_loc: the Laplacian of the cell's
+ * sub-cells with its coarse faces closed).
+ */
+ps_status mr_prolong_velocity(ps_mr_t mr, const double* u, const double* v, const double* w,
+                              double* uf, double* vf, double* wf, void* stream);
+
+/*
+ * mr_restrict_temperature - tc[k][j][i] (coarse z-face field) = mean of
+ * tf[rz k][ry j + b][rx i + a] over a < rx, b < ry: the temperature the
+ * momentum equations' buoyancy sees.
+ */
+ps_status mr_restrict_temperature(ps_mr_t mr, const double* tf, double* tc, void* stream);
+
+/*
+ * mr_temperature_step - advance tf over dt by nsub RK3 / Crank-Nicolson
+ * steps of dt / nsub on the temperature grid (the substep formulas of
+ * rk3_substep for T, diffusivity kappa); each stage's advecting velocity is
+ * (1 - s) vel0 + s vel1 at its start time s (fraction of dt; RK3 stages
+ * start at 0, 8/15, 2/3 of a sub-step).  vel0, vel1: fine face velocities
+ * (three pointers each).
+ */
+ps_status mr_temperature_step(ps_mr_t mr, double dt, double kappa, const double* const* vel0,
+                              const double* const* vel1, double* tf, void* stream);
+
+/*
+ * rk3_step_mr - one coupled step: the momentum RK3 step (three substeps,
+ * Sec. 2.1) with the buoyancy of the restricted temperature, frozen over
+ * the step, then mr_temperature_step over the same dt with the prolonged
+ * velocities of the step's start and end.  dt, cfl_target, dt_max, dt_used,
+ * info as rk3_step (the Courant number is the momentum grid's).  u, v, w, p:
+ * momentum-grid state; tf: temperature-grid temperature; all in place.
+ */
+ps_status rk3_step_mr(ps_mr_t mr, double dt, double cfl_target, double dt_max, double nu, double kappa,
+                      double* u, double* v, double* w, double* p, double* tf, double* dt_used,
+                      void* stream, ps_info* info);
+
+/*
  * ps_debug_stage - run one stage of poisson_solve on the plan's own layout
  * (test and measurement entry; same kernels as poisson_solve).
  *   stage 0: forward x FFT   f (nz x ny x nx FP64)     -> spectral buffer A

@@ -50,6 +50,14 @@ SIGNATURES = {
     "rk3_step": (c_int, [_P, c_double, c_double, c_double, c_double, c_double, _D, _D, _D, _D, _D,
                          POINTER(c_double), c_void_p, POINTER(PsInfo)]),
     "ps_heat_flux": (c_int, [_P, _D, _D, c_double, _D, _D, c_void_p]),
+    "mr_create": (c_int, [_PP, _P, c_int, c_int, c_int, c_int]),
+    "mr_destroy": (c_int, [_P]),
+    "mr_shape": (c_int, [_P, POINTER(c_int), POINTER(c_int), POINTER(c_int)]),
+    "mr_prolong_velocity": (c_int, [_P, _D, _D, _D, _D, _D, _D, c_void_p]),
+    "mr_restrict_temperature": (c_int, [_P, _D, _D, c_void_p]),
+    "mr_temperature_step": (c_int, [_P, c_double, c_double, _PP, _PP, _D, c_void_p]),
+    "rk3_step_mr": (c_int, [_P, c_double, c_double, c_double, c_double, c_double, _D, _D, _D, _D, _D,
+                            POINTER(c_double), c_void_p, POINTER(PsInfo)]),
     "ps_debug_stage": (c_int, [_P, c_int, _D, _D, c_void_p]),
     "ps_spectral_layout": (c_int, [_P, POINTER(c_int), POINTER(c_int)]),
     "ps_spectral_elems": (c_size_t, [_P]),

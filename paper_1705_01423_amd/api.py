@@ -243,6 +243,78 @@ class Plan:
         return torch.view_as_real(t.contiguous()).reshape(-1).contiguous()
 
 
+class MultiRes:
+    """Temperature grid refining a plan's grid by (rx, ry, rz) (1 or 2 each), with nsub
+    temperature RK3 steps per momentum step (the multiple-resolution strategy of Sec. 6)."""
+
+    def __init__(self, plan, rx, ry, rz, nsub=1):
+        self.plan = plan
+        self._lib = plan._lib
+        h = ctypes.c_void_p()
+        check(self._lib.mr_create(ctypes.byref(h), plan._h, int(rx), int(ry), int(rz), int(nsub)))
+        self._h = h
+        self.rx, self.ry, self.rz, self.nsub = int(rx), int(ry), int(rz), int(nsub)
+        self.nxf, self.nyf, self.nzf = plan.nx * rx, plan.ny * ry, plan.nz * rz
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.mr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def centre_shape(self):
+        return (self.nzf, self.nyf, self.nxf)
+
+    @property
+    def face_shape(self):
+        return (self.nzf + 1, self.nyf, self.nxf)
+
+    def prolong_velocity(self, u, v, w, out=None):
+        p = self.plan
+        uf, vf, wf = out if out is not None else (
+            torch.empty(self.centre_shape, dtype=F64, device=u.device),
+            torch.empty(self.centre_shape, dtype=F64, device=u.device),
+            torch.empty(self.face_shape, dtype=F64, device=u.device))
+        check(self._lib.mr_prolong_velocity(self._h, _ptr(u, "u", p.centre_shape), _ptr(v, "v", p.centre_shape),
+                                            _ptr(w, "w", p.face_shape), _ptr(uf, "uf", self.centre_shape),
+                                            _ptr(vf, "vf", self.centre_shape), _ptr(wf, "wf", self.face_shape),
+                                            _stream()))
+        return uf, vf, wf
+
+    def restrict_temperature(self, tf, out=None):
+        tc = torch.empty(self.plan.face_shape, dtype=F64, device=tf.device) if out is None else out
+        check(self._lib.mr_restrict_temperature(self._h, _ptr(tf, "tf", self.face_shape),
+                                                _ptr(tc, "tc", self.plan.face_shape), _stream()))
+        return tc
+
+    def temperature_step(self, dt, kappa, vel0, vel1, tf):
+        shapes = (self.centre_shape, self.centre_shape, self.face_shape)
+        v0 = (ctypes.c_void_p * 3)(*[_ptr(x, "vel0", s).value for x, s in zip(vel0, shapes)])
+        v1 = (ctypes.c_void_p * 3)(*[_ptr(x, "vel1", s).value for x, s in zip(vel1, shapes)])
+        check(self._lib.mr_temperature_step(self._h, float(dt), float(kappa), v0, v1,
+                                            _ptr(tf, "tf", self.face_shape), _stream()))
+        return tf
+
+    def step(self, nu, kappa, u, v, w, p, tf, dt=0.0, cfl=1.3, dt_max=float("inf")):
+        """One coupled step (momentum on the plan's grid, temperature on this grid), in place.
+        Returns (dt taken, info)."""
+        pl = self.plan
+        used = ctypes.c_double()
+        info = PsInfo()
+        check(self._lib.rk3_step_mr(self._h, float(dt), float(cfl), float(dt_max), float(nu), float(kappa),
+                                    _ptr(u, "u", pl.centre_shape), _ptr(v, "v", pl.centre_shape),
+                                    _ptr(w, "w", pl.face_shape), _ptr(p, "p", pl.centre_shape),
+                                    _ptr(tf, "tf", self.face_shape), ctypes.byref(used), _stream(),
+                                    ctypes.byref(info)))
+        return used.value, info.as_dict()
+
+
 class PoissonSolveFn(torch.autograd.Function):
     """phi = S f with the hand-written adjoint (transposed solve) as its backward."""
 

@@ -27,6 +27,7 @@ UNITS = [
     ("zsolve_kernels.hip", "zsolve.o", []),
     ("field_kernels.hip", "field.o", []),
     ("substep_kernels.hip", "substep.o", []),
+    ("multires_kernels.hip", "multires.o", []),
 ]
 
 

@@ -74,7 +74,7 @@ struct ps_plan_s {
     size_t plane;         // nx * ny
     double sum_dz;
     // host metrics
-    std::vector<double> dz, dzc, o, dzw, lamx, lamy, inv_dz, inv_dzw;
+    std::vector<double> zf, dz, dzc, o, dzw, lamx, lamy, inv_dz, inv_dzw;
     // device tables (one allocation)
     void* d_tables = nullptr;
     double *d_dz, *d_dzc, *d_o, *d_dzw, *d_lamx, *d_lamy, *d_inv_dz, *d_inv_dzw;
@@ -504,6 +504,77 @@ ps_status static_scratch(int device, void** out) {
     return PS_OK;
 }
 
+// One substep; advance_t = false leaves T as given (its buoyancy is still applied): the
+// momentum part of a step whose temperature is advanced elsewhere.
+ps_status substep_impl(ps_plan_t p, int l, double dt, double nu, double kappa, double* u, double* v, double* w,
+                       double* t, double* pr, const double* const* h_prev, double* const* h_out, void* stream,
+                       ps_info* info, bool advance_t) {
+    PS_CHECK(check_plan(p));
+    if (l < 1 || l > 3) return fail(PS_EINVAL, "substep index l=%d must be 1, 2 or 3", l);
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(PS_EINVAL, "dt must be positive");
+    if (!(nu >= 0) || !(kappa >= 0) || !std::isfinite(nu) || !std::isfinite(kappa))
+        return fail(PS_EINVAL, "nu and kappa must be non-negative");
+    PS_CHECK(check_ptr(u, "u"));
+    PS_CHECK(check_ptr(v, "v"));
+    PS_CHECK(check_ptr(w, "w"));
+    PS_CHECK(check_ptr(t, "t"));
+    PS_CHECK(check_ptr(pr, "p"));
+    const double gam = kGamma[l - 1], rho = kRho[l - 1], alp = gam + rho;
+    if (rho != 0.0) {
+        if (!h_prev) return fail(PS_EINVAL, "h_prev is required for l=%d", l);
+        for (int q = 0; q < 4; ++q) PS_CHECK(check_ptr(h_prev[q], "h_prev[q]"));
+    }
+    if (h_out)
+        for (int q = 0; q < 4; ++q) PS_CHECK(check_ptr(h_out[q], "h_out[q]"));
+    PS_CHECK(ensure_substep_buffers(p));
+    hipStream_t st = (hipStream_t)stream;
+    double* ru = sub_field(p, 0);
+    double* rv = sub_field(p, 1);
+    double* rw = sub_field(p, 2);
+    double* rt = sub_field(p, 3);
+    SubstepArgs a{};
+    a.u = u;
+    a.v = v;
+    a.w = w;
+    a.t = t;
+    a.p = pr;
+    if (rho != 0.0) {
+        a.hpu = h_prev[0];
+        a.hpv = h_prev[1];
+        a.hpw = h_prev[2];
+        a.hpt = h_prev[3];
+    }
+    a.ru = ru;
+    a.rv = rv;
+    a.rw = rw;
+    a.rt = advance_t ? rt : nullptr;
+    if (h_out) {
+        a.hu = h_out[0];
+        a.hv = h_out[1];
+        a.hw = h_out[2];
+        a.ht = h_out[3];
+    }
+    a.dt = dt;
+    a.nu = nu;
+    a.ka = kappa;
+    a.gam = gam;
+    a.rho = rho;
+    a.alp = alp;
+    PS_HIP(launch_explicit(p->gd, a, st), "explicit terms");
+    const double bnu = alp * dt * nu / 2.0, bka = alp * dt * kappa / 2.0;
+    double* fc = cn_slot(p, 0);
+    double* ff = cn_slot(p, 1);
+    double* fk = cn_slot(p, 2);
+    PS_HIP(launch_cn_factor(p->gd, PS_CENTER, bnu, fc, st), "cn factor");
+    PS_HIP(launch_cn_factor(p->gd, PS_FACE, bnu, ff, st), "cn factor");
+    PS_HIP(launch_cn_factor(p->gd, PS_FACE, bka, fk, st), "cn factor");
+    PS_HIP(launch_cn_solve_add(p->gd, PS_CENTER, fc, ru, u, st), "cn solve u");
+    PS_HIP(launch_cn_solve_add(p->gd, PS_CENTER, fc, rv, v, st), "cn solve v");
+    PS_HIP(launch_cn_solve_add(p->gd, PS_FACE, ff, rw, w, st), "cn solve w");
+    if (advance_t) PS_HIP(launch_cn_solve_add(p->gd, PS_FACE, fk, rt, t, st), "cn solve T");
+    return project(p, u, v, w, pr, nullptr, alp * dt, bnu, stream, info);
+}
+
 }  // namespace
 
 // ============================================================================
@@ -544,6 +615,7 @@ ps_status poisson_plan_create(ps_plan_t* out, int nx, int ny, int nz, double lx,
     p->npts = (size_t)nx * ny * nz;
     p->plane = (size_t)nx * ny;
     // metrics (same formulas as the problem definition)
+    p->zf.assign(zf, zf + nz + 1);
     p->dz.resize(nz);
     for (int k = 0; k < nz; ++k) p->dz[k] = zf[k + 1] - zf[k];
     p->dzc.assign(nz + 1, 0.0);
@@ -800,70 +872,7 @@ ps_status ps_cfl(ps_plan_t p, const double* u, const double* v, const double* w,
 ps_status rk3_substep(ps_plan_t p, int l, double dt, double nu, double kappa, double* u, double* v, double* w,
                       double* t, double* pr, const double* const* h_prev, double* const* h_out, void* stream,
                       ps_info* info) {
-    PS_CHECK(check_plan(p));
-    if (l < 1 || l > 3) return fail(PS_EINVAL, "substep index l=%d must be 1, 2 or 3", l);
-    if (!(dt > 0) || !std::isfinite(dt)) return fail(PS_EINVAL, "dt must be positive");
-    if (!(nu >= 0) || !(kappa >= 0) || !std::isfinite(nu) || !std::isfinite(kappa))
-        return fail(PS_EINVAL, "nu and kappa must be non-negative");
-    PS_CHECK(check_ptr(u, "u"));
-    PS_CHECK(check_ptr(v, "v"));
-    PS_CHECK(check_ptr(w, "w"));
-    PS_CHECK(check_ptr(t, "t"));
-    PS_CHECK(check_ptr(pr, "p"));
-    const double gam = kGamma[l - 1], rho = kRho[l - 1], alp = gam + rho;
-    if (rho != 0.0) {
-        if (!h_prev) return fail(PS_EINVAL, "h_prev is required for l=%d", l);
-        for (int q = 0; q < 4; ++q) PS_CHECK(check_ptr(h_prev[q], "h_prev[q]"));
-    }
-    if (h_out)
-        for (int q = 0; q < 4; ++q) PS_CHECK(check_ptr(h_out[q], "h_out[q]"));
-    PS_CHECK(ensure_substep_buffers(p));
-    hipStream_t st = (hipStream_t)stream;
-    double* ru = sub_field(p, 0);
-    double* rv = sub_field(p, 1);
-    double* rw = sub_field(p, 2);
-    double* rt = sub_field(p, 3);
-    SubstepArgs a{};
-    a.u = u;
-    a.v = v;
-    a.w = w;
-    a.t = t;
-    a.p = pr;
-    if (rho != 0.0) {
-        a.hpu = h_prev[0];
-        a.hpv = h_prev[1];
-        a.hpw = h_prev[2];
-        a.hpt = h_prev[3];
-    }
-    a.ru = ru;
-    a.rv = rv;
-    a.rw = rw;
-    a.rt = rt;
-    if (h_out) {
-        a.hu = h_out[0];
-        a.hv = h_out[1];
-        a.hw = h_out[2];
-        a.ht = h_out[3];
-    }
-    a.dt = dt;
-    a.nu = nu;
-    a.ka = kappa;
-    a.gam = gam;
-    a.rho = rho;
-    a.alp = alp;
-    PS_HIP(launch_explicit(p->gd, a, st), "explicit terms");
-    const double bnu = alp * dt * nu / 2.0, bka = alp * dt * kappa / 2.0;
-    double* fc = cn_slot(p, 0);
-    double* ff = cn_slot(p, 1);
-    double* fk = cn_slot(p, 2);
-    PS_HIP(launch_cn_factor(p->gd, PS_CENTER, bnu, fc, st), "cn factor");
-    PS_HIP(launch_cn_factor(p->gd, PS_FACE, bnu, ff, st), "cn factor");
-    PS_HIP(launch_cn_factor(p->gd, PS_FACE, bka, fk, st), "cn factor");
-    PS_HIP(launch_cn_solve_add(p->gd, PS_CENTER, fc, ru, u, st), "cn solve u");
-    PS_HIP(launch_cn_solve_add(p->gd, PS_CENTER, fc, rv, v, st), "cn solve v");
-    PS_HIP(launch_cn_solve_add(p->gd, PS_FACE, ff, rw, w, st), "cn solve w");
-    PS_HIP(launch_cn_solve_add(p->gd, PS_FACE, fk, rt, t, st), "cn solve T");
-    return project(p, u, v, w, pr, nullptr, alp * dt, bnu, stream, info);
+    return substep_impl(p, l, dt, nu, kappa, u, v, w, t, pr, h_prev, h_out, stream, info, true);
 }
 
 ps_status rk3_step(ps_plan_t p, double dt, double cfl_target, double dt_max, double nu, double kappa, double* u,
@@ -1209,3 +1218,331 @@ ps_status check_finite(ps_plan_t p, const double* f, hipStream_t st) {
     return PS_OK;
 }
 }  // namespace
+
+// ============================================================================
+// Multiple-resolution temperature grid (Sec. 6)
+struct ps_mr_s {
+    ps_plan_t plan;
+    int rx, ry, rz, nsub;
+    int nxf, nyf, nzf;
+    size_t fc, ff;        // values per fine centre / face field
+    GridDev gf;           // temperature grid
+    MrDev md;
+    void* d_tab = nullptr;
+    double* cnfac;        // Crank-Nicolson factors of the temperature grid, 3 (nzf + 1)
+    double* buf = nullptr;
+    double *u0, *v0, *w0, *u1, *v1, *w1, *rt, *h, *tc;
+};
+
+namespace {
+
+// (L_loc)^+ of the rx x ry x rz sub-cells of one coarse cell (spacings hx, hy, hz, closed outer
+// faces), from the eigenvectors of the one-dimensional Neumann Laplacians:
+// v_p[n] = cos(pi p (n + 1/2) / r), eigenvalue -(4 / h^2) sin^2(pi p / (2 r)).
+void local_pinv(int rx, int ry, int rz, double hx, double hy, double hz, double* out) {
+    const int ns = rx * ry * rz;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    auto vec = [&](int r, int p, int n) { return (double)cosl(pi * p * (n + 0.5L) / r); };
+    auto mu = [&](int r, int p, double h) {
+        const double sn = (double)sinl(pi * p / (2.0L * r));
+        return -(4.0 / (h * h)) * sn * sn;
+    };
+    for (int q = 0; q < ns * ns; ++q) out[q] = 0.0;
+    for (int pz = 0; pz < rz; ++pz)
+        for (int py = 0; py < ry; ++py)
+            for (int px = 0; px < rx; ++px) {
+                if (px == 0 && py == 0 && pz == 0) continue;
+                const double lam = mu(rx, px, hx) + mu(ry, py, hy) + mu(rz, pz, hz);
+                const double nrm = (px ? rx / 2.0 : rx) * (py ? ry / 2.0 : ry) * (pz ? rz / 2.0 : rz);
+                std::vector<double> e(ns);
+                for (int c = 0; c < rz; ++c)
+                    for (int b = 0; b < ry; ++b)
+                        for (int a = 0; a < rx; ++a)
+                            e[(c * ry + b) * rx + a] = vec(rx, px, a) * vec(ry, py, b) * vec(rz, pz, c);
+                for (int s = 0; s < ns; ++s)
+                    for (int t = 0; t < ns; ++t) out[s * ns + t] += e[s] * e[t] / (nrm * lam);
+            }
+}
+
+ps_status check_mr(ps_mr_t m) {
+    if (!m) return fail(PS_EINVAL, "multi-resolution object is NULL");
+    return check_plan(m->plan);
+}
+
+}  // namespace
+
+extern "C" {
+
+ps_status mr_create(ps_mr_t* out, ps_plan_t p, int rx, int ry, int rz, int nsub) {
+    if (!out) return fail(PS_EINVAL, "out is NULL");
+    *out = nullptr;
+    PS_CHECK(check_plan(p));
+    if (!mr_factors_supported(rx, ry, rz))
+        return fail(PS_EINVAL, "refinement factors (%d, %d, %d): each must be 1 or 2", rx, ry, rz);
+    if (nsub < 1 || nsub > 64) return fail(PS_EINVAL, "nsub=%d: need 1 <= nsub <= 64", nsub);
+    const int nzf = p->nz * rz;
+    if (nzf > 2048) return fail(PS_EINVAL, "temperature grid of %d levels: at most 2048", nzf);
+    ps_mr_t m = new ps_mr_s();
+    m->plan = p;
+    m->rx = rx;
+    m->ry = ry;
+    m->rz = rz;
+    m->nsub = nsub;
+    m->nxf = p->nx * rx;
+    m->nyf = p->ny * ry;
+    m->nzf = nzf;
+    const size_t planef = (size_t)m->nxf * m->nyf;
+    m->fc = planef * nzf;
+    m->ff = planef * (nzf + 1);
+    // temperature-grid faces: every momentum cell split into rz equal sub-cells
+    const int nz = p->nz;
+    std::vector<double> zff(nzf + 1);
+    for (int k = 0; k < nz; ++k)
+        for (int q = 0; q < rz; ++q) zff[k * rz + q] = p->zf[k] + ((double)q / rz) * p->dz[k];
+    zff[nzf] = p->zf[nz];
+    std::vector<double> dzf(nzf), dzcf(nzf + 1, 0.0), of(nzf + 1, 0.0), dzwf(nzf + 1, 0.0), idzf(nzf),
+        idzwf(nzf + 1);
+    for (int k = 0; k < nzf; ++k) {
+        dzf[k] = zff[k + 1] - zff[k];
+        idzf[k] = 1.0 / dzf[k];
+    }
+    for (int k = 1; k < nzf; ++k) {
+        dzcf[k] = 0.5 * (dzf[k - 1] + dzf[k]);
+        of[k] = 1.0 / dzcf[k];
+        dzwf[k] = dzcf[k];
+    }
+    dzwf[0] = 0.5 * dzf[0];
+    dzwf[nzf] = 0.5 * dzf[nzf - 1];
+    for (int k = 0; k <= nzf; ++k) idzwf[k] = 1.0 / dzwf[k];
+    // slope stencil distances and local pseudo-inverses per momentum level
+    const int ns = rx * ry * rz;
+    std::vector<double> zc(nz), zhm(nz), zhp(nz), linv((size_t)nz * ns * ns);
+    for (int k = 0; k < nz; ++k) zc[k] = 0.5 * (p->zf[k] + p->zf[k + 1]);
+    for (int k = 0; k < nz; ++k) {
+        zhm[k] = zc[k] - (k > 0 ? zc[k - 1] : p->zf[0]);
+        zhp[k] = (k + 1 < nz ? zc[k + 1] : p->zf[nz]) - zc[k];
+        local_pinv(rx, ry, rz, p->lx / m->nxf, p->ly / m->nyf, p->dz[k] / rz, linv.data() + (size_t)k * ns * ns);
+    }
+    // one device table: fine metrics, mr tables, CN factors
+    std::vector<double> host;
+    auto put = [&](const std::vector<double>& vv) {
+        const size_t at = host.size();
+        host.insert(host.end(), vv.begin(), vv.end());
+        while (host.size() % 32) host.push_back(0.0);
+        return at;
+    };
+    const size_t a_dz = put(dzf), a_dzc = put(dzcf), a_o = put(of), a_dzw = put(dzwf), a_idz = put(idzf),
+                 a_idzw = put(idzwf), a_hm = put(zhm), a_hp = put(zhp), a_li = put(linv);
+    const size_t a_cn = host.size();
+    host.resize(host.size() + 3 * (size_t)(nzf + 1) + 32, 0.0);
+    if (!dev_alloc(&m->d_tab, host.size() * sizeof(double))) {
+        delete m;
+        return fail(PS_ENOMEM, "cannot allocate the temperature-grid tables");
+    }
+    if (hipMemcpy(m->d_tab, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        hipFree(m->d_tab);
+        delete m;
+        return fail(PS_EDEVICE, "cannot upload the temperature-grid tables");
+    }
+    const double* d = (const double*)m->d_tab;
+    GridDev& g = m->gf;
+    g.nx = m->nxf;
+    g.ny = m->nyf;
+    g.nz = nzf;
+    g.dx = p->lx / m->nxf;
+    g.dy = p->ly / m->nyf;
+    g.dz = d + a_dz;
+    g.dzc = d + a_dzc;
+    g.o = d + a_o;
+    g.dzw = d + a_dzw;
+    g.lamx = nullptr;
+    g.lamy = nullptr;
+    g.idz = d + a_idz;
+    g.idzw = d + a_idzw;
+    m->md.rx = rx;
+    m->md.ry = ry;
+    m->md.rz = rz;
+    m->md.dxf = g.dx;
+    m->md.dyf = g.dy;
+    m->md.dzf = g.dz;
+    m->md.zhm = d + a_hm;
+    m->md.zhp = d + a_hp;
+    m->md.linv = d + a_li;
+    m->cnfac = (double*)m->d_tab + a_cn;
+    // fields: two temperature-grid velocities, the temperature right-hand side and H, and the
+    // temperature the momentum equations see
+    const size_t per = align256(m->ff * sizeof(double));
+    const size_t coarse = align256((p->npts + p->plane) * sizeof(double));
+    if (!dev_alloc((void**)&m->buf, per * 8 + coarse)) {
+        hipFree(m->d_tab);
+        delete m;
+        return fail(PS_ENOMEM, "cannot allocate %zu bytes of temperature-grid fields", per * 8 + coarse);
+    }
+    double* f[9];
+    for (int q = 0; q < 9; ++q) f[q] = (double*)((char*)m->buf + per * q);
+    m->u0 = f[0];
+    m->v0 = f[1];
+    m->w0 = f[2];
+    m->u1 = f[3];
+    m->v1 = f[4];
+    m->w1 = f[5];
+    m->rt = f[6];
+    m->h = f[7];
+    m->tc = f[8];
+    *out = m;
+    return PS_OK;
+}
+
+ps_status mr_destroy(ps_mr_t m) {
+    if (!m) return PS_OK;
+    if (m->buf) hipFree(m->buf);
+    if (m->d_tab) hipFree(m->d_tab);
+    delete m;
+    return PS_OK;
+}
+
+ps_status mr_shape(ps_mr_t m, int* nxf, int* nyf, int* nzf) {
+    if (!m) return fail(PS_EINVAL, "multi-resolution object is NULL");
+    if (nxf) *nxf = m->nxf;
+    if (nyf) *nyf = m->nyf;
+    if (nzf) *nzf = m->nzf;
+    return PS_OK;
+}
+
+ps_status mr_prolong_velocity(ps_mr_t m, const double* u, const double* v, const double* w, double* uf, double* vf,
+                              double* wf, void* stream) {
+    PS_CHECK(check_mr(m));
+    const void* ps[6] = {u, v, w, uf, vf, wf};
+    const char* names[6] = {"u", "v", "w", "uf", "vf", "wf"};
+    for (int q = 0; q < 6; ++q) PS_CHECK(check_ptr(ps[q], names[q]));
+    for (int q = 0; q < 3; ++q)
+        for (int r = 3; r < 6; ++r)
+            if (ps[q] == ps[r]) return fail(PS_EINVAL, "outputs may not alias inputs");
+    PS_HIP(launch_mr_prolong(m->plan->gd, m->md, u, v, w, uf, vf, wf, (hipStream_t)stream), "prolongation");
+    return PS_OK;
+}
+
+ps_status mr_restrict_temperature(ps_mr_t m, const double* tf, double* tc, void* stream) {
+    PS_CHECK(check_mr(m));
+    PS_CHECK(check_ptr(tf, "tf"));
+    PS_CHECK(check_ptr(tc, "tc"));
+    if ((const void*)tf == (const void*)tc) return fail(PS_EINVAL, "tc may not alias tf");
+    PS_HIP(launch_mr_restrict(m->plan->gd, m->md, tf, tc, (hipStream_t)stream), "restriction");
+    return PS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// nsub RK3 steps of dt / nsub for the temperature on its grid; stage velocity linear in time
+// between vel0 and vel1 at the stage's start time.
+ps_status mr_tstep(ps_mr_t m, double dt, double kappa, const double* const* v0, const double* const* v1, double* tf,
+                   hipStream_t st) {
+    const double start[3] = {0.0, 8.0 / 15.0, 2.0 / 3.0};
+    const double dts = dt / m->nsub;
+    for (int s = 0; s < m->nsub; ++s)
+        for (int l = 1; l <= 3; ++l) {
+            const double gam = kGamma[l - 1], rho = kRho[l - 1], alp = gam + rho;
+            MrTArgs a{};
+            a.u0 = v0[0];
+            a.v0 = v0[1];
+            a.w0 = v0[2];
+            a.u1 = v1[0];
+            a.v1 = v1[1];
+            a.w1 = v1[2];
+            a.t = tf;
+            a.hp = m->h;
+            a.rt = m->rt;
+            a.hout = l < 3 ? m->h : nullptr;
+            a.th = (s + start[l - 1]) / m->nsub;
+            a.dt = dts;
+            a.ka = kappa;
+            a.gam = gam;
+            a.rho = rho;
+            a.alp = alp;
+            PS_HIP(launch_mr_explicit_t(m->gf, a, st), "temperature explicit terms");
+            PS_HIP(launch_cn_factor(m->gf, PS_FACE, alp * dts * kappa / 2.0, m->cnfac, st), "cn factor");
+            PS_HIP(launch_cn_solve_add(m->gf, PS_FACE, m->cnfac, m->rt, tf, st), "cn solve T");
+        }
+    return PS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ps_status mr_temperature_step(ps_mr_t m, double dt, double kappa, const double* const* vel0,
+                              const double* const* vel1, double* tf, void* stream) {
+    PS_CHECK(check_mr(m));
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(PS_EINVAL, "dt must be positive");
+    if (!(kappa >= 0) || !std::isfinite(kappa)) return fail(PS_EINVAL, "kappa must be non-negative");
+    if (!vel0 || !vel1) return fail(PS_EINVAL, "vel0 and vel1 are required");
+    for (int q = 0; q < 3; ++q) {
+        PS_CHECK(check_ptr(vel0[q], "vel0[q]"));
+        PS_CHECK(check_ptr(vel1[q], "vel1[q]"));
+        if ((const void*)vel0[q] == (const void*)tf || (const void*)vel1[q] == (const void*)tf)
+            return fail(PS_EINVAL, "tf may not alias a velocity");
+    }
+    PS_CHECK(check_ptr(tf, "tf"));
+    return mr_tstep(m, dt, kappa, vel0, vel1, tf, (hipStream_t)stream);
+}
+
+ps_status rk3_step_mr(ps_mr_t m, double dt, double cfl_target, double dt_max, double nu, double kappa, double* u,
+                      double* v, double* w, double* pr, double* tf, double* dt_used, void* stream, ps_info* info) {
+    PS_CHECK(check_mr(m));
+    ps_plan_t p = m->plan;
+    PS_CHECK(check_ptr(u, "u"));
+    PS_CHECK(check_ptr(v, "v"));
+    PS_CHECK(check_ptr(w, "w"));
+    PS_CHECK(check_ptr(pr, "p"));
+    PS_CHECK(check_ptr(tf, "tf"));
+    if (!(nu >= 0) || !(kappa >= 0) || !std::isfinite(nu) || !std::isfinite(kappa))
+        return fail(PS_EINVAL, "nu and kappa must be non-negative");
+    hipStream_t st = (hipStream_t)stream;
+    if (!(dt > 0)) {
+        if (!(cfl_target > 0) || !std::isfinite(cfl_target)) return fail(PS_EINVAL, "cfl_target must be positive");
+        if (!(dt_max > 0)) return fail(PS_EINVAL, "dt_max must be positive");
+        PS_HIP(launch_cfl(p->gd, u, v, w, p->small + R_CFL, st), "cfl");
+        PS_CHECK(read_small(p, st));
+        const double c = p->h_res[R_CFL];
+        if (!std::isfinite(c)) return fail(PS_ENONFINITE, "Courant number is not finite");
+        dt = std::min(dt_max, cfl_target / std::max(c, 1e-8));
+    }
+    if (!std::isfinite(dt)) return fail(PS_EINVAL, "dt must be finite");
+    PS_CHECK(ensure_substep_buffers(p));
+    // buoyancy: the temperature restricted to the momentum grid, frozen over the step
+    PS_HIP(launch_mr_restrict(p->gd, m->md, tf, m->tc, st), "restriction");
+    PS_HIP(launch_mr_prolong(p->gd, m->md, u, v, w, m->u0, m->v0, m->w0, st), "prolongation");
+    double* h[4] = {sub_field(p, 4), sub_field(p, 5), sub_field(p, 6), sub_field(p, 7)};
+    const double* hc[4] = {h[0], h[1], h[2], h[3]};
+    ps_info acc{};
+    ps_status result = PS_OK;
+    std::string first_msg;
+    for (int l = 1; l <= 3; ++l) {
+        ps_info li{};
+        const ps_status r = substep_impl(p, l, dt, nu, kappa, u, v, w, m->tc, pr, l > 1 ? hc : nullptr,
+                                         l < 3 ? h : nullptr, stream, info ? &li : nullptr, false);
+        if (r != PS_OK && r != PS_ENOTCONVERGED) return r;
+        if (r == PS_ENOTCONVERGED && result == PS_OK) {
+            result = r;
+            first_msg = g_last_error;
+        }
+        acc.iterations += li.iterations;
+        acc.rel_update = std::max(acc.rel_update, li.rel_update);
+        acc.rel_residual = std::max(acc.rel_residual, li.rel_residual);
+        acc.compat_defect = li.compat_defect;
+        acc.gauge_shift = li.gauge_shift;
+    }
+    PS_HIP(launch_mr_prolong(p->gd, m->md, u, v, w, m->u1, m->v1, m->w1, st), "prolongation");
+    const double* v0[3] = {m->u0, m->v0, m->w0};
+    const double* v1[3] = {m->u1, m->v1, m->w1};
+    PS_CHECK(mr_tstep(m, dt, kappa, v0, v1, tf, st));
+    if (dt_used) *dt_used = dt;
+    if (info) *info = acc;
+    if (result != PS_OK) return fail(result, "%s", first_msg.c_str());
+    return PS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,375 @@
+// Multiple-resolution temperature grid (paper Sec. 6): the temperature lives on a grid that
+// refines the momentum grid by integer factors (rx, ry, rz), every momentum cell split into
+// rx ry rz equal sub-cells.
+//
+//   k_mr_prolong    momentum-grid face velocity -> temperature-grid face velocity, one
+//                   thread per momentum cell: linear profiles across the coarse faces
+//                   (coarse fluxes kept), linear interpolation along the normal inside the
+//                   cell, then the local correction G psi, psi = -(L_loc)^+ r, that gives
+//                   every sub-cell the divergence of its coarse cell (L_loc: Laplacian of
+//                   the cell's sub-cells with closed coarse faces; (L_loc)^+ per coarse
+//                   level from the host)
+//   k_mr_restrict   temperature -> coarse z-faces: mean over the rx ry fine columns of each
+//                   coarse column, at the coarse face's height
+//   k_mr_explicit_t explicit terms of the temperature equation on its own grid, with the
+//                   advecting velocity interpolated in time between two fine velocity
+//                   fields (z-marching over column tiles, as k_explicit)
+#include "ps_internal.h"
+
+namespace ps {
+
+namespace {
+__device__ __forceinline__ double sq(double a) { return a * a; }
+}  // namespace
+
+// Offsets of the R sub-cell centres from the coarse centre, for a spacing h.
+template <int R>
+__device__ __forceinline__ double sub_offset(int b, double h) {
+    return ((b + 0.5) / R - 0.5) * h;
+}
+
+template <int RX, int RY, int RZ>
+__global__ void __launch_bounds__(kStencilBlock)
+k_mr_prolong(const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w,
+             double* __restrict__ uf, double* __restrict__ vf, double* __restrict__ wf, GridDev g, MrDev m) {
+    constexpr int NS = RX * RY * RZ;
+    int i, j, k;
+    if (!stencil_cell(g, i, j, k)) return;
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const size_t plane = (size_t)nx * ny;
+    const int im = (i == 0) ? nx - 1 : i - 1, ip = (i + 1 == nx) ? 0 : i + 1;
+    const int jm = (j == 0) ? ny - 1 : j - 1, jp = (j + 1 == ny) ? 0 : j + 1;
+    const bool lo = k > 0, hi = k + 1 < nz;
+    const int km = lo ? k - 1 : k, kp = hi ? k + 1 : k;
+    auto at = [&](int kk, int jj, int ii) { return (size_t)kk * plane + (size_t)jj * nx + ii; };
+    // coarse faces of this cell and the neighbours of each across it (all loads unconditional)
+    const double uL = u[at(k, j, i)], uLyp = u[at(k, jp, i)], uLym = u[at(k, jm, i)], uLzm = u[at(km, j, i)],
+                 uLzp = u[at(kp, j, i)];
+    const double uR = u[at(k, j, ip)], uRyp = u[at(k, jp, ip)], uRym = u[at(k, jm, ip)], uRzm = u[at(km, j, ip)],
+                 uRzp = u[at(kp, j, ip)];
+    const double vF = v[at(k, j, i)], vFxp = v[at(k, j, ip)], vFxm = v[at(k, j, im)], vFzm = v[at(km, j, i)],
+                 vFzp = v[at(kp, j, i)];
+    const double vB = v[at(k, jp, i)], vBxp = v[at(k, jp, ip)], vBxm = v[at(k, jp, im)], vBzm = v[at(km, jp, i)],
+                 vBzp = v[at(kp, jp, i)];
+    const double wD = w[at(k, j, i)], wDxp = w[at(k, j, ip)], wDxm = w[at(k, j, im)], wDyp = w[at(k, jp, i)],
+                 wDym = w[at(k, jm, i)];
+    const double wU = w[at(k + 1, j, i)], wUxp = w[at(k + 1, j, ip)], wUxm = w[at(k + 1, j, im)],
+                 wUyp = w[at(k + 1, jp, i)], wUym = w[at(k + 1, jm, i)];
+    anchor(uL); anchor(uLyp); anchor(uLym); anchor(uLzm); anchor(uLzp);
+    anchor(uR); anchor(uRyp); anchor(uRym); anchor(uRzm); anchor(uRzp);
+    anchor(vF); anchor(vFxp); anchor(vFxm); anchor(vFzm); anchor(vFzp);
+    anchor(vB); anchor(vBxp); anchor(vBxm); anchor(vBzm); anchor(vBzp);
+    anchor(wD); anchor(wDxp); anchor(wDxm); anchor(wDyp); anchor(wDym);
+    anchor(wU); anchor(wUxp); anchor(wUxm); anchor(wUyp); anchor(wUym);
+    // wall-normal slopes at the coarse centre: three-point formula, the no-slip wall value 0
+    // at the wall as the outer point
+    const double hm = m.zhm[k], hp = m.zhp[k];
+    auto zsl = [&](double qm, double qc, double qp) {
+        qm = lo ? qm : 0.0;
+        qp = hi ? qp : 0.0;
+        return (hm * hm * (qp - qc) + hp * hp * (qc - qm)) / (hm * hp * (hm + hp));
+    };
+    const double syL = (uLyp - uLym) / (2 * g.dy), szL = zsl(uLzm, uL, uLzp);
+    const double syR = (uRyp - uRym) / (2 * g.dy), szR = zsl(uRzm, uR, uRzp);
+    const double sxF = (vFxp - vFxm) / (2 * g.dx), szF = zsl(vFzm, vF, vFzp);
+    const double sxB = (vBxp - vBxm) / (2 * g.dx), szB = zsl(vBzm, vB, vBzp);
+    const double sxD = (wDxp - wDxm) / (2 * g.dx), syD = (wDyp - wDym) / (2 * g.dy);
+    const double sxU = (wUxp - wUxm) / (2 * g.dx), syU = (wUyp - wUym) / (2 * g.dy);
+    const double dzk = g.dz[k];
+    double ex[RX], ey[RY], ez[RZ];
+#pragma unroll
+    for (int a = 0; a < RX; ++a) ex[a] = sub_offset<RX>(a, g.dx);
+#pragma unroll
+    for (int b = 0; b < RY; ++b) ey[b] = sub_offset<RY>(b, g.dy);
+#pragma unroll
+    for (int c = 0; c < RZ; ++c) ez[c] = sub_offset<RZ>(c, dzk);
+    // fine face values: fu[a][b][c] on the x-faces a = 0..RX of the cell (0, RX: coarse faces)
+    double fu[RX + 1][RY][RZ], fv[RX][RY + 1][RZ], fw[RX][RY][RZ + 1];
+#pragma unroll
+    for (int b = 0; b < RY; ++b)
+#pragma unroll
+        for (int c = 0; c < RZ; ++c) {
+            fu[0][b][c] = uL + syL * ey[b] + szL * ez[c];
+            fu[RX][b][c] = uR + syR * ey[b] + szR * ez[c];
+#pragma unroll
+            for (int a = 1; a < RX; ++a)
+                fu[a][b][c] = (1 - (double)a / RX) * fu[0][b][c] + ((double)a / RX) * fu[RX][b][c];
+        }
+#pragma unroll
+    for (int a = 0; a < RX; ++a)
+#pragma unroll
+        for (int c = 0; c < RZ; ++c) {
+            fv[a][0][c] = vF + sxF * ex[a] + szF * ez[c];
+            fv[a][RY][c] = vB + sxB * ex[a] + szB * ez[c];
+#pragma unroll
+            for (int b = 1; b < RY; ++b)
+                fv[a][b][c] = (1 - (double)b / RY) * fv[a][0][c] + ((double)b / RY) * fv[a][RY][c];
+        }
+#pragma unroll
+    for (int a = 0; a < RX; ++a)
+#pragma unroll
+        for (int b = 0; b < RY; ++b) {
+            fw[a][b][0] = wD + sxD * ex[a] + syD * ey[b];
+            fw[a][b][RZ] = wU + sxU * ex[a] + syU * ey[b];
+#pragma unroll
+            for (int c = 1; c < RZ; ++c)
+                fw[a][b][c] = (1 - (double)c / RZ) * fw[a][b][0] + ((double)c / RZ) * fw[a][b][RZ];
+        }
+    if constexpr (NS > 1) {
+        // sub-cell divergences, then psi = (L_loc)^+ r and the correction -(G psi) on the
+        // interior faces; sub-cell (a, b, c) has index (c RY + b) RX + a
+        const double dxf = m.dxf, dyf = m.dyf;
+        double r[NS];
+#pragma unroll
+        for (int c = 0; c < RZ; ++c) {
+            const double dzf = m.dzf[k * RZ + c];
+#pragma unroll
+            for (int b = 0; b < RY; ++b)
+#pragma unroll
+                for (int a = 0; a < RX; ++a)
+                    r[(c * RY + b) * RX + a] = ((fu[a + 1][b][c] - fu[a][b][c]) / dxf +
+                                                (fv[a][b + 1][c] - fv[a][b][c]) / dyf) +
+                                               (fw[a][b][c + 1] - fw[a][b][c]) / dzf;
+        }
+        const double* L = m.linv + (size_t)k * NS * NS;   // uniform per block: scalar loads
+        double psi[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            double acc = 0.0;
+#pragma unroll
+            for (int t = 0; t < NS; ++t) acc += L[s * NS + t] * r[t];
+            psi[s] = acc;
+        }
+#pragma unroll
+        for (int c = 0; c < RZ; ++c)
+#pragma unroll
+            for (int b = 0; b < RY; ++b)
+#pragma unroll
+                for (int a = 1; a < RX; ++a)
+                    fu[a][b][c] -= (psi[(c * RY + b) * RX + a] - psi[(c * RY + b) * RX + a - 1]) / dxf;
+#pragma unroll
+        for (int c = 0; c < RZ; ++c)
+#pragma unroll
+            for (int b = 1; b < RY; ++b)
+#pragma unroll
+                for (int a = 0; a < RX; ++a)
+                    fv[a][b][c] -= (psi[(c * RY + b) * RX + a] - psi[(c * RY + b - 1) * RX + a]) / dyf;
+#pragma unroll
+        for (int c = 1; c < RZ; ++c) {
+            const double dzc = m.dzf[k * RZ + c];   // sub-cells of one coarse cell: equal heights
+#pragma unroll
+            for (int b = 0; b < RY; ++b)
+#pragma unroll
+                for (int a = 0; a < RX; ++a)
+                    fw[a][b][c] -= (psi[(c * RY + b) * RX + a] - psi[((c - 1) * RY + b) * RX + a]) / dzc;
+        }
+    }
+    // this cell's faces of the fine grid: its lower x, y and z coarse faces and the interior ones
+    const size_t NX = (size_t)nx * RX, NYX = NX * (size_t)(ny * RY);
+#pragma unroll
+    for (int c = 0; c < RZ; ++c)
+#pragma unroll
+        for (int b = 0; b < RY; ++b) {
+            const size_t row = (size_t)(k * RZ + c) * NYX + (size_t)(j * RY + b) * NX + (size_t)i * RX;
+#pragma unroll
+            for (int a = 0; a < RX; ++a) {
+                uf[row + a] = fu[a][b][c];
+                vf[row + a] = fv[a][b][c];
+                wf[row + a] = fw[a][b][c];
+            }
+        }
+    if (!hi) {
+#pragma unroll
+        for (int b = 0; b < RY; ++b) {
+            const size_t row = (size_t)(nz * RZ) * NYX + (size_t)(j * RY + b) * NX + (size_t)i * RX;
+#pragma unroll
+            for (int a = 0; a < RX; ++a) wf[row + a] = fw[a][b][RZ];
+        }
+    }
+}
+
+// tc[k][j][i] = mean of tf[rz k][ry j + b][rx i + a], k = 0..nz (one thread per coarse face point)
+__global__ void __launch_bounds__(256)
+k_mr_restrict(const double* __restrict__ tf, double* __restrict__ tc, int nx, int ny, int nz, int rx, int ry,
+              int rz) {
+    const size_t n = (size_t)nx * ny * (nz + 1);
+    const size_t id = (size_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (id >= n) return;
+    const int i = (int)(id % nx);
+    const size_t r = id / nx;
+    const int j = (int)(r % ny);
+    const int k = (int)(r / ny);
+    const size_t NX = (size_t)nx * rx, NY = (size_t)ny * ry;
+    const double* base = tf + (size_t)k * rz * NX * NY + (size_t)j * ry * NX + (size_t)i * rx;
+    double s = 0.0;
+    for (int b = 0; b < ry; ++b)
+        for (int a = 0; a < rx; ++a) s += base[(size_t)b * NX + a];
+    tc[id] = s / (double)(rx * ry);
+}
+
+// ---- explicit terms of the temperature equation on its own grid ------------------------
+// z-marching over 32 x 8 column tiles with a three-plane LDS ring of u, v, w, T (the velocity
+// staged as (1 - th) vel0 + th vel1), as in k_explicit.  Writes rt = dt [gamma H + rho Hprev
+// + alpha kappa Dzz T] on interior faces (walls 0) and H (optional).
+constexpr int kMtTX = 32, kMtTY = 8, kMtZSEG = 64;
+
+template <int NF, int TX, int TY>
+struct MtRing {
+    static constexpr int HX = TX + 2, HY = TY + 2, PL = HX * HY;
+    static constexpr int NQ = (PL + TX * TY - 1) / (TX * TY);
+    double* s;
+    int tx, ty;
+    __device__ __forceinline__ static int slot(int kk) { return (kk + 3) % 3; }
+    __device__ __forceinline__ double operator()(int k, int f, int dk, int dj, int di) const {
+        return s[(slot(k + dk) * NF + f) * PL + (ty + 1 + dj) * HX + (tx + 1 + di)];
+    }
+};
+
+__global__ void __launch_bounds__(kMtTX * kMtTY) k_mr_explicit_t(MrTArgs a, GridDev g) {
+    constexpr int TX = kMtTX, TY = kMtTY, NF = 4;
+    using RingT = MtRing<NF, TX, TY>;
+    constexpr int NQ = RingT::NQ, PL = RingT::PL, HX = RingT::HX;
+    enum { FU, FV, FW, FT };
+    __shared__ double lds[3 * NF * PL];
+    const int nxt = (g.nx + TX - 1) / TX, nyt = (g.ny + TY - 1) / TY;
+    int rb = xcd_remap(blockIdx.x, gridDim.x);
+    const int xt = rb % nxt;
+    rb /= nxt;
+    const int yt = rb % nyt;
+    const int zs = rb / nyt;
+    const int i0 = xt * TX, j0 = yt * TY, kb = zs * kMtZSEG, ke = min(g.nz, kb + kMtZSEG);
+    RingT R{lds, (int)threadIdx.x % TX, (int)threadIdx.x / TX};
+    const int i = i0 + R.tx, j = j0 + R.ty;
+    const bool valid = i < g.nx && j < g.ny;
+    const size_t plane = (size_t)g.nx * g.ny;
+    // periodic column offsets of this thread's halo cells (the same for every plane)
+    unsigned off[NQ];
+#pragma unroll
+    for (int qi = 0; qi < NQ; ++qi) {
+        const int q = min((int)threadIdx.x + qi * TX * TY, PL - 1);
+        const int hy = q / HX, hx = q - hy * HX;
+        int gj = j0 - 1 + hy, gi = i0 - 1 + hx;
+        gj = gj < 0 ? gj + g.ny : gj % g.ny;
+        gi = gi < 0 ? gi + g.nx : gi % g.nx;
+        off[qi] = (unsigned)gj * (unsigned)g.nx + (unsigned)gi;
+    }
+    const double th = a.th, th1 = 1.0 - a.th;
+    double stv[NQ][NF];
+    // plane kk of every field into registers (velocity blended in time; zeros outside a field)
+    auto fetch = [&](int kk) {
+        const int kc = kk < 0 ? 0 : (kk > g.nz - 1 ? g.nz - 1 : kk);
+        const int kf = kk < 0 ? 0 : (kk > g.nz ? g.nz : kk);
+        const bool okc = kk >= 0 && kk < g.nz, okf = kk >= 0 && kk <= g.nz;
+        const size_t pc = (size_t)kc * plane, pf = (size_t)kf * plane;
+#pragma unroll
+        for (int qi = 0; qi < NQ; ++qi) {
+            const size_t oc = pc + off[qi], of = pf + off[qi];
+            const double u0 = a.u0[oc], u1 = a.u1[oc], v0 = a.v0[oc], v1 = a.v1[oc];
+            const double w0 = a.w0[of], w1 = a.w1[of], tt = a.t[of];
+            stv[qi][FU] = okc ? th1 * u0 + th * u1 : 0.0;
+            stv[qi][FV] = okc ? th1 * v0 + th * v1 : 0.0;
+            stv[qi][FW] = okf ? th1 * w0 + th * w1 : 0.0;
+            stv[qi][FT] = okf ? tt : 0.0;
+        }
+    };
+    auto put = [&](int kk) {
+        const int sl = RingT::slot(kk);
+#pragma unroll
+        for (int qi = 0; qi < NQ; ++qi) {
+            const int q = (int)threadIdx.x + qi * TX * TY;
+            if (q < PL) {
+#pragma unroll
+                for (int f = 0; f < NF; ++f) lds[(sl * NF + f) * PL + q] = stv[qi][f];
+            }
+        }
+    };
+    const double idx = 1.0 / g.dx, idy = 1.0 / g.dy;
+    const double idx2 = idx * idx, idy2 = idy * idy;
+    const int nz = g.nz;
+    fetch(kb - 1);
+    put(kb - 1);
+    fetch(kb);
+    put(kb);
+    fetch(kb + 1);
+    for (int k = kb; k < ke; ++k) {
+        put(k + 1);
+        __syncthreads();
+        const size_t id = (size_t)k * plane + (size_t)j * g.nx + i;
+        double hp = 0.0;
+        if (a.rho != 0.0) hp = a.hp[valid ? id : (size_t)k * plane];
+        if (k + 2 <= ke) fetch(k + 2);
+        if (valid) {
+            auto L = [&](int f, int dk, int dj, int di) { return R(k, f, dk, dj, di); };
+            if (k == 0) {
+                a.rt[id] = 0.0;
+                if (a.hout) a.hout[id] = 0.0;
+            } else {
+                const double dzm = g.dz[k - 1], dzp = g.dz[k], den = 0.5 * g.o[k];
+                const double uwl = (dzm * L(FU, -1, 0, 0) + dzp * L(FU, 0, 0, 0)) * den;
+                const double uwr = (dzm * L(FU, -1, 0, 1) + dzp * L(FU, 0, 0, 1)) * den;
+                const double vwb = (dzm * L(FV, -1, 0, 0) + dzp * L(FV, 0, 0, 0)) * den;
+                const double vwt = (dzm * L(FV, -1, 1, 0) + dzp * L(FV, 0, 1, 0)) * den;
+                const double wc = L(FW, 0, 0, 0), wkm = L(FW, -1, 0, 0), wkp = L(FW, 1, 0, 0);
+                const double tc = L(FT, 0, 0, 0), tim = L(FT, 0, 0, -1), tip = L(FT, 0, 0, 1);
+                const double tjm = L(FT, 0, -1, 0), tjp = L(FT, 0, 1, 0);
+                const double tkm = L(FT, -1, 0, 0), tkp = L(FT, 1, 0, 0);
+                const double idzc = g.o[k];
+                const double wtop = 0.5 * (wc + wkp), wbot = 0.5 * (wkm + wc);
+                const double ax = (uwr * (0.5 * (tc + tip)) - uwl * (0.5 * (tim + tc))) * idx;
+                const double ay = (vwt * (0.5 * (tc + tjp)) - vwb * (0.5 * (tjm + tc))) * idy;
+                const double az = (wtop * (0.5 * (tc + tkp)) - wbot * (0.5 * (tkm + tc))) * idzc;
+                const double h = -(ax + ay + az) + a.ka * ((tip - 2.0 * tc + tim) * idx2 + (tjp - 2.0 * tc + tjm) * idy2);
+                const double dzz = ((tkp - tc) * g.idz[k] - (tc - tkm) * g.idz[k - 1]) * idzc;
+                double r = a.gam * h + a.alp * (a.ka * dzz);
+                if (a.rho != 0.0) r += a.rho * hp;
+                a.rt[id] = a.dt * r;
+                if (a.hout) a.hout[id] = h;
+            }
+            if (k + 1 == nz) {
+                a.rt[id + plane] = 0.0;
+                if (a.hout) a.hout[id + plane] = 0.0;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---- launchers ------------------------------------------------------------------------------
+bool mr_factors_supported(int rx, int ry, int rz) {
+    return rx >= 1 && rx <= 2 && ry >= 1 && ry <= 2 && rz >= 1 && rz <= 2;
+}
+
+hipError_t launch_mr_prolong(const GridDev& g, const MrDev& m, const double* u, const double* v, const double* w,
+                             double* uf, double* vf, double* wf, hipStream_t st) {
+    const dim3 grid(stencil_blocks(g)), block(kStencilBlock);
+#define PS_MR_CASE(X, Y, Z)                                                                          \
+    if (m.rx == X && m.ry == Y && m.rz == Z) {                                                       \
+        hipLaunchKernelGGL((k_mr_prolong<X, Y, Z>), grid, block, 0, st, u, v, w, uf, vf, wf, g, m); \
+        return hipGetLastError();                                                                    \
+    }
+    PS_MR_CASE(1, 1, 1)
+    PS_MR_CASE(2, 1, 1)
+    PS_MR_CASE(1, 2, 1)
+    PS_MR_CASE(2, 2, 1)
+    PS_MR_CASE(1, 1, 2)
+    PS_MR_CASE(2, 1, 2)
+    PS_MR_CASE(1, 2, 2)
+    PS_MR_CASE(2, 2, 2)
+#undef PS_MR_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_mr_restrict(const GridDev& g, const MrDev& m, const double* tf, double* tc, hipStream_t st) {
+    const size_t n = (size_t)g.nx * g.ny * (g.nz + 1);
+    hipLaunchKernelGGL(k_mr_restrict, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, tf, tc, g.nx, g.ny, g.nz,
+                       m.rx, m.ry, m.rz);
+    return hipGetLastError();
+}
+
+hipError_t launch_mr_explicit_t(const GridDev& gf, const MrTArgs& a, hipStream_t st) {
+    const int nblk = ((gf.nx + kMtTX - 1) / kMtTX) * ((gf.ny + kMtTY - 1) / kMtTY) * ((gf.nz + kMtZSEG - 1) / kMtZSEG);
+    hipLaunchKernelGGL(k_mr_explicit_t, dim3(nblk), dim3(kMtTX * kMtTY), 0, st, a, gf);
+    return hipGetLastError();
+}
+
+}  // namespace ps

@@ -279,4 +279,28 @@ hipError_t launch_cn_solve_add(const GridDev& g, int kind, const double* fac, do
 hipError_t launch_cn_solve_t(const GridDev& g, int kind, const double* fac, const double* in, double* out,
                              hipStream_t st);
 
+// Multiple-resolution temperature grid (multires_kernels.hip).
+struct MrDev {
+    int rx, ry, rz;              // refinement factors
+    double dxf, dyf;             // temperature-grid spacings lx / (rx nx), ly / (ry ny)
+    const double* dzf;           // temperature-grid cell heights, rz nz
+    const double* zhm;           // per momentum level k: zc_k - (zc_{k-1} or the lower wall)
+    const double* zhp;           // per momentum level k: (zc_{k+1} or the upper wall) - zc_k
+    const double* linv;          // per momentum level k: (L_loc)^+, (rx ry rz)^2 entries
+};
+struct MrTArgs {
+    const double *u0, *v0, *w0;  // temperature-grid velocity at the start of the interval
+    const double *u1, *v1, *w1;  // ... and at its end
+    const double* t;             // temperature (fine z-faces)
+    const double* hp;            // previous substep's H (rho != 0)
+    double* rt;                  // right-hand side of the Crank-Nicolson solve
+    double* hout;                // this substep's H (optional; may alias hp)
+    double th, dt, ka, gam, rho, alp;
+};
+bool mr_factors_supported(int rx, int ry, int rz);
+hipError_t launch_mr_prolong(const GridDev& g, const MrDev& m, const double* u, const double* v, const double* w,
+                             double* uf, double* vf, double* wf, hipStream_t st);
+hipError_t launch_mr_restrict(const GridDev& g, const MrDev& m, const double* tf, double* tc, hipStream_t st);
+hipError_t launch_mr_explicit_t(const GridDev& gf, const MrTArgs& a, hipStream_t st);
+
 }  // namespace ps

@@ -232,11 +232,13 @@ __global__ void __launch_bounds__(kExTX * kExTY) k_explicit(SubstepArgs a, GridD
                 if (a.hv) a.hv[id] = h;
             }
             // ---- w and T at (x-centre i, y-centre j, z-face k), interior faces ----
+            // (rt NULL: the temperature is not advanced, only its buoyancy is used)
+            const bool with_t = a.rt != nullptr;
             if (k == 0) {
                 a.rw[id] = 0.0;
-                a.rt[id] = 0.0;
+                if (with_t) a.rt[id] = 0.0;
                 if (a.hw) a.hw[id] = 0.0;
-                if (a.ht) a.ht[id] = 0.0;
+                if (a.ht && with_t) a.ht[id] = 0.0;
             } else {
                 const double dzm = g.dz[k - 1], dzp = g.dz[k], den = 0.5 * g.o[k];   // o = 1/dzc (interior face)
                 // volume-weighted horizontal transport on the side faces
@@ -267,7 +269,7 @@ __global__ void __launch_bounds__(kExTX * kExTY) k_explicit(SubstepArgs a, GridD
                     if (a.hw) a.hw[id] = h;
                 }
                 // T
-                {
+                if (with_t) {
                     const double ax = (uwr * (0.5 * (tc + tip)) - uwl * (0.5 * (tim + tc))) * idx;
                     const double ay = (vwt * (0.5 * (tc + tjp)) - vwb * (0.5 * (tjm + tc))) * idy;
                     const double az = (wtop * (0.5 * (tc + tkp)) - wbot * (0.5 * (tkm + tc))) * idzc;
@@ -282,9 +284,9 @@ __global__ void __launch_bounds__(kExTX * kExTY) k_explicit(SubstepArgs a, GridD
             if (k + 1 == nz) {
                 const size_t top = id + plane;
                 a.rw[top] = 0.0;
-                a.rt[top] = 0.0;
+                if (with_t) a.rt[top] = 0.0;
                 if (a.hw) a.hw[top] = 0.0;
-                if (a.ht) a.ht[top] = 0.0;
+                if (a.ht && with_t) a.ht[top] = 0.0;
             }
         }
         __syncthreads();

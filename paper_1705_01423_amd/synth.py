@@ -35,7 +35,7 @@ import numpy as np
 
 __all__ = [
     "Config", "CONFIGS", "zfaces", "cell_centres", "random_face_velocity",
-    "mode_velocity", "rb_state", "face_weights",
+    "mode_velocity", "rb_state", "rb_temperature", "face_weights",
 ]
 
 
@@ -66,6 +66,8 @@ CONFIGS = {
     "couette1024x1024x512": Config("couette1024x1024x512", 1024, 1024, 512, 4.0, 4.0, 3.0, 1002, {"couette": True}),
     "slab256x256x192": Config("slab256x256x192", 256, 256, 192, 2.0, 2.0, 3.0, 1003),
     "rb768x768x512": Config("rb768x768x512", 768, 768, 512, 1.0, 1.0, 3.0, 1004, {"ra": 1e8, "pr": 1.0}),
+    # momentum on the Ra = 1e8 grid of Table 3, temperature refined twice in every direction
+    "rb384x384x256": Config("rb384x384x256", 384, 384, 256, 1.0, 1.0, 3.0, 1005, {"ra": 1e8, "pr": 1.0}),
 }
 
 
@@ -225,6 +227,18 @@ def rb_state(cfg: Config, tnoise: float = 1e-3, unoise: float = 1e-2):
     w[1:nz] -= w[1:nz].mean()
     p = np.zeros((nz, ny, nx), dtype=np.float64)
     return u, v, w, t, p
+
+
+def rb_temperature(cfg: Config, zf: np.ndarray, nx: int, ny: int, tnoise: float = 1e-3, seed_tag: int = 25):
+    """Temperature on faces ``zf`` of an nx x ny grid: 1 - z plus N(0, tnoise^2) at interior
+    faces, walls exact (for a temperature grid finer than the momentum grid of ``cfg``)."""
+    nzf = len(zf) - 1
+    t = np.empty((nzf + 1, ny, nx), dtype=np.float64)
+    t[:] = (1.0 - np.asarray(zf))[:, None, None]
+    t[1:nzf] += _normal_planes(cfg.seed, seed_tag, (nzf - 1, ny, nx), tnoise)
+    t[0] = 1.0
+    t[nzf] = 0.0
+    return t
 
 
 def face_weights(cfg: Config, seed_tag: int = 31):
