@@ -56,6 +56,19 @@ def recorded_traffic(stage):
     return None if k is None else k["traffic_bytes"]
 
 
+def cpu_model():
+    """The host CPU's model name (lscpu), or None."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+    except (OSError, subprocess.SubprocessError):
+        return None
+    for line in out.splitlines():
+        if line.startswith("Model name:"):
+            return line.split(":", 1)[1].strip()
+    return None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -67,6 +80,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="couette1024x1024x512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-single-thread", action="store_true", help="skip the single-thread oracle solve")
     ap.add_argument("--no-refined", action="store_true")
     ap.add_argument("--stage-reps", type=int, default=10)
     ap.add_argument("--no-extra", action="store_true", help="skip the projection/adjoint/substep legs")
@@ -149,22 +163,21 @@ def main():
     plan.solve_nosync(f, phi)
     torch.cuda.synchronize()
 
-    # copy reference: read + write one field
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    # practical ceiling: the library's streaming copy (read + write one field), and torch's copy_
+    from paper_1705_01423_amd.api import stream_copy
     tmp = torch.empty_like(f)
-    tmp.copy_(f)
-    e0.record(stream)
-    for _ in range(5):
-        tmp.copy_(f)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    copy_gbs = 2 * f.numel() * 8 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    stream_copy(tmp, f)
+    copy_ms = _event_ms(lambda: stream_copy(tmp, f), 5)
+    copy_gbs = 2 * f.numel() * 8 / (copy_ms * 1e-3) / 1e9
+    torch_copy_gbs = 2 * f.numel() * 8 / (_event_ms(lambda: tmp.copy_(f), 5) * 1e-3) / 1e9
     del tmp
 
     dominant = max(stage_ms, key=stage_ms.get)
     alg_bytes = 16.0 * npts        # one read + one write of the field's spectral/physical data
     achieved = alg_bytes / (stage_ms[dominant] * 1e-3) / 1e9
+    stage_frac = {k: {"gbs": round(alg_bytes / (x * 1e-3) / 1e9, 1),
+                      "frac_peak": round(alg_bytes / (x * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                      "frac_copy": round(alg_bytes / (x * 1e-3) / 1e9 / copy_gbs, 4)} for k, x in stage_ms.items()}
     roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(dominant),
                 "alg_bytes_per_launch": alg_bytes}
@@ -204,18 +217,28 @@ def main():
         g = Grid(nx, ny, nz, cfg.lx, cfg.ly, zf)
         fo = op.divergence(_t.as_tensor(u), _t.as_tensor(v), _t.as_tensor(w), g)
         del u, v, w
-        # repeated full-size solves until about 10 s of CPU time (at most 8)
-        reps, t_tot = 0, 0.0
-        while reps < 8 and (reps == 0 or t_tot < 10.0):
+        # three full-size solves on all host threads (median), then one on a single thread
+        times = []
+        for _ in range(3):
             t0 = time.perf_counter()
             ref = poisson.solve(fo, g)
-            t_tot += time.perf_counter() - t0
-            reps += 1
-        t_cpu = t_tot / reps
-        cpu_baseline = {"value": round(1.0 / t_cpu, 5), "unit": "solves/s", "cores": _t.get_num_threads(),
+            times.append(time.perf_counter() - t0)
+        t_cpu = sorted(times)[1]
+        nthreads = _t.get_num_threads()
+        t_single = None
+        if not args.no_single_thread:
+            _t.set_num_threads(1)
+            t0 = time.perf_counter()
+            poisson.solve(fo, g)
+            t_single = time.perf_counter() - t0
+            _t.set_num_threads(nthreads)
+        cpu_baseline = {"value": round(1.0 / t_cpu, 5), "unit": "solves/s", "cores": nthreads,
                         "kind": "oracle", "gpoints_per_s": round(npts / t_cpu / 1e9, 4),
-                        "sample": f"{reps} full {nx}x{ny}x{nz} FP64 solves of the same input "
-                                  f"({t_tot:.1f} s, {t_cpu:.2f} s each)"}
+                        "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+                        "single_thread_solves_per_s": None if t_single is None else round(1.0 / t_single, 5),
+                        "sample": f"median of 3 full {nx}x{ny}x{nz} FP64 solves of the same input on {nthreads} "
+                                  f"threads ({', '.join(f'{x:.2f}' for x in times)} s)"
+                                  + ("" if t_single is None else f"; one solve on 1 thread: {t_single:.1f} s")}
         phih = phi.cpu()
         parity = {"fp64_rel_l2_vs_oracle": float((phih - ref).norm() / ref.norm()),
                   "rhs_rel_diff_gpu_vs_oracle": float((f.cpu() - fo).norm() / fo.norm())}
@@ -247,6 +270,8 @@ def main():
         "model_frac_hbm": round(total_gbs / HBM_PEAK_GBS, 4),
         "stages_ms": {k: round(x, 4) for k, x in stage_ms.items()},
         "copy_gbs": round(copy_gbs, 1),
+        "torch_copy_gbs": round(torch_copy_gbs, 1),
+        "stages_roofline": stage_frac,
         "fp32_refined": refined,
         "roofline": roofline,
         "cpu_baseline": cpu_baseline,

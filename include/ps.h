@@ -410,6 +410,14 @@ ps_status ps_debug_stage(ps_plan_t plan, int stage, const void* in, void* out, v
 ps_status ps_spectral_layout(ps_plan_t plan, int* w_tile, int* nkxb);
 size_t ps_spectral_elems(ps_plan_t plan);
 
+/*
+ * ps_stream_copy - dst[0..bytes) = src[0..bytes) on the device (16-byte
+ * non-temporal loads and stores).  A measurement utility: the HBM rate of a
+ * plain one-read / one-write pass, the practical ceiling of the solve's
+ * stages.  src, dst: 16-byte aligned, not overlapping.  Asynchronous.
+ */
+ps_status ps_stream_copy(void* dst, const void* src, size_t bytes, void* stream);
+
 const char* ps_last_error(void);
 
 #ifdef __cplusplus

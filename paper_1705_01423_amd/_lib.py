@@ -61,6 +61,7 @@ SIGNATURES = {
     "ps_debug_stage": (c_int, [_P, c_int, _D, _D, c_void_p]),
     "ps_spectral_layout": (c_int, [_P, POINTER(c_int), POINTER(c_int)]),
     "ps_spectral_elems": (c_size_t, [_P]),
+    "ps_stream_copy": (c_int, [_D, _D, c_size_t, c_void_p]),
     "ps_last_error": (ctypes.c_char_p, []),
 }
 

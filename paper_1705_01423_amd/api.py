@@ -34,6 +34,16 @@ def _ptr(t, name, shape=None):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def stream_copy(dst, src):
+    """ps_stream_copy of src into dst (same number of bytes; device tensors)."""
+    lib = _lib.load()
+    n = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != n:
+        raise ValueError("dst and src differ in size")
+    check(lib.ps_stream_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), n, _stream()))
+    return dst
+
+
 class Plan:
     """One grid (nx, ny, nz, lx, ly, zf) at one precision; owns its device workspace."""
 

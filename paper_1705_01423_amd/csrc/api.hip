@@ -1129,6 +1129,22 @@ ps_status rk3_step_adjoint(ps_plan_t p, double dt, double nu, double kappa, cons
     return PS_OK;
 }
 
+ps_status ps_stream_copy(void* dst, const void* src, size_t bytes, void* stream) {
+    if (!dst || !src || ((uintptr_t)dst) % 16 || ((uintptr_t)src) % 16)
+        return fail(PS_EINVAL, "src and dst must be 16-byte aligned device pointers");
+    const char* s0 = (const char*)src;
+    const char* d0 = (const char*)dst;
+    if (d0 < s0 + bytes && s0 < d0 + bytes && bytes) return fail(PS_EINVAL, "src and dst overlap");
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        ncu = 0;
+    }
+    PS_HIP(launch_stream_copy(dst, src, bytes, ncu, (hipStream_t)stream), "stream copy");
+    return PS_OK;
+}
+
 ps_status ps_spectral_layout(ps_plan_t p, int* w_tile, int* nkxb) {
     if (!p) return fail(PS_EINVAL, "plan is NULL");
     if (w_tile) *w_tile = p->w_tile;

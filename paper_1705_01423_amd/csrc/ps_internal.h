@@ -233,6 +233,8 @@ hipError_t launch_adj_update(const GridDev& g, const double* gu, const double* g
 // out[0..ncomp) = sums over nblk blocks of partial[b * ncomp + c]; scratch holds 1024 * ncomp doubles.
 hipError_t launch_reduce2(const double* partial, int nblk, int ncomp, double* scratch, double* out, hipStream_t st);
 hipError_t launch_fill(double* p, size_t n, double v, hipStream_t st);
+// dst[0..bytes) = src[0..bytes): 16-byte non-temporal loads and stores (src, dst 16-byte aligned)
+hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, int ncu, hipStream_t st);
 // out[0..n) = c * in[0..n) (out may alias in)
 hipError_t launch_scale(const double* in, double* out, double c, size_t n, hipStream_t st);
 hipError_t launch_scale_planes(const GridDev& g, const double* in, double* out, const double* zs, int nplanes,

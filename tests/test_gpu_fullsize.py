@@ -52,7 +52,20 @@ def test_couette_solve_fp64(couette):
     assert err < 1e-12
     assert abs(info["compat_defect"] - defect) < 1e-14
     # gauge: dz-weighted zero mean
-    assert abs(op.weighted_sum(phi.cpu(), g)) < 1e-12 * float(phi.abs().sum())
+    phc = phi.cpu()
+    assert abs(op.weighted_sum(phc, g)) < 1e-12 * float(phi.abs().sum())
+    # plane by plane (a wall row or a single plane's error would hide in the whole-field norm)
+    # and the singular (0, 0) mode alone (the plane means)
+    amax = float(ref.abs().max())
+    plane_err = (phc - ref).abs().amax(dim=(1, 2))
+    print(f"couette fp64 worst plane max-error {float(plane_err.max()):.3e} (max|phi| {amax:.3e})", flush=True)
+    assert float(plane_err.max()) < 1e-12 * amax
+    # the (0, 0) column (plane means, ~1e-7 here against max|phi| ~ 0.7): its own relative error
+    mean_err = (phc - ref).mean(dim=(1, 2)).abs()
+    mean_ref = float(ref.mean(dim=(1, 2)).abs().max())
+    print(f"couette fp64 (0,0) column max error {float(mean_err.max()):.3e} (max plane mean {mean_ref:.3e})",
+          flush=True)
+    assert float(mean_err.max()) < 1e-9 * mean_ref
 
 
 @pytest.mark.timeout(900)
@@ -219,6 +232,12 @@ def test_rb768_substep_forward(rb768):
         inc = rel(a - x0, b - x0) if float((b - x0).norm()) > 0 else 0.0
         print(f"rb768 {name} rel-L2 {err:.3e} (increment {inc:.3e})", flush=True)
         assert err < 1e-10 and inc < 1e-9
+        # every plane, including the wall rows of w and T, within the same bound in max-norm
+        scale = float(b.abs().max())
+        plane_err = (a - b).abs().amax(dim=(1, 2))
+        assert float(plane_err.max()) < 1e-9 * scale, name
+    for name, a in (("w", out[2]), ("T", out[3])):
+        assert torch.equal(a[0], state["wT".index(name) + 2][0]) and torch.equal(a[-1], state["wT".index(name) + 2][-1])
 
 
 @pytest.mark.timeout(900)
@@ -257,3 +276,76 @@ def test_rb768_substep_adjoint_fd(rb768):
         err = abs(fd - an) / max(abs(an), gnorm)
         print(f"rb768 FD trial {trial}: fd {fd:.9e} adjoint {an:.9e} rel {err:.2e}", flush=True)
         assert err <= 1e-6
+
+
+@pytest.mark.timeout(1200)
+def test_rb768_step_adjoint_fd(rb768):
+    """Whole-step VJP (three substeps, fixed dt) at 768^2 x 512 vs central differences of the
+    library's own step, 4 directions."""
+    cfg, zf, g, state, dt, nu, ka = rb768
+    banner("rb768 step adjoint FD")
+    plan = Plan(cfg.nx, cfg.ny, cfg.nz, cfg.lx, cfg.ly, zf, precision="fp64")
+    dstate = [a.to("cuda") for a in state]
+    rng = np.random.default_rng(78)
+    cot = [torch.as_tensor(rng.standard_normal(tuple(a.shape))).to("cuda") for a in state]
+    for c in (cot[2], cot[3]):
+        c[0] = 0
+        c[-1] = 0
+    gin = plan.step_adjoint(dt, nu, ka, *dstate, cot)
+    gnorm = float(torch.sqrt(sum((g_ * g_).sum() for g_ in gin)))
+
+    def forward(st):
+        s2 = [a.clone() for a in st]
+        plan.step(nu, ka, *s2, dt=dt)
+        return s2
+
+    for trial in range(4):
+        d = [torch.as_tensor(rng.standard_normal(tuple(a.shape))).to("cuda") for a in state]
+        for x in (d[2], d[3]):
+            x[0] = 0
+            x[-1] = 0
+        h = 1e-6
+        sp = forward([a + h * b for a, b in zip(dstate, d)])
+        sm = forward([a - h * b for a, b in zip(dstate, d)])
+        fd = float(sum(((x - y) * c).sum() for x, y, c in zip(sp, sm, cot))) / (2 * h)
+        del sp, sm
+        an = float(sum((gi * di).sum() for gi, di in zip(gin, d)))
+        err = abs(fd - an) / max(abs(an), gnorm)
+        print(f"rb768 step FD trial {trial}: fd {fd:.9e} adjoint {an:.9e} rel {err:.2e}", flush=True)
+        assert err <= 1e-6
+    del gin
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(900)
+def test_rb384_multires_full_size():
+    """The benchmark's multiple-resolution configuration (momentum 384^2 x 256, temperature
+    768^2 x 512): the prolonged velocity of a projected state is divergence free on the
+    temperature grid, the restriction matches the oracle, and one coupled step keeps the
+    temperature's wall rows and stays finite."""
+    from oracle import multires as mr
+    from paper_1705_01423_amd.api import MultiRes
+    banner("rb384 multires full size")
+    cfg, zf, g = _setup("rb384x384x256")
+    plan = Plan(cfg.nx, cfg.ny, cfg.nz, cfg.lx, cfg.ly, zf, precision="fp64")
+    m = MultiRes(plan, 2, 2, 2, nsub=2)
+    u, v, w, _, p = (torch.as_tensor(a).to("cuda") for a in synth.rb_state(cfg, unoise=0.1))
+    plan.project(u, v, w)
+    uf, vf, wf = m.prolong_velocity(u, v, w)
+    gf = mr.fine_grid(g, 2, 2, 2)
+    dzf = gf.dz.to("cuda")
+    div = ((torch.roll(uf, -1, 2) - uf) / gf.dx + (torch.roll(vf, -1, 1) - vf) / gf.dy
+           + (wf[1:] - wf[:-1]) / dzf[:, None, None])
+    scale = float(uf.abs().max()) / float(gf.dz.min())
+    print(f"rb384 prolonged max|div| {float(div.abs().max()):.3e} (scale {scale:.3e})", flush=True)
+    assert float(div.abs().max()) < 1e-12 * scale
+    del div, uf, vf, wf
+    zff = mr.fine_faces(zf, 2)
+    tf = torch.as_tensor(synth.rb_temperature(cfg, zff, m.nxf, m.nyf))
+    tc = m.restrict_temperature(tf.to("cuda")).cpu()
+    ref = mr.restrict_temperature(tf, g, 2, 2, 2)
+    assert float((tc - ref).abs().max()) <= 1e-15
+    td = tf.to("cuda")
+    dt, _ = m.step(math.sqrt(1e-8), 1e-4, u, v, w, p, td, dt=0.0, cfl=1.3)
+    assert dt > 0 and bool(torch.isfinite(td).all())
+    assert bool((td[0] == 1.0).all()) and bool((td[-1] == 0.0).all())

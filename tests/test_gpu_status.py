@@ -220,3 +220,19 @@ def test_out_of_memory_then_recovers():
     f = _rhs(plan, seed=9)
     phi, _ = plan.solve(f.to("cuda"))
     assert rel(phi, poisson.solve(f, g)) < 1e-12
+
+
+def test_stream_copy():
+    from paper_1705_01423_amd.api import stream_copy
+    src = torch.as_tensor(np.random.default_rng(11).standard_normal(1001)).to("cuda")
+    dst = torch.zeros_like(src)
+    stream_copy(dst, src)
+    assert torch.equal(dst, src)
+    big = torch.as_tensor(np.random.default_rng(12).standard_normal(3 * 1024 * 1024 + 7)).to("cuda")
+    out = torch.empty_like(big)
+    stream_copy(out, big)
+    assert torch.equal(out, big)
+    lib, P = _lib.load(), ctypes.c_void_p
+    s = P(torch.cuda.current_stream().cuda_stream)
+    assert lib.ps_stream_copy(P(dst.data_ptr() + 8), P(src.data_ptr()), 64, s) == _lib.PS_EINVAL
+    assert lib.ps_stream_copy(P(src.data_ptr() + 16), P(src.data_ptr()), 64, s) == _lib.PS_EINVAL
