@@ -151,6 +151,11 @@ __global__ void __launch_bounds__(kExTX * kExTY) k_explicit(SubstepArgs a, GridD
     const size_t plane = (size_t)g.nx * g.ny;
     const double idx = 1.0 / g.dx, idy = 1.0 / g.dy;
     const double idx2 = idx * idx, idy2 = idy * idy;
+    const double qx = 0.25 * idx, qy = 0.25 * idy;                 // flux products of two sums
+    const double nux = a.nu * idx2, nuy = a.nu * idy2, kax = a.ka * idx2, kay = a.ka * idy2;
+    // RK3 weights times dt: rhs = dt [gamma H + rho H_prev - alpha G p + alpha nu Dzz q]
+    const double cg = a.dt * a.gam, cr = a.dt * a.rho, ca = a.dt * a.alp;
+    const double can = ca * a.nu, cak = ca * a.ka;
     const int nz = g.nz;
     typename Ring<NF, TX, TY>::Stage st;
     R.fetch(tile.kb - 1, F, face, g, cols, st);
@@ -175,60 +180,52 @@ __global__ void __launch_bounds__(kExTX * kExTY) k_explicit(SubstepArgs a, GridD
         if (k + 2 <= tile.ke) R.fetch(k + 2, F, face, g, cols, st);
         if (valid) {
             auto L = [&](int f, int dk, int dj, int di) { return R(k, f, dk, dj, di); };
+            // The two-point averages of every flux product are taken as plain sums, their
+            // factor 1/4 folded into the per-direction scale with the inverse spacing; a
+            // difference of squared averages is formed as (a - b)(a + b); dt folds into the
+            // RK3 weights.  The same discrete operators, fewer FP64 instructions.
+            const double idzk = g.idz[k];
+            const bool lo = k > 0, hi = k + 1 < nz;
             // ---- u at (x-face i, y-centre j, z-centre k) ----
             {
                 const double uc = L(FU, 0, 0, 0), uim = L(FU, 0, 0, -1), uip = L(FU, 0, 0, 1);
                 const double ujm = L(FU, 0, -1, 0), ujp = L(FU, 0, 1, 0);
-                const double ax = (sq(0.5 * (uc + uip)) - sq(0.5 * (uim + uc))) * idx;
-                const double fyb = 0.5 * (L(FV, 0, 0, 0) + L(FV, 0, 0, -1)) * (0.5 * (uc + ujm));
-                const double fyt = 0.5 * (L(FV, 0, 1, 0) + L(FV, 0, 1, -1)) * (0.5 * (ujp + uc));
-                const double ay = (fyt - fyb) * idy;
-                double fzb = 0.0, fzt = 0.0, ukm = 0.0, ukp = 0.0;
-                if (k > 0) {
-                    ukm = L(FU, -1, 0, 0);
-                    fzb = 0.5 * (L(FW, 0, 0, 0) + L(FW, 0, 0, -1)) * (0.5 * (ukm + uc));
-                }
-                if (k + 1 < nz) {
-                    ukp = L(FU, 1, 0, 0);
-                    fzt = 0.5 * (L(FW, 1, 0, 0) + L(FW, 1, 0, -1)) * (0.5 * (uc + ukp));
-                }
-                const double az = (fzt - fzb) * g.idz[k];
-                const double h = -(ax + ay + az) + a.nu * ((uip - 2.0 * uc + uim) * idx2 + (ujp - 2.0 * uc + ujm) * idy2);
-                const double fb = (k > 0) ? (uc - ukm) * g.idzw[k] : uc * g.idzw[0];
-                const double ft = (k + 1 < nz) ? (ukp - uc) * g.idzw[k + 1] : -uc * g.idzw[nz];
-                const double dzz = (ft - fb) * g.idz[k];
+                const double ukm = L(FU, -1, 0, 0), ukp = L(FU, 1, 0, 0);
+                const double ax = (uip - uim) * (uip + uim + 2.0 * uc) * qx;
+                const double ay = ((L(FV, 0, 1, 0) + L(FV, 0, 1, -1)) * (ujp + uc) -
+                                   (L(FV, 0, 0, 0) + L(FV, 0, 0, -1)) * (uc + ujm)) * qy;
+                const double fzb = lo ? (L(FW, 0, 0, 0) + L(FW, 0, 0, -1)) * (ukm + uc) : 0.0;
+                const double fzt = hi ? (L(FW, 1, 0, 0) + L(FW, 1, 0, -1)) * (uc + ukp) : 0.0;
+                const double az = (fzt - fzb) * (0.25 * idzk);
+                const double h = (nux * (uip + uim - 2.0 * uc) + nuy * (ujp + ujm - 2.0 * uc)) - (ax + ay + az);
+                const double fb = lo ? (uc - ukm) * g.idzw[k] : uc * g.idzw[0];
+                const double ft = hi ? (ukp - uc) * g.idzw[k + 1] : -uc * g.idzw[nz];
+                const double dzz = (ft - fb) * idzk;
                 const double gp = (L(FP, 0, 0, 0) - L(FP, 0, 0, -1)) * idx;
-                double r = a.gam * h - a.alp * gp + a.alp * (a.nu * dzz);
-                if (a.rho != 0.0) r += a.rho * hp[0];
-                a.ru[id] = a.dt * r;
+                double r = cg * h - ca * gp + can * dzz;
+                if (a.rho != 0.0) r += cr * hp[0];
+                a.ru[id] = r;
                 if (a.hu) a.hu[id] = h;
             }
             // ---- v at (x-centre i, y-face j, z-centre k) ----
             {
                 const double vc = L(FV, 0, 0, 0), vjm = L(FV, 0, -1, 0), vjp = L(FV, 0, 1, 0);
                 const double vim = L(FV, 0, 0, -1), vip = L(FV, 0, 0, 1);
-                const double ay = (sq(0.5 * (vc + vjp)) - sq(0.5 * (vjm + vc))) * idy;
-                const double fxl = 0.5 * (L(FU, 0, 0, 0) + L(FU, 0, -1, 0)) * (0.5 * (vc + vim));
-                const double fxr = 0.5 * (L(FU, 0, 0, 1) + L(FU, 0, -1, 1)) * (0.5 * (vip + vc));
-                const double ax = (fxr - fxl) * idx;
-                double fzb = 0.0, fzt = 0.0, vkm = 0.0, vkp = 0.0;
-                if (k > 0) {
-                    vkm = L(FV, -1, 0, 0);
-                    fzb = 0.5 * (L(FW, 0, 0, 0) + L(FW, 0, -1, 0)) * (0.5 * (vkm + vc));
-                }
-                if (k + 1 < nz) {
-                    vkp = L(FV, 1, 0, 0);
-                    fzt = 0.5 * (L(FW, 1, 0, 0) + L(FW, 1, -1, 0)) * (0.5 * (vc + vkp));
-                }
-                const double az = (fzt - fzb) * g.idz[k];
-                const double h = -(ax + ay + az) + a.nu * ((vip - 2.0 * vc + vim) * idx2 + (vjp - 2.0 * vc + vjm) * idy2);
-                const double fb = (k > 0) ? (vc - vkm) * g.idzw[k] : vc * g.idzw[0];
-                const double ft = (k + 1 < nz) ? (vkp - vc) * g.idzw[k + 1] : -vc * g.idzw[nz];
-                const double dzz = (ft - fb) * g.idz[k];
+                const double vkm = L(FV, -1, 0, 0), vkp = L(FV, 1, 0, 0);
+                const double ay = (vjp - vjm) * (vjp + vjm + 2.0 * vc) * qy;
+                const double ax = ((L(FU, 0, 0, 1) + L(FU, 0, -1, 1)) * (vip + vc) -
+                                   (L(FU, 0, 0, 0) + L(FU, 0, -1, 0)) * (vc + vim)) * qx;
+                const double fzb = lo ? (L(FW, 0, 0, 0) + L(FW, 0, -1, 0)) * (vkm + vc) : 0.0;
+                const double fzt = hi ? (L(FW, 1, 0, 0) + L(FW, 1, -1, 0)) * (vc + vkp) : 0.0;
+                const double az = (fzt - fzb) * (0.25 * idzk);
+                const double h = (nux * (vip + vim - 2.0 * vc) + nuy * (vjp + vjm - 2.0 * vc)) - (ax + ay + az);
+                const double fb = lo ? (vc - vkm) * g.idzw[k] : vc * g.idzw[0];
+                const double ft = hi ? (vkp - vc) * g.idzw[k + 1] : -vc * g.idzw[nz];
+                const double dzz = (ft - fb) * idzk;
                 const double gp = (L(FP, 0, 0, 0) - L(FP, 0, -1, 0)) * idy;
-                double r = a.gam * h - a.alp * gp + a.alp * (a.nu * dzz);
-                if (a.rho != 0.0) r += a.rho * hp[1];
-                a.rv[id] = a.dt * r;
+                double r = cg * h - ca * gp + can * dzz;
+                if (a.rho != 0.0) r += cr * hp[1];
+                a.rv[id] = r;
                 if (a.hv) a.hv[id] = h;
             }
             // ---- w and T at (x-centre i, y-centre j, z-face k), interior faces ----
@@ -240,44 +237,43 @@ __global__ void __launch_bounds__(kExTX * kExTY) k_explicit(SubstepArgs a, GridD
                 if (a.hw) a.hw[id] = 0.0;
                 if (a.ht && with_t) a.ht[id] = 0.0;
             } else {
-                const double dzm = g.dz[k - 1], dzp = g.dz[k], den = 0.5 * g.o[k];   // o = 1/dzc (interior face)
-                // volume-weighted horizontal transport on the side faces
-                const double uwl = (dzm * L(FU, -1, 0, 0) + dzp * L(FU, 0, 0, 0)) * den;
-                const double uwr = (dzm * L(FU, -1, 0, 1) + dzp * L(FU, 0, 0, 1)) * den;
-                const double vwb = (dzm * L(FV, -1, 0, 0) + dzp * L(FV, 0, 0, 0)) * den;
-                const double vwt = (dzm * L(FV, -1, 1, 0) + dzp * L(FV, 0, 1, 0)) * den;
+                const double dzm = g.dz[k - 1], dzp = g.dz[k], idzc = g.o[k];   // o = 1/dzc (interior face)
+                // volume-weighted horizontal transport on the side faces (times 2 dzc)
+                const double uwl = dzm * L(FU, -1, 0, 0) + dzp * L(FU, 0, 0, 0);
+                const double uwr = dzm * L(FU, -1, 0, 1) + dzp * L(FU, 0, 0, 1);
+                const double vwb = dzm * L(FV, -1, 0, 0) + dzp * L(FV, 0, 0, 0);
+                const double vwt = dzm * L(FV, -1, 1, 0) + dzp * L(FV, 0, 1, 0);
+                const double sx = qx * idzc, sy = qy * idzc, sz = 0.25 * idzc;
                 const double wc = L(FW, 0, 0, 0), wim = L(FW, 0, 0, -1), wip = L(FW, 0, 0, 1);
                 const double wjm = L(FW, 0, -1, 0), wjp = L(FW, 0, 1, 0);
                 const double wkm = L(FW, -1, 0, 0), wkp = L(FW, 1, 0, 0);
                 const double tc = L(FT, 0, 0, 0), tim = L(FT, 0, 0, -1), tip = L(FT, 0, 0, 1);
                 const double tjm = L(FT, 0, -1, 0), tjp = L(FT, 0, 1, 0);
                 const double tkm = L(FT, -1, 0, 0), tkp = L(FT, 1, 0, 0);
-                const double idzc = g.o[k];
-                const double wtop = 0.5 * (wc + wkp), wbot = 0.5 * (wkm + wc);   // at centres k, k-1
+                const double wtop = wc + wkp, wbot = wkm + wc;   // twice the centre values k, k-1
                 // w
                 {
-                    const double ax = (uwr * (0.5 * (wc + wip)) - uwl * (0.5 * (wim + wc))) * idx;
-                    const double ay = (vwt * (0.5 * (wc + wjp)) - vwb * (0.5 * (wjm + wc))) * idy;
-                    const double az = (sq(wtop) - sq(wbot)) * idzc;
-                    const double h = -(ax + ay + az) +
-                                     a.nu * ((wip - 2.0 * wc + wim) * idx2 + (wjp - 2.0 * wc + wjm) * idy2) + tc;
-                    const double dzz = ((wkp - wc) * g.idz[k] - (wc - wkm) * g.idz[k - 1]) * idzc;
+                    const double ax = (uwr * (wc + wip) - uwl * (wim + wc)) * sx;
+                    const double ay = (vwt * (wc + wjp) - vwb * (wjm + wc)) * sy;
+                    const double az = (wkp - wkm) * (wtop + wbot) * sz;
+                    const double h = (nux * (wip + wim - 2.0 * wc) + nuy * (wjp + wjm - 2.0 * wc) + tc) - (ax + ay + az);
+                    const double dzz = ((wkp - wc) * idzk - (wc - wkm) * g.idz[k - 1]) * idzc;
                     const double gp = (L(FP, 0, 0, 0) - L(FP, -1, 0, 0)) * idzc;
-                    double r = a.gam * h - a.alp * gp + a.alp * (a.nu * dzz);
-                    if (a.rho != 0.0) r += a.rho * hp[2];
-                    a.rw[id] = a.dt * r;
+                    double r = cg * h - ca * gp + can * dzz;
+                    if (a.rho != 0.0) r += cr * hp[2];
+                    a.rw[id] = r;
                     if (a.hw) a.hw[id] = h;
                 }
                 // T
                 if (with_t) {
-                    const double ax = (uwr * (0.5 * (tc + tip)) - uwl * (0.5 * (tim + tc))) * idx;
-                    const double ay = (vwt * (0.5 * (tc + tjp)) - vwb * (0.5 * (tjm + tc))) * idy;
-                    const double az = (wtop * (0.5 * (tc + tkp)) - wbot * (0.5 * (tkm + tc))) * idzc;
-                    const double h = -(ax + ay + az) + a.ka * ((tip - 2.0 * tc + tim) * idx2 + (tjp - 2.0 * tc + tjm) * idy2);
-                    const double dzz = ((tkp - tc) * g.idz[k] - (tc - tkm) * g.idz[k - 1]) * idzc;
-                    double r = a.gam * h + a.alp * (a.ka * dzz);
-                    if (a.rho != 0.0) r += a.rho * hp[3];
-                    a.rt[id] = a.dt * r;
+                    const double ax = (uwr * (tc + tip) - uwl * (tim + tc)) * sx;
+                    const double ay = (vwt * (tc + tjp) - vwb * (tjm + tc)) * sy;
+                    const double az = (wtop * (tc + tkp) - wbot * (tkm + tc)) * sz;
+                    const double h = (kax * (tip + tim - 2.0 * tc) + kay * (tjp + tjm - 2.0 * tc)) - (ax + ay + az);
+                    const double dzz = ((tkp - tc) * idzk - (tc - tkm) * g.idz[k - 1]) * idzc;
+                    double r = cg * h + cak * dzz;
+                    if (a.rho != 0.0) r += cr * hp[3];
+                    a.rt[id] = r;
                     if (a.ht) a.ht[id] = h;
                 }
             }
