@@ -400,7 +400,12 @@ def other_workloads(args):
     hf_ms = _event_ms(lambda: plan.heat_flux(st[2], st[3], ka), 5)
     mean_t, flux = plan.heat_flux(st[2], st[3], ka)
     nu_prof = (flux / ka).cpu()
+    # the whole step's adjoint (fixed dt: the intermediate states recomputed, three substep adjoints)
+    plan.step_adjoint(used[-1], nu, ka, *saved, cot)
+    sadj_ms = _event_ms(lambda: plan.step_adjoint(used[-1], nu, ka, *saved, cot), 3)
     res["rk3_step_768x768x512_fp64_poisson"] = {"ms": round(step_ms, 3), "dt": used[-1],
+                                                "adjoint_ms": round(sadj_ms, 3),
+                                                "adjoint_over_forward": round(sadj_ms / step_ms, 3),
                                                 "heat_flux_ms": round(hf_ms, 3),
                                                 "nusselt_wall_mean": round(float(0.5 * (nu_prof[0] + nu_prof[-1])), 6)}
     plan.close()

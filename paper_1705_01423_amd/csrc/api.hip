@@ -1025,30 +1025,17 @@ ps_status rk3_substep_adjoint(ps_plan_t p, int l, double dt, double nu, double k
     a.ka = kappa;
     a.gam = gam;
     a.alp = alp;
-    PS_HIP(launch_explicit_adj(p->gd, a, st), "explicit adjoint");
+    // the cotangent of this substep's H output joins dt gamma lambda wherever H acts
     if (g_hout) {
-        // cotangent of this substep's H output: H's own VJP at the input state, added in a
-        // second pass of the same kernel (H enters the right-hand sides as dt gamma H, so
-        // dt = gamma = 1 and alpha = 0 leave exactly H's derivative; g_in is read and
-        // rewritten point by point)
-        SubstepAdjArgs b = a;
-        b.lu = g_hout[0];
-        b.lv = g_hout[1];
-        b.lw = g_hout[2];
-        b.lt = g_hout[3];
-        b.du = g_in[0];
-        b.dv = g_in[1];
-        b.dw = g_in[2];
-        b.dt_ = g_in[3];
-        b.dp = g_in[4];
-        b.dt = 1.0;
-        b.gam = 1.0;
-        b.alp = 0.0;
-        PS_HIP(launch_explicit_adj(p->gd, b, st), "H adjoint");
+        a.ghu = g_hout[0];
+        a.ghv = g_hout[1];
+        a.ghw = g_hout[2];
+        a.ght = g_hout[3];
     }
+    PS_HIP(launch_explicit_adj(p->gd, a, st), "explicit adjoint");
     if (g_hprev) {
         // the previous substep's H enters the right-hand sides as dt rho H^{l-1} (zero for l = 1);
-        // written after the H pass so that g_hprev may share g_hout's buffers
+        // written after the explicit adjoint has read g_hout, so that g_hprev may share its buffers
         const double c = dt * rho;
         const size_t nc = p->npts, nf = p->npts + p->plane;
         PS_HIP(launch_scale(lu, g_hprev[0], c, nc, st), "h_prev adjoint");

@@ -254,8 +254,10 @@ __global__ void __launch_bounds__(kMtTX * kMtTY) k_mr_explicit_t(MrTArgs a, Grid
         off[qi] = (unsigned)gj * (unsigned)g.nx + (unsigned)gi;
     }
     const double th = a.th, th1 = 1.0 - a.th;
-    double stv[NQ][NF];
-    // plane kk of every field into registers (velocity blended in time; zeros outside a field)
+    // plane kk of every field into registers, both velocity time levels as loaded (zeros
+    // outside a field); put() blends them in time into the ring, so that the loads of a stage
+    // are not waited for until the next step
+    double s0[NQ][3], s1[NQ][3], stt[NQ];
     auto fetch = [&](int kk) {
         const int kc = kk < 0 ? 0 : (kk > g.nz - 1 ? g.nz - 1 : kk);
         const int kf = kk < 0 ? 0 : (kk > g.nz ? g.nz : kk);
@@ -266,10 +268,13 @@ __global__ void __launch_bounds__(kMtTX * kMtTY) k_mr_explicit_t(MrTArgs a, Grid
             const size_t oc = pc + off[qi], of = pf + off[qi];
             const double u0 = a.u0[oc], u1 = a.u1[oc], v0 = a.v0[oc], v1 = a.v1[oc];
             const double w0 = a.w0[of], w1 = a.w1[of], tt = a.t[of];
-            stv[qi][FU] = okc ? th1 * u0 + th * u1 : 0.0;
-            stv[qi][FV] = okc ? th1 * v0 + th * v1 : 0.0;
-            stv[qi][FW] = okf ? th1 * w0 + th * w1 : 0.0;
-            stv[qi][FT] = okf ? tt : 0.0;
+            s0[qi][FU] = okc ? u0 : 0.0;
+            s1[qi][FU] = okc ? u1 : 0.0;
+            s0[qi][FV] = okc ? v0 : 0.0;
+            s1[qi][FV] = okc ? v1 : 0.0;
+            s0[qi][FW] = okf ? w0 : 0.0;
+            s1[qi][FW] = okf ? w1 : 0.0;
+            stt[qi] = okf ? tt : 0.0;
         }
     };
     auto put = [&](int kk) {
@@ -279,7 +284,8 @@ __global__ void __launch_bounds__(kMtTX * kMtTY) k_mr_explicit_t(MrTArgs a, Grid
             const int q = (int)threadIdx.x + qi * TX * TY;
             if (q < PL) {
 #pragma unroll
-                for (int f = 0; f < NF; ++f) lds[(sl * NF + f) * PL + q] = stv[qi][f];
+                for (int f = 0; f < 3; ++f) lds[(sl * NF + f) * PL + q] = th1 * s0[qi][f] + th * s1[qi][f];
+                lds[(sl * NF + FT) * PL + q] = stt[qi];
             }
         }
     };

@@ -268,6 +268,7 @@ struct SubstepArgs {
 struct SubstepAdjArgs {
     const double *u, *v, *w, *t;           // input state (advection is evaluated there)
     const double *lu, *lv, *lw, *lt;       // cotangents of the right-hand sides
+    const double *ghu, *ghv, *ghw, *ght;   // cotangent of the substep's H output (all NULL: none)
     const double *du, *dv, *dw, *dt_, *dp; // direct cotangents of q* (and T', p')
     double *gu, *gv, *gw, *gt, *gp;        // outputs
     double dt, nu, ka, gam, alp;

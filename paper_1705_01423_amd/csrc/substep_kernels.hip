@@ -356,8 +356,12 @@ k_cn_solve_t(GridDev g, int kind, const double* __restrict__ fac, const double* 
 // point.  For a control-volume equation sum_faces +-F_f / h with cotangent kappa,
 // each face carries Lambda_f = kappa_c / h_c - kappa_{c+1} / h_{c+1}; a flux
 // F = U Q sends Lambda U dQ and Lambda Q dU to the points averaged into Q and U.
-// z-marching blocks as in k_explicit, with the state and the right-hand-side
-// cotangents in the LDS ring.
+// The right-hand sides hold H through dt gamma H, and the substep's own H output may carry
+// a cotangent gH: everything that acts through H (advection, horizontal diffusion,
+// buoyancy) is driven by mu = dt gamma lambda + gH, which the LDS ring holds; the terms
+// weighted by alpha (wall-normal diffusion, pressure gradient) act on lambda itself, read
+// from memory along the thread's column.  z-marching blocks as in k_explicit, with the
+// state and mu in the LDS ring.
 #ifndef PS_AD_TX
 #define PS_AD_TX 64
 #endif
@@ -368,52 +372,145 @@ constexpr int kAdTX = PS_AD_TX, kAdTY = PS_AD_TY, kAdZSEG = 64;
 // The next plane is prefetched through registers as in k_explicit (the LDS ring already
 // limits the adjoint to two waves per SIMD, so the staged values cost no occupancy):
 // 768^2 x 512, 18.6 -> 16.0 ms against loading each plane when needed.
+// GHV: a cotangent gH is given (the ring then cannot give lambda back, which is read along
+// the thread's column instead); without it lambda = mu / (dt gamma) comes from the ring.
+template <bool GHV>
 __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a, GridDev g) {
     constexpr int TX = kAdTX, TY = kAdTY, NF = 8;
-    enum { FU, FV, FW, FT, FLU, FLV, FLW, FLT };
+    using RingT = Ring<NF, TX, TY>;
+    constexpr int NQ = RingT::NQ;
+    enum { FU, FV, FW, FT, FMU, FMV, FMW, FMT };
     __shared__ double lds[3 * NF * (TX + 2) * (TY + 2)];
     const ExTile tile = ex_tile<TX, TY, kAdZSEG>(g);
-    Ring<NF, TX, TY> R{lds, (int)threadIdx.x % TX, (int)threadIdx.x / TX};
-    const typename Ring<NF, TX, TY>::Cols cols = Ring<NF, TX, TY>::columns(g, tile.i0, tile.j0);
+    RingT R{lds, (int)threadIdx.x % TX, (int)threadIdx.x / TX};
+    const typename RingT::Cols cols = RingT::columns(g, tile.i0, tile.j0);
     const int i = tile.i0 + R.tx, j = tile.j0 + R.ty;
     const bool valid = i < g.nx && j < g.ny;
     const double* const F[NF] = {a.u, a.v, a.w, a.t, a.lu, a.lv, a.lw, a.lt};
+    const double* const GH[4] = {a.ghu, a.ghv, a.ghw, a.ght};
     const bool face[NF] = {false, false, true, true, false, false, true, true};
+    constexpr bool with_gh = GHV;
     const int nz = g.nz;
     const size_t plane = (size_t)g.nx * g.ny;
     const double idx = 1.0 / g.dx, idy = 1.0 / g.dy;
     const double idx2 = idx * idx, idy2 = idy * idy;
-    const double cadv = -a.dt * a.gam;   // kappa = cadv * lambda (A enters the rhs as -dt gamma A)
-    typename Ring<NF, TX, TY>::Stage st;
-    R.fetch(tile.kb - 1, F, face, g, cols, st);
-    R.put(tile.kb - 1, st);
-    R.fetch(tile.kb, F, face, g, cols, st);
-    R.put(tile.kb, st);
-    R.fetch(tile.kb + 1, F, face, g, cols, st);
+    const double muc = a.dt * a.gam;        // mu = dt gamma lambda + gH
+    const double cal = a.dt * a.alp;        // weight of the alpha terms (on lambda)
+    // plane kk of the state, lambda and gH into registers (zeros outside a field); the loaded
+    // values are not touched until put() blends mu = dt gamma lambda + gH into the ring, so
+    // that every load of the stage stays in flight together
+    double sgh[NQ][4];
+    auto fetch = [&](int kk, typename RingT::Stage& st) {
+        const int kc = kk < 0 ? 0 : (kk > nz - 1 ? nz - 1 : kk);
+        const int kf = kk < 0 ? 0 : (kk > nz ? nz : kk);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const bool ok = kk >= 0 && (kk < nz || (face[f] && kk == nz));
+            const size_t po = (size_t)(face[f] ? kf : kc) * plane;
+#pragma unroll
+            for (int qi = 0; qi < NQ; ++qi) {
+                const double v = F[f][po + cols.off[qi]];
+                st.v[qi][f] = ok ? v : 0.0;
+                if (f >= FMU) {
+                    const double gv = with_gh ? GH[f - FMU][po + cols.off[qi]] : 0.0;
+                    sgh[qi][f - FMU] = ok ? gv : 0.0;
+                }
+            }
+        }
+    };
+    auto put = [&](int kk, typename RingT::Stage& st) {
+#pragma unroll
+        for (int qi = 0; qi < NQ; ++qi)
+#pragma unroll
+            for (int f = FMU; f < NF; ++f) st.v[qi][f] = muc * st.v[qi][f] + sgh[qi][f - FMU];
+        R.put(kk, st);
+    };
+    // lambda along this thread's column (planes k - 1, k, k + 1, rotated as the block marches,
+    // the plane above fetched one step ahead like the ring) and at the x / y neighbours the
+    // pressure-gradient transpose needs; cells outside the box use column (0, 0), missing
+    // planes the nearest one (their values are never used)
+    const int ic = valid ? i : 0, jc = valid ? j : 0;
+    const int ip = (ic + 1 == g.nx) ? 0 : ic + 1, jp = (jc + 1 == g.ny) ? 0 : jc + 1;
+    const size_t col = (size_t)jc * g.nx + ic, col_ip = (size_t)jc * g.nx + ip, col_jp = (size_t)jp * g.nx + ic;
+    auto lcol = [&](const double* L, int kk, bool facef) {
+        const int kc = kk < 0 ? 0 : (kk > (facef ? nz : nz - 1) ? (facef ? nz : nz - 1) : kk);
+        return L[(size_t)kc * plane + col];
+    };
+    auto kcen = [&](int kk) { return (size_t)(kk > nz - 1 ? nz - 1 : kk) * plane; };
+    double cu[3] = {0, 0, 0}, cv[3] = {0, 0, 0}, cw[3] = {0, 0, 0}, ct[3] = {0, 0, 0};
+    double lu_ip = 0.0, lv_jp = 0.0;
+    if constexpr (GHV) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            cu[q] = lcol(a.lu, tile.kb - 1 + q, false);
+            cv[q] = lcol(a.lv, tile.kb - 1 + q, false);
+            cw[q] = lcol(a.lw, tile.kb - 1 + q, true);
+            ct[q] = lcol(a.lt, tile.kb - 1 + q, true);
+        }
+        lu_ip = a.lu[kcen(tile.kb) + col_ip];
+        lv_jp = a.lv[kcen(tile.kb) + col_jp];
+    }
+    const double imuc = 1.0 / muc;
+    typename RingT::Stage st;
+    fetch(tile.kb - 1, st);
+    put(tile.kb - 1, st);
+    fetch(tile.kb, st);
+    put(tile.kb, st);
+    fetch(tile.kb + 1, st);
     for (int k = tile.kb; k < tile.ke; ++k) {
-        R.put(k + 1, st);
+        put(k + 1, st);
         __syncthreads();
         const size_t id = (size_t)k * plane + (size_t)j * g.nx + i;
-        // direct cotangents of this cell, loaded before the next plane's prefetch
-        // (cells outside the box read the plane's first cell: no load under a per-lane branch)
+        // direct cotangents of this cell, and lambda for the next step, loaded before the
+        // next plane's prefetch (cells outside the box read the plane's first cell)
         const size_t idd = valid ? id : (size_t)k * plane;
         double dd[5] = {a.du[idd], a.dv[idd], a.dw[idd], a.dt_[idd], a.dp[idd]};
-        if (k + 2 <= tile.ke) R.fetch(k + 2, F, face, g, cols, st);
+        double nu_ = 0.0, nv_ = 0.0, nw_ = 0.0, nt_ = 0.0, nuip = 0.0, nvjp = 0.0;
+        if constexpr (GHV) {
+            nu_ = lcol(a.lu, k + 2, false);
+            nv_ = lcol(a.lv, k + 2, false);
+            nw_ = lcol(a.lw, k + 2, true);
+            nt_ = lcol(a.lt, k + 2, true);
+            nuip = a.lu[kcen(k + 1) + col_ip];
+            nvjp = a.lv[kcen(k + 1) + col_jp];
+        } else {
+            // lambda from the ring (mu / (dt gamma)); planes outside a field read zero there
+            cu[0] = R(k, FMU, -1, 0, 0) * imuc;
+            cu[1] = R(k, FMU, 0, 0, 0) * imuc;
+            cu[2] = R(k, FMU, 1, 0, 0) * imuc;
+            cv[0] = R(k, FMV, -1, 0, 0) * imuc;
+            cv[1] = R(k, FMV, 0, 0, 0) * imuc;
+            cv[2] = R(k, FMV, 1, 0, 0) * imuc;
+            cw[0] = R(k, FMW, -1, 0, 0) * imuc;
+            cw[1] = R(k, FMW, 0, 0, 0) * imuc;
+            cw[2] = R(k, FMW, 1, 0, 0) * imuc;
+            ct[0] = R(k, FMT, -1, 0, 0) * imuc;
+            ct[1] = R(k, FMT, 0, 0, 0) * imuc;
+            ct[2] = R(k, FMT, 1, 0, 0) * imuc;
+            lu_ip = R(k, FMU, 0, 0, 1) * imuc;
+            lv_jp = R(k, FMV, 0, 1, 0) * imuc;
+        }
+        const double lum = cu[0], lu0 = cu[1], lup = cu[2];
+        const double lvm = cv[0], lv0 = cv[1], lvp = cv[2];
+        const double lwm = cw[0], lw0 = cw[1], lwp = cw[2];
+        const double ltm = ct[0], lt0 = ct[1], ltp = ct[2];
+        if (k + 2 <= tile.ke) fetch(k + 2, st);
         if (valid) {
             // fields at absolute plane kk (k - 1 <= kk <= k + 1) and horizontal offsets (dj, di)
             auto U = [&](int kk, int dj, int di) { return R(k, FU, kk - k, dj, di); };
             auto V = [&](int kk, int dj, int di) { return R(k, FV, kk - k, dj, di); };
             auto Wf = [&](int kk, int dj, int di) { return R(k, FW, kk - k, dj, di); };
             auto Tf = [&](int kk, int dj, int di) { return R(k, FT, kk - k, dj, di); };
-            auto LU = [&](int kk, int dj, int di) { return R(k, FLU, kk - k, dj, di); };
-            auto LV = [&](int kk, int dj, int di) { return R(k, FLV, kk - k, dj, di); };
-            auto LW = [&](int kk, int dj, int di) { return R(k, FLW, kk - k, dj, di); };
-            auto LT = [&](int kk, int dj, int di) { return R(k, FLT, kk - k, dj, di); };
-            auto KU = [&](int kk, int dj, int di) { return cadv * LU(kk, dj, di); };
-            auto KV = [&](int kk, int dj, int di) { return cadv * LV(kk, dj, di); };
-            // kappa of interior z-face equations (zero on the wall rows)
-            auto KW = [&](int kk, int dj, int di) { return (kk >= 1 && kk <= nz - 1) ? cadv * LW(kk, dj, di) : 0.0; };
-            auto KT = [&](int kk, int dj, int di) { return (kk >= 1 && kk <= nz - 1) ? cadv * LT(kk, dj, di) : 0.0; };
+            auto MU = [&](int kk, int dj, int di) { return R(k, FMU, kk - k, dj, di); };
+            auto MV = [&](int kk, int dj, int di) { return R(k, FMV, kk - k, dj, di); };
+            auto MW = [&](int kk, int dj, int di) { return R(k, FMW, kk - k, dj, di); };
+            auto MT = [&](int kk, int dj, int di) { return R(k, FMT, kk - k, dj, di); };
+            // kappa = -mu (advection enters H with a minus sign); zero on the wall rows of
+            // z-face equations
+            auto KU = [&](int kk, int dj, int di) { return -MU(kk, dj, di); };
+            auto KV = [&](int kk, int dj, int di) { return -MV(kk, dj, di); };
+            auto KW = [&](int kk, int dj, int di) { return (kk >= 1 && kk <= nz - 1) ? -MW(kk, dj, di) : 0.0; };
+            auto KT = [&](int kk, int dj, int di) { return (kk >= 1 && kk <= nz - 1) ? -MT(kk, dj, di) : 0.0; };
             auto idzc = [&](int kk) { return g.o[kk]; };   // 1/dzc at interior faces, 0 at the walls
             // volume-weighted transport at (x-face or y-face, z-face kk)
             auto UW = [&](int kk, int dj, int di) {
@@ -421,6 +518,13 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
             };
             auto VW = [&](int kk, int dj, int di) {
                 return (g.dz[kk - 1] * V(kk - 1, dj, di) + g.dz[kk] * V(kk, dj, di)) * (0.5 * g.o[kk]);
+            };
+            // transpose of the centre-field Dzz (dz Dzz dz^-1, Dirichlet walls) applied to lambda
+            auto dzzt_c = [&](double lm, double l0, double lp) {
+                const double mc = l0 * g.idz[k];
+                const double fb = (k > 0) ? (mc - lm * g.idz[k - 1]) * g.idzw[k] : mc * g.idzw[0];
+                const double ft = (k + 1 < nz) ? (lp * g.idz[k + 1] - mc) * g.idzw[k + 1] : -mc * g.idzw[nz];
+                return ft - fb;
             };
 
             // ================= g_u at (k, j, i) =================
@@ -463,18 +567,11 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
                     const double Lt = (KT(kf, 0, -1) - KT(kf, 0, 0)) * idx, Qt = 0.5 * (Tf(kf, 0, -1) + Tf(kf, 0, 0));
                     s += wt * (Lw * Qw + Lt * Qt);
                 }
-                // linear terms: horizontal diffusion (symmetric) and Dzz^T = dz Dzz dz^-1
-                const double lc = LU(k, 0, 0);
-                double lin = a.gam * a.nu *
-                             ((LU(k, 0, 1) - 2.0 * lc + LU(k, 0, -1)) * idx2 +
-                              (LU(k, 1, 0) - 2.0 * lc + LU(k, -1, 0)) * idy2);
-                {
-                    const double mc = lc * g.idz[k];
-                    const double fb = (k > 0) ? (mc - LU(k - 1, 0, 0) * g.idz[k - 1]) * g.idzw[k] : mc * g.idzw[0];
-                    const double ft = (k + 1 < nz) ? (LU(k + 1, 0, 0) * g.idz[k + 1] - mc) * g.idzw[k + 1] : -mc * g.idzw[nz];
-                    lin += a.alp * a.nu * (ft - fb);
-                }
-                a.gu[id] = dd[0] + s + a.dt * lin;
+                // linear terms: horizontal diffusion of mu (symmetric), Dzz^T of lambda
+                const double mc = MU(k, 0, 0);
+                const double hd = a.nu * ((MU(k, 0, 1) - 2.0 * mc + MU(k, 0, -1)) * idx2 +
+                                          (MU(k, 1, 0) - 2.0 * mc + MU(k, -1, 0)) * idy2);
+                a.gu[id] = dd[0] + s + hd + cal * a.nu * dzzt_c(lum, lu0, lup);
             }
             // ================= g_v at (k, j, i) =================
             {
@@ -512,31 +609,24 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
                     const double Lt = (KT(kf, -1, 0) - KT(kf, 0, 0)) * idy, Qt = 0.5 * (Tf(kf, -1, 0) + Tf(kf, 0, 0));
                     s += wt * (Lw * Qw + Lt * Qt);
                 }
-                const double lc = LV(k, 0, 0);
-                double lin = a.gam * a.nu *
-                             ((LV(k, 0, 1) - 2.0 * lc + LV(k, 0, -1)) * idx2 +
-                              (LV(k, 1, 0) - 2.0 * lc + LV(k, -1, 0)) * idy2);
-                {
-                    const double mc = lc * g.idz[k];
-                    const double fb = (k > 0) ? (mc - LV(k - 1, 0, 0) * g.idz[k - 1]) * g.idzw[k] : mc * g.idzw[0];
-                    const double ft = (k + 1 < nz) ? (LV(k + 1, 0, 0) * g.idz[k + 1] - mc) * g.idzw[k + 1] : -mc * g.idzw[nz];
-                    lin += a.alp * a.nu * (ft - fb);
-                }
-                a.gv[id] = dd[1] + s + a.dt * lin;
+                const double mc = MV(k, 0, 0);
+                const double hd = a.nu * ((MV(k, 0, 1) - 2.0 * mc + MV(k, 0, -1)) * idx2 +
+                                          (MV(k, 1, 0) - 2.0 * mc + MV(k, -1, 0)) * idy2);
+                a.gv[id] = dd[1] + s + hd + cal * a.nu * dzzt_c(lvm, lv0, lvp);
             }
             // ================= g_p at (k, j, i):  -dt alpha G^T lambda =================
             {
-                double gt = (LU(k, 0, 0) - LU(k, 0, 1)) * idx + (LV(k, 0, 0) - LV(k, 1, 0)) * idy;
-                if (k >= 1) gt += LW(k, 0, 0) * g.o[k];
-                if (k + 1 <= nz - 1) gt -= LW(k + 1, 0, 0) * g.o[k + 1];
-                a.gp[id] = dd[4] - a.dt * a.alp * gt;
+                double gt = (lu0 - lu_ip) * idx + (lv0 - lv_jp) * idy;
+                if (k >= 1) gt += lw0 * g.o[k];
+                if (k + 1 <= nz - 1) gt -= lwp * g.o[k + 1];
+                a.gp[id] = dd[4] - cal * gt;
             }
             // ================= g_w, g_T at z-face k (interior) =================
             if (k == 0) {
                 a.gw[id] = 0.0;
                 a.gt[id] = 0.0;
             } else {
-                double sw = 0.0, st = 0.0;
+                double sw = 0.0, st_ = 0.0;
                 // w-eq z faces at centres k and k-1: F = U^2, U = avg w
                 {
                     const double L0 = KW(k, 0, 0) * idzc(k) - KW(k + 1, 0, 0) * idzc(k + 1);
@@ -548,7 +638,7 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
                     const double L0 = KT(k, 0, 0) * idzc(k) - KT(k + 1, 0, 0) * idzc(k + 1);
                     const double L1 = KT(k - 1, 0, 0) * idzc(k - 1) - KT(k, 0, 0) * idzc(k);
                     sw += 0.5 * (L0 * 0.5 * (Tf(k, 0, 0) + Tf(k + 1, 0, 0)) + L1 * 0.5 * (Tf(k - 1, 0, 0) + Tf(k, 0, 0)));
-                    st += 0.5 * (L0 * 0.5 * (Wf(k, 0, 0) + Wf(k + 1, 0, 0)) + L1 * 0.5 * (Wf(k - 1, 0, 0) + Wf(k, 0, 0)));
+                    st_ += 0.5 * (L0 * 0.5 * (Wf(k, 0, 0) + Wf(k + 1, 0, 0)) + L1 * 0.5 * (Wf(k - 1, 0, 0) + Wf(k, 0, 0)));
                 }
                 // w- and T-eq x faces i, i+1 (transport UW) and y faces j, j+1 (transport VW)
                 {
@@ -556,12 +646,12 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
                     const double Lt0 = (KT(k, 0, -1) - KT(k, 0, 0)) * idx, Lt1 = (KT(k, 0, 0) - KT(k, 0, 1)) * idx;
                     const double U0 = UW(k, 0, 0), U1 = UW(k, 0, 1);
                     sw += 0.5 * (Lw0 * U0 + Lw1 * U1);
-                    st += 0.5 * (Lt0 * U0 + Lt1 * U1);
+                    st_ += 0.5 * (Lt0 * U0 + Lt1 * U1);
                     const double Mw0 = (KW(k, -1, 0) - KW(k, 0, 0)) * idy, Mw1 = (KW(k, 0, 0) - KW(k, 1, 0)) * idy;
                     const double Mt0 = (KT(k, -1, 0) - KT(k, 0, 0)) * idy, Mt1 = (KT(k, 0, 0) - KT(k, 1, 0)) * idy;
                     const double V0 = VW(k, 0, 0), V1 = VW(k, 1, 0);
                     sw += 0.5 * (Mw0 * V0 + Mw1 * V1);
-                    st += 0.5 * (Mt0 * V0 + Mt1 * V1);
+                    st_ += 0.5 * (Mt0 * V0 + Mt1 * V1);
                 }
                 // u-eq z faces at (x-faces i, i+1; z-face k): W = avg of w over x, Q = avg of u over z
                 {
@@ -575,31 +665,41 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
                     const double L1 = KV(k - 1, 1, 0) * g.idz[k - 1] - KV(k, 1, 0) * g.idz[k];
                     sw += 0.5 * (L0 * 0.5 * (V(k - 1, 0, 0) + V(k, 0, 0)) + L1 * 0.5 * (V(k - 1, 1, 0) + V(k, 1, 0)));
                 }
-                // linear terms
-                const double lwc = LW(k, 0, 0), ltc = LT(k, 0, 0);
-                double linw = a.gam * a.nu *
-                              ((LW(k, 0, 1) - 2.0 * lwc + LW(k, 0, -1)) * idx2 +
-                               (LW(k, 1, 0) - 2.0 * lwc + LW(k, -1, 0)) * idy2);
-                double lint = a.gam * a.ka *
-                              ((LT(k, 0, 1) - 2.0 * ltc + LT(k, 0, -1)) * idx2 +
-                               (LT(k, 1, 0) - 2.0 * ltc + LT(k, -1, 0)) * idy2);
-                {
-                    // Dzz^T on faces = dzc Dzz dzc^-1 (wall rows of lambda are zero)
-                    const double mw = lwc * idzc(k), mwm = LW(k - 1, 0, 0) * idzc(k - 1),
-                                 mwp = LW(k + 1, 0, 0) * idzc(k + 1);
-                    const double mt = ltc * idzc(k), mtm = LT(k - 1, 0, 0) * idzc(k - 1),
-                                 mtp = LT(k + 1, 0, 0) * idzc(k + 1);
-                    linw += a.alp * a.nu * ((mwp - mw) * g.idz[k] - (mw - mwm) * g.idz[k - 1]);
-                    lint += a.alp * a.ka * ((mtp - mt) * g.idz[k] - (mt - mtm) * g.idz[k - 1]);
-                }
-                a.gw[id] = dd[2] + sw + a.dt * linw;
-                a.gt[id] = dd[3] + st + a.dt * lint + a.dt * a.gam * lwc;   // buoyancy +T in the w equation
+                // linear terms: horizontal diffusion of mu, Dzz^T (faces: dzc Dzz dzc^-1) of lambda
+                // (lambda's wall rows are zero), buoyancy +T in the w equation (through H)
+                const double mwc = MW(k, 0, 0), mtc = MT(k, 0, 0);
+                const double hdw = a.nu * ((MW(k, 0, 1) - 2.0 * mwc + MW(k, 0, -1)) * idx2 +
+                                           (MW(k, 1, 0) - 2.0 * mwc + MW(k, -1, 0)) * idy2);
+                const double hdt = a.ka * ((MT(k, 0, 1) - 2.0 * mtc + MT(k, 0, -1)) * idx2 +
+                                           (MT(k, 1, 0) - 2.0 * mtc + MT(k, -1, 0)) * idy2);
+                const double mw = lw0 * idzc(k), mwm = lwm * idzc(k - 1), mwp = lwp * idzc(k + 1);
+                const double mt = lt0 * idzc(k), mtm = ltm * idzc(k - 1), mtp = ltp * idzc(k + 1);
+                const double dzw_ = (mwp - mw) * g.idz[k] - (mw - mwm) * g.idz[k - 1];
+                const double dzt_ = (mtp - mt) * g.idz[k] - (mt - mtm) * g.idz[k - 1];
+                a.gw[id] = dd[2] + sw + hdw + cal * a.nu * dzw_;
+                a.gt[id] = dd[3] + st_ + hdt + cal * a.ka * dzt_ + mwc;
             }
             if (k + 1 == nz) {
                 a.gw[id + plane] = 0.0;
                 a.gt[id + plane] = 0.0;
             }
 
+        }
+        if constexpr (GHV) {
+            cu[0] = cu[1];
+            cu[1] = cu[2];
+            cu[2] = nu_;
+            cv[0] = cv[1];
+            cv[1] = cv[2];
+            cv[2] = nv_;
+            cw[0] = cw[1];
+            cw[1] = cw[2];
+            cw[2] = nw_;
+            ct[0] = ct[1];
+            ct[1] = ct[2];
+            ct[2] = nt_;
+            lu_ip = nuip;
+            lv_jp = nvjp;
         }
         __syncthreads();
     }
@@ -615,7 +715,11 @@ hipError_t launch_cn_solve_t(const GridDev& g, int kind, const double* fac, cons
 }
 
 hipError_t launch_explicit_adj(const GridDev& g, const SubstepAdjArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL(k_explicit_adj, dim3(ex_blocks<kAdTX, kAdTY, kAdZSEG>(g)), dim3(kAdTX * kAdTY), 0, st, a, g);
+    const dim3 grid(ex_blocks<kAdTX, kAdTY, kAdZSEG>(g)), block(kAdTX * kAdTY);
+    if (a.ghu)
+        hipLaunchKernelGGL(k_explicit_adj<true>, grid, block, 0, st, a, g);
+    else
+        hipLaunchKernelGGL(k_explicit_adj<false>, grid, block, 0, st, a, g);
     return hipGetLastError();
 }
 
