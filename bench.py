@@ -84,15 +84,20 @@ def main():
     ap.add_argument("--no-refined", action="store_true")
     ap.add_argument("--stage-reps", type=int, default=10)
     ap.add_argument("--no-extra", action="store_true", help="skip the projection/adjoint/substep legs")
-    ap.add_argument("--only-extra", action="store_true",
-                    help="run only the projection/adjoint/substep legs and print their JSON (profiling)")
+    ap.add_argument("--only-extra", nargs="?", const="all", default=None,
+                    help="run only the other workloads and print their JSON (profiling); optionally a "
+                         "comma-separated subset of " + ",".join(EXTRA_LEGS))
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this library runs one box on one GPU; runs on more than one GPU are not supported",
               file=sys.stderr)
         sys.exit(2)
     if args.only_extra:
-        print(json.dumps(other_workloads(args)), flush=True)
+        legs = EXTRA_LEGS if args.only_extra == "all" else tuple(args.only_extra.split(","))
+        bad = [x for x in legs if x not in EXTRA_LEGS]
+        if bad:
+            ap.error(f"unknown workloads {bad}; choose from {EXTRA_LEGS}")
+        print(json.dumps(other_workloads(args, legs)), flush=True)
         return
 
     import numpy as np
@@ -295,10 +300,26 @@ def _event_ms(fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def other_workloads(args):
+EXTRA_LEGS = ("projection", "adjoint", "substep", "step", "multires")
+
+
+def other_workloads(args, legs=EXTRA_LEGS):
     """Projection (512^2 x 384), adjoint/forward ratio (256^2 x 192), RK3 substep and its
-    adjoint (768^2 x 512, FP32-refined Poisson), each on its own seeded input."""
-    import math
+    adjoint (768^2 x 512, FP32-refined and FP64 Poisson), the full RK3 step and its adjoint,
+    and the multiple-resolution step, each on its own seeded input."""
+    res = {}
+    if "projection" in legs:
+        res.update(_projection_workload())
+    if "adjoint" in legs:
+        res.update(_adjoint_workload())
+    if "substep" in legs or "step" in legs:
+        res.update(_substep_workloads("substep" in legs, "step" in legs))
+    if "multires" in legs:
+        res.update(multires_workload())
+    return res
+
+
+def _projection_workload():
     import torch
 
     from paper_1705_01423_amd import synth
@@ -328,7 +349,16 @@ def other_workloads(args):
                                   "model_bytes_per_point": 184, "model_gbs": round(184 * npts / t / 1e6, 1)}
     del u, v, w, us, vs, ws, p, plan
     torch.cuda.empty_cache()
+    return res
 
+
+def _adjoint_workload():
+    import torch
+
+    from paper_1705_01423_amd import synth
+    from paper_1705_01423_amd.api import Plan
+
+    res = {}
     # ---- adjoint / forward cost, 256 x 256 x 192 ----
     cfg = synth.CONFIGS["slab256x256x192"]
     zf = synth.zfaces(cfg.nz, cfg.alpha)
@@ -343,7 +373,17 @@ def other_workloads(args):
                                   "adjoint_over_forward": round(adj / fwd, 3)}
     del u, v, w, us, vs, ws, om, plan
     torch.cuda.empty_cache()
+    return res
 
+
+def _substep_workloads(substeps=True, steps=True):
+    import math
+    import torch
+
+    from paper_1705_01423_amd import synth
+    from paper_1705_01423_amd.api import Plan
+
+    res = {}
     # ---- RK3 substep and its adjoint, 768 x 768 x 512, Ra = 1e8, Pr = 1 ----
     cfg = synth.CONFIGS["rb768x768x512"]
     zf = synth.zfaces(cfg.nz, cfg.alpha)
@@ -365,55 +405,54 @@ def other_workloads(args):
         reset()
         infos.append(plan.substep(1, dt, nu, ka, *st))
 
-    step()
     reset_ms = _event_ms(reset, 3)
-    fwd = _event_ms(step, 3) - reset_ms
     cot = [torch.randn_like(a) for a in saved]
     for c in (cot[2], cot[3]):
         c[0] = 0
         c[-1] = 0
-    plan.substep_adjoint(dt, nu, ka, *saved, cot)
-    adj = _event_ms(lambda: plan.substep_adjoint(dt, nu, ka, *saved, cot), 3)
     npts = cfg.nx * cfg.ny * cfg.nz
-    res["rk3_substep_768x768x512"] = {"dt": dt, "forward_ms": round(fwd, 3), "adjoint_ms": round(adj, 3),
-                                      "adjoint_over_forward": round(adj / fwd, 3),
-                                      "poisson_iterations": infos[-1]["iterations"],
-                                      "gpoints_per_s": round(npts / fwd / 1e6, 3)}
+    if substeps:
+        step()
+        fwd = _event_ms(step, 3) - reset_ms
+        plan.substep_adjoint(dt, nu, ka, *saved, cot)
+        adj = _event_ms(lambda: plan.substep_adjoint(dt, nu, ka, *saved, cot), 3)
+        res["rk3_substep_768x768x512"] = {"dt": dt, "forward_ms": round(fwd, 3), "adjoint_ms": round(adj, 3),
+                                          "adjoint_over_forward": round(adj / fwd, 3),
+                                          "poisson_iterations": infos[-1]["iterations"],
+                                          "gpoints_per_s": round(npts / fwd / 1e6, 3)}
     plan.close()
     # the same substep with the FP64 solve (one pass instead of three FP32 ones)
     plan = Plan(cfg.nx, cfg.ny, cfg.nz, cfg.lx, cfg.ly, zf, precision="fp64")
-    step()
-    fwd64 = _event_ms(step, 3) - reset_ms
-    plan.substep_adjoint(dt, nu, ka, *saved, cot)
-    adj64 = _event_ms(lambda: plan.substep_adjoint(dt, nu, ka, *saved, cot), 3)
-    res["rk3_substep_768x768x512_fp64_poisson"] = {"forward_ms": round(fwd64, 3), "adjoint_ms": round(adj64, 3),
-                                                   "gpoints_per_s": round(npts / fwd64 / 1e6, 3)}
-    # one full RK3 step (three substeps, Courant-limited dt) and the heat-flux statistics
-    used = []
+    if substeps:
+        step()
+        fwd64 = _event_ms(step, 3) - reset_ms
+        plan.substep_adjoint(dt, nu, ka, *saved, cot)
+        adj64 = _event_ms(lambda: plan.substep_adjoint(dt, nu, ka, *saved, cot), 3)
+        res["rk3_substep_768x768x512_fp64_poisson"] = {"forward_ms": round(fwd64, 3), "adjoint_ms": round(adj64, 3),
+                                                       "gpoints_per_s": round(npts / fwd64 / 1e6, 3)}
+    if steps:
+        # one full RK3 step (three substeps, Courant-limited dt) and the heat-flux statistics
+        used = []
 
-    def full_step():
-        reset()
-        used.append(plan.step(nu, ka, *st, dt=0.0, cfl=1.3)[0])
+        def full_step():
+            reset()
+            used.append(plan.step(nu, ka, *st, dt=0.0, cfl=1.3)[0])
 
-    full_step()
-    step_ms = _event_ms(full_step, 3) - reset_ms
-    hf_ms = _event_ms(lambda: plan.heat_flux(st[2], st[3], ka), 5)
-    mean_t, flux = plan.heat_flux(st[2], st[3], ka)
-    nu_prof = (flux / ka).cpu()
-    # the whole step's adjoint (fixed dt: the intermediate states recomputed, three substep adjoints)
-    plan.step_adjoint(used[-1], nu, ka, *saved, cot)
-    sadj_ms = _event_ms(lambda: plan.step_adjoint(used[-1], nu, ka, *saved, cot), 3)
-    res["rk3_step_768x768x512_fp64_poisson"] = {"ms": round(step_ms, 3), "dt": used[-1],
-                                                "adjoint_ms": round(sadj_ms, 3),
-                                                "adjoint_over_forward": round(sadj_ms / step_ms, 3),
-                                                "heat_flux_ms": round(hf_ms, 3),
-                                                "nusselt_wall_mean": round(float(0.5 * (nu_prof[0] + nu_prof[-1])), 6)}
+        full_step()
+        step_ms = _event_ms(full_step, 3) - reset_ms
+        hf_ms = _event_ms(lambda: plan.heat_flux(st[2], st[3], ka), 5)
+        mean_t, flux = plan.heat_flux(st[2], st[3], ka)
+        nu_prof = (flux / ka).cpu()
+        # the whole step's adjoint (fixed dt: the intermediate states recomputed, three substep adjoints)
+        plan.step_adjoint(used[-1], nu, ka, *saved, cot)
+        sadj_ms = _event_ms(lambda: plan.step_adjoint(used[-1], nu, ka, *saved, cot), 3)
+        res["rk3_step_768x768x512_fp64_poisson"] = {
+            "ms": round(step_ms, 3), "dt": used[-1], "adjoint_ms": round(sadj_ms, 3),
+            "adjoint_over_forward": round(sadj_ms / step_ms, 3), "heat_flux_ms": round(hf_ms, 3),
+            "nusselt_wall_mean": round(float(0.5 * (nu_prof[0] + nu_prof[-1])), 6)}
     plan.close()
     del st, saved, cot
     torch.cuda.empty_cache()
-
-    # ---- multiple-resolution step: momentum 384 x 384 x 256, temperature 768 x 768 x 512 ----
-    res.update(multires_workload())
     return res
 
 

@@ -16,6 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.environ.get("PS_BUILD_DIR") or os.path.join(HERE, "_build")
 LIB = os.environ.get("PS_LIB_OUT") or os.path.join(HERE, "libps_mi355x.so")
 ARCH = os.environ.get("PS_OFFLOAD_ARCH", "gfx950")
+ROCM_LIB = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
 # extra compile flags, e.g. launch-shape defines (-DPS_X_LDS=...) for tuning builds
 EXTRA = os.environ.get("PS_EXTRA_FLAGS", "").split()
 
@@ -66,7 +67,9 @@ def build(verbose: bool = True) -> str:
     with ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, units))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), "-shared", "-o", tmp] + objs + [f"--offload-arch={ARCH}", "-fPIC"]
+    # ROCTx for the host-side trace ranges of the entry points
+    cmd = [hipcc(), "-shared", "-o", tmp] + objs + [f"--offload-arch={ARCH}", "-fPIC", "-L", ROCM_LIB,
+                                                    "-Wl,-rpath," + ROCM_LIB, "-lrocprofiler-sdk-roctx"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")

@@ -15,6 +15,8 @@
 #include "../../include/ps.h"
 #include "ps_internal.h"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 using namespace ps;
 
 namespace {
@@ -40,6 +42,25 @@ ps_status hipfail(hipError_t e, const char* where) {
         hipError_t e_ = (expr);                          \
         if (e_ != hipSuccess) return hipfail(e_, where); \
     } while (0)
+
+// Host-side trace ranges (ROCTx): every entry point, and the phases of the composite ones,
+// appear as named ranges in a marker trace (rocprofv3 --marker-trace), so that a timeline
+// shows which library call issued which kernels.  Without a tracing tool attached a range
+// costs one indirect call.
+struct Range {
+    explicit Range(const char* name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    // ends this range and opens the next phase's in its place
+    void next(const char* name) {
+        roctxRangePop();
+        roctxRangePushA(name);
+    }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
+#define PS_RANGE_CAT2(a, b) a##b
+#define PS_RANGE_CAT(a, b) PS_RANGE_CAT2(a, b)
+#define PS_RANGE(name) Range PS_RANGE_CAT(ps_range_, __LINE__)(name)
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
@@ -95,6 +116,9 @@ struct ps_plan_s {
     double* fbuf;     // npts
     double* phibuf;   // npts
     double* rbuf;     // npts
+    double* rowsum = nullptr;   // FP32 plans: FP64 row sums of the transformed input, ny nz
+    double* psum = nullptr;     // FP32 plans: FP64 plane sums, nz
+    double* col00 = nullptr;    // FP32 plans: FP64 (0,0) column of the solution, nz
     double* partial;  // nblk_max * 4
     double* red_scratch;  // 1024 * 4
     double* small;    // 64 + cn factors
@@ -159,6 +183,9 @@ SpecDev<float> spec_of<float>(ps_plan_t p) {
     s.piv = (float*)p->piv;
     s.etab = (const float*)p->d_etab;
     s.ncu = p->ncu;
+    s.rowsum = p->rowsum;
+    s.psum = p->psum;
+    s.col00 = p->col00;
     return s;
 }
 
@@ -181,6 +208,10 @@ size_t workspace_layout(ps_plan_t p, bool carve) {
     p->fbuf = (double*)take(p->npts * sizeof(double));
     p->phibuf = (double*)take(p->npts * sizeof(double));
     p->rbuf = (double*)take(p->npts * sizeof(double));
+    const bool fp32 = p->prec != PS_FP64;
+    p->rowsum = fp32 ? (double*)take((size_t)p->ny * p->nz * sizeof(double)) : nullptr;
+    p->psum = fp32 ? (double*)take((size_t)p->nz * sizeof(double)) : nullptr;
+    p->col00 = fp32 ? (double*)take((size_t)p->nz * sizeof(double)) : nullptr;
     p->partial = (double*)take((size_t)p->nblk_max * 4 * sizeof(double));
     p->red_scratch = (double*)take(1024 * 4 * sizeof(double));
     p->small = (double*)take((R_NSLOTS + 9 * (size_t)(p->nz + 1)) * sizeof(double));
@@ -421,6 +452,7 @@ ps_status solve_impl(ps_plan_t p, const double* in, double* out, const double* z
             double prev = 1.0;
             bool converged = false;
             for (int it = 0; it < p->max_iter; ++it) {
+                PS_RANGE("refinement correction");
                 // correction: residual of the current iterate (formed in the x transform), FP32 solve,
                 // FP64 update with the gauge re-imposed
                 PS_CHECK(spectral_solve<float>(p, f, out, 1, p->small + R_XW, inv_den(p), nullptr, nullptr, false,
@@ -584,6 +616,7 @@ const char* ps_last_error(void) { return g_last_error.c_str(); }
 
 ps_status poisson_plan_create(ps_plan_t* out, int nx, int ny, int nz, double lx, double ly, const double* zf,
                               int prec, double tol, int max_iter, unsigned flags) {
+    PS_RANGE("poisson_plan_create");
     if (!out) return fail(PS_EINVAL, "out is NULL");
     *out = nullptr;
     if (nx < 4 || nx % 2 != 0 || nx > 4096 || !is_23(nx) || !fft_length_supported(nx / 2))
@@ -723,6 +756,7 @@ ps_status poisson_plan_create(ps_plan_t* out, int nx, int ny, int nz, double lx,
 size_t poisson_plan_workspace_bytes(ps_plan_t p) { return p ? p->ws_bytes : 0; }
 
 ps_status poisson_plan_set_workspace(ps_plan_t p, void* dev, size_t bytes) {
+    PS_RANGE("poisson_plan_set_workspace");
     if (!p) return fail(PS_EINVAL, "plan is NULL");
     if (dev) {
         if (bytes < p->ws_bytes) return fail(PS_EINVAL, "workspace too small: %zu < %zu", bytes, p->ws_bytes);
@@ -745,6 +779,7 @@ ps_status poisson_plan_set_workspace(ps_plan_t p, void* dev, size_t bytes) {
 }
 
 ps_status poisson_plan_destroy(ps_plan_t p) {
+    PS_RANGE("poisson_plan_destroy");
     if (!p) return PS_OK;
     if (p->ws_owned && p->ws) hipFree(p->ws);
     if (p->d_tables) hipFree(p->d_tables);
@@ -757,6 +792,7 @@ ps_status poisson_plan_destroy(ps_plan_t p) {
 }
 
 ps_status poisson_solve(ps_plan_t p, const double* f, double* phi, void* stream, ps_info* info) {
+    PS_RANGE("poisson_solve");
     PS_CHECK(check_plan(p));
     PS_CHECK(check_ptr(f, "f"));
     PS_CHECK(check_ptr(phi, "phi"));
@@ -765,6 +801,7 @@ ps_status poisson_solve(ps_plan_t p, const double* f, double* phi, void* stream,
 }
 
 ps_status poisson_solve_adjoint(ps_plan_t p, const double* g_phi, double* g_rhs, void* stream, ps_info* info) {
+    PS_RANGE("poisson_solve_adjoint");
     PS_CHECK(check_plan(p));
     PS_CHECK(check_ptr(g_phi, "g_phi"));
     PS_CHECK(check_ptr(g_rhs, "g_rhs"));
@@ -773,6 +810,7 @@ ps_status poisson_solve_adjoint(ps_plan_t p, const double* g_phi, double* g_rhs,
 }
 
 ps_status poisson_solve_static(ps_plan_t p, const double* f, double* phi, void* stream, ps_info* info) {
+    PS_RANGE("poisson_solve_static");
     PS_CHECK(check_plan(p));
     PS_CHECK(check_ptr(f, "f"));
     PS_CHECK(check_ptr(phi, "phi"));
@@ -795,6 +833,7 @@ ps_status poisson_solve_static(ps_plan_t p, const double* f, double* phi, void* 
 
 ps_status project(ps_plan_t p, double* u, double* v, double* w, double* pr, double* phi_out, double s, double c,
                   void* stream, ps_info* info) {
+    PS_RANGE("project");
     PS_CHECK(check_plan(p));
     PS_CHECK(check_ptr(u, "u"));
     PS_CHECK(check_ptr(v, "v"));
@@ -824,6 +863,7 @@ ps_status project(ps_plan_t p, double* u, double* v, double* w, double* pr, doub
 ps_status project_adjoint(ps_plan_t p, const double* g_u, const double* g_v, const double* g_w, const double* g_p,
                           double* gu_star, double* gv_star, double* gw_star, double s, double c, void* stream,
                           ps_info* info) {
+    PS_RANGE("project_adjoint");
     PS_CHECK(check_plan(p));
     PS_CHECK(check_ptr(g_u, "g_u"));
     PS_CHECK(check_ptr(g_v, "g_v"));
@@ -848,6 +888,7 @@ ps_status project_adjoint(ps_plan_t p, const double* g_u, const double* g_v, con
 }
 
 ps_status cn_solve(ps_plan_t p, int kind, double beta, double* x, void* stream) {
+    PS_RANGE("cn_solve");
     PS_CHECK(check_plan(p));
     PS_CHECK(check_ptr(x, "rhs_inout"));
     if (kind != PS_CENTER && kind != PS_FACE) return fail(PS_EINVAL, "unknown kind %d", kind);
@@ -860,6 +901,7 @@ ps_status cn_solve(ps_plan_t p, int kind, double beta, double* x, void* stream) 
 }
 
 ps_status ps_cfl(ps_plan_t p, const double* u, const double* v, const double* w, double* cfl_dev, void* stream) {
+    PS_RANGE("ps_cfl");
     PS_CHECK(check_plan(p));
     PS_CHECK(check_ptr(u, "u"));
     PS_CHECK(check_ptr(v, "v"));
@@ -872,11 +914,13 @@ ps_status ps_cfl(ps_plan_t p, const double* u, const double* v, const double* w,
 ps_status rk3_substep(ps_plan_t p, int l, double dt, double nu, double kappa, double* u, double* v, double* w,
                       double* t, double* pr, const double* const* h_prev, double* const* h_out, void* stream,
                       ps_info* info) {
+    PS_RANGE("rk3_substep");
     return substep_impl(p, l, dt, nu, kappa, u, v, w, t, pr, h_prev, h_out, stream, info, true);
 }
 
 ps_status rk3_step(ps_plan_t p, double dt, double cfl_target, double dt_max, double nu, double kappa, double* u,
                    double* v, double* w, double* t, double* pr, double* dt_used, void* stream, ps_info* info) {
+    PS_RANGE("rk3_step");
     PS_CHECK(check_plan(p));
     PS_CHECK(check_ptr(u, "u"));
     PS_CHECK(check_ptr(v, "v"));
@@ -931,6 +975,7 @@ ps_status rk3_step(ps_plan_t p, double dt, double cfl_target, double dt_max, dou
 
 ps_status ps_heat_flux(ps_plan_t p, const double* w, const double* t, double kappa, double* mean_t, double* flux,
                        void* stream) {
+    PS_RANGE("ps_heat_flux");
     PS_CHECK(check_plan(p));
     PS_CHECK(check_ptr(w, "w"));
     PS_CHECK(check_ptr(t, "t"));
@@ -945,6 +990,7 @@ ps_status rk3_substep_adjoint(ps_plan_t p, int l, double dt, double nu, double k
                               const double* v, const double* w, const double* t, const double* pr,
                               const double* const* g_out, const double* const* g_hout, double* const* g_in,
                               double* const* g_hprev, void* stream, ps_info* info) {
+    PS_RANGE("rk3_substep_adjoint");
     PS_CHECK(check_plan(p));
     if (l < 1 || l > 3) return fail(PS_EINVAL, "substep index l=%d must be 1, 2 or 3", l);
     if (!(dt > 0) || !std::isfinite(dt)) return fail(PS_EINVAL, "dt must be positive");
@@ -1054,6 +1100,7 @@ constexpr int kStepAdjFields = 28;
 ps_status rk3_step_adjoint(ps_plan_t p, double dt, double nu, double kappa, const double* u, const double* v,
                            const double* w, const double* t, const double* pr, const double* const* g_out,
                            double* const* g_in, void* stream, ps_info* info) {
+    PS_RANGE("rk3_step_adjoint");
     PS_CHECK(check_plan(p));
     if (!(dt > 0) || !std::isfinite(dt)) return fail(PS_EINVAL, "dt must be positive (the step adjoint takes dt fixed)");
     if (!(nu >= 0) || !(kappa >= 0) || !std::isfinite(nu) || !std::isfinite(kappa))
@@ -1086,6 +1133,7 @@ ps_status rk3_step_adjoint(ps_plan_t p, double dt, double nu, double kappa, cons
     const size_t bytes_c = p->npts * sizeof(double), bytes_f = (p->npts + p->plane) * sizeof(double);
     const size_t fb[5] = {bytes_c, bytes_c, bytes_f, bytes_f, bytes_c};
     // forward recomputation from the stored input: states after substeps 1 and 2
+    Range phase("forward recomputation");
     for (int q = 0; q < 5; ++q)
         PS_HIP(hipMemcpyAsync(s1[q], in[q], fb[q], hipMemcpyDeviceToDevice, st), "copy state");
     ps_status worst = PS_OK;
@@ -1099,6 +1147,7 @@ ps_status rk3_step_adjoint(ps_plan_t p, double dt, double nu, double kappa, cons
         PS_HIP(hipMemcpyAsync(s2[q], s1[q], fb[q], hipMemcpyDeviceToDevice, st), "copy state");
     r = rk3_substep(p, 2, dt, nu, kappa, s2[0], s2[1], s2[2], s2[3], s2[4], hc, nullptr, stream, nullptr);
     if (!note(r)) return r;
+    phase.next("reverse sweep");
     // reverse sweep: substep 3 at s2, substep 2 at s1 (with the cotangent of H^2), substep 1
     // at the input (with the cotangent of H^1); H^l's cotangent is handed down in place
     const double* go[5] = {g_out[0], g_out[1], g_out[2], g_out[3], g_out[4]};
@@ -1117,6 +1166,7 @@ ps_status rk3_step_adjoint(ps_plan_t p, double dt, double nu, double kappa, cons
 }
 
 ps_status ps_stream_copy(void* dst, const void* src, size_t bytes, void* stream) {
+    PS_RANGE("ps_stream_copy");
     if (!dst || !src || ((uintptr_t)dst) % 16 || ((uintptr_t)src) % 16)
         return fail(PS_EINVAL, "src and dst must be 16-byte aligned device pointers");
     const char* s0 = (const char*)src;
@@ -1142,6 +1192,7 @@ ps_status ps_spectral_layout(ps_plan_t p, int* w_tile, int* nkxb) {
 size_t ps_spectral_elems(ps_plan_t p) { return p ? p->spec_elems : 0; }
 
 ps_status ps_debug_stage(ps_plan_t p, int stage, const void* in, void* out, void* stream) {
+    PS_RANGE("ps_debug_stage");
     PS_CHECK(check_plan(p));
     hipStream_t st = (hipStream_t)stream;
     const size_t eb = elem_bytes(p->prec);
@@ -1158,16 +1209,20 @@ ps_status ps_debug_stage(ps_plan_t p, int stage, const void* in, void* out, void
     };
     const bool f64 = p->prec == PS_FP64;
     const GridDev& g = p->gd;
+    // each stage alone, on the spectrum as it stands: FP32 stages keep the (0,0) entry in
+    // the spectrum (no FP64 side column)
+    SpecDev<float> sf = spec_of<float>(p);
+    sf.rowsum = sf.psum = sf.col00 = nullptr;
     switch (stage) {
         case 0:
             PS_CHECK(check_ptr(in, "in"));
             PS_HIP(f64 ? launch_xfwd<double>(g, spec_of<double>(p), (const double*)in, nullptr, nullptr, st)
-                       : launch_xfwd<float>(g, spec_of<float>(p), (const double*)in, nullptr, nullptr, st),
+                       : launch_xfwd<float>(g, sf, (const double*)in, nullptr, nullptr, st),
                    "x forward FFT");
             return copy_out(p->spec_a);
         case 1:
             PS_CHECK(copy_in(p->spec_a));
-            PS_HIP(f64 ? launch_yfwd<double>(g, spec_of<double>(p), st) : launch_yfwd<float>(g, spec_of<float>(p), st),
+            PS_HIP(f64 ? launch_yfwd<double>(g, spec_of<double>(p), st) : launch_yfwd<float>(g, sf, st),
                    "y forward FFT");
             return copy_out(p->spec_b);
         case 2: {
@@ -1181,7 +1236,7 @@ ps_status ps_debug_stage(ps_plan_t p, int stage, const void* in, void* out, void
                 PS_HIP(launch_zsolve<double>(g, sz, st), "z solve");
                 PS_HIP(launch_zsolve00<double>(g, sz, p->small + R_DEFECT, st), "z solve (0,0)");
             } else {
-                SpecDev<float> sz = spec_of<float>(p);
+                SpecDev<float> sz = sf;
                 if (oop) sz.bz = sz.a;
                 PS_HIP(launch_zsolve<float>(g, sz, st), "z solve");
                 PS_HIP(launch_zsolve00<float>(g, sz, p->small + R_DEFECT, st), "z solve (0,0)");
@@ -1190,7 +1245,7 @@ ps_status ps_debug_stage(ps_plan_t p, int stage, const void* in, void* out, void
         }
         case 3:
             PS_CHECK(copy_in(p->spec_b));
-            PS_HIP(f64 ? launch_yinv<double>(g, spec_of<double>(p), st) : launch_yinv<float>(g, spec_of<float>(p), st),
+            PS_HIP(f64 ? launch_yinv<double>(g, spec_of<double>(p), st) : launch_yinv<float>(g, sf, st),
                    "y inverse FFT");
             return copy_out(p->spec_a);
         case 4: {
@@ -1198,7 +1253,7 @@ ps_status ps_debug_stage(ps_plan_t p, int stage, const void* in, void* out, void
             PS_CHECK(check_ptr(out, "out"));
             const double scale = 1.0 / ((double)p->nx * (double)p->ny);
             PS_HIP(f64 ? launch_xinv<double>(g, spec_of<double>(p), (double*)out, scale, 0, nullptr, 0.0, nullptr, nullptr, st)
-                       : launch_xinv<float>(g, spec_of<float>(p), (double*)out, scale, 0, nullptr, 0.0, nullptr, nullptr, st),
+                       : launch_xinv<float>(g, sf, (double*)out, scale, 0, nullptr, 0.0, nullptr, nullptr, st),
                    "x inverse FFT");
             return PS_OK;
         }
@@ -1277,6 +1332,7 @@ ps_status check_mr(ps_mr_t m) {
 extern "C" {
 
 ps_status mr_create(ps_mr_t* out, ps_plan_t p, int rx, int ry, int rz, int nsub) {
+    PS_RANGE("mr_create");
     if (!out) return fail(PS_EINVAL, "out is NULL");
     *out = nullptr;
     PS_CHECK(check_plan(p));
@@ -1398,6 +1454,7 @@ ps_status mr_create(ps_mr_t* out, ps_plan_t p, int rx, int ry, int rz, int nsub)
 }
 
 ps_status mr_destroy(ps_mr_t m) {
+    PS_RANGE("mr_destroy");
     if (!m) return PS_OK;
     if (m->buf) hipFree(m->buf);
     if (m->d_tab) hipFree(m->d_tab);
@@ -1415,6 +1472,7 @@ ps_status mr_shape(ps_mr_t m, int* nxf, int* nyf, int* nzf) {
 
 ps_status mr_prolong_velocity(ps_mr_t m, const double* u, const double* v, const double* w, double* uf, double* vf,
                               double* wf, void* stream) {
+    PS_RANGE("mr_prolong_velocity");
     PS_CHECK(check_mr(m));
     const void* ps[6] = {u, v, w, uf, vf, wf};
     const char* names[6] = {"u", "v", "w", "uf", "vf", "wf"};
@@ -1427,6 +1485,7 @@ ps_status mr_prolong_velocity(ps_mr_t m, const double* u, const double* v, const
 }
 
 ps_status mr_restrict_temperature(ps_mr_t m, const double* tf, double* tc, void* stream) {
+    PS_RANGE("mr_restrict_temperature");
     PS_CHECK(check_mr(m));
     PS_CHECK(check_ptr(tf, "tf"));
     PS_CHECK(check_ptr(tc, "tc"));
@@ -1478,6 +1537,7 @@ extern "C" {
 
 ps_status mr_temperature_step(ps_mr_t m, double dt, double kappa, const double* const* vel0,
                               const double* const* vel1, double* tf, void* stream) {
+    PS_RANGE("mr_temperature_step");
     PS_CHECK(check_mr(m));
     if (!(dt > 0) || !std::isfinite(dt)) return fail(PS_EINVAL, "dt must be positive");
     if (!(kappa >= 0) || !std::isfinite(kappa)) return fail(PS_EINVAL, "kappa must be non-negative");
@@ -1494,6 +1554,7 @@ ps_status mr_temperature_step(ps_mr_t m, double dt, double kappa, const double* 
 
 ps_status rk3_step_mr(ps_mr_t m, double dt, double cfl_target, double dt_max, double nu, double kappa, double* u,
                       double* v, double* w, double* pr, double* tf, double* dt_used, void* stream, ps_info* info) {
+    PS_RANGE("rk3_step_mr");
     PS_CHECK(check_mr(m));
     ps_plan_t p = m->plan;
     PS_CHECK(check_ptr(u, "u"));
@@ -1516,8 +1577,10 @@ ps_status rk3_step_mr(ps_mr_t m, double dt, double cfl_target, double dt_max, do
     if (!std::isfinite(dt)) return fail(PS_EINVAL, "dt must be finite");
     PS_CHECK(ensure_substep_buffers(p));
     // buoyancy: the temperature restricted to the momentum grid, frozen over the step
+    Range phase("restriction and prolongation");
     PS_HIP(launch_mr_restrict(p->gd, m->md, tf, m->tc, st), "restriction");
     PS_HIP(launch_mr_prolong(p->gd, m->md, u, v, w, m->u0, m->v0, m->w0, st), "prolongation");
+    phase.next("momentum substeps");
     double* h[4] = {sub_field(p, 4), sub_field(p, 5), sub_field(p, 6), sub_field(p, 7)};
     const double* hc[4] = {h[0], h[1], h[2], h[3]};
     ps_info acc{};
@@ -1538,6 +1601,7 @@ ps_status rk3_step_mr(ps_mr_t m, double dt, double cfl_target, double dt_max, do
         acc.compat_defect = li.compat_defect;
         acc.gauge_shift = li.gauge_shift;
     }
+    phase.next("temperature step");
     PS_HIP(launch_mr_prolong(p->gd, m->md, u, v, w, m->u1, m->v1, m->w1, st), "prolongation");
     const double* v0[3] = {m->u0, m->v0, m->w0};
     const double* v1[3] = {m->u1, m->v1, m->w1};

@@ -142,11 +142,35 @@ struct ResidIn {
 #ifndef PS_XI_WPE
 #define PS_XI_WPE 1
 #endif
+// FP64 sum of x over the NT consecutive threads of each row (NT a power of two); every
+// thread of the row receives it.  red: THREADS / 64 doubles of LDS (NT > 64 only).  The
+// whole block calls this (it synchronises when rows span several waves).
+template <int NT>
+__device__ __forceinline__ double row_sum(double x, int tid, double* red) {
+    static_assert((NT & (NT - 1)) == 0, "threads per row: a power of two");
+    if constexpr (NT <= 64) {
+#pragma unroll
+        for (int o = NT / 2; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+        return x;
+    } else {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+        if ((tid & 63) == 0) red[tid >> 6] = x;
+        __syncthreads();
+        const int w0 = (tid / NT) * (NT / 64);
+        double sum = 0.0;
+#pragma unroll
+        for (int i = 0; i < NT / 64; ++i) sum += red[w0 + i];
+        return sum;
+    }
+}
+
 template <typename T, int M, int LM>
 __global__ void __launch_bounds__((XShape<T, M>::THREADS), (LM == XL_RESID ? PS_XR_WPE : PS_XF_WPE))
 k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny, int nkxb,
        const cx<T>* __restrict__ tw, const cx<T>* __restrict__ ptw, const double* __restrict__ scale_z,
-       const double* __restrict__ dz, double* __restrict__ partial, ResidIn rin, GridDev g) {
+       const double* __restrict__ dz, double* __restrict__ partial, ResidIn rin, GridDev g,
+       double* __restrict__ rowsum) {
     using X = XShape<T, M>;
     constexpr int NT = X::NT, R = X::R, LROW = X::LROW;
     constexpr int W = TileW<T>::value;
@@ -179,6 +203,7 @@ k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny,
     const double zs = scale_z ? scale_z[row / ny] : 1.0;
     cx<T>* lrow = smem + rl * LROW;
     double acc0 = 0.0, acc1 = 0.0;
+    double accs = 0.0;   // residual mode: the row's sum of r (FP64), for the (0,0) column
     // residual mode: row (z, y) of the whole box and its neighbours
     const int zl = row / ny;
     const int zg = rin.z0 + zl;
@@ -225,6 +250,7 @@ k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny,
             v.y = valid ? f1 - l1 : 0.0;
             acc0 += v.x * v.x + v.y * v.y;
             acc1 += valid ? f0 * f0 + f1 * f1 : 0.0;
+            accs += v.x + v.y;
             // the values of every PS_XR_GROUP elements are formed at the group's end (an empty
             // asm reads them): the loads of one group are in flight together; without it every
             // element's stencil is hoisted at once and held in registers (one wave per SIMD)
@@ -296,6 +322,14 @@ k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny,
         if (q < NTOT && row2 < nrows && kxb < nkxb)
             st_stream<PS_NT_XF>(out + (((size_t)z * nkxb + kxb) * ny + y) * W + w, xv);
     }
+    if constexpr (std::is_same<T, float>::value) {
+        // the row's FP64 sum (plain and divergence loaders: acc0 holds it)
+        if (rowsum) {
+            __shared__ double red[X::THREADS / 64 > 0 ? X::THREADS / 64 : 1];
+            const double rs = row_sum<NT>(RESID ? accs : acc0, tid, red);
+            if (t == 0 && valid) rowsum[row] = rs;
+        }
+    }
     if (partial) {
         if constexpr (RESID) {
             double v[2] = {acc0, acc1};   // sum r^2, sum (f - mu)^2
@@ -314,7 +348,7 @@ __global__ void __launch_bounds__((XShape<T, M, true>::THREADS), PS_XI_WPE)
 k_xinv(const cx<T>* __restrict__ in, double* __restrict__ out, int nrows, int ny, int nkxb,
        const cx<T>* __restrict__ tw, const cx<T>* __restrict__ ptw, double scale,
        const double* __restrict__ mu, double mu_scale, const double* __restrict__ scale_z,
-       const double* __restrict__ dz, double* __restrict__ partial) {
+       const double* __restrict__ dz, double* __restrict__ partial, const double* __restrict__ col00) {
     using X = XShape<T, M, true>;
     constexpr int NT = X::NT, R = X::R, LROW = X::LROW;
     constexpr int W = TileW<T>::value;
@@ -381,6 +415,8 @@ k_xinv(const cx<T>* __restrict__ in, double* __restrict__ out, int nrows, int ny
     double* orow = out + (size_t)row * (2 * M);
     const double sc = scale * (scale_z ? scale_z[row / ny] : 1.0);
     const double m0 = MODE == 1 ? mu[0] * mu_scale : 0.0;
+    // the FP64 (0,0) coefficient of this plane (FP32 spectra, whose own (0,0) entry is zero)
+    const double off = col00 ? col00[row / ny] * sc : 0.0;
     double s_d2 = 0.0, s_o2 = 0.0, s_o = 0.0;
     // MODE 1: the values being accumulated into, loaded before the transform (all in
     // flight together) in the order in which the transform hands out its results:
@@ -398,7 +434,7 @@ k_xinv(const cx<T>* __restrict__ in, double* __restrict__ out, int nrows, int ny
     }
     int sidx = 0;
     auto st = [&](int e, cx<T> val) {
-        double2 r = {(double)val.x * sc, (double)val.y * sc};
+        double2 r = {(double)val.x * sc + off, (double)val.y * sc + off};
         double2 o;
         if constexpr (MODE == 1) {
             const double2 old = acc_old[sidx++];
@@ -495,13 +531,14 @@ static hipError_t xfwd_launch_t(const GridDev& g, const SpecDev<T>& s, const dou
     const size_t zoff = (size_t)s.z0 * g.nx * g.ny;
     const int nrows = g.ny * nzl;
     const int nblk = (nrows + X::R - 1) / X::R;
+    double* rsum = s.rowsum ? s.rowsum + (size_t)s.z0 * g.ny : nullptr;   // rows of this launch
     if (mode == XL_RESID) {
         // the residual form is used by the refinement, which runs its solves in FP32
         if constexpr (std::is_same<T, float>::value) {
             ResidIn r = *rin;
             r.z0 = s.z0;
             hipLaunchKernelGGL((k_xfwd<T, M, XL_RESID>), dim3(nblk), dim3(X::THREADS), X::LDS, st, f + zoff, s.a,
-                               nrows, g.ny, s.nkxb, s.twx, s.ptw, nullptr, g.dz + s.z0, partial, r, g);
+                               nrows, g.ny, s.nkxb, s.twx, s.ptw, nullptr, g.dz + s.z0, partial, r, g, rsum);
             return hipGetLastError();
         }
         return hipErrorInvalidValue;
@@ -513,12 +550,12 @@ static hipError_t xfwd_launch_t(const GridDev& g, const SpecDev<T>& s, const dou
         r.v += zoff;
         r.w += zoff;
         hipLaunchKernelGGL((k_xfwd<T, M, XL_DIV>), dim3(nblk), dim3(X::THREADS), X::LDS, st, nullptr, s.a, nrows, g.ny,
-                           s.nkxb, s.twx, s.ptw, nullptr, g.dz + s.z0, partial, r, g);
+                           s.nkxb, s.twx, s.ptw, nullptr, g.dz + s.z0, partial, r, g, rsum);
         return hipGetLastError();
     }
     hipLaunchKernelGGL((k_xfwd<T, M, XL_PLAIN>), dim3(nblk), dim3(X::THREADS), X::LDS, st, f + zoff, s.a, nrows,
                        g.ny, s.nkxb, s.twx, s.ptw, scale_z ? scale_z + s.z0 : nullptr, g.dz + s.z0, partial,
-                       ResidIn{}, g);
+                       ResidIn{}, g, rsum);
     return hipGetLastError();
 }
 
@@ -534,11 +571,11 @@ static hipError_t xinv_launch_t(const GridDev& g, const SpecDev<T>& s, double* o
     if (mode == 1)
         hipLaunchKernelGGL((k_xinv<T, M, 1>), dim3(nblk), dim3(X::THREADS), X::LDS, st, s.a, out + zoff, nrows,
                            g.ny, s.nkxb, s.twx, s.ptw, scale, mu, mu_scale, scale_z ? scale_z + s.z0 : nullptr,
-                           g.dz + s.z0, partial);
+                           g.dz + s.z0, partial, s.col00 ? s.col00 + s.z0 : nullptr);
     else
         hipLaunchKernelGGL((k_xinv<T, M, 0>), dim3(nblk), dim3(X::THREADS), X::LDS, st, s.a, out + zoff, nrows,
                            g.ny, s.nkxb, s.twx, s.ptw, scale, mu, mu_scale, scale_z ? scale_z + s.z0 : nullptr,
-                           g.dz + s.z0, partial);
+                           g.dz + s.z0, partial, s.col00 ? s.col00 + s.z0 : nullptr);
     return hipGetLastError();
 }
 

@@ -162,6 +162,13 @@ struct SpecDev {
     T* piv;                   // z-solve pivots, same layout as b (real); tall columns only
     const T* etab = nullptr;  // pivot excess entering each lane chunk of the tiled z solve
     cx<T>* bz = nullptr;      // z solve output in the b layout (nullptr: in place in b)
+    // FP32 spectra: the singular (0,0) column is carried in FP64 beside them.  The x transform
+    // writes each row's FP64 sum (rowsum, [nz][ny]), the plane sums (psum, [nz]) feed the
+    // (0,0) column solve, whose FP64 result (col00, [nz]) the inverse x transform adds to
+    // every point of its plane (the spectrum's own (0,0) entry is then zero).
+    double* rowsum = nullptr;
+    double* psum = nullptr;
+    double* col00 = nullptr;
     // Plane range of the x / y stages: planes [z0, z0 + nzc) (nzc = 0: all).  Buffer a
     // is then indexed relative to z0 (it may hold just those planes); b stays absolute.
     int ncu = 0;              // compute units of the plan's device (persistent launches)

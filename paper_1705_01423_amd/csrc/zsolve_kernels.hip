@@ -523,12 +523,29 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// FP64 plane sums from the x transform's row sums: one block per plane, a fixed
+// summation order (the same result on every run).
+__global__ void __launch_bounds__(256) k_plane_sums(const double* __restrict__ rowsum, int ny,
+                                                    double* __restrict__ psum) {
+    __shared__ double red[4];
+    const int z = blockIdx.x;
+    double v = 0.0;
+    for (int y = threadIdx.x; y < ny; y += 256) v += rowsum[(size_t)z * ny + y];
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) psum[z] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
 // The singular (0,0) column, always in FP64.  One wave; lane l owns rows
-// [l K, l K + K).  Column (kx, ky, w) = (0, 0, 0) of buffer b.
+// [l K, l K + K).  Column (kx, ky, w) = (0, 0, 0) of buffer b.  With psum (FP32
+// spectra) the plane sums come from there in FP64 and the result goes to col00 in FP64,
+// the spectrum's own entry being set to zero.
 template <typename T>
 __global__ void __launch_bounds__(64)
 k_zsolve00(const cx<T>* b, cx<T>* bo, int nz, int nxny, const double* __restrict__ dz,
-           const double* __restrict__ dzc, double* __restrict__ defect) {
+           const double* __restrict__ dzc, double* __restrict__ defect, const double* __restrict__ psum,
+           double* __restrict__ col00) {
     constexpr int W = TileW<T>::value;
     constexpr int KMAX = 32;   // nz <= 2048
     const int lane = threadIdx.x;
@@ -541,7 +558,7 @@ k_zsolve00(const cx<T>* b, cx<T>* bo, int nz, int nxny, const double* __restrict
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) {
         const int kc = min(k0 + i, nz - 1);
-        fv[i] = (double)b[(size_t)kc * W].x;
+        fv[i] = psum ? psum[kc] : (double)b[(size_t)kc * W].x;
         dzv[i] = dz[kc];
         dzcv[i] = dzc[kc];
     }
@@ -601,7 +618,14 @@ k_zsolve00(const cx<T>* b, cx<T>* bo, int nz, int nxny, const double* __restrict
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) {
         const int k = k0 + i;
-        if (i < K && k < nz) bo[(size_t)k * W] = cx<T>{(T)(fv[i] - shift), (T)0};
+        if (i < K && k < nz) {
+            if (col00) {
+                col00[k] = fv[i] - shift;
+                bo[(size_t)k * W] = cx<T>{(T)0, (T)0};
+            } else {
+                bo[(size_t)k * W] = cx<T>{(T)(fv[i] - shift), (T)0};
+            }
+        }
     }
     if (lane == 0 && defect) defect[0] = mean_plane / (double)nxny;
 }
@@ -757,8 +781,13 @@ hipError_t launch_zexcess(const GridDev& g, int nkxb, T* etab, hipStream_t st) {
 
 template <typename T>
 hipError_t launch_zsolve00(const GridDev& g, const SpecDev<T>& s, double* defect, hipStream_t st) {
+    if (s.rowsum) {
+        hipLaunchKernelGGL(k_plane_sums, dim3(g.nz), dim3(256), 0, st, s.rowsum, g.ny, s.psum);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL((k_zsolve00<T>), dim3(1), dim3(64), 0, st, s.b, s.bz ? s.bz : s.b, g.nz, g.nx * g.ny, g.dz,
-                       g.dzc, defect);
+                       g.dzc, defect, s.rowsum ? s.psum : nullptr, s.rowsum ? s.col00 : nullptr);
     return hipGetLastError();
 }
 

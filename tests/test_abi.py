@@ -34,6 +34,20 @@ def test_library_exports_all_symbols():
     assert set(_declared()) <= set(_lib.SIGNATURES)
 
 
+def test_library_marks_trace_ranges():
+    """Every entry point opens a ROCTx range (host-side trace annotation): the library
+    imports the range calls from the ROCTx runtime."""
+    import shutil
+    import subprocess
+    if shutil.which("nm") is None:
+        pytest.skip("nm not available")
+    out = subprocess.run(["nm", "-D", "--undefined-only", _lib.LIB_PATH], capture_output=True, text=True).stdout
+    assert "roctxRangePushA" in out and "roctxRangePop" in out
+    src = open(os.path.join(ROOT, "paper_1705_01423_amd", "csrc", "api.hip")).read()
+    for n in ("poisson_solve", "project", "rk3_substep", "rk3_step", "rk3_step_adjoint", "rk3_step_mr"):
+        assert f'PS_RANGE("{n}")' in src, n
+
+
 def _create(nx, ny, nz, zf=None, prec=0):
     lib = _lib.load()
     zf = np.linspace(0, 1, nz + 1) if zf is None else zf

@@ -203,3 +203,21 @@ def test_cube64_parity():
     ref = poisson.solve(f, g)
     phi, _ = plan.solve(f.to("cuda"))
     assert rel(phi, ref) < 1e-12
+
+
+@pytest.mark.parametrize("shape,chunk", [((48, 32, 40), 0), ((96, 6, 7), 3), ((8, 6, 2048), 0)])
+def test_fp32_singular_column_in_fp64(shape, chunk, monkeypatch):
+    """FP32 spectra, FP64 singular mode (Sec. 2.2): the plane means of phi, i.e. the (0,0)
+    column, come from FP64 plane sums and an FP64 column solve, so they match the oracle to
+    FP64 accuracy even though the rest of the unrefined FP32 solve is good to about 1e-6."""
+    banner(f"fp32 (0,0) column {shape} chunk={chunk}")
+    if chunk:
+        monkeypatch.setenv("PS_CHUNK_PLANES", str(chunk))
+    g, plan = grids(*shape, lx=2.0, ly=2.0, precision="fp32")
+    zc = g.zc
+    f = torch.cos(math.pi * zc)[:, None, None] + 1e-3 * _rng_field(plan.centre_shape, 21)
+    ref = poisson.solve(f, g)
+    phi, _ = plan.solve(f.to("cuda"))
+    assert rel(phi, ref) < 1e-5
+    pm, pm_ref = phi.mean(dim=(1, 2)).cpu(), ref.mean(dim=(1, 2))
+    assert float((pm - pm_ref).abs().max()) <= 1e-10 * float(pm_ref.abs().max())
