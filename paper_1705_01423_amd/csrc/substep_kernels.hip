@@ -21,6 +21,18 @@ namespace {
 
 __device__ __forceinline__ double sq(double a) { return a * a; }
 
+// Stores of the explicit kernels' outputs (right-hand sides, H, gradients): each is read
+// again only by a later kernel, after far more data than the caches hold has passed.
+#ifndef PS_EX_NT_STORE
+#define PS_EX_NT_STORE 1
+#endif
+__device__ __forceinline__ void st_out(double* p, double v) {
+    if (PS_EX_NT_STORE)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
 }  // namespace
 
 
@@ -99,6 +111,66 @@ struct Ring {
     }
 };
 
+// The same z-marching scheme with a window of its own depth for each field: field f keeps
+// Win::ns(f) consecutive planes (1 to 3) in LDS, so that a field whose neighbours are
+// needed on fewer planes takes less LDS (and more blocks fit one CU).  Values on the
+// thread's own column below the window are carried in registers by the kernel.
+template <int TX, int TY, class Win>
+struct WinRing {
+    static constexpr int NF = Win::NF;
+    static constexpr int HX = TX + 2, HY = TY + 2, PL = HX * HY;
+    static constexpr int NQ = (PL + TX * TY - 1) / (TX * TY);
+    static constexpr int base(int f) { return f == 0 ? 0 : base(f - 1) + Win::ns(f - 1); }
+    static constexpr int PLANES = base(NF);
+    double* s;        // PLANES planes of PL cells
+    int tx, ty;
+    __device__ __forceinline__ static int slot(int f, int kk) {
+        const int n = Win::ns(f);
+        return base(f) + (n == 1 ? 0 : ((kk % n) + n) % n);
+    }
+    // field f at plane kk, (j + dj, i + di) of this thread's cell
+    __device__ __forceinline__ double at(int f, int kk, int dj, int di) const {
+        return s[slot(f, kk) * PL + (ty + 1 + dj) * HX + (tx + 1 + di)];
+    }
+    // raw loaded values and, per field, whether the plane exists (uniform): the zeroing of
+    // absent planes waits for put(), so that no value is touched (and waited for) before
+    // the next step's stores into the ring
+    struct Stage {
+        double v[NQ][NF];
+        bool ok[NF];
+    };
+    using Cols = typename Ring<Win::NF, TX, TY>::Cols;
+    // plane kk[f] of field f for the fields with want[f] (the others keep their values)
+    __device__ __forceinline__ void fetch(const int (&kk)[NF], const bool (&want)[NF], const double* const (&F)[NF],
+                                          const bool (&face)[NF], const GridDev& g, const Cols& cols,
+                                          Stage& st) const {
+        const size_t plane = (size_t)g.nx * g.ny;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            if (!want[f]) continue;
+            const int k = kk[f];
+            const int kc = k < 0 ? 0 : (k > g.nz - 1 ? g.nz - 1 : k);
+            const int kf = k < 0 ? 0 : (k > g.nz ? g.nz : k);
+            st.ok[f] = k >= 0 && (k < g.nz || (face[f] && k == g.nz));
+            const double* base_f = F[f] + (size_t)(face[f] ? kf : kc) * plane;
+#pragma unroll
+            for (int qi = 0; qi < NQ; ++qi) st.v[qi][f] = base_f[cols.off[qi]];
+        }
+    }
+    __device__ __forceinline__ void put(const int (&kk)[NF], const bool (&want)[NF], const Stage& st) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            if (!want[f]) continue;
+            double* d = s + slot(f, kk[f]) * PL;
+#pragma unroll
+            for (int qi = 0; qi < NQ; ++qi) {
+                const int q = (int)threadIdx.x + qi * TX * TY;
+                if (q < PL) d[q] = st.ok[f] ? st.v[qi][f] : 0.0;
+            }
+        }
+    }
+};
+
 // Column tile of the forward kernel: 32 x 8 (halo 1.33 cells per cell, 40.8 KB of LDS: four
 // blocks fit one CU's 160 KB) measured 7.60 -> 6.9-7.1 ms against 64 x 4 at 768^2 x 512; 16 x 16:
 // 7.24 ms.  The adjoint's eight-field ring keeps 64 x 4 (32 x 8 measured the same).
@@ -137,13 +209,57 @@ inline int ex_blocks(const GridDev& g) {
 
 // Right-hand sides of u, v at the cell's x/y faces and of w, T at its bottom z-face k
 // (interior faces; wall rows are zeroed).
-__global__ void __launch_bounds__(kExTX * kExTY) k_explicit(SubstepArgs a, GridDev g) {
-    constexpr int TX = kExTX, TY = kExTY, NF = 5;
+//
+// Windows (step k computes u, v of cell plane k and w, T of its bottom face k): u and v
+// are read with neighbours on planes k - 1 (by the face terms) and k, and on their own
+// column at k + 1; w with neighbours on faces k and k + 1; T and p with neighbours on
+// plane k only.  So u, v keep planes k-1..k+1, w and T faces k..k+1, p plane k: 11 planes
+// of LDS instead of 15 (29.9 KB for a 32 x 8 tile: five blocks per CU instead of three).
+// The own-column values of w, T, p at k - 1 are the previous step's centre values, carried
+// in registers.
+struct ExWin {
+    static constexpr int NF = 5;   // u, v, w, T, p
+    __host__ __device__ static constexpr int ns(int f) { return f < 2 ? 3 : (f < 4 ? 2 : 1); }
+};
+// Waves per SIMD the register allocation must allow (0: no cap).
+#ifndef PS_EX_WPE
+#define PS_EX_WPE 0
+#endif
+#ifndef PS_EX_SPLIT
+#define PS_EX_SPLIT 1
+#endif
+#if PS_EX_SPLIT
+#define PS_EX_FENCE() asm volatile("" ::: "memory")
+#else
+#define PS_EX_FENCE() ((void)0)
+#endif
+#if PS_EX_WPE > 0
+#define PS_EX_ATTR __attribute__((amdgpu_waves_per_eu(PS_EX_WPE)))
+#else
+#define PS_EX_ATTR
+#endif
+__global__ void __launch_bounds__(kExTX * kExTY) PS_EX_ATTR k_explicit(SubstepArgs a, GridDev g) {
+    constexpr int TX = kExTX, TY = kExTY, NF = ExWin::NF;
     enum { FU, FV, FW, FT, FP };
-    __shared__ double lds[3 * NF * (TX + 2) * (TY + 2)];
+    using RR = WinRing<TX, TY, ExWin>;
+    static_assert(RR::PLANES == 11, "window planes");
+    __shared__ double lds[RR::PLANES * RR::PL];
+    // the segment's grid metrics: LDS reads, so that no global load inside a step makes the
+    // wave wait for the next plane's prefetch (a vector-memory wait counts every load)
+    constexpr int ZT = kExZSEG + 1;
+    __shared__ double m_idz[ZT], m_dz[ZT], m_idzw[ZT], m_o[ZT];
     const ExTile tile = ex_tile<TX, TY, kExZSEG>(g);
-    Ring<NF, TX, TY> R{lds, (int)threadIdx.x % TX, (int)threadIdx.x / TX};
-    const typename Ring<NF, TX, TY>::Cols cols = Ring<NF, TX, TY>::columns(g, tile.i0, tile.j0);
+    RR R{lds, (int)threadIdx.x % TX, (int)threadIdx.x / TX};
+    for (int q = threadIdx.x; q < ZT; q += TX * TY) {
+        const int kc = min(max(tile.kb - 1 + q, 0), g.nz - 1);   // cell planes kb - 1 .. (clamped)
+        const int kf = min(tile.kb + q, g.nz);                    // face planes kb ..
+        m_idz[q] = g.idz[kc];
+        m_dz[q] = g.dz[kc];
+        m_idzw[q] = g.idzw[kf];
+        m_o[q] = g.o[kf];
+    }
+    const double idzw_lo = g.idzw[0], idzw_hi = g.idzw[g.nz];
+    const typename RR::Cols cols = Ring<NF, TX, TY>::columns(g, tile.i0, tile.j0);
     const int i = tile.i0 + R.tx, j = tile.j0 + R.ty;
     const bool valid = i < g.nx && j < g.ny;
     const double* const F[NF] = {a.u, a.v, a.w, a.t, a.p};
@@ -157,34 +273,66 @@ __global__ void __launch_bounds__(kExTX * kExTY) k_explicit(SubstepArgs a, GridD
     const double cg = a.dt * a.gam, cr = a.dt * a.rho, ca = a.dt * a.alp;
     const double can = ca * a.nu, cak = ca * a.ka;
     const int nz = g.nz;
-    typename Ring<NF, TX, TY>::Stage st;
-    R.fetch(tile.kb - 1, F, face, g, cols, st);
-    R.put(tile.kb - 1, st);
-    R.fetch(tile.kb, F, face, g, cols, st);
-    R.put(tile.kb, st);
-    R.fetch(tile.kb + 1, F, face, g, cols, st);
-    for (int k = tile.kb; k < tile.ke; ++k) {
-        R.put(k + 1, st);
+    const int kb = tile.kb;
+    typename RR::Stage st;
+    // prologue: u, v at kb - 1 and kb, w and T at kb; then the step's leading planes
+    // (u, v, w, T at k + 1 and p at k), which the loop stores at the top of step k
+    constexpr bool kUV[NF] = {true, true, false, false, false};
+    constexpr bool kUVWT[NF] = {true, true, true, true, false};
+    constexpr bool kAll[NF] = {true, true, true, true, true};
+    {
+        const int p0[NF] = {kb - 1, kb - 1, kb - 1, kb - 1, kb - 1};
+        R.fetch(p0, kUV, F, face, g, cols, st);
+        R.put(p0, kUV, st);
+        const int p1[NF] = {kb, kb, kb, kb, kb};
+        R.fetch(p1, kUVWT, F, face, g, cols, st);
+        R.put(p1, kUVWT, st);
+        const int p2[NF] = {kb + 1, kb + 1, kb + 1, kb + 1, kb};
+        R.fetch(p2, kAll, F, face, g, cols, st);
+    }
+    // own-column values at k - 1 of w (face), T (face) and p (cell); zero below the box
+    const size_t own = valid ? (size_t)j * g.nx + i : 0;
+    double w_km = 0.0, t_km = 0.0, p_km = 0.0;
+    if (kb > 0) {
+        w_km = a.w[(size_t)(kb - 1) * plane + own];
+        t_km = a.t[(size_t)(kb - 1) * plane + own];
+        p_km = a.p[(size_t)(kb - 1) * plane + own];
+    }
+    for (int k = kb; k < tile.ke; ++k) {
+        {
+            const int pk[NF] = {k + 1, k + 1, k + 1, k + 1, k};
+            R.put(pk, kAll, st);
+        }
         __syncthreads();
         const size_t id = (size_t)k * plane + (size_t)j * g.nx + i;
-        // previous-substep H of this cell, loaded before the next plane's prefetch (cells
-        // outside the box read the plane's first cell: no load under a per-lane branch)
-        double hp[4] = {0.0, 0.0, 0.0, 0.0};
-        if (a.rho != 0.0) {
-            const size_t ih = valid ? id : (size_t)k * plane;
-            hp[0] = a.hpu[ih];
-            hp[1] = a.hpv[ih];
-            hp[2] = a.hpw[ih];
-            hp[3] = a.hpt[ih];
+        // Previous-substep H of this cell, loaded before the next plane's prefetch (cells
+        // outside the box read the plane's first cell).  These loads and the prefetch are
+        // unconditional (substep 1 reads u in place of H and drops it; the last step fetches a
+        // plane it never stores): a load under a branch would make every wait after the
+        // branch's end count conservatively, and so wait for the whole prefetch.
+        const size_t ih = valid ? id : (size_t)k * plane;
+        const bool use_hp = a.rho != 0.0;
+        double hp[4];
+        hp[0] = (use_hp ? a.hpu : a.u)[ih];
+        hp[1] = (use_hp ? a.hpv : a.v)[ih];
+        hp[2] = (use_hp ? a.hpw : a.w)[ih];
+        hp[3] = (use_hp ? a.hpt : a.t)[ih];
+        asm volatile("" ::: "memory");   // issue order: H first, then the prefetch
+        {
+            const int pn[NF] = {k + 2, k + 2, k + 2, k + 2, k + 1};
+            R.fetch(pn, kAll, F, face, g, cols, st);
         }
-        if (k + 2 <= tile.ke) R.fetch(k + 2, F, face, g, cols, st);
+        // this step's own-column centre values of w, T, p (carried to the next step)
+        const double w_kc = R.at(FW, k, 0, 0), t_kc = R.at(FT, k, 0, 0), p_kc = R.at(FP, k, 0, 0);
         if (valid) {
-            auto L = [&](int f, int dk, int dj, int di) { return R(k, f, dk, dj, di); };
+            // neighbours on the window's planes; the own column at k - 1 of w, T, p from registers
+            auto L = [&](int f, int dk, int dj, int di) { return R.at(f, k + dk, dj, di); };
             // The two-point averages of every flux product are taken as plain sums, their
             // factor 1/4 folded into the per-direction scale with the inverse spacing; a
             // difference of squared averages is formed as (a - b)(a + b); dt folds into the
             // RK3 weights.  The same discrete operators, fewer FP64 instructions.
-            const double idzk = g.idz[k];
+            const int mq = k - tile.kb;   // metric tables: cell plane k at mq + 1, face k at mq
+            const double idzk = m_idz[mq + 1];
             const bool lo = k > 0, hi = k + 1 < nz;
             // ---- u at (x-face i, y-centre j, z-centre k) ----
             {
@@ -198,15 +346,19 @@ __global__ void __launch_bounds__(kExTX * kExTY) k_explicit(SubstepArgs a, GridD
                 const double fzt = hi ? (L(FW, 1, 0, 0) + L(FW, 1, 0, -1)) * (uc + ukp) : 0.0;
                 const double az = (fzt - fzb) * (0.25 * idzk);
                 const double h = (nux * (uip + uim - 2.0 * uc) + nuy * (ujp + ujm - 2.0 * uc)) - (ax + ay + az);
-                const double fb = lo ? (uc - ukm) * g.idzw[k] : uc * g.idzw[0];
-                const double ft = hi ? (ukp - uc) * g.idzw[k + 1] : -uc * g.idzw[nz];
+                const double fb = lo ? (uc - ukm) * m_idzw[mq] : uc * idzw_lo;
+                const double ft = hi ? (ukp - uc) * m_idzw[mq + 1] : -uc * idzw_hi;
                 const double dzz = (ft - fb) * idzk;
                 const double gp = (L(FP, 0, 0, 0) - L(FP, 0, 0, -1)) * idx;
                 double r = cg * h - ca * gp + can * dzz;
                 if (a.rho != 0.0) r += cr * hp[0];
-                a.ru[id] = r;
-                if (a.hu) a.hu[id] = h;
+                st_out(a.ru + (id), r);
+                if (a.hu) st_out(a.hu + (id), h);
             }
+            // (the three blocks run one after the other: their LDS reads are not hoisted
+            // together, which keeps the register count, and the occupancy, where the window's
+            // LDS size allows)
+            PS_EX_FENCE();
             // ---- v at (x-centre i, y-face j, z-centre k) ----
             {
                 const double vc = L(FV, 0, 0, 0), vjm = L(FV, 0, -1, 0), vjp = L(FV, 0, 1, 0);
@@ -219,25 +371,26 @@ __global__ void __launch_bounds__(kExTX * kExTY) k_explicit(SubstepArgs a, GridD
                 const double fzt = hi ? (L(FW, 1, 0, 0) + L(FW, 1, -1, 0)) * (vc + vkp) : 0.0;
                 const double az = (fzt - fzb) * (0.25 * idzk);
                 const double h = (nux * (vip + vim - 2.0 * vc) + nuy * (vjp + vjm - 2.0 * vc)) - (ax + ay + az);
-                const double fb = lo ? (vc - vkm) * g.idzw[k] : vc * g.idzw[0];
-                const double ft = hi ? (vkp - vc) * g.idzw[k + 1] : -vc * g.idzw[nz];
+                const double fb = lo ? (vc - vkm) * m_idzw[mq] : vc * idzw_lo;
+                const double ft = hi ? (vkp - vc) * m_idzw[mq + 1] : -vc * idzw_hi;
                 const double dzz = (ft - fb) * idzk;
                 const double gp = (L(FP, 0, 0, 0) - L(FP, 0, -1, 0)) * idy;
                 double r = cg * h - ca * gp + can * dzz;
                 if (a.rho != 0.0) r += cr * hp[1];
-                a.rv[id] = r;
-                if (a.hv) a.hv[id] = h;
+                st_out(a.rv + (id), r);
+                if (a.hv) st_out(a.hv + (id), h);
             }
+            PS_EX_FENCE();
             // ---- w and T at (x-centre i, y-centre j, z-face k), interior faces ----
             // (rt NULL: the temperature is not advanced, only its buoyancy is used)
             const bool with_t = a.rt != nullptr;
             if (k == 0) {
-                a.rw[id] = 0.0;
-                if (with_t) a.rt[id] = 0.0;
-                if (a.hw) a.hw[id] = 0.0;
-                if (a.ht && with_t) a.ht[id] = 0.0;
+                st_out(a.rw + (id), 0.0);
+                if (with_t) st_out(a.rt + (id), 0.0);
+                if (a.hw) st_out(a.hw + (id), 0.0);
+                if (a.ht && with_t) st_out(a.ht + (id), 0.0);
             } else {
-                const double dzm = g.dz[k - 1], dzp = g.dz[k], idzc = g.o[k];   // o = 1/dzc (interior face)
+                const double dzm = m_dz[mq], dzp = m_dz[mq + 1], idzc = m_o[mq];   // o = 1/dzc (interior face)
                 // volume-weighted horizontal transport on the side faces (times 2 dzc)
                 const double uwl = dzm * L(FU, -1, 0, 0) + dzp * L(FU, 0, 0, 0);
                 const double uwr = dzm * L(FU, -1, 0, 1) + dzp * L(FU, 0, 0, 1);
@@ -246,10 +399,10 @@ __global__ void __launch_bounds__(kExTX * kExTY) k_explicit(SubstepArgs a, GridD
                 const double sx = qx * idzc, sy = qy * idzc, sz = 0.25 * idzc;
                 const double wc = L(FW, 0, 0, 0), wim = L(FW, 0, 0, -1), wip = L(FW, 0, 0, 1);
                 const double wjm = L(FW, 0, -1, 0), wjp = L(FW, 0, 1, 0);
-                const double wkm = L(FW, -1, 0, 0), wkp = L(FW, 1, 0, 0);
+                const double wkm = w_km, wkp = L(FW, 1, 0, 0);
                 const double tc = L(FT, 0, 0, 0), tim = L(FT, 0, 0, -1), tip = L(FT, 0, 0, 1);
                 const double tjm = L(FT, 0, -1, 0), tjp = L(FT, 0, 1, 0);
-                const double tkm = L(FT, -1, 0, 0), tkp = L(FT, 1, 0, 0);
+                const double tkm = t_km, tkp = L(FT, 1, 0, 0);
                 const double wtop = wc + wkp, wbot = wkm + wc;   // twice the centre values k, k-1
                 // w
                 {
@@ -257,12 +410,12 @@ __global__ void __launch_bounds__(kExTX * kExTY) k_explicit(SubstepArgs a, GridD
                     const double ay = (vwt * (wc + wjp) - vwb * (wjm + wc)) * sy;
                     const double az = (wkp - wkm) * (wtop + wbot) * sz;
                     const double h = (nux * (wip + wim - 2.0 * wc) + nuy * (wjp + wjm - 2.0 * wc) + tc) - (ax + ay + az);
-                    const double dzz = ((wkp - wc) * idzk - (wc - wkm) * g.idz[k - 1]) * idzc;
-                    const double gp = (L(FP, 0, 0, 0) - L(FP, -1, 0, 0)) * idzc;
+                    const double dzz = ((wkp - wc) * idzk - (wc - wkm) * m_idz[mq]) * idzc;
+                    const double gp = (L(FP, 0, 0, 0) - p_km) * idzc;
                     double r = cg * h - ca * gp + can * dzz;
                     if (a.rho != 0.0) r += cr * hp[2];
-                    a.rw[id] = r;
-                    if (a.hw) a.hw[id] = h;
+                    st_out(a.rw + (id), r);
+                    if (a.hw) st_out(a.hw + (id), h);
                 }
                 // T
                 if (with_t) {
@@ -270,21 +423,24 @@ __global__ void __launch_bounds__(kExTX * kExTY) k_explicit(SubstepArgs a, GridD
                     const double ay = (vwt * (tc + tjp) - vwb * (tjm + tc)) * sy;
                     const double az = (wtop * (tc + tkp) - wbot * (tkm + tc)) * sz;
                     const double h = (kax * (tip + tim - 2.0 * tc) + kay * (tjp + tjm - 2.0 * tc)) - (ax + ay + az);
-                    const double dzz = ((tkp - tc) * idzk - (tc - tkm) * g.idz[k - 1]) * idzc;
+                    const double dzz = ((tkp - tc) * idzk - (tc - tkm) * m_idz[mq]) * idzc;
                     double r = cg * h + cak * dzz;
                     if (a.rho != 0.0) r += cr * hp[3];
-                    a.rt[id] = r;
-                    if (a.ht) a.ht[id] = h;
+                    st_out(a.rt + (id), r);
+                    if (a.ht) st_out(a.ht + (id), h);
                 }
             }
             if (k + 1 == nz) {
                 const size_t top = id + plane;
-                a.rw[top] = 0.0;
-                if (with_t) a.rt[top] = 0.0;
-                if (a.hw) a.hw[top] = 0.0;
-                if (a.ht && with_t) a.ht[top] = 0.0;
+                st_out(a.rw + (top), 0.0);
+                if (with_t) st_out(a.rt + (top), 0.0);
+                if (a.hw) st_out(a.hw + (top), 0.0);
+                if (a.ht && with_t) st_out(a.ht + (top), 0.0);
             }
         }
+        w_km = w_kc;
+        t_km = t_kc;
+        p_km = p_kc;
         __syncthreads();
     }
 }
@@ -374,6 +530,24 @@ constexpr int kAdTX = PS_AD_TX, kAdTY = PS_AD_TY, kAdZSEG = 64;
 // 768^2 x 512, 18.6 -> 16.0 ms against loading each plane when needed.
 // GHV: a cotangent gH is given (the ring then cannot give lambda back, which is read along
 // the thread's column instead); without it lambda = mu / (dt gamma) comes from the ring.
+// Grid metrics of planes [k0, k0 + N) in LDS (indices outside clamp into the table; the
+// kernels use such entries only in terms that are then discarded).  Reading them from LDS
+// keeps global loads out of the steps: a vector-memory wait inside a step would also wait
+// for the next plane's prefetch.
+template <int N>
+struct ZTab {
+    double idz_[N], dz_[N], idzw_[N], o_[N];
+    __device__ __forceinline__ void fill(const GridDev& g, int k0) {
+        for (int q = threadIdx.x; q < N; q += blockDim.x) {
+            const int kc = min(max(k0 + q, 0), g.nz - 1), kf = min(max(k0 + q, 0), g.nz);
+            idz_[q] = g.idz[kc];
+            dz_[q] = g.dz[kc];
+            idzw_[q] = g.idzw[kf];
+            o_[q] = g.o[kf];
+        }
+    }
+};
+
 template <bool GHV>
 __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a, GridDev g) {
     constexpr int TX = kAdTX, TY = kAdTY, NF = 8;
@@ -381,8 +555,18 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
     constexpr int NQ = RingT::NQ;
     enum { FU, FV, FW, FT, FMU, FMV, FMW, FMT };
     __shared__ double lds[3 * NF * (TX + 2) * (TY + 2)];
+    constexpr int ZN = kAdZSEG + 5;   // planes kb - 2 .. ke + 2
+    __shared__ ZTab<ZN> zt;
     const ExTile tile = ex_tile<TX, TY, kAdZSEG>(g);
     RingT R{lds, (int)threadIdx.x % TX, (int)threadIdx.x / TX};
+    const int zk0 = tile.kb - 2;
+    zt.fill(g, zk0);
+    auto zq = [&](int kk) { const int q = kk - zk0; return q < 0 ? 0 : (q >= ZN ? ZN - 1 : q); };
+    auto m_idz = [&](int kk) { return zt.idz_[zq(kk)]; };
+    auto m_dz = [&](int kk) { return zt.dz_[zq(kk)]; };
+    auto m_idzw = [&](int kk) { return zt.idzw_[zq(kk)]; };
+    auto m_o = [&](int kk) { return zt.o_[zq(kk)]; };
+    const double idzw_lo = g.idzw[0], idzw_hi = g.idzw[g.nz];
     const typename RingT::Cols cols = RingT::columns(g, tile.i0, tile.j0);
     const int i = tile.i0 + R.tx, j = tile.j0 + R.ty;
     const bool valid = i < g.nx && j < g.ny;
@@ -400,21 +584,18 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
     // values are not touched until put() blends mu = dt gamma lambda + gH into the ring, so
     // that every load of the stage stays in flight together
     double sgh[NQ][4];
+    bool sok[NF];   // whether the staged plane exists, per field (uniform)
     auto fetch = [&](int kk, typename RingT::Stage& st) {
         const int kc = kk < 0 ? 0 : (kk > nz - 1 ? nz - 1 : kk);
         const int kf = kk < 0 ? 0 : (kk > nz ? nz : kk);
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
-            const bool ok = kk >= 0 && (kk < nz || (face[f] && kk == nz));
+            sok[f] = kk >= 0 && (kk < nz || (face[f] && kk == nz));
             const size_t po = (size_t)(face[f] ? kf : kc) * plane;
 #pragma unroll
             for (int qi = 0; qi < NQ; ++qi) {
-                const double v = F[f][po + cols.off[qi]];
-                st.v[qi][f] = ok ? v : 0.0;
-                if (f >= FMU) {
-                    const double gv = with_gh ? GH[f - FMU][po + cols.off[qi]] : 0.0;
-                    sgh[qi][f - FMU] = ok ? gv : 0.0;
-                }
+                st.v[qi][f] = F[f][po + cols.off[qi]];
+                if (f >= FMU) sgh[qi][f - FMU] = with_gh ? GH[f - FMU][po + cols.off[qi]] : 0.0;
             }
         }
     };
@@ -422,7 +603,10 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
 #pragma unroll
         for (int qi = 0; qi < NQ; ++qi)
 #pragma unroll
-            for (int f = FMU; f < NF; ++f) st.v[qi][f] = muc * st.v[qi][f] + sgh[qi][f - FMU];
+            for (int f = 0; f < NF; ++f) {
+                const double v = f >= FMU ? muc * st.v[qi][f] + sgh[qi][f - FMU] : st.v[qi][f];
+                st.v[qi][f] = sok[f] ? v : 0.0;
+            }
         R.put(kk, st);
     };
     // lambda along this thread's column (planes k - 1, k, k + 1, rotated as the block marches,
@@ -494,7 +678,11 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
         const double lvm = cv[0], lv0 = cv[1], lvp = cv[2];
         const double lwm = cw[0], lw0 = cw[1], lwp = cw[2];
         const double ltm = ct[0], lt0 = ct[1], ltp = ct[2];
-        if (k + 2 <= tile.ke) fetch(k + 2, st);
+        // the next plane's prefetch, unconditional and issued after this step's loads (a
+        // conditional one would make later waits count conservatively; the last step fetches
+        // a clamped plane it never stores)
+        asm volatile("" ::: "memory");
+        fetch(k + 2, st);
         if (valid) {
             // fields at absolute plane kk (k - 1 <= kk <= k + 1) and horizontal offsets (dj, di)
             auto U = [&](int kk, int dj, int di) { return R(k, FU, kk - k, dj, di); };
@@ -511,19 +699,19 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
             auto KV = [&](int kk, int dj, int di) { return -MV(kk, dj, di); };
             auto KW = [&](int kk, int dj, int di) { return (kk >= 1 && kk <= nz - 1) ? -MW(kk, dj, di) : 0.0; };
             auto KT = [&](int kk, int dj, int di) { return (kk >= 1 && kk <= nz - 1) ? -MT(kk, dj, di) : 0.0; };
-            auto idzc = [&](int kk) { return g.o[kk]; };   // 1/dzc at interior faces, 0 at the walls
+            auto idzc = [&](int kk) { return m_o(kk); };   // 1/dzc at interior faces, 0 at the walls
             // volume-weighted transport at (x-face or y-face, z-face kk)
             auto UW = [&](int kk, int dj, int di) {
-                return (g.dz[kk - 1] * U(kk - 1, dj, di) + g.dz[kk] * U(kk, dj, di)) * (0.5 * g.o[kk]);
+                return (m_dz(kk - 1) * U(kk - 1, dj, di) + m_dz(kk) * U(kk, dj, di)) * (0.5 * m_o(kk));
             };
             auto VW = [&](int kk, int dj, int di) {
-                return (g.dz[kk - 1] * V(kk - 1, dj, di) + g.dz[kk] * V(kk, dj, di)) * (0.5 * g.o[kk]);
+                return (m_dz(kk - 1) * V(kk - 1, dj, di) + m_dz(kk) * V(kk, dj, di)) * (0.5 * m_o(kk));
             };
             // transpose of the centre-field Dzz (dz Dzz dz^-1, Dirichlet walls) applied to lambda
             auto dzzt_c = [&](double lm, double l0, double lp) {
-                const double mc = l0 * g.idz[k];
-                const double fb = (k > 0) ? (mc - lm * g.idz[k - 1]) * g.idzw[k] : mc * g.idzw[0];
-                const double ft = (k + 1 < nz) ? (lp * g.idz[k + 1] - mc) * g.idzw[k + 1] : -mc * g.idzw[nz];
+                const double mc = l0 * m_idz(k);
+                const double fb = (k > 0) ? (mc - lm * m_idz(k - 1)) * m_idzw(k) : mc * idzw_lo;
+                const double ft = (k + 1 < nz) ? (lp * m_idz(k + 1) - mc) * m_idzw(k + 1) : -mc * idzw_hi;
                 return ft - fb;
             };
 
@@ -546,11 +734,11 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
                 }
                 // u-eq, z faces k, k+1 (interior): Q = avg u
                 if (k >= 1) {
-                    const double L = KU(k - 1, 0, 0) * g.idz[k - 1] - KU(k, 0, 0) * g.idz[k];
+                    const double L = KU(k - 1, 0, 0) * m_idz(k - 1) - KU(k, 0, 0) * m_idz(k);
                     s += 0.5 * L * 0.5 * (Wf(k, 0, 0) + Wf(k, 0, -1));
                 }
                 if (k + 1 <= nz - 1) {
-                    const double L = KU(k, 0, 0) * g.idz[k] - KU(k + 1, 0, 0) * g.idz[k + 1];
+                    const double L = KU(k, 0, 0) * m_idz(k) - KU(k + 1, 0, 0) * m_idz(k + 1);
                     s += 0.5 * L * 0.5 * (Wf(k + 1, 0, 0) + Wf(k + 1, 0, -1));
                 }
                 // v-eq, x faces at (x-face i, y-faces j and j+1): U = avg of u over y
@@ -562,7 +750,7 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
                 // w- and T-eq, x faces at (x-face i, z-faces k and k+1): volume-weighted u
                 for (int kf = k; kf <= k + 1; ++kf) {
                     if (kf < 1 || kf > nz - 1) continue;
-                    const double wt = g.dz[k] * (0.5 * g.o[kf]);
+                    const double wt = m_dz(k) * (0.5 * m_o(kf));
                     const double Lw = (KW(kf, 0, -1) - KW(kf, 0, 0)) * idx, Qw = 0.5 * (Wf(kf, 0, -1) + Wf(kf, 0, 0));
                     const double Lt = (KT(kf, 0, -1) - KT(kf, 0, 0)) * idx, Qt = 0.5 * (Tf(kf, 0, -1) + Tf(kf, 0, 0));
                     s += wt * (Lw * Qw + Lt * Qt);
@@ -571,7 +759,7 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
                 const double mc = MU(k, 0, 0);
                 const double hd = a.nu * ((MU(k, 0, 1) - 2.0 * mc + MU(k, 0, -1)) * idx2 +
                                           (MU(k, 1, 0) - 2.0 * mc + MU(k, -1, 0)) * idy2);
-                a.gu[id] = dd[0] + s + hd + cal * a.nu * dzzt_c(lum, lu0, lup);
+                st_out(a.gu + (id), dd[0] + s + hd + cal * a.nu * dzzt_c(lum, lu0, lup));
             }
             // ================= g_v at (k, j, i) =================
             {
@@ -589,11 +777,11 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
                     s += 0.5 * (Li * Ui + Lp * Up);
                 }
                 if (k >= 1) {
-                    const double L = KV(k - 1, 0, 0) * g.idz[k - 1] - KV(k, 0, 0) * g.idz[k];
+                    const double L = KV(k - 1, 0, 0) * m_idz(k - 1) - KV(k, 0, 0) * m_idz(k);
                     s += 0.5 * L * 0.5 * (Wf(k, 0, 0) + Wf(k, -1, 0));
                 }
                 if (k + 1 <= nz - 1) {
-                    const double L = KV(k, 0, 0) * g.idz[k] - KV(k + 1, 0, 0) * g.idz[k + 1];
+                    const double L = KV(k, 0, 0) * m_idz(k) - KV(k + 1, 0, 0) * m_idz(k + 1);
                     s += 0.5 * L * 0.5 * (Wf(k + 1, 0, 0) + Wf(k + 1, -1, 0));
                 }
                 // u-eq, y faces at (x-faces i and i+1, y-face j): V = avg of v over x
@@ -604,7 +792,7 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
                 }
                 for (int kf = k; kf <= k + 1; ++kf) {
                     if (kf < 1 || kf > nz - 1) continue;
-                    const double wt = g.dz[k] * (0.5 * g.o[kf]);
+                    const double wt = m_dz(k) * (0.5 * m_o(kf));
                     const double Lw = (KW(kf, -1, 0) - KW(kf, 0, 0)) * idy, Qw = 0.5 * (Wf(kf, -1, 0) + Wf(kf, 0, 0));
                     const double Lt = (KT(kf, -1, 0) - KT(kf, 0, 0)) * idy, Qt = 0.5 * (Tf(kf, -1, 0) + Tf(kf, 0, 0));
                     s += wt * (Lw * Qw + Lt * Qt);
@@ -612,19 +800,19 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
                 const double mc = MV(k, 0, 0);
                 const double hd = a.nu * ((MV(k, 0, 1) - 2.0 * mc + MV(k, 0, -1)) * idx2 +
                                           (MV(k, 1, 0) - 2.0 * mc + MV(k, -1, 0)) * idy2);
-                a.gv[id] = dd[1] + s + hd + cal * a.nu * dzzt_c(lvm, lv0, lvp);
+                st_out(a.gv + (id), dd[1] + s + hd + cal * a.nu * dzzt_c(lvm, lv0, lvp));
             }
             // ================= g_p at (k, j, i):  -dt alpha G^T lambda =================
             {
                 double gt = (lu0 - lu_ip) * idx + (lv0 - lv_jp) * idy;
-                if (k >= 1) gt += lw0 * g.o[k];
-                if (k + 1 <= nz - 1) gt -= lwp * g.o[k + 1];
-                a.gp[id] = dd[4] - cal * gt;
+                if (k >= 1) gt += lw0 * m_o(k);
+                if (k + 1 <= nz - 1) gt -= lwp * m_o(k + 1);
+                st_out(a.gp + (id), dd[4] - cal * gt);
             }
             // ================= g_w, g_T at z-face k (interior) =================
             if (k == 0) {
-                a.gw[id] = 0.0;
-                a.gt[id] = 0.0;
+                st_out(a.gw + (id), 0.0);
+                st_out(a.gt + (id), 0.0);
             } else {
                 double sw = 0.0, st_ = 0.0;
                 // w-eq z faces at centres k and k-1: F = U^2, U = avg w
@@ -655,14 +843,14 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
                 }
                 // u-eq z faces at (x-faces i, i+1; z-face k): W = avg of w over x, Q = avg of u over z
                 {
-                    const double L0 = KU(k - 1, 0, 0) * g.idz[k - 1] - KU(k, 0, 0) * g.idz[k];
-                    const double L1 = KU(k - 1, 0, 1) * g.idz[k - 1] - KU(k, 0, 1) * g.idz[k];
+                    const double L0 = KU(k - 1, 0, 0) * m_idz(k - 1) - KU(k, 0, 0) * m_idz(k);
+                    const double L1 = KU(k - 1, 0, 1) * m_idz(k - 1) - KU(k, 0, 1) * m_idz(k);
                     sw += 0.5 * (L0 * 0.5 * (U(k - 1, 0, 0) + U(k, 0, 0)) + L1 * 0.5 * (U(k - 1, 0, 1) + U(k, 0, 1)));
                 }
                 // v-eq z faces at (y-faces j, j+1; z-face k)
                 {
-                    const double L0 = KV(k - 1, 0, 0) * g.idz[k - 1] - KV(k, 0, 0) * g.idz[k];
-                    const double L1 = KV(k - 1, 1, 0) * g.idz[k - 1] - KV(k, 1, 0) * g.idz[k];
+                    const double L0 = KV(k - 1, 0, 0) * m_idz(k - 1) - KV(k, 0, 0) * m_idz(k);
+                    const double L1 = KV(k - 1, 1, 0) * m_idz(k - 1) - KV(k, 1, 0) * m_idz(k);
                     sw += 0.5 * (L0 * 0.5 * (V(k - 1, 0, 0) + V(k, 0, 0)) + L1 * 0.5 * (V(k - 1, 1, 0) + V(k, 1, 0)));
                 }
                 // linear terms: horizontal diffusion of mu, Dzz^T (faces: dzc Dzz dzc^-1) of lambda
@@ -674,14 +862,14 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
                                            (MT(k, 1, 0) - 2.0 * mtc + MT(k, -1, 0)) * idy2);
                 const double mw = lw0 * idzc(k), mwm = lwm * idzc(k - 1), mwp = lwp * idzc(k + 1);
                 const double mt = lt0 * idzc(k), mtm = ltm * idzc(k - 1), mtp = ltp * idzc(k + 1);
-                const double dzw_ = (mwp - mw) * g.idz[k] - (mw - mwm) * g.idz[k - 1];
-                const double dzt_ = (mtp - mt) * g.idz[k] - (mt - mtm) * g.idz[k - 1];
-                a.gw[id] = dd[2] + sw + hdw + cal * a.nu * dzw_;
-                a.gt[id] = dd[3] + st_ + hdt + cal * a.ka * dzt_ + mwc;
+                const double dzw_ = (mwp - mw) * m_idz(k) - (mw - mwm) * m_idz(k - 1);
+                const double dzt_ = (mtp - mt) * m_idz(k) - (mt - mtm) * m_idz(k - 1);
+                st_out(a.gw + (id), dd[2] + sw + hdw + cal * a.nu * dzw_);
+                st_out(a.gt + (id), dd[3] + st_ + hdt + cal * a.ka * dzt_ + mwc);
             }
             if (k + 1 == nz) {
-                a.gw[id + plane] = 0.0;
-                a.gt[id + plane] = 0.0;
+                st_out(a.gw + (id + plane), 0.0);
+                st_out(a.gt + (id + plane), 0.0);
             }
 
         }
