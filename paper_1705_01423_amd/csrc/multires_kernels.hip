@@ -254,27 +254,27 @@ __global__ void __launch_bounds__(kMtTX * kMtTY) k_mr_explicit_t(MrTArgs a, Grid
         off[qi] = (unsigned)gj * (unsigned)g.nx + (unsigned)gi;
     }
     const double th = a.th, th1 = 1.0 - a.th;
-    // plane kk of every field into registers, both velocity time levels as loaded (zeros
-    // outside a field); put() blends them in time into the ring, so that the loads of a stage
-    // are not waited for until the next step
+    // plane kk of every field into registers, both velocity time levels as loaded; put()
+    // blends them in time and zeroes absent planes (uniform flags) into the ring, so that the
+    // loads of a stage are not waited for until the next step
     double s0[NQ][3], s1[NQ][3], stt[NQ];
+    bool okc = false, okf = false;
     auto fetch = [&](int kk) {
         const int kc = kk < 0 ? 0 : (kk > g.nz - 1 ? g.nz - 1 : kk);
         const int kf = kk < 0 ? 0 : (kk > g.nz ? g.nz : kk);
-        const bool okc = kk >= 0 && kk < g.nz, okf = kk >= 0 && kk <= g.nz;
+        okc = kk >= 0 && kk < g.nz;
+        okf = kk >= 0 && kk <= g.nz;
         const size_t pc = (size_t)kc * plane, pf = (size_t)kf * plane;
 #pragma unroll
         for (int qi = 0; qi < NQ; ++qi) {
             const size_t oc = pc + off[qi], of = pf + off[qi];
-            const double u0 = a.u0[oc], u1 = a.u1[oc], v0 = a.v0[oc], v1 = a.v1[oc];
-            const double w0 = a.w0[of], w1 = a.w1[of], tt = a.t[of];
-            s0[qi][FU] = okc ? u0 : 0.0;
-            s1[qi][FU] = okc ? u1 : 0.0;
-            s0[qi][FV] = okc ? v0 : 0.0;
-            s1[qi][FV] = okc ? v1 : 0.0;
-            s0[qi][FW] = okf ? w0 : 0.0;
-            s1[qi][FW] = okf ? w1 : 0.0;
-            stt[qi] = okf ? tt : 0.0;
+            s0[qi][FU] = a.u0[oc];
+            s1[qi][FU] = a.u1[oc];
+            s0[qi][FV] = a.v0[oc];
+            s1[qi][FV] = a.v1[oc];
+            s0[qi][FW] = a.w0[of];
+            s1[qi][FW] = a.w1[of];
+            stt[qi] = a.t[of];
         }
     };
     auto put = [&](int kk) {
@@ -284,11 +284,24 @@ __global__ void __launch_bounds__(kMtTX * kMtTY) k_mr_explicit_t(MrTArgs a, Grid
             const int q = (int)threadIdx.x + qi * TX * TY;
             if (q < PL) {
 #pragma unroll
-                for (int f = 0; f < 3; ++f) lds[(sl * NF + f) * PL + q] = th1 * s0[qi][f] + th * s1[qi][f];
-                lds[(sl * NF + FT) * PL + q] = stt[qi];
+                for (int f = 0; f < 3; ++f) {
+                    const bool ok = f == FW ? okf : okc;
+                    lds[(sl * NF + f) * PL + q] = ok ? th1 * s0[qi][f] + th * s1[qi][f] : 0.0;
+                }
+                lds[(sl * NF + FT) * PL + q] = okf ? stt[qi] : 0.0;
             }
         }
     };
+    // the segment's grid metrics (cell planes kb - 1 .. ke, face planes kb .. ke + 1) in LDS:
+    // a global load inside a step would make the wave wait for the next plane's prefetch too
+    constexpr int ZT = kMtZSEG + 2;
+    __shared__ double m_idz[ZT], m_dz[ZT], m_o[ZT];
+    for (int q = threadIdx.x; q < ZT; q += TX * TY) {
+        const int kc = min(max(kb - 1 + q, 0), g.nz - 1), kf = min(kb + q, g.nz);
+        m_idz[q] = g.idz[kc];
+        m_dz[q] = g.dz[kc];
+        m_o[q] = g.o[kf];
+    }
     const double idx = 1.0 / g.dx, idy = 1.0 / g.dy;
     const double idx2 = idx * idx, idy2 = idy * idy;
     const int nz = g.nz;
@@ -301,16 +314,19 @@ __global__ void __launch_bounds__(kMtTX * kMtTY) k_mr_explicit_t(MrTArgs a, Grid
         put(k + 1);
         __syncthreads();
         const size_t id = (size_t)k * plane + (size_t)j * g.nx + i;
-        double hp = 0.0;
-        if (a.rho != 0.0) hp = a.hp[valid ? id : (size_t)k * plane];
-        if (k + 2 <= ke) fetch(k + 2);
+        // previous H (substep 1 reads T in its place and drops it), then the next plane's
+        // prefetch, both unconditional (the last step fetches a clamped plane it never stores)
+        const double hp = (a.rho != 0.0 ? a.hp : a.t)[valid ? id : (size_t)k * plane];
+        asm volatile("" ::: "memory");
+        fetch(k + 2);
         if (valid) {
             auto L = [&](int f, int dk, int dj, int di) { return R(k, f, dk, dj, di); };
             if (k == 0) {
                 a.rt[id] = 0.0;
                 if (a.hout) a.hout[id] = 0.0;
             } else {
-                const double dzm = g.dz[k - 1], dzp = g.dz[k], den = 0.5 * g.o[k];
+                const int mq = k - kb;   // tables: cell plane k - 1 at mq, face k at mq
+                const double dzm = m_dz[mq], dzp = m_dz[mq + 1], den = 0.5 * m_o[mq];
                 const double uwl = (dzm * L(FU, -1, 0, 0) + dzp * L(FU, 0, 0, 0)) * den;
                 const double uwr = (dzm * L(FU, -1, 0, 1) + dzp * L(FU, 0, 0, 1)) * den;
                 const double vwb = (dzm * L(FV, -1, 0, 0) + dzp * L(FV, 0, 0, 0)) * den;
@@ -319,17 +335,17 @@ __global__ void __launch_bounds__(kMtTX * kMtTY) k_mr_explicit_t(MrTArgs a, Grid
                 const double tc = L(FT, 0, 0, 0), tim = L(FT, 0, 0, -1), tip = L(FT, 0, 0, 1);
                 const double tjm = L(FT, 0, -1, 0), tjp = L(FT, 0, 1, 0);
                 const double tkm = L(FT, -1, 0, 0), tkp = L(FT, 1, 0, 0);
-                const double idzc = g.o[k];
+                const double idzc = m_o[mq];
                 const double wtop = 0.5 * (wc + wkp), wbot = 0.5 * (wkm + wc);
                 const double ax = (uwr * (0.5 * (tc + tip)) - uwl * (0.5 * (tim + tc))) * idx;
                 const double ay = (vwt * (0.5 * (tc + tjp)) - vwb * (0.5 * (tjm + tc))) * idy;
                 const double az = (wtop * (0.5 * (tc + tkp)) - wbot * (0.5 * (tkm + tc))) * idzc;
                 const double h = -(ax + ay + az) + a.ka * ((tip - 2.0 * tc + tim) * idx2 + (tjp - 2.0 * tc + tjm) * idy2);
-                const double dzz = ((tkp - tc) * g.idz[k] - (tc - tkm) * g.idz[k - 1]) * idzc;
+                const double dzz = ((tkp - tc) * m_idz[mq + 1] - (tc - tkm) * m_idz[mq]) * idzc;
                 double r = a.gam * h + a.alp * (a.ka * dzz);
                 if (a.rho != 0.0) r += a.rho * hp;
-                a.rt[id] = a.dt * r;
-                if (a.hout) a.hout[id] = h;
+                __builtin_nontemporal_store(a.dt * r, a.rt + id);
+                if (a.hout) __builtin_nontemporal_store(h, a.hout + id);
             }
             if (k + 1 == nz) {
                 a.rt[id + plane] = 0.0;
