@@ -207,8 +207,8 @@ __host__ __device__ constexpr int plan_ls(RadixPlan p, int i) {
 
 // elements per thread: the largest E <= emax dividing n for which a schedule exists
 __host__ __device__ constexpr int choose_e(int n, int emax) {
-    const int cand[9] = {16, 12, 8, 6, 4, 3, 2, 1, 1};
-    for (int i = 0; i < 8; ++i) {
+    const int cand[9] = {32, 16, 12, 8, 6, 4, 3, 2, 1};
+    for (int i = 0; i < 9; ++i) {
         int e = cand[i];
         if (e <= emax && n % e == 0 && make_plan(n, e).np > 0) return e;
     }
@@ -306,6 +306,71 @@ __device__ __forceinline__ void fft_run(int t, cx<T>* base, int stride, const cx
 #pragma unroll
             for (int m = 0; m < r; ++m) v[b * r + m] = base[lds_pad(t + b * NT + m * (N / r)) * stride];
         }
+        pass_compute<T, N, EMAX, S, I>(v, t, tw);
+    });
+    {
+        constexpr int r = Sh::P.r[NP - 1];
+        constexpr int Ls = plan_ls(Sh::P, NP - 1);
+        static_assert(Ls * r == N, "schedule");
+#pragma unroll
+        for (int b = 0; b < E / r; ++b) {
+#pragma unroll
+            for (int m = 0; m < r; ++m) st(t + b * NT + m * Ls, v[b * r + m]);
+        }
+    }
+}
+
+// The same transform with the LDS exchange done in two halves, real parts then imaginary
+// parts, through a T (not cx<T>) scratch of lds_len(N) slots per transform: half the LDS,
+// two more barriers per exchange.
+template <typename T, int N, int EMAX, int S, class Ld, class St>
+__device__ __forceinline__ void fft_run_split(int t, T* base, int stride, const cx<T>* __restrict__ tw, Ld&& ld,
+                                              St&& st) {
+    using Sh = FftShape<N, EMAX>;
+    constexpr int E = Sh::E;
+    constexpr int NT = Sh::NT;
+    constexpr int NP = Sh::NP;
+    cx<T> v[E];
+    {
+        constexpr int r = Sh::P.r[0];
+#pragma unroll
+        for (int b = 0; b < E / r; ++b) {
+#pragma unroll
+            for (int m = 0; m < r; ++m) v[b * r + m] = ld(t + b * NT + m * (N / r));
+        }
+    }
+    pass_compute<T, N, EMAX, S, 0>(v, t, tw);
+    static_for<1, NP>([&](auto ic) {
+        constexpr int I = decltype(ic)::value;
+        constexpr int rp = Sh::P.r[I - 1];
+        constexpr int Lp = plan_ls(Sh::P, I - 1);
+        constexpr int r = Sh::P.r[I];
+        // half q = 0: real parts, q = 1: imaginary parts; each value is read back into the
+        // same component it came from, the other component still holding the old order
+        static_for<0, 2>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            __syncthreads();
+#pragma unroll
+            for (int b = 0; b < E / rp; ++b) {
+                const int j = t + b * NT;
+                const int k = j % Lp;
+                const int o0 = (j - k) * rp + k;
+#pragma unroll
+                for (int m = 0; m < rp; ++m) base[lds_pad(o0 + m * Lp) * stride] = q == 0 ? v[b * rp + m].x : v[b * rp + m].y;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int b = 0; b < E / r; ++b) {
+#pragma unroll
+                for (int m = 0; m < r; ++m) {
+                    const T x = base[lds_pad(t + b * NT + m * (N / r)) * stride];
+                    if (q == 0)
+                        v[b * r + m].x = x;
+                    else
+                        v[b * r + m].y = x;
+                }
+            }
+        });
         pass_compute<T, N, EMAX, S, I>(v, t, tw);
     });
     {

@@ -95,18 +95,30 @@ struct XShape {
     static constexpr size_t LDS = (size_t)R * LROW * sizeof(cx<T>);
 };
 
+// FP64 inverse y transforms of columns of 512 or 1024: 32 elements per thread and the LDS
+// exchange in two halves (real, then imaginary parts), so that a whole tile takes half the
+// LDS (70 KB) and two blocks share a CU: one block's arithmetic then runs under the other's
+// loads.  (A single block per CU alternates the two; its arithmetic was exposed.)
+#ifndef PS_Y_SPLIT_INV
+#define PS_Y_SPLIT_INV 1
+#endif
+
 // Columns of one block (a power of two dividing the tile width).
-template <typename T, int N>
+template <typename T, int N, int S = -1>
 struct YShape {
-    using Sh = FftShape<N, kYEmax>;
+    static constexpr bool SPLIT = S > 0 && PS_Y_SPLIT_INV && sizeof(T) == 8 && (N == 512 || N == 1024) &&
+                                  choose_e(N, 32) == 32;
+    static constexpr int EMAX = SPLIT ? 32 : kYEmax;
+    using Sh = FftShape<N, EMAX>;
     static constexpr int NT = Sh::NT;
     static constexpr int W = TileW<T>::value;
-    static constexpr int A = PS_Y_LDS / (lds_len(N) * (int)sizeof(cx<T>));
-    static constexpr int B = PS_Y_THREADS / NT;
+    static constexpr int EB = SPLIT ? (int)sizeof(T) : (int)sizeof(cx<T>);   // bytes of one LDS slot
+    static constexpr int A = SPLIT ? W : PS_Y_LDS / (lds_len(N) * EB);
+    static constexpr int B = SPLIT ? W : PS_Y_THREADS / NT;
     static constexpr int WY0 = (W < A ? W : A) < B ? (W < A ? W : A) : B;
     static constexpr int WY = WY0 >= 16 ? 16 : (WY0 >= 8 ? 8 : (WY0 >= 4 ? 4 : (WY0 >= 2 ? 2 : 1)));
     static constexpr int THREADS = WY * NT;
-    static constexpr size_t LDS = (size_t)lds_len(N) * WY * sizeof(cx<T>);
+    static constexpr size_t LDS = (size_t)lds_len(N) * WY * EB;
 };
 
 // ---------------------------------------------------------------------------
@@ -459,10 +471,10 @@ k_xinv(const cx<T>* __restrict__ in, double* __restrict__ out, int nrows, int ny
 // ---------------------------------------------------------------------------
 // fwd = 1: a -> b (forward transform), fwd = 0: b -> a (inverse transform)
 template <typename T, int N, int S>
-__global__ void __launch_bounds__((YShape<T, N>::THREADS))
+__global__ void __launch_bounds__((YShape<T, N, S>::THREADS))
 k_yfft(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int nzs, int nkxb,
        const cx<T>* __restrict__ tw) {
-    using Y = YShape<T, N>;
+    using Y = YShape<T, N, S>;
     constexpr int NT = Y::NT, WY = Y::WY, W = TileW<T>::value;
     constexpr int NSUB = W / WY;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -502,7 +514,10 @@ k_yfft(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int nzs, int nkxb,
         else
             st_stream<PS_NT_YI_STORE>(out + abase + (size_t)e * W, val);
     };
-    fft_run<T, N, kYEmax, S>(t, smem + c, WY, tw, ld, st);
+    if constexpr (Y::SPLIT)
+        fft_run_split<T, N, Y::EMAX, S>(t, reinterpret_cast<T*>(smem_raw) + c, WY, tw, ld, st);
+    else
+        fft_run<T, N, kYEmax, S>(t, smem + c, WY, tw, ld, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -581,7 +596,7 @@ static hipError_t xinv_launch_t(const GridDev& g, const SpecDev<T>& s, double* o
 
 template <typename T, int N, int S>
 static hipError_t yfft_launch_t(const GridDev& g, const SpecDev<T>& s, hipStream_t st) {
-    using Y = YShape<T, N>;
+    using Y = YShape<T, N, S>;
     constexpr int NSUB = TileW<T>::value / Y::WY;
     const int nzl = s.nzc > 0 ? s.nzc : g.nz;
     const int nblk = nzl * s.nkxb * NSUB;
