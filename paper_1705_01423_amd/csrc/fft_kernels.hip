@@ -145,9 +145,6 @@ struct ResidIn {
 #ifndef PS_XF_WPE
 #define PS_XF_WPE 1
 #endif
-#ifndef PS_XR_GROUP
-#define PS_XR_GROUP 1
-#endif
 #ifndef PS_XR_WPE
 #define PS_XR_WPE 1
 #endif
@@ -226,29 +223,49 @@ k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny,
     const double* xjm = RESID ? rin.x + (size_t)zg * plane + (size_t)(yr == 0 ? ny - 1 : yr - 1) * (2 * M) : nullptr;
     const double* xjp = RESID ? rin.x + (size_t)zg * plane + (size_t)(yr + 1 == ny ? 0 : yr + 1) * (2 * M) : nullptr;
     const double mu = RESID ? rin.mu[0] * rin.mu_scale : 0.0;
-    int rgroup = 0;   // residual loader: elements formed so far (a compile-time count once unrolled)
-    double2 rpend[PS_XR_GROUP];
+    // Residual loader: the stencil of the next element (in the order the transform asks for
+    // them) is requested before this element's values are used, so that two elements'
+    // loads are in flight at a time; each element's value is formed before the next call
+    // (an empty asm reads it), which keeps one element's stencil per register set.
+    struct RawR {
+        double2 f, c, a, b, qu, qd;
+        double xl, xr;
+    };
+    const bool up = zg + 1 < g.nz, dn = zg > 0;
+    // a missing neighbour's coefficient is zero (its difference is zero too), so the sums
+    // are those of the present terms alone
+    const double ou = RESID && up ? g.o[zg + 1] : 0.0, od = RESID && dn ? g.o[zg] : 0.0;
+    const double iz = RESID ? g.idz[zg] : 0.0;
+    auto rload = [&](int e, RawR& r) {
+        const int n = 2 * M;
+        r.f = ld_stream2<PS_NT_XF>(frow + 2 * e);
+        r.c = *reinterpret_cast<const double2*>(xrow + 2 * e);
+        // periodic x neighbours and the z neighbours (the row itself stands in for a missing
+        // one; its term is dropped), addressed by index arithmetic so that every load is
+        // unconditional
+        const int il = 2 * e - 1 + (int)(e == 0) * n;
+        const int ir = 2 * e + 2 - (int)(2 * e + 2 == n) * n;
+        r.xl = xrow[il];
+        r.xr = xrow[ir];
+        r.a = *reinterpret_cast<const double2*>(xjm + 2 * e);
+        r.b = *reinterpret_cast<const double2*>(xjp + 2 * e);
+        r.qu = *reinterpret_cast<const double2*>(xrow + (size_t)up * plane + 2 * e);
+        r.qd = *reinterpret_cast<const double2*>(xrow - (size_t)dn * plane + 2 * e);
+    };
+    using ShX = FftShape<M, X::EM>;
+    constexpr int R0 = ShX::P.r[0];
+    auto elem_of = [&](int q) { return t + (q / R0) * NT + (q % R0) * (M / R0); };
+    RawR rcur, rnxt;
+    int rcall = 0;   // residual loader calls so far (a compile-time count once unrolled)
     auto ld = [&](int e) -> cx<T> {
         double2 v = {0.0, 0.0};
-        if constexpr (LM != XL_DIV) v = ld_stream2<PS_NT_XF>(frow + 2 * e);
+        if constexpr (LM == XL_PLAIN) v = ld_stream2<PS_NT_XF>(frow + 2 * e);
         if constexpr (RESID) {
-            const int n = 2 * M;
-            const double2 c = *reinterpret_cast<const double2*>(xrow + 2 * e);
-            // periodic x neighbours and the z neighbours (the row itself stands in for a
-            // missing one; its term is dropped), addressed by index arithmetic so that every
-            // load is unconditional
-            const int il = 2 * e - 1 + (int)(e == 0) * n;
-            const int ir = 2 * e + 2 - (int)(2 * e + 2 == n) * n;
-            const double xl = xrow[il];
-            const double xr = xrow[ir];
-            const double2 a = *reinterpret_cast<const double2*>(xjm + 2 * e);
-            const double2 b = *reinterpret_cast<const double2*>(xjp + 2 * e);
-            const bool up = zg + 1 < g.nz, dn = zg > 0;
-            const double2 qu = *reinterpret_cast<const double2*>(xrow + (size_t)up * plane + 2 * e);
-            const double2 qd = *reinterpret_cast<const double2*>(xrow - (size_t)dn * plane + 2 * e);
-            // a missing neighbour's coefficient is zero (its difference is zero too), so the
-            // sums are those of the present terms alone
-            const double ou = up ? g.o[zg + 1] : 0.0, od = dn ? g.o[zg] : 0.0, iz = g.idz[zg];
+            if (rcall == 0) rload(e, rcur);
+            if (rcall + 1 < ShX::E) rload(elem_of(rcall + 1), rnxt);
+            v = rcur.f;
+            const double2 c = rcur.c, a = rcur.a, b = rcur.b, qu = rcur.qu, qd = rcur.qd;
+            const double xl = rcur.xl, xr = rcur.xr;
             const double idx2 = 1.0 / (g.dx * g.dx), idy2 = 1.0 / (g.dy * g.dy);
             double lz0 = 0.0, lz1 = 0.0;
             lz0 += (qu.x - c.x) * ou;
@@ -263,14 +280,9 @@ k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny,
             acc0 += v.x * v.x + v.y * v.y;
             acc1 += valid ? f0 * f0 + f1 * f1 : 0.0;
             accs += v.x + v.y;
-            // the values of every PS_XR_GROUP elements are formed at the group's end (an empty
-            // asm reads them): the loads of one group are in flight together; without it every
-            // element's stencil is hoisted at once and held in registers (one wave per SIMD)
-            rpend[rgroup % PS_XR_GROUP] = v;
-            if (++rgroup % PS_XR_GROUP == 0) {
-#pragma unroll
-                for (int q = 0; q < PS_XR_GROUP; ++q) asm volatile("" : "+v"(rpend[q].x), "+v"(rpend[q].y));
-            }
+            asm volatile("" : "+v"(v.x), "+v"(v.y));
+            rcur = rnxt;
+            ++rcall;
         } else if constexpr (LM == XL_DIV) {
             // f = (D u*) / s at the cells (2e, 2e + 1) of row (z, y): periodic x and y, w at z-faces
             const int n = 2 * M;
