@@ -134,7 +134,7 @@ __device__ __forceinline__ Aff<T> shfl_down_aff(const Aff<T>& m, int d) {
 #define PS_Z_ROWS64 16
 #endif
 #ifndef PS_Z_ROWS32
-#define PS_Z_ROWS32 8
+#define PS_Z_ROWS32 16
 #endif
 #ifndef PS_Z_COLS64
 #define PS_Z_COLS64 8
@@ -419,11 +419,14 @@ k_zsolve_scan(const cx<T>* b, cx<T>* bo, const T* __restrict__ etab, int nz, int
 // the other half of a double LDS buffer by global->LDS copies (1 KB per wave
 // instruction), so every CU keeps a tile of loads in flight through the solve.  The
 // scans' barriers are LDS-only so that they do not wait for those copies.
-// Measured at 1024^2 x 512: FP32 z solve 1.36 -> 1.03 ms; in FP64 the solve work of
-// the streaming blocks is the limit (1.92 ms register-tile kernel against 1.98 ms with a
-// double buffer and 2.14 ms with one buffer and two blocks per CU), so it is not used there.
+// Measured at 1024^2 x 512: FP32 z solve 1.36 -> 1.03 ms against the register-tile kernel
+// of that time; in FP64 the solve work of the streaming blocks is the limit (1.92 ms
+// register-tile kernel against 1.98 ms with a double buffer and 2.14 ms with one buffer and
+// two blocks per CU).  Since the register-tile kernel reads and writes non-temporally with 16
+// rows per lane it is faster in both precisions (FP32 0.82 ms against 1.03 ms streamed), so
+// the streamed kernel is off by default (kept, and selectable, for measurement).
 #ifndef PS_Z_PIPE32
-#define PS_Z_PIPE32 1
+#define PS_Z_PIPE32 0
 #endif
 #ifndef PS_Z_PIPE64
 #define PS_Z_PIPE64 0
