@@ -98,7 +98,7 @@ __device__ __forceinline__ void st_stream2(double* p, double2 v) {
 #define PS_NT_YI_LOAD64 1
 #endif
 #ifndef PS_NT_YI_LOAD32
-#define PS_NT_YI_LOAD32 0
+#define PS_NT_YI_LOAD32 1
 #endif
 #ifndef PS_NT_YI_STORE
 #define PS_NT_YI_STORE 1
