@@ -18,6 +18,10 @@
 
 namespace ps {
 
+// Stores of the prolonged velocity: non-temporal (the fine fields are several times the
+// caches and are read again only by the temperature steps; 768^2 x 512: 3.40 -> 3.29 ms).
+__device__ __forceinline__ void mr_st(double* p, double v) { __builtin_nontemporal_store(v, p); }
+
 namespace {
 __device__ __forceinline__ double sq(double a) { return a * a; }
 }  // namespace
@@ -173,9 +177,9 @@ k_mr_prolong(const double* __restrict__ u, const double* __restrict__ v, const d
             const size_t row = (size_t)(k * RZ + c) * NYX + (size_t)(j * RY + b) * NX + (size_t)i * RX;
 #pragma unroll
             for (int a = 0; a < RX; ++a) {
-                uf[row + a] = fu[a][b][c];
-                vf[row + a] = fv[a][b][c];
-                wf[row + a] = fw[a][b][c];
+                mr_st(uf + row + a, fu[a][b][c]);
+                mr_st(vf + row + a, fv[a][b][c]);
+                mr_st(wf + row + a, fw[a][b][c]);
             }
         }
     if (!hi) {
@@ -183,7 +187,7 @@ k_mr_prolong(const double* __restrict__ u, const double* __restrict__ v, const d
         for (int b = 0; b < RY; ++b) {
             const size_t row = (size_t)(nz * RZ) * NYX + (size_t)(j * RY + b) * NX + (size_t)i * RX;
 #pragma unroll
-            for (int a = 0; a < RX; ++a) wf[row + a] = fw[a][b][RZ];
+            for (int a = 0; a < RX; ++a) mr_st(wf + row + a, fw[a][b][RZ]);
         }
     }
 }

@@ -530,7 +530,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // FP64 plane sums from the x transform's row sums: one block per plane, a fixed
 // summation order (the same result on every run).
-__global__ void __launch_bounds__(256) k_plane_sums(const double* __restrict__ rowsum, int ny,
+__global__ void __launch_bounds__(256) k_rows_to_planes(const double* __restrict__ rowsum, int ny,
                                                     double* __restrict__ psum) {
     __shared__ double red[4];
     const int z = blockIdx.x;
@@ -787,7 +787,7 @@ hipError_t launch_zexcess(const GridDev& g, int nkxb, T* etab, hipStream_t st) {
 template <typename T>
 hipError_t launch_zsolve00(const GridDev& g, const SpecDev<T>& s, double* defect, hipStream_t st) {
     if (s.rowsum) {
-        hipLaunchKernelGGL(k_plane_sums, dim3(g.nz), dim3(256), 0, st, s.rowsum, g.ny, s.psum);
+        hipLaunchKernelGGL(k_rows_to_planes, dim3(g.nz), dim3(256), 0, st, s.rowsum, g.ny, s.psum);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
