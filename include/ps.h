@@ -272,7 +272,7 @@ ps_status rk3_substep_adjoint(ps_plan_t plan, int l, double dt, double nu, doubl
  * (Sec. 2.1) are recomputed from the input state (u, v, w, t, p, not
  * modified), then their adjoints run in reverse, each handing the cotangent
  * of H^l down to substep l.  g_out[0..4]: cotangents of the step's output
- * state; g_in[0..4] receive those of its input.  Allocates 28 field-sized
+ * state; g_in[0..4] receive those of its input.  Allocates 32 field-sized
  * temporaries in the plan on first use.  Returns PS_ENOTCONVERGED (outputs
  * written) when a refinement stopped above the tolerance.
  */

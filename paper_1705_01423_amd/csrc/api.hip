@@ -305,6 +305,23 @@ const double kRho[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
 // Crank-Nicolson factor slots (3 (nz+1) doubles each): 0 centre, 1 face, 2 face (diffusivity)
 double* cn_slot(ps_plan_t p, int s) { return p->cnfac + (size_t)s * 3 * (p->nz + 1); }
 
+// Factors of a substep's three Crank-Nicolson operators (one launch): slot 0 the velocity's
+// centre rows, slot 1 its face rows (w), slot 2 the temperature's face rows.
+hipError_t substep_factors(ps_plan_t p, double bnu, double bka, hipStream_t st) {
+    CnFactorJobs fj{};
+    fj.fac[0] = cn_slot(p, 0);
+    fj.beta[0] = bnu;
+    fj.kind[0] = PS_CENTER;
+    fj.fac[1] = cn_slot(p, 1);
+    fj.beta[1] = bnu;
+    fj.kind[1] = PS_FACE;
+    fj.fac[2] = cn_slot(p, 2);
+    fj.beta[2] = bka;
+    fj.kind[2] = PS_FACE;
+    fj.n = 3;
+    return launch_cn_factor(p->gd, fj, st);
+}
+
 constexpr int kSubFields = 8;
 
 // Field-sized temporaries of the substep and its adjoint, allocated on first use.
@@ -331,6 +348,11 @@ struct DivSrc {
     const double* v;
     const double* w;
     double scale;
+    // projection adjoint: (u, v, w) are the velocity cotangents, gp the pressure's (or NULL),
+    // scale = 1/s, and c the pressure update's Dzz weight
+    bool adjoint;
+    const double* gp;
+    double c;
 };
 
 // One spectral solve with the plan's kernels at precision T:
@@ -369,7 +391,8 @@ ps_status spectral_solve(ps_plan_t p, const double* in, double* out, int mode, c
                    "x forward FFT (residual)");
         else if (div)
             PS_HIP(launch_xfwd_div<T>(g, sc, div->u, div->v, div->w, div->scale,
-                                      want_wsum ? p->partial + (size_t)nbx : nullptr, st),
+                                      want_wsum ? p->partial + (size_t)nbx : nullptr, st, div->adjoint, div->gp,
+                                      div->c),
                    "x forward FFT (divergence)");
         else
             PS_HIP(launch_xfwd<T>(g, sc, in, zin, want_wsum ? p->partial + (size_t)nbx : nullptr, st),
@@ -592,18 +615,19 @@ ps_status substep_impl(ps_plan_t p, int l, double dt, double nu, double kappa, d
     a.gam = gam;
     a.rho = rho;
     a.alp = alp;
-    PS_HIP(launch_explicit(p->gd, a, st), "explicit terms");
     const double bnu = alp * dt * nu / 2.0, bka = alp * dt * kappa / 2.0;
-    double* fc = cn_slot(p, 0);
-    double* ff = cn_slot(p, 1);
-    double* fk = cn_slot(p, 2);
-    PS_HIP(launch_cn_factor(p->gd, PS_CENTER, bnu, fc, st), "cn factor");
-    PS_HIP(launch_cn_factor(p->gd, PS_FACE, bnu, ff, st), "cn factor");
-    PS_HIP(launch_cn_factor(p->gd, PS_FACE, bka, fk, st), "cn factor");
-    PS_HIP(launch_cn_solve_add(p->gd, PS_CENTER, fc, ru, u, st), "cn solve u");
-    PS_HIP(launch_cn_solve_add(p->gd, PS_CENTER, fc, rv, v, st), "cn solve v");
-    PS_HIP(launch_cn_solve_add(p->gd, PS_FACE, ff, rw, w, st), "cn solve w");
-    if (advance_t) PS_HIP(launch_cn_solve_add(p->gd, PS_FACE, fk, rt, t, st), "cn solve T");
+    a.bnu = bnu;
+    a.bka = bka;
+    PS_HIP(launch_explicit(p->gd, a, st), "explicit terms");
+    // the explicit kernel wrote s = C q + rhs: q* = C^-1 s, all fields in one launch
+    PS_HIP(substep_factors(p, bnu, bka, st), "cn factor");
+    CnJobs jobs{};
+    jobs.j[0] = CnJob{cn_slot(p, 0), ru, u, nullptr, 0.0, PS_CENTER};
+    jobs.j[1] = CnJob{cn_slot(p, 0), rv, v, nullptr, 0.0, PS_CENTER};
+    jobs.j[2] = CnJob{cn_slot(p, 1), rw, w, nullptr, 0.0, PS_FACE};
+    jobs.j[3] = CnJob{cn_slot(p, 2), rt, t, nullptr, 0.0, PS_FACE};
+    jobs.n = advance_t ? 4 : 3;
+    PS_HIP(launch_cn_jobs(p->gd, CN_PUT, jobs, st), "cn solves");
     return project(p, u, v, w, pr, nullptr, alp * dt, bnu, stream, info);
 }
 
@@ -847,7 +871,7 @@ ps_status project(ps_plan_t p, double* u, double* v, double* w, double* pr, doub
     ps_status r;
     if (p->prec == PS_FP64 && !(p->flags & (PS_FLAG_CHECK_FINITE | PS_FLAG_STRICT_COMPAT))) {
         // the divergence is formed inside the x transform and never stored
-        const DivSrc d{u, v, w, 1.0 / s};
+        const DivSrc d{u, v, w, 1.0 / s, false, nullptr, 0.0};
         r = solve_impl(p, nullptr, phi, nullptr, nullptr, st, info, &d);
     } else {
         // the refinement's residual (and the finiteness and compatibility checks) need the
@@ -880,8 +904,15 @@ ps_status project_adjoint(ps_plan_t p, const double* g_u, const double* g_v, con
         for (const void* b : outs)
             if (a && a == b) return fail(PS_EINVAL, "outputs may not alias inputs");
     hipStream_t st = (hipStream_t)stream;
-    PS_HIP(launch_adj_rhs(p->gd, g_u, g_v, g_w, g_p, p->fbuf, 1.0 / s, c, st), "adjoint rhs");
-    ps_status r = solve_impl(p, p->fbuf, p->phibuf, nullptr, nullptr, st, info);
+    ps_status r;
+    if (p->prec == PS_FP64 && !(p->flags & (PS_FLAG_CHECK_FINITE | PS_FLAG_STRICT_COMPAT))) {
+        // the solve's right-hand side is formed inside the x transform and never stored
+        const DivSrc d{g_u, g_v, g_w, 1.0 / s, true, g_p, c};
+        r = solve_impl(p, nullptr, p->phibuf, nullptr, nullptr, st, info, &d);
+    } else {
+        PS_HIP(launch_adj_rhs(p->gd, g_u, g_v, g_w, g_p, p->fbuf, 1.0 / s, c, st), "adjoint rhs");
+        r = solve_impl(p, p->fbuf, p->phibuf, nullptr, nullptr, st, info);
+    }
     if (r != PS_OK && r != PS_ENOTCONVERGED) return r;
     PS_HIP(launch_adj_update(p->gd, g_u, g_v, g_w, p->phibuf, gu_star, gv_star, gw_star, st), "adjoint update");
     return r;
@@ -895,7 +926,12 @@ ps_status cn_solve(ps_plan_t p, int kind, double beta, double* x, void* stream) 
     if (!(beta >= 0) || !std::isfinite(beta)) return fail(PS_EINVAL, "beta must be non-negative");
     hipStream_t st = (hipStream_t)stream;
     double* fac = cn_slot(p, kind == PS_CENTER ? 0 : 1);
-    PS_HIP(launch_cn_factor(p->gd, kind, beta, fac, st), "cn factor");
+    CnFactorJobs fj{};
+    fj.fac[0] = fac;
+    fj.beta[0] = beta;
+    fj.kind[0] = kind;
+    fj.n = 1;
+    PS_HIP(launch_cn_factor(p->gd, fj, st), "cn factor");
     PS_HIP(launch_cn_solve(p->gd, kind, fac, x, st), "cn solve");
     return PS_OK;
 }
@@ -1036,16 +1072,26 @@ ps_status rk3_substep_adjoint(ps_plan_t p, int l, double dt, double nu, double k
     ps_status r = project_adjoint(p, g_out[0], g_out[1], g_out[2], g_out[4], du, dv, dw, alp * dt, bnu, stream, info);
     if (r != PS_OK && r != PS_ENOTCONVERGED) return r;
     // Crank-Nicolson solves (linear): cotangents of the right-hand sides
-    double* fc = cn_slot(p, 0);
-    double* ff = cn_slot(p, 1);
-    double* fk = cn_slot(p, 2);
-    PS_HIP(launch_cn_factor(p->gd, PS_CENTER, bnu, fc, st), "cn factor");
-    PS_HIP(launch_cn_factor(p->gd, PS_FACE, bnu, ff, st), "cn factor");
-    PS_HIP(launch_cn_factor(p->gd, PS_FACE, bka, fk, st), "cn factor");
-    PS_HIP(launch_cn_solve_t(p->gd, PS_CENTER, fc, du, lu, st), "cn adjoint u");
-    PS_HIP(launch_cn_solve_t(p->gd, PS_CENTER, fc, dv, lv, st), "cn adjoint v");
-    PS_HIP(launch_cn_solve_t(p->gd, PS_FACE, ff, dw, lw, st), "cn adjoint w");
-    PS_HIP(launch_cn_solve_t(p->gd, PS_FACE, fk, g_out[3], lt, st), "cn adjoint T");
+    // The previous substep's H enters the right-hand sides as dt rho H^{l-1}: its cotangent is
+    // dt rho lambda, written by the same launch unless it shares memory with g_hout (which the
+    // explicit adjoint below still reads; then it is scaled after that kernel).
+    bool hprev_shared = false;
+    if (g_hprev && g_hout)
+        for (int q = 0; q < 4; ++q)
+            for (int r = 0; r < 4; ++r) hprev_shared |= (const void*)g_hprev[q] == (const void*)g_hout[r];
+    const bool hprev_fused = g_hprev && !hprev_shared;
+    double* h2[4] = {nullptr, nullptr, nullptr, nullptr};
+    if (hprev_fused)
+        for (int q = 0; q < 4; ++q) h2[q] = g_hprev[q];
+    const double crho = dt * rho;
+    PS_HIP(substep_factors(p, bnu, bka, st), "cn factor");
+    CnJobs jobs{};
+    jobs.j[0] = CnJob{cn_slot(p, 0), du, lu, h2[0], crho, PS_CENTER};
+    jobs.j[1] = CnJob{cn_slot(p, 0), dv, lv, h2[1], crho, PS_CENTER};
+    jobs.j[2] = CnJob{cn_slot(p, 1), dw, lw, h2[2], crho, PS_FACE};
+    jobs.j[3] = CnJob{cn_slot(p, 2), g_out[3], lt, h2[3], crho, PS_FACE};
+    jobs.n = 4;
+    PS_HIP(launch_cn_jobs(p->gd, CN_T, jobs, st), "cn adjoint solves");
     // explicit terms (bilinear advection at the input state, linear operators, buoyancy, pressure)
     SubstepAdjArgs a{};
     a.u = u;
@@ -1056,10 +1102,6 @@ ps_status rk3_substep_adjoint(ps_plan_t p, int l, double dt, double nu, double k
     a.lv = lv;
     a.lw = lw;
     a.lt = lt;
-    a.du = du;
-    a.dv = dv;
-    a.dw = dw;
-    a.dt_ = g_out[3];
     a.dp = g_out[4];
     a.gu = g_in[0];
     a.gv = g_in[1];
@@ -1071,6 +1113,8 @@ ps_status rk3_substep_adjoint(ps_plan_t p, int l, double dt, double nu, double k
     a.ka = kappa;
     a.gam = gam;
     a.alp = alp;
+    a.bnu = bnu;
+    a.bka = bka;
     // the cotangent of this substep's H output joins dt gamma lambda wherever H acts
     if (g_hout) {
         a.ghu = g_hout[0];
@@ -1079,23 +1123,22 @@ ps_status rk3_substep_adjoint(ps_plan_t p, int l, double dt, double nu, double k
         a.ght = g_hout[3];
     }
     PS_HIP(launch_explicit_adj(p->gd, a, st), "explicit adjoint");
-    if (g_hprev) {
-        // the previous substep's H enters the right-hand sides as dt rho H^{l-1} (zero for l = 1);
-        // written after the explicit adjoint has read g_hout, so that g_hprev may share its buffers
-        const double c = dt * rho;
+    if (g_hprev && !hprev_fused) {
+        // g_hprev shares memory with g_hout: written now that the explicit adjoint has read it
         const size_t nc = p->npts, nf = p->npts + p->plane;
-        PS_HIP(launch_scale(lu, g_hprev[0], c, nc, st), "h_prev adjoint");
-        PS_HIP(launch_scale(lv, g_hprev[1], c, nc, st), "h_prev adjoint");
-        PS_HIP(launch_scale(lw, g_hprev[2], c, nf, st), "h_prev adjoint");
-        PS_HIP(launch_scale(lt, g_hprev[3], c, nf, st), "h_prev adjoint");
+        PS_HIP(launch_scale(lu, g_hprev[0], crho, nc, st), "h_prev adjoint");
+        PS_HIP(launch_scale(lv, g_hprev[1], crho, nc, st), "h_prev adjoint");
+        PS_HIP(launch_scale(lw, g_hprev[2], crho, nf, st), "h_prev adjoint");
+        PS_HIP(launch_scale(lt, g_hprev[3], crho, nf, st), "h_prev adjoint");
     }
     return r;
 }
 
 // Field-sized temporaries of the step adjoint (allocated on first use): the states after
 // substeps 1 and 2 (five fields each), the H hand-over (four), two sets of state
-// cotangents (five each) and the H cotangent (four).
-constexpr int kStepAdjFields = 28;
+// cotangents (five each) and two H cotangents (four each: substep 2 reads one while its
+// Crank-Nicolson adjoint writes the other).
+constexpr int kStepAdjFields = 32;
 
 ps_status rk3_step_adjoint(ps_plan_t p, double dt, double nu, double kappa, const double* u, const double* v,
                            const double* w, const double* t, const double* pr, const double* const* g_out,
@@ -1127,8 +1170,10 @@ ps_status rk3_step_adjoint(ps_plan_t p, double dt, double nu, double kappa, cons
     double* ga[5] = {fld(14), fld(15), fld(16), fld(17), fld(18)};
     double* gb[5] = {fld(19), fld(20), fld(21), fld(22), fld(23)};
     double* gh[4] = {fld(24), fld(25), fld(26), fld(27)};
+    double* gh2[4] = {fld(28), fld(29), fld(30), fld(31)};
     const double* hc[4] = {h[0], h[1], h[2], h[3]};
     const double* ghc[4] = {gh[0], gh[1], gh[2], gh[3]};
+    const double* gh2c[4] = {gh2[0], gh2[1], gh2[2], gh2[3]};
     hipStream_t st = (hipStream_t)stream;
     const size_t bytes_c = p->npts * sizeof(double), bytes_f = (p->npts + p->plane) * sizeof(double);
     const size_t fb[5] = {bytes_c, bytes_c, bytes_f, bytes_f, bytes_c};
@@ -1149,17 +1194,17 @@ ps_status rk3_step_adjoint(ps_plan_t p, double dt, double nu, double kappa, cons
     if (!note(r)) return r;
     phase.next("reverse sweep");
     // reverse sweep: substep 3 at s2, substep 2 at s1 (with the cotangent of H^2), substep 1
-    // at the input (with the cotangent of H^1); H^l's cotangent is handed down in place
+    // at the input (with the cotangent of H^1); the two H cotangents in separate buffers
     const double* go[5] = {g_out[0], g_out[1], g_out[2], g_out[3], g_out[4]};
     const double* gac[5] = {ga[0], ga[1], ga[2], ga[3], ga[4]};
     const double* gbc[5] = {gb[0], gb[1], gb[2], gb[3], gb[4]};
     r = rk3_substep_adjoint(p, 3, dt, nu, kappa, s2[0], s2[1], s2[2], s2[3], s2[4], go, nullptr, ga, gh, stream,
                             nullptr);
     if (!note(r)) return r;
-    r = rk3_substep_adjoint(p, 2, dt, nu, kappa, s1[0], s1[1], s1[2], s1[3], s1[4], gac, ghc, gb, gh, stream,
+    r = rk3_substep_adjoint(p, 2, dt, nu, kappa, s1[0], s1[1], s1[2], s1[3], s1[4], gac, ghc, gb, gh2, stream,
                             nullptr);
     if (!note(r)) return r;
-    r = rk3_substep_adjoint(p, 1, dt, nu, kappa, u, v, w, t, pr, gbc, ghc, g_in, nullptr, stream, info);
+    r = rk3_substep_adjoint(p, 1, dt, nu, kappa, u, v, w, t, pr, gbc, gh2c, g_in, nullptr, stream, info);
     if (!note(r)) return r;
     if (worst != PS_OK) return fail(worst, "a Poisson refinement of the step adjoint stopped above the tolerance");
     return PS_OK;
@@ -1524,9 +1569,19 @@ ps_status mr_tstep(ps_mr_t m, double dt, double kappa, const double* const* v0, 
             a.gam = gam;
             a.rho = rho;
             a.alp = alp;
+            a.bka = alp * dts * kappa / 2.0;
             PS_HIP(launch_mr_explicit_t(m->gf, a, st), "temperature explicit terms");
-            PS_HIP(launch_cn_factor(m->gf, PS_FACE, alp * dts * kappa / 2.0, m->cnfac, st), "cn factor");
-            PS_HIP(launch_cn_solve_add(m->gf, PS_FACE, m->cnfac, m->rt, tf, st), "cn solve T");
+            CnFactorJobs fj{};
+            fj.fac[0] = m->cnfac;
+            fj.beta[0] = a.bka;
+            fj.kind[0] = PS_FACE;
+            fj.n = 1;
+            PS_HIP(launch_cn_factor(m->gf, fj, st), "cn factor");
+            // rt holds C T + rhs: T* = C^-1 rt on the interior faces
+            CnJobs jobs{};
+            jobs.j[0] = CnJob{m->cnfac, m->rt, tf, nullptr, 0.0, PS_FACE};
+            jobs.n = 1;
+            PS_HIP(launch_cn_jobs(m->gf, CN_PUT, jobs, st), "cn solve T");
         }
     return PS_OK;
 }

@@ -128,17 +128,23 @@ struct YShape {
 //            L x read from the FP64 iterate x around each point.
 //  XL_DIV:   the divergence D u* / s of a face velocity (u at x-faces, v at y-faces,
 //            w at z-faces with nz + 1 planes), so that the projection never stores f.
-enum { XL_PLAIN = 0, XL_RESID = 1, XL_DIV = 2 };
+//  XL_ADJ:   the right-hand side of the projection adjoint's solve, D (g / V) of the
+//            velocity cotangents plus the pressure cotangent's terms (the arithmetic of
+//            k_adj_rhs), so that the adjoint never stores it either.
+enum { XL_PLAIN = 0, XL_RESID = 1, XL_DIV = 2, XL_ADJ = 3 };
 struct ResidIn {
     const double* x;      // current iterate (whole box; the f pointer is offset to the launch's first plane)
     const double* mu;     // mu[0] * mu_scale = weighted mean of f
     double mu_scale;
     int z0;               // first plane of this launch (for the z neighbours)
     // XL_DIV: velocity components offset to the launch's first plane, and 1/s
+    // (XL_ADJ: the cotangents g_u, g_v, g_w, and g_p or NULL, with 1/s and c)
     const double* u;
     const double* v;
     const double* w;
     double div_scale;
+    const double* gp;
+    double adj_c;
 };
 
 // Minimum waves per SIMD of the x transforms (register caps; 1: none).
@@ -299,6 +305,49 @@ k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny,
             v.x = rin.div_scale * ((uc.y - uc.x) * idx + (vp.x - vc.x) * idy + (wp.x - wc.x) * idzk);
             v.y = rin.div_scale * ((ur - uc.y) * idx + (vp.y - vc.y) * idy + (wp.y - wc.y) * idzk);
             v.x = valid ? v.x : 0.0;   // selects, not branches: the loads stay unconditional
+            v.y = valid ? v.y : 0.0;
+            acc0 += v.x + v.y;
+        } else if constexpr (LM == XL_ADJ) {
+            // f = D (g / V) + (1/s) (g_p / dz - c Dzz (g_p / dz)) at the cells (2e, 2e + 1) of
+            // row (z, y): g_u, g_v differenced forward in x / y, g_w / dzc at the cell's
+            // interior faces (wall faces carry none); every load unconditional (a missing z
+            // neighbour reads the row itself, an absent g_p reads g_u), terms selected away
+            const int n = 2 * M;
+            const size_t rb = (size_t)row * n;
+            const bool hi = zg + 1 < g.nz, lo = zg > 0;
+            const double2 uc = ld_stream2<PS_NT_XF>(rin.u + rb + 2 * e);
+            const double ur = rin.u[rb + (2 * e + 2 == n ? 0 : 2 * e + 2)];
+            const double2 vc = ld_stream2<PS_NT_XF>(rin.v + rb + 2 * e);
+            const double2 vp = *reinterpret_cast<const double2*>(rin.v + (rb - (size_t)yr * n) +
+                                                                 (size_t)(yr + 1 == ny ? 0 : yr + 1) * n + 2 * e);
+            const double2 wb = *reinterpret_cast<const double2*>(rin.w + rb + 2 * e);
+            const double2 wt = *reinterpret_cast<const double2*>(rin.w + rb + plane + 2 * e);
+            const double* hp = rin.gp ? rin.gp : rin.u;
+            const double2 h0 = *reinterpret_cast<const double2*>(hp + rb + 2 * e);
+            const double2 hu = *reinterpret_cast<const double2*>(hp + rb + (size_t)hi * plane + 2 * e);
+            const double2 hd = *reinterpret_cast<const double2*>(hp + rb - (size_t)lo * plane + 2 * e);
+            const double idz = 1.0 / g.dz[zg];
+            const double dzc_t = g.dzc[hi ? zg + 1 : zg], dzc_b = g.dzc[zg];
+            const double dz_u = g.dz[hi ? zg + 1 : zg], dz_d = g.dz[lo ? zg - 1 : zg];
+            const double o_u = g.o[zg + 1], o_d = g.o[zg], dzk = g.dz[zg];
+            auto cell = [&](double u0, double u1, double v0, double v1, double w0, double w1, double c0, double cu,
+                            double cd) {
+                const double du = (u1 - u0) * idz / g.dx;
+                const double dv = (v1 - v0) * idz / g.dy;
+                const double tt = hi ? w1 / dzc_t : 0.0;
+                const double bb = lo ? w0 / dzc_b : 0.0;
+                double val = du + dv + (tt - bb) / dzk;
+                if (rin.gp) {
+                    const double hc = c0 * idz;
+                    const double fp = hi ? (cu / dz_u - hc) * o_u : 0.0;
+                    const double fm = lo ? (hc - cd / dz_d) * o_d : 0.0;
+                    val += rin.div_scale * (hc - rin.adj_c * ((fp - fm) / dzk));
+                }
+                return val;
+            };
+            v.x = cell(uc.x, uc.y, vc.x, vp.x, wb.x, wt.x, h0.x, hu.x, hd.x);
+            v.y = cell(uc.y, ur, vc.y, vp.y, wb.y, wt.y, h0.y, hu.y, hd.y);
+            v.x = valid ? v.x : 0.0;
             v.y = valid ? v.y : 0.0;
             acc0 += v.x + v.y;
         } else {
@@ -580,6 +629,21 @@ static hipError_t xfwd_launch_t(const GridDev& g, const SpecDev<T>& s, const dou
                            s.nkxb, s.twx, s.ptw, nullptr, g.dz + s.z0, partial, r, g, rsum);
         return hipGetLastError();
     }
+    if (mode == XL_ADJ) {
+        // the adjoint's fused right-hand side is used on FP64 plans only
+        if constexpr (std::is_same<T, double>::value) {
+            ResidIn r = *rin;
+            r.z0 = s.z0;
+            r.u += zoff;
+            r.v += zoff;
+            r.w += zoff;
+            if (r.gp) r.gp += zoff;
+            hipLaunchKernelGGL((k_xfwd<T, M, XL_ADJ>), dim3(nblk), dim3(X::THREADS), X::LDS, st, nullptr, s.a, nrows,
+                               g.ny, s.nkxb, s.twx, s.ptw, nullptr, g.dz + s.z0, partial, r, g, rsum);
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
     hipLaunchKernelGGL((k_xfwd<T, M, XL_PLAIN>), dim3(nblk), dim3(X::THREADS), X::LDS, st, f + zoff, s.a, nrows,
                        g.ny, s.nkxb, s.twx, s.ptw, scale_z ? scale_z + s.z0 : nullptr, g.dz + s.z0, partial,
                        ResidIn{}, g, rsum);
@@ -639,12 +703,14 @@ hipError_t launch_xfwd(const GridDev& g, const SpecDev<T>& s, const double* f, c
 
 template <typename T>
 hipError_t launch_xfwd_div(const GridDev& g, const SpecDev<T>& s, const double* u, const double* v, const double* w,
-                           double div_scale, double* partial, hipStream_t st) {
-    ResidIn rin{nullptr, nullptr, 0.0, 0, u, v, w, div_scale};
+                           double div_scale, double* partial, hipStream_t st, bool adjoint, const double* gp,
+                           double adj_c) {
+    ResidIn rin{nullptr, nullptr, 0.0, 0, u, v, w, div_scale, gp, adj_c};
+    const int mode = adjoint ? XL_ADJ : XL_DIV;
     switch (g.nx / 2) {
 #define PS_CASE(L) \
     case L:        \
-        return xfwd_launch_t<T, L>(g, s, nullptr, nullptr, partial, &rin, XL_DIV, st);
+        return xfwd_launch_t<T, L>(g, s, nullptr, nullptr, partial, &rin, mode, st);
         PS_FFT_LENGTHS(PS_CASE)
 #undef PS_CASE
         default:
@@ -732,7 +798,8 @@ int xinv_blocks(const GridDev& g) {
     template hipError_t launch_xfwd<T>(const GridDev&, const SpecDev<T>&, const double*, const double*,     \
                                        double*, hipStream_t, const double*, const double*, double);         \
     template hipError_t launch_xfwd_div<T>(const GridDev&, const SpecDev<T>&, const double*, const double*, \
-                                           const double*, double, double*, hipStream_t);                    \
+                                           const double*, double, double*, hipStream_t, bool, const double*,  \
+                                           double);                                                           \
     template hipError_t launch_xinv<T>(const GridDev&, const SpecDev<T>&, double*, double, int,             \
                                        const double*, double, const double*, double*, hipStream_t);         \
     template hipError_t launch_yfwd<T>(const GridDev&, const SpecDev<T>&, hipStream_t);                    \

@@ -102,9 +102,13 @@ __global__ void k_scale_planes(const double* in, double* out,
 // kind 0 (centre): n = nz rows, wall half a cell beyond the end centres.
 // kind 1 (face):   n = nz - 1 interior faces.
 // The off-diagonal coupling coefficients are formed in parallel into LDS (nz <= 2048),
-// then one thread runs the LU recurrence.
-__global__ void __launch_bounds__(256) k_cn_factor(GridDev g, int kind, double beta, double* __restrict__ fac) {
+// then one thread runs the LU recurrence; one block per factorisation (up to four).
+__global__ void __launch_bounds__(256) k_cn_factor(GridDev g, CnFactorJobs jobs) {
     __shared__ double am_s[2048], ap_s[2048];
+    const int jy = blockIdx.x;
+    const int kind = jy == 0 ? jobs.kind[0] : (jy == 1 ? jobs.kind[1] : (jy == 2 ? jobs.kind[2] : jobs.kind[3]));
+    const double beta = jy == 0 ? jobs.beta[0] : (jy == 1 ? jobs.beta[1] : (jy == 2 ? jobs.beta[2] : jobs.beta[3]));
+    double* fac = jy == 0 ? jobs.fac[0] : (jy == 1 ? jobs.fac[1] : (jy == 2 ? jobs.fac[2] : jobs.fac[3]));
     const int n = kind == 0 ? g.nz : g.nz - 1;
     for (int r = threadIdx.x; r < n; r += blockDim.x) {
         if (kind == 0) {
@@ -117,7 +121,7 @@ __global__ void __launch_bounds__(256) k_cn_factor(GridDev g, int kind, double b
         }
     }
     __syncthreads();
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (threadIdx.x != 0) return;
     double* l = fac;
     double* invd = fac + n;
     double* cs = fac + 2 * n;
@@ -137,48 +141,23 @@ __global__ void __launch_bounds__(256) k_cn_factor(GridDev g, int kind, double b
     }
 }
 
-__global__ void __launch_bounds__(256)
-k_cn_solve(GridDev g, int kind, const double* __restrict__ fac, double* __restrict__ x) {
-    const size_t plane = (size_t)g.nx * g.ny;
-    const size_t col = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (col >= plane) return;
-    const int n = kind == 0 ? g.nz : g.nz - 1;
-    const int off = kind == 0 ? 0 : 1;
-    const double* l = fac;
-    const double* invd = fac + n;
-    const double* cs = fac + 2 * n;
-    double* q = x + (size_t)off * plane + col;
-    double y = q[0];
-    for (int r = 1; r < n; ++r) {
-        y = q[(size_t)r * plane] - l[r] * y;
-        q[(size_t)r * plane] = y;
-    }
-    double xv = y * invd[n - 1];
-    q[(size_t)(n - 1) * plane] = xv;
-    for (int r = n - 2; r >= 0; --r) {
-        xv = (q[(size_t)r * plane] - cs[r] * xv) * invd[r];
-        q[(size_t)r * plane] = xv;
-    }
-    if (kind == 1) {
-        x[col] = 0.0;
-        x[(size_t)g.nz * plane + col] = 0.0;
-    }
-}
-
 // Tiled CN solve: a block holds 64 consecutive columns (one per lane) and all n rows,
 // wave w owning rows [w KZ, w KZ + KZ).  With the shared LU factors the forward sweep
 // y_r = x_r - l_r y_{r-1} and the backward sweep d_r = invd_r (y_r - c_r d_{r+1}) are
 // affine maps whose slopes do not depend on the column, so each wave runs its chunk
 // from a zero entry value, the chunk results are combined across waves through LDS, and
 // each wave adds (running product of slopes) x (true entry value).  Every value is read
-// and written once.
-//   CN_ADD: out += C^-1 in       CN_SET: out = C^-1 in (in may alias out)
-//   CN_T:   out = V C^-1 V^-1 in (V = dz for centre fields, dzc for interior faces);
-//           CN_SET / CN_T zero the two wall rows of face fields.
-enum { CN_ADD = 0, CN_SET = 1, CN_T = 2 };
+// and written once.  One launch per field: with the factors a __restrict__ kernel argument
+// their per-row loads are scalar loads (selecting them per block from an argument struct
+// turned them into vector loads, 1.35 -> 1.87 ms per field at 768^2 x 512).
+//   CN_PUT: out = C^-1 in on the solved rows (face walls untouched; in may alias out)
+//   CN_SET: as CN_PUT, and the two wall rows of face fields zeroed
+//   CN_T:   out = V C^-1 V^-1 in (V = dz for centre fields, dzc for interior faces), face
+//           walls zeroed; with out2, also out2 = c2 out
 template <int KZ, int MODE>
 __global__ void __launch_bounds__(1024)
-k_cn_tiled(GridDev g, int kind, const double* __restrict__ fac, const double* in, double* out) {
+k_cn_tiled(GridDev g, int kind, const double* __restrict__ fac, const double* __restrict__ wv,
+           const double* __restrict__ iwv, const double* in, double* out, double* out2, double c2) {
     __shared__ double bs[16][64];
     __shared__ double as[16];
     const size_t plane = (size_t)g.nx * g.ny;
@@ -187,8 +166,8 @@ k_cn_tiled(GridDev g, int kind, const double* __restrict__ fac, const double* in
     const double* l = fac;
     const double* invd = fac + n;
     const double* cs = fac + 2 * n;
-    const double* wv = kind == 0 ? g.dz : g.dzc;
-    // the wave index is uniform, so the per-row factors are scalar loads
+    // the wave index is uniform, so the per-row factors (and CN_T's weights V and 1/V, also
+    // __restrict__ arguments) are scalar loads
     const int lane = threadIdx.x & 63, nwave = blockDim.x >> 6;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const size_t col = (size_t)xcd_remap(blockIdx.x, gridDim.x) * 64 + lane;
@@ -206,7 +185,7 @@ k_cn_tiled(GridDev g, int kind, const double* __restrict__ fac, const double* in
     if constexpr (MODE == CN_T) {
 #pragma unroll
         for (int i = 0; i < KZ; ++i)
-            if (r0 + i < n) x[i] /= wv[r0 + i + ko];
+            if (r0 + i < n) x[i] *= iwv[r0 + i + ko];
     }
     // forward sweep from a zero entry value
     double b = 0.0, a = 1.0;
@@ -261,101 +240,143 @@ k_cn_tiled(GridDev g, int kind, const double* __restrict__ fac, const double* in
         }
     }
     if (!valid) return;
-    if constexpr (MODE == CN_ADD) {
-        // the values added to, read in groups of 8 rows ahead of their stores (one wait
-        // per group rather than one per row)
-        constexpr int G = KZ < 8 ? KZ : 8;
+    if (MODE != CN_T) out2 = nullptr;
 #pragma unroll
-        for (int i0 = 0; i0 < KZ; i0 += G) {
-            double ov[G];
-#pragma unroll
-            for (int i = 0; i < G; ++i) ov[i] = out[base + (size_t)min(r0 + i0 + i, n - 1) * plane];
-#pragma unroll
-            for (int i = 0; i < G; ++i) anchor(ov[i]);
-#pragma unroll
-            for (int i = 0; i < G; ++i) {
-                const int r = r0 + i0 + i;
-                if (r < n) out[base + (size_t)r * plane] = ov[i] + x[i0 + i];
-            }
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < KZ; ++i) {
-            const int r = r0 + i;
-            if (r < n) {
-                double* o = out + base + (size_t)r * plane;
-                if (MODE == CN_SET)
-                    *o = x[i];
-                else
-                    *o = x[i] * wv[r + ko];
+    for (int i = 0; i < KZ; ++i) {
+        const int r = r0 + i;
+        if (r < n) {
+            const size_t o = base + (size_t)r * plane;
+            if (MODE == CN_T) {
+                const double y = x[i] * wv[r + ko];
+                out[o] = y;
+                if (out2) out2[o] = c2 * y;
+            } else {
+                out[o] = x[i];
             }
         }
     }
-    if (MODE != CN_ADD && kind == 1 && wave == 0) {
+    if (MODE != CN_PUT && kind == 1 && wave == 0) {
         out[col] = 0.0;
         out[(size_t)g.nz * plane + col] = 0.0;
+        if (out2) {
+            out2[col] = 0.0;
+            out2[(size_t)g.nz * plane + col] = 0.0;
+        }
     }
 }
 
-// Launch the tiled CN solve when the rows fit 16 waves of at most 32 rows each;
-// returns false (nothing launched) otherwise.
-template <int MODE>
-static bool cn_tiled_launch(const GridDev& g, int kind, const double* fac, const double* in, double* out,
-                            hipStream_t st, hipError_t* err) {
-    const int n = kind == 0 ? g.nz : g.nz - 1;
+// Lane-per-column form for columns taller than the tiled kernel holds (one job per launch).
+//   put:   out = C^-1 in on the solved rows (in may alias out; face walls untouched)
+//   trans: out = V C^-1 V^-1 in, face walls zeroed (and out2 = c2 out when given)
+__global__ void __launch_bounds__(256) k_cn_column(GridDev g, CnJob jb, int trans) {
     const size_t plane = (size_t)g.nx * g.ny;
-    const int nblk = (int)((plane + 63) / 64);
-    int kz = 0;
-    for (int c : {4, 8, 16, 32})
-        if ((n + c - 1) / c <= 16) {
-            kz = c;
-            break;
-        }
-    if (kz == 0) return false;
-    const int threads = 64 * ((n + kz - 1) / kz);
-    switch (kz) {
-        case 4:
-            hipLaunchKernelGGL((k_cn_tiled<4, MODE>), dim3(nblk), dim3(threads), 0, st, g, kind, fac, in, out);
-            break;
-        case 8:
-            hipLaunchKernelGGL((k_cn_tiled<8, MODE>), dim3(nblk), dim3(threads), 0, st, g, kind, fac, in, out);
-            break;
-        case 16:
-            hipLaunchKernelGGL((k_cn_tiled<16, MODE>), dim3(nblk), dim3(threads), 0, st, g, kind, fac, in, out);
-            break;
-        default:
-            hipLaunchKernelGGL((k_cn_tiled<32, MODE>), dim3(nblk), dim3(threads), 0, st, g, kind, fac, in, out);
-            break;
+    const size_t col = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= plane) return;
+    const int kind = jb.kind;
+    const int n = kind == 0 ? g.nz : g.nz - 1;
+    const int ko = kind == 0 ? 0 : 1;
+    const double* wv = kind == 0 ? g.dz : g.dzc;
+    const double* l = jb.fac;
+    const double* invd = jb.fac + n;
+    const double* cs = jb.fac + 2 * n;
+    const double* r = jb.in + (size_t)ko * plane + col;
+    double* x = jb.out + (size_t)ko * plane + col;
+    double y = trans ? r[0] / wv[ko] : r[0];
+    x[0] = y;
+    for (int k = 1; k < n; ++k) {
+        const double rk = trans ? r[(size_t)k * plane] / wv[k + ko] : r[(size_t)k * plane];
+        y = rk - l[k] * y;
+        x[(size_t)k * plane] = y;
     }
-    *err = hipGetLastError();
-    return true;
+    double d = y * invd[n - 1];
+    x[(size_t)(n - 1) * plane] = trans ? d * wv[n - 1 + ko] : d;
+    for (int k = n - 2; k >= 0; --k) {
+        d = (x[(size_t)k * plane] - cs[k] * d) * invd[k];
+        x[(size_t)k * plane] = trans ? d * wv[k + ko] : d;
+    }
+    double* x2 = jb.out2 ? jb.out2 + (size_t)ko * plane + col : nullptr;
+    if (trans && x2)
+        for (int k = 0; k < n; ++k) x2[(size_t)k * plane] = jb.c2 * x[(size_t)k * plane];
+    if (trans && kind == 1) {
+        jb.out[col] = 0.0;
+        jb.out[(size_t)g.nz * plane + col] = 0.0;
+        if (jb.out2) {
+            jb.out2[col] = 0.0;
+            jb.out2[(size_t)g.nz * plane + col] = 0.0;
+        }
+    }
+}
+
+// Rows per wave of the tiled kernel for columns of up to nz rows (16 waves at most); 0 when
+// the columns are taller than 16 x 32 rows.
+static int cn_rows_per_wave(int nz) {
+    for (int c : {4, 8, 16, 32})
+        if ((nz + c - 1) / c <= 16) return c;
+    return 0;
+}
+
+template <int MODE>
+static hipError_t cn_tiled_launch(const GridDev& g, const CnJob& j, int kz, hipStream_t st) {
+    const size_t plane = (size_t)g.nx * g.ny;
+    const int n = j.kind == 0 ? g.nz : g.nz - 1;
+    const dim3 grid((unsigned)((plane + 63) / 64));
+    const dim3 block(64 * ((n + kz - 1) / kz));
+    // CN_T's weights: V = dz (centre rows) or dzc (interior faces), and 1/V
+    const double* wv = j.kind == 0 ? g.dz : g.dzc;
+    const double* iwv = j.kind == 0 ? g.idz : g.o;
+#define PS_CN_ARGS g, j.kind, j.fac, wv, iwv, j.in, j.out, j.out2, j.c2
+    switch (kz) {
+        case 4: hipLaunchKernelGGL((k_cn_tiled<4, MODE>), grid, block, 0, st, PS_CN_ARGS); break;
+        case 8: hipLaunchKernelGGL((k_cn_tiled<8, MODE>), grid, block, 0, st, PS_CN_ARGS); break;
+        case 16: hipLaunchKernelGGL((k_cn_tiled<16, MODE>), grid, block, 0, st, PS_CN_ARGS); break;
+        default: hipLaunchKernelGGL((k_cn_tiled<32, MODE>), grid, block, 0, st, PS_CN_ARGS); break;
+    }
+#undef PS_CN_ARGS
+    return hipGetLastError();
 }
 
 // ---- CFL (Listing 1) ------------------------------------------------------
-// A fixed grid of blocks strides over the cells; each block reduces its maximum and
+// A fixed grid of blocks strides over the rows; each block reduces its maximum and
 // posts it with one atomic max (non-negative doubles order like their bit patterns, and
 // every NaN pattern lies above +Inf).  The maximum propagates NaN (fmax would drop it), so
 // a non-finite velocity gives a non-finite Courant number.
 constexpr int kCflBlocks = 2048;
 __device__ __forceinline__ double nan_max(double q, double c) { return (c > q || c != c) ? c : q; }
+// Blocks stride over the (y, z) rows, threads along x; the loads of up to four x
+// positions per thread are issued together (clamped indices, unused values dropped).
 __global__ void __launch_bounds__(256)
 k_cfl(const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w, GridDev g,
       unsigned long long* __restrict__ out) {
     __shared__ double wmax[4];
-    const size_t n = (size_t)g.nx * g.ny * g.nz;
     const size_t plane = (size_t)g.nx * g.ny;
+    const int nrows = g.ny * g.nz;
+    constexpr int E = 4;
     double q = 0.0;
-    for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < n; id += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(id % g.nx);
-        const size_t jk = id / g.nx;
-        const int j = (int)(jk % g.ny);
-        const int k = (int)(jk / g.ny);
-        const int ip = (i + 1 == g.nx) ? 0 : i + 1;
+    for (int r = blockIdx.x; r < nrows; r += gridDim.x) {
+        const int k = r / g.ny, j = r - k * g.ny;
         const int jp = (j + 1 == g.ny) ? 0 : j + 1;
-        double c = fabs(w[id] + w[id + plane]) / g.dz[k] +
-                   fabs(v[id] + v[(size_t)k * plane + (size_t)jp * g.nx + i]) / g.dy +
-                   fabs(u[id] + u[(size_t)k * plane + (size_t)j * g.nx + ip]) / g.dx;
-        q = nan_max(q, 0.5 * c);
+        const size_t rb = (size_t)r * g.nx, rn = ((size_t)k * g.ny + jp) * g.nx;
+        const double dzk = g.dz[k];
+        for (int i0 = threadIdx.x; i0 < g.nx; i0 += E * blockDim.x) {
+            double uc[E], un[E], vc[E], vn[E], wb[E], wt[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int i = min(i0 + e * (int)blockDim.x, g.nx - 1);
+                const int ip = (i + 1 == g.nx) ? 0 : i + 1;
+                uc[e] = u[rb + i];
+                un[e] = u[rb + ip];
+                vc[e] = v[rb + i];
+                vn[e] = v[rn + i];
+                wb[e] = w[rb + i];
+                wt[e] = w[rb + plane + i];
+            }
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const double c = fabs(wb[e] + wt[e]) / dzk + fabs(vc[e] + vn[e]) / g.dy + fabs(uc[e] + un[e]) / g.dx;
+                // positions past the row's end repeat its last point: the maximum is unchanged
+                q = nan_max(q, 0.5 * c);
+            }
+        }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) q = nan_max(q, __shfl_xor(q, off, 64));
@@ -592,26 +613,45 @@ hipError_t launch_heat_flux(const GridDev& g, const double* w, const double* t, 
     return hipGetLastError();
 }
 
-hipError_t launch_cn_factor(const GridDev& g, int kind, double beta, double* fac, hipStream_t st) {
-    hipLaunchKernelGGL(k_cn_factor, dim3(1), dim3(256), 0, st, g, kind, beta, fac);
+hipError_t launch_cn_factor(const GridDev& g, const CnFactorJobs& jobs, hipStream_t st) {
+    hipLaunchKernelGGL(k_cn_factor, dim3(jobs.n), dim3(256), 0, st, g, jobs);
     return hipGetLastError();
 }
 
-bool launch_cn_tiled_add(const GridDev& g, int kind, const double* fac, const double* rhs, double* q,
-                         hipStream_t st, hipError_t* err) {
-    return cn_tiled_launch<CN_ADD>(g, kind, fac, rhs, q, st, err);
-}
-bool launch_cn_tiled_t(const GridDev& g, int kind, const double* fac, const double* in, double* out,
-                       hipStream_t st, hipError_t* err) {
-    return cn_tiled_launch<CN_T>(g, kind, fac, in, out, st, err);
+hipError_t launch_cn_jobs(const GridDev& g, int mode, const CnJobs& jobs, hipStream_t st) {
+    if (jobs.n < 1 || jobs.n > 4) return hipErrorInvalidValue;
+    const int kz = cn_rows_per_wave(g.nz);
+    if (kz > 0) {
+        for (int q = 0; q < jobs.n; ++q) {
+            hipError_t e;
+            switch (mode) {
+                case CN_PUT: e = cn_tiled_launch<CN_PUT>(g, jobs.j[q], kz, st); break;
+                case CN_SET: e = cn_tiled_launch<CN_SET>(g, jobs.j[q], kz, st); break;
+                default: e = cn_tiled_launch<CN_T>(g, jobs.j[q], kz, st); break;
+            }
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    const size_t plane = (size_t)g.nx * g.ny;
+    for (int q = 0; q < jobs.n; ++q) {
+        CnJob jb = jobs.j[q];
+        hipLaunchKernelGGL(k_cn_column, dim3(nblocks(plane, 256)), dim3(256), 0, st, g, jb, mode == CN_T ? 1 : 0);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        if (mode == CN_SET && jb.kind == 1) {
+            if ((e = launch_fill(jb.out, plane, 0.0, st)) != hipSuccess) return e;
+            if ((e = launch_fill(jb.out + (size_t)g.nz * plane, plane, 0.0, st)) != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_cn_solve(const GridDev& g, int kind, const double* fac, double* x, hipStream_t st) {
-    hipError_t e;
-    if (cn_tiled_launch<CN_SET>(g, kind, fac, x, x, st, &e)) return e;
-    const size_t plane = (size_t)g.nx * g.ny;
-    hipLaunchKernelGGL(k_cn_solve, dim3(nblocks(plane, 256)), dim3(256), 0, st, g, kind, fac, x);
-    return hipGetLastError();
+    CnJobs jobs{};
+    jobs.j[0] = CnJob{fac, x, x, nullptr, 0.0, kind};
+    jobs.n = 1;
+    return launch_cn_jobs(g, CN_SET, jobs, st);
 }
 
 hipError_t launch_absmax(const double* p, size_t n, size_t plane, const double* zs, double* out, hipStream_t st) {
@@ -624,10 +664,9 @@ hipError_t launch_absmax(const double* p, size_t n, size_t plane, const double* 
 
 hipError_t launch_cfl(const GridDev& g, const double* u, const double* v, const double* w, double* out,
                       hipStream_t st) {
-    const size_t n = (size_t)g.nx * g.ny * g.nz;
     hipError_t e = launch_fill(out, 1, 1e-8, st);
     if (e != hipSuccess) return e;
-    const int nb = (int)std::min<size_t>((size_t)kCflBlocks, (n + 255) / 256);
+    const int nb = (int)std::min<size_t>((size_t)kCflBlocks, (size_t)g.ny * g.nz);
     hipLaunchKernelGGL(k_cfl, dim3(nb), dim3(256), 0, st, u, v, w, g, reinterpret_cast<unsigned long long*>(out));
     return hipGetLastError();
 }

@@ -213,8 +213,9 @@ k_mr_restrict(const double* __restrict__ tf, double* __restrict__ tc, int nx, in
 
 // ---- explicit terms of the temperature equation on its own grid ------------------------
 // z-marching over 32 x 8 column tiles with a three-plane LDS ring of u, v, w, T (the velocity
-// staged as (1 - th) vel0 + th vel1), as in k_explicit.  Writes rt = dt [gamma H + rho Hprev
-// + alpha kappa Dzz T] on interior faces (walls 0) and H (optional).
+// staged as (1 - th) vel0 + th vel1), as in k_explicit.  Writes the Crank-Nicolson input
+// rt = C T + dt [gamma H + rho Hprev + alpha kappa Dzz T] on interior faces (C = I - bka Dzz~,
+// Dzz~ with zero wall values; walls 0, never read by the solve) and H (optional).
 constexpr int kMtTX = 32, kMtTY = 8, kMtZSEG = 64;
 
 template <int NF, int TX, int TY>
@@ -346,9 +347,11 @@ __global__ void __launch_bounds__(kMtTX * kMtTY) k_mr_explicit_t(MrTArgs a, Grid
                 const double az = (wtop * (0.5 * (tc + tkp)) - wbot * (0.5 * (tkm + tc))) * idzc;
                 const double h = -(ax + ay + az) + a.ka * ((tip - 2.0 * tc + tim) * idx2 + (tjp - 2.0 * tc + tjm) * idy2);
                 const double dzz = ((tkp - tc) * m_idz[mq + 1] - (tc - tkm) * m_idz[mq]) * idzc;
+                const double dzh = dzz - (k == 1 ? tkm * m_idz[mq] * idzc : 0.0) -
+                                   (k + 1 == nz ? tkp * m_idz[mq + 1] * idzc : 0.0);
                 double r = a.gam * h + a.alp * (a.ka * dzz);
                 if (a.rho != 0.0) r += a.rho * hp;
-                __builtin_nontemporal_store(a.dt * r, a.rt + id);
+                __builtin_nontemporal_store(tc + (a.dt * r - a.bka * dzh), a.rt + id);
                 if (a.hout) __builtin_nontemporal_store(h, a.hout + id);
             }
             if (k + 1 == nz) {

@@ -192,9 +192,12 @@ hipError_t launch_xfwd(const GridDev& g, const SpecDev<T>& s, const double* f, c
                        const double* resid_mu = nullptr, double mu_scale = 0.0);
 // The x transform of the divergence (D u*) * div_scale of a face velocity (u, v: nz planes,
 // w: nz + 1 planes), formed while loading; partial (optional) receives sum dz f per block.
+// adjoint (FP64 only): instead the projection adjoint's right-hand side from the velocity
+// cotangents (u, v, w) and the pressure cotangent gp (or NULL), with 1/s = div_scale and c.
 template <typename T>
 hipError_t launch_xfwd_div(const GridDev& g, const SpecDev<T>& s, const double* u, const double* v, const double* w,
-                           double div_scale, double* partial, hipStream_t st);
+                           double div_scale, double* partial, hipStream_t st, bool adjoint = false,
+                           const double* gp = nullptr, double adj_c = 0.0);
 template <typename T>
 hipError_t launch_yfwd(const GridDev& g, const SpecDev<T>& s, hipStream_t st);
 template <typename T>
@@ -252,13 +255,36 @@ hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, int ncu,
 hipError_t launch_scale(const double* in, double* out, double c, size_t n, hipStream_t st);
 hipError_t launch_scale_planes(const GridDev& g, const double* in, double* out, const double* zs, int nplanes,
                                size_t plane, hipStream_t st);
-hipError_t launch_cn_factor(const GridDev& g, int kind, double beta, double* fac, hipStream_t st);
-// Tiled CN solves (columns of up to 512 rows): q += C^-1 rhs, and out = V C^-1 V^-1 in.
-// Return false, launching nothing, when the columns are too tall; *err gets the launch status.
-bool launch_cn_tiled_add(const GridDev& g, int kind, const double* fac, const double* rhs, double* q,
-                         hipStream_t st, hipError_t* err);
-bool launch_cn_tiled_t(const GridDev& g, int kind, const double* fac, const double* in, double* out,
-                       hipStream_t st, hipError_t* err);
+// Factorisations of I - beta Dzz for up to four (kind, beta) pairs, one block each:
+// fac[q] = [l (n), invd (n), c (n)], n = nz (centre) or nz - 1 (face).
+struct CnFactorJobs {
+    double* fac[4];
+    double beta[4];
+    int kind[4];
+    int n;
+};
+hipError_t launch_cn_factor(const GridDev& g, const CnFactorJobs& jobs, hipStream_t st);
+// Crank-Nicolson column solves with factored operators C = I - beta Dzz, up to four fields
+// (one launch each).
+//   CN_PUT: out = C^-1 in on the solved rows (face walls untouched; in may alias out)
+//   CN_SET: as CN_PUT, and the wall rows of face fields zeroed
+//   CN_T:   out = V C^-1 V^-1 in (the transpose: V = dz for centre fields, dzc for faces),
+//           face walls zeroed; with out2 != NULL also out2 = c2 out
+enum { CN_PUT = 0, CN_SET = 1, CN_T = 2 };
+struct CnJob {
+    const double* fac;
+    const double* in;
+    double* out;
+    double* out2;
+    double c2;
+    int kind;
+};
+struct CnJobs {
+    CnJob j[4];
+    int n;
+};
+hipError_t launch_cn_jobs(const GridDev& g, int mode, const CnJobs& jobs, hipStream_t st);
+// x = C^-1 x (CN_SET, one field)
 hipError_t launch_cn_solve(const GridDev& g, int kind, const double* fac, double* x, hipStream_t st);
 // Plane means of T (nz + 1 faces) and total vertical heat flux through the nz centre planes;
 // sums: 2 (nz + 1) doubles of scratch.
@@ -273,27 +299,24 @@ hipError_t launch_absmax(const double* p, size_t n, size_t plane, const double* 
 struct SubstepArgs {
     const double *u, *v, *w, *t, *p;
     const double *hpu, *hpv, *hpw, *hpt;   // previous H (rho != 0)
-    double *ru, *rv, *rw, *rt;             // right-hand sides
+    double *ru, *rv, *rw, *rt;             // Crank-Nicolson inputs C q + rhs
     double *hu, *hv, *hw, *ht;             // this substep's H (optional)
     double dt, nu, ka, gam, rho, alp;
+    double bnu, bka;                       // Crank-Nicolson beta of the velocity and of T
 };
 
 struct SubstepAdjArgs {
     const double *u, *v, *w, *t;           // input state (advection is evaluated there)
     const double *lu, *lv, *lw, *lt;       // cotangents of the right-hand sides
     const double *ghu, *ghv, *ghw, *ght;   // cotangent of the substep's H output (all NULL: none)
-    const double *du, *dv, *dw, *dt_, *dp; // direct cotangents of q* (and T', p')
+    const double* dp;                      // direct cotangent of p'
     double *gu, *gv, *gw, *gt, *gp;        // outputs
     double dt, nu, ka, gam, alp;
+    double bnu, bka;                       // Crank-Nicolson beta of the velocity and of T
 };
 
 hipError_t launch_explicit(const GridDev& g, const SubstepArgs& a, hipStream_t st);
 hipError_t launch_explicit_adj(const GridDev& g, const SubstepAdjArgs& a, hipStream_t st);
-// q += (I - beta Dzz)^-1 rhs (rhs is overwritten)
-hipError_t launch_cn_solve_add(const GridDev& g, int kind, const double* fac, double* rhs, double* q, hipStream_t st);
-// out = V (I - beta Dzz)^-1 V^-1 in  (transpose of the CN solve)
-hipError_t launch_cn_solve_t(const GridDev& g, int kind, const double* fac, const double* in, double* out,
-                             hipStream_t st);
 
 // Multiple-resolution temperature grid (multires_kernels.hip).
 struct MrDev {
@@ -309,9 +332,9 @@ struct MrTArgs {
     const double *u1, *v1, *w1;  // ... and at its end
     const double* t;             // temperature (fine z-faces)
     const double* hp;            // previous substep's H (rho != 0)
-    double* rt;                  // right-hand side of the Crank-Nicolson solve
+    double* rt;                  // Crank-Nicolson input C T + rhs (C = I - bka Dzz~)
     double* hout;                // this substep's H (optional; may alias hp)
-    double th, dt, ka, gam, rho, alp;
+    double th, dt, ka, gam, rho, alp, bka;
 };
 bool mr_factors_supported(int rx, int ry, int rz);
 hipError_t launch_mr_prolong(const GridDev& g, const MrDev& m, const double* u, const double* v, const double* w,

@@ -3,7 +3,11 @@
 // Forward, substep l with coefficients gamma, rho, alpha = gamma + rho:
 //   H_q   = -A(q) + nu (Dxx + Dyy) q   (+ T on w; kappa for T)
 //   rhs_q = dt [gamma H_q + rho H_q^prev - alpha G_q p + alpha nu Dzz q]
-//   (I - alpha dt nu/2 Dzz) dq = rhs_q, q* = q + dq           (k_cn_solve_add)
+//   (I - alpha dt nu/2 Dzz) dq = rhs_q, q* = q + dq
+// The explicit kernel writes s_q = C q + rhs_q with C = I - alpha dt nu/2 Dzz~ (Dzz~: Dzz
+// with zero wall values, the operator of the Crank-Nicolson rows), so that the solve is
+// q* = C^-1 s_q: the same q* = q + C^-1 rhs_q, but the solve reads one field and writes
+// one instead of reading two (8 B per point and field less).
 //   projection of (u*, v*, w*) with s = alpha dt, c = alpha dt nu / 2
 //
 // Advection A is the conservative central form on the staggered grid: for each
@@ -207,8 +211,8 @@ inline int ex_blocks(const GridDev& g) {
     return ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) * ((g.nz + ZSEG - 1) / ZSEG);
 }
 
-// Right-hand sides of u, v at the cell's x/y faces and of w, T at its bottom z-face k
-// (interior faces; wall rows are zeroed).
+// Crank-Nicolson inputs s_q = C q + rhs_q of u, v at the cell's x/y faces and of w, T at
+// its bottom z-face k (interior faces; wall rows are zeroed and never read by the solve).
 //
 // Windows (step k computes u, v of cell plane k and w, T of its bottom face k): u and v
 // are read with neighbours on planes k - 1 (by the face terms) and k, and on their own
@@ -272,6 +276,9 @@ __global__ void __launch_bounds__(kExTX * kExTY) PS_EX_ATTR k_explicit(SubstepAr
     // RK3 weights times dt: rhs = dt [gamma H + rho H_prev - alpha G p + alpha nu Dzz q]
     const double cg = a.dt * a.gam, cr = a.dt * a.rho, ca = a.dt * a.alp;
     const double can = ca * a.nu, cak = ca * a.ka;
+    // centre fields: Dzz already has homogeneous wall rows (the wall value is zero), so the
+    // rhs weight and the Crank-Nicolson beta combine
+    const double cdn = can - a.bnu;
     const int nz = g.nz;
     const int kb = tile.kb;
     typename RR::Stage st;
@@ -350,9 +357,9 @@ __global__ void __launch_bounds__(kExTX * kExTY) PS_EX_ATTR k_explicit(SubstepAr
                 const double ft = hi ? (ukp - uc) * m_idzw[mq + 1] : -uc * idzw_hi;
                 const double dzz = (ft - fb) * idzk;
                 const double gp = (L(FP, 0, 0, 0) - L(FP, 0, 0, -1)) * idx;
-                double r = cg * h - ca * gp + can * dzz;
+                double r = cg * h - ca * gp + cdn * dzz;
                 if (a.rho != 0.0) r += cr * hp[0];
-                st_out(a.ru + (id), r);
+                st_out(a.ru + (id), uc + r);
                 if (a.hu) st_out(a.hu + (id), h);
             }
             // (the three blocks run one after the other: their LDS reads are not hoisted
@@ -375,9 +382,9 @@ __global__ void __launch_bounds__(kExTX * kExTY) PS_EX_ATTR k_explicit(SubstepAr
                 const double ft = hi ? (vkp - vc) * m_idzw[mq + 1] : -vc * idzw_hi;
                 const double dzz = (ft - fb) * idzk;
                 const double gp = (L(FP, 0, 0, 0) - L(FP, 0, -1, 0)) * idy;
-                double r = cg * h - ca * gp + can * dzz;
+                double r = cg * h - ca * gp + cdn * dzz;
                 if (a.rho != 0.0) r += cr * hp[1];
-                st_out(a.rv + (id), r);
+                st_out(a.rv + (id), vc + r);
                 if (a.hv) st_out(a.hv + (id), h);
             }
             PS_EX_FENCE();
@@ -411,10 +418,14 @@ __global__ void __launch_bounds__(kExTX * kExTY) PS_EX_ATTR k_explicit(SubstepAr
                     const double az = (wkp - wkm) * (wtop + wbot) * sz;
                     const double h = (nux * (wip + wim - 2.0 * wc) + nuy * (wjp + wjm - 2.0 * wc) + tc) - (ax + ay + az);
                     const double dzz = ((wkp - wc) * idzk - (wc - wkm) * m_idz[mq]) * idzc;
+                    // the Crank-Nicolson operator has homogeneous wall rows: the wall values'
+                    // share of Dzz is left out of its beta term
+                    const double dzh = dzz - (k == 1 ? wkm * m_idz[mq] * idzc : 0.0) -
+                                       (k + 1 == nz ? wkp * idzk * idzc : 0.0);
                     const double gp = (L(FP, 0, 0, 0) - p_km) * idzc;
-                    double r = cg * h - ca * gp + can * dzz;
+                    double r = cg * h - ca * gp + can * dzz - a.bnu * dzh;
                     if (a.rho != 0.0) r += cr * hp[2];
-                    st_out(a.rw + (id), r);
+                    st_out(a.rw + (id), wc + r);
                     if (a.hw) st_out(a.hw + (id), h);
                 }
                 // T
@@ -424,9 +435,11 @@ __global__ void __launch_bounds__(kExTX * kExTY) PS_EX_ATTR k_explicit(SubstepAr
                     const double az = (wtop * (tc + tkp) - wbot * (tkm + tc)) * sz;
                     const double h = (kax * (tip + tim - 2.0 * tc) + kay * (tjp + tjm - 2.0 * tc)) - (ax + ay + az);
                     const double dzz = ((tkp - tc) * idzk - (tc - tkm) * m_idz[mq]) * idzc;
-                    double r = cg * h + cak * dzz;
+                    const double dzh = dzz - (k == 1 ? tkm * m_idz[mq] * idzc : 0.0) -
+                                       (k + 1 == nz ? tkp * idzk * idzc : 0.0);
+                    double r = cg * h + cak * dzz - a.bka * dzh;
                     if (a.rho != 0.0) r += cr * hp[3];
-                    st_out(a.rt + (id), r);
+                    st_out(a.rt + (id), tc + r);
                     if (a.ht) st_out(a.ht + (id), h);
                 }
             }
@@ -444,69 +457,6 @@ __global__ void __launch_bounds__(kExTX * kExTY) PS_EX_ATTR k_explicit(SubstepAr
         __syncthreads();
     }
 }
-
-// Crank-Nicolson solve with the column-independent LU factors (fac = [l, invd, c]),
-// rhs used as scratch, result added to q: q += (I - beta Dzz)^-1 rhs.
-__global__ void __launch_bounds__(256)
-k_cn_solve_add(GridDev g, int kind, const double* __restrict__ fac, double* __restrict__ rhs, double* __restrict__ q) {
-    const size_t plane = (size_t)g.nx * g.ny;
-    const size_t col = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (col >= plane) return;
-    const int n = kind == 0 ? g.nz : g.nz - 1;
-    const size_t off = (kind == 0 ? 0 : plane) + col;
-    const double* l = fac;
-    const double* invd = fac + n;
-    const double* cs = fac + 2 * n;
-    double* r = rhs + off;
-    double* x = q + off;
-    double y = r[0];
-    for (int k = 1; k < n; ++k) {
-        y = r[(size_t)k * plane] - l[k] * y;
-        r[(size_t)k * plane] = y;
-    }
-    double d = y * invd[n - 1];
-    x[(size_t)(n - 1) * plane] += d;
-    for (int k = n - 2; k >= 0; --k) {
-        d = (r[(size_t)k * plane] - cs[k] * d) * invd[k];
-        x[(size_t)k * plane] += d;
-    }
-}
-
-// out = V (I - beta Dzz)^-1 V^-1 in: the transpose of the CN solve (V = dz for centre
-// fields, dzc for interior faces; V (I - beta Dzz) is symmetric).  Face walls -> 0.
-__global__ void __launch_bounds__(256)
-k_cn_solve_t(GridDev g, int kind, const double* __restrict__ fac, const double* __restrict__ in,
-             double* __restrict__ out) {
-    const size_t plane = (size_t)g.nx * g.ny;
-    const size_t col = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (col >= plane) return;
-    const int n = kind == 0 ? g.nz : g.nz - 1;
-    const int ko = kind == 0 ? 0 : 1;
-    const double* wv = kind == 0 ? g.dz : g.dzc;
-    const double* l = fac;
-    const double* invd = fac + n;
-    const double* cs = fac + 2 * n;
-    const double* r = in + (size_t)ko * plane + col;
-    double* x = out + (size_t)ko * plane + col;
-    double y = r[0] / wv[ko];
-    x[0] = y;
-    for (int k = 1; k < n; ++k) {
-        y = r[(size_t)k * plane] / wv[k + ko] - l[k] * y;
-        x[(size_t)k * plane] = y;
-    }
-    double d = y * invd[n - 1];
-    x[(size_t)(n - 1) * plane] = d * wv[n - 1 + ko];
-    for (int k = n - 2; k >= 0; --k) {
-        d = (x[(size_t)k * plane] - cs[k] * d) * invd[k];
-        x[(size_t)k * plane] = d * wv[k + ko];
-    }
-    if (kind == 1) {
-        out[col] = 0.0;
-        out[(size_t)g.nz * plane + col] = 0.0;
-    }
-}
-
-
 
 // Vector-Jacobian product of the explicit right-hand sides, gathered per output
 // point.  For a control-volume equation sum_faces +-F_f / h with cotangent kappa,
@@ -580,6 +530,10 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
     const double idx2 = idx * idx, idy2 = idy * idy;
     const double muc = a.dt * a.gam;        // mu = dt gamma lambda + gH
     const double cal = a.dt * a.alp;        // weight of the alpha terms (on lambda)
+    // The direct cotangent of q* (q* = C^-1 (C q + rhs), C = I - beta Dzz~) is C^T lambda =
+    // lambda - beta Dzz~^T lambda, formed here from lambda instead of being read: with the
+    // rhs's alpha-weighted Dzz^T it gives lambda + (dt alpha nu - beta) Dzz^T lambda.
+    const double cdn = cal * a.nu - a.bnu, cdk = cal * a.ka - a.bka;
     // plane kk of the state, lambda and gH into registers (zeros outside a field); the loaded
     // values are not touched until put() blends mu = dt gamma lambda + gH into the ring, so
     // that every load of the stage stays in flight together
@@ -645,10 +599,10 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
         put(k + 1, st);
         __syncthreads();
         const size_t id = (size_t)k * plane + (size_t)j * g.nx + i;
-        // direct cotangents of this cell, and lambda for the next step, loaded before the
+        // the direct pressure cotangent of this cell, and lambda for the next step, loaded before the
         // next plane's prefetch (cells outside the box read the plane's first cell)
         const size_t idd = valid ? id : (size_t)k * plane;
-        double dd[5] = {a.du[idd], a.dv[idd], a.dw[idd], a.dt_[idd], a.dp[idd]};
+        const double dpc = a.dp[idd];
         double nu_ = 0.0, nv_ = 0.0, nw_ = 0.0, nt_ = 0.0, nuip = 0.0, nvjp = 0.0;
         if constexpr (GHV) {
             nu_ = lcol(a.lu, k + 2, false);
@@ -759,7 +713,7 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
                 const double mc = MU(k, 0, 0);
                 const double hd = a.nu * ((MU(k, 0, 1) - 2.0 * mc + MU(k, 0, -1)) * idx2 +
                                           (MU(k, 1, 0) - 2.0 * mc + MU(k, -1, 0)) * idy2);
-                st_out(a.gu + (id), dd[0] + s + hd + cal * a.nu * dzzt_c(lum, lu0, lup));
+                st_out(a.gu + (id), lu0 + s + hd + cdn * dzzt_c(lum, lu0, lup));
             }
             // ================= g_v at (k, j, i) =================
             {
@@ -800,14 +754,14 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
                 const double mc = MV(k, 0, 0);
                 const double hd = a.nu * ((MV(k, 0, 1) - 2.0 * mc + MV(k, 0, -1)) * idx2 +
                                           (MV(k, 1, 0) - 2.0 * mc + MV(k, -1, 0)) * idy2);
-                st_out(a.gv + (id), dd[1] + s + hd + cal * a.nu * dzzt_c(lvm, lv0, lvp));
+                st_out(a.gv + (id), lv0 + s + hd + cdn * dzzt_c(lvm, lv0, lvp));
             }
             // ================= g_p at (k, j, i):  -dt alpha G^T lambda =================
             {
                 double gt = (lu0 - lu_ip) * idx + (lv0 - lv_jp) * idy;
                 if (k >= 1) gt += lw0 * m_o(k);
                 if (k + 1 <= nz - 1) gt -= lwp * m_o(k + 1);
-                st_out(a.gp + (id), dd[4] - cal * gt);
+                st_out(a.gp + (id), dpc - cal * gt);
             }
             // ================= g_w, g_T at z-face k (interior) =================
             if (k == 0) {
@@ -864,8 +818,8 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
                 const double mt = lt0 * idzc(k), mtm = ltm * idzc(k - 1), mtp = ltp * idzc(k + 1);
                 const double dzw_ = (mwp - mw) * m_idz(k) - (mw - mwm) * m_idz(k - 1);
                 const double dzt_ = (mtp - mt) * m_idz(k) - (mt - mtm) * m_idz(k - 1);
-                st_out(a.gw + (id), dd[2] + sw + hdw + cal * a.nu * dzw_);
-                st_out(a.gt + (id), dd[3] + st_ + hdt + cal * a.ka * dzt_ + mwc);
+                st_out(a.gw + (id), lw0 + sw + hdw + cdn * dzw_);
+                st_out(a.gt + (id), lt0 + st_ + hdt + cdk * dzt_ + mwc);
             }
             if (k + 1 == nz) {
                 st_out(a.gw + (id + plane), 0.0);
@@ -893,15 +847,6 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
     }
 }
 
-hipError_t launch_cn_solve_t(const GridDev& g, int kind, const double* fac, const double* in, double* out,
-                             hipStream_t st) {
-    hipError_t e;
-    if (launch_cn_tiled_t(g, kind, fac, in, out, st, &e)) return e;
-    const size_t plane = (size_t)g.nx * g.ny;
-    hipLaunchKernelGGL(k_cn_solve_t, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, st, g, kind, fac, in, out);
-    return hipGetLastError();
-}
-
 hipError_t launch_explicit_adj(const GridDev& g, const SubstepAdjArgs& a, hipStream_t st) {
     const dim3 grid(ex_blocks<kAdTX, kAdTY, kAdZSEG>(g)), block(kAdTX * kAdTY);
     if (a.ghu)
@@ -913,15 +858,6 @@ hipError_t launch_explicit_adj(const GridDev& g, const SubstepAdjArgs& a, hipStr
 
 hipError_t launch_explicit(const GridDev& g, const SubstepArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_explicit, dim3(ex_blocks<kExTX, kExTY, kExZSEG>(g)), dim3(kExTX * kExTY), 0, st, a, g);
-    return hipGetLastError();
-}
-
-hipError_t launch_cn_solve_add(const GridDev& g, int kind, const double* fac, double* rhs, double* q,
-                               hipStream_t st) {
-    hipError_t e;
-    if (launch_cn_tiled_add(g, kind, fac, rhs, q, st, &e)) return e;
-    const size_t plane = (size_t)g.nx * g.ny;
-    hipLaunchKernelGGL(k_cn_solve_add, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, st, g, kind, fac, rhs, q);
     return hipGetLastError();
 }
 

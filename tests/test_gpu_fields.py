@@ -162,6 +162,36 @@ def test_project_adjoint_vs_autograd(with_p):
     assert float(dw[0].abs().max()) == 0.0 and float(dw[-1].abs().max()) == 0.0
 
 
+@pytest.mark.parametrize("shape", [(48, 32, 24), (24, 6, 10), (96, 24, 40)])
+@pytest.mark.parametrize("with_p", [False, True])
+def test_project_adjoint_fused_rhs(shape, with_p):
+    """FP64 projection adjoints form the solve's right-hand side inside the x transform; with
+    the finiteness check it is stored first by its own kernel (the same arithmetic).  Both
+    match the oracle's VJP, and each other to rounding."""
+    nx, ny, nz = shape
+    banner(f"project adjoint fused rhs {shape} with_p={with_p}")
+    g, fused = grids(nx, ny, nz, 2.0, 2.0)
+    _, stored = grids(nx, ny, nz, 2.0, 2.0, flags=2)   # PS_FLAG_CHECK_FINITE
+    u, v, w = _modes(nx, ny, nz, 2.0, 2.0)
+    rng = np.random.default_rng(11)
+    gu = torch.as_tensor(rng.standard_normal(fused.centre_shape))
+    gv = torch.as_tensor(rng.standard_normal(fused.centre_shape))
+    gw = torch.as_tensor(rng.standard_normal(fused.face_shape))
+    gw[0] = 0
+    gw[-1] = 0
+    p = torch.zeros(fused.centre_shape, dtype=F64)
+    gp = torch.as_tensor(rng.standard_normal(fused.centre_shape)) if with_p else torch.zeros_like(p)
+    s, c = (0.4, 0.02) if with_p else (1.0, 0.0)
+    ref = _project_vjp(g, u, v, w, p, s, c, gu, gv, gw, gp)
+    outs = [plan.project_adjoint(*_cuda(gu, gv, gw), gp.to("cuda") if with_p else None, s, c)
+            for plan in (fused, stored)]
+    for a, b in zip(*outs):
+        assert rel(a, b) < 1e-14
+    du, dv, dw = outs[0]
+    assert rel(du, ref[0]) < 1e-12 and rel(dv, ref[1]) < 1e-12
+    assert rel(dw[1:-1], ref[2][1:-1]) < 1e-12
+
+
 def test_project_autograd_finite_difference():
     """ProjectFn backward (hand-written adjoint) vs central differences, h = 1e-6."""
     banner("project FD")
