@@ -310,8 +310,9 @@ k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny,
         } else if constexpr (LM == XL_ADJ) {
             // f = D (g / V) + (1/s) (g_p / dz - c Dzz (g_p / dz)) at the cells (2e, 2e + 1) of
             // row (z, y): g_u, g_v differenced forward in x / y, g_w / dzc at the cell's
-            // interior faces (wall faces carry none); every load unconditional (a missing z
-            // neighbour reads the row itself, an absent g_p reads g_u), terms selected away
+            // interior faces (o = 1/dzc is zero on the walls, which carry none); every load
+            // unconditional (a missing z neighbour reads the row itself, its weight o is zero;
+            // an absent g_p reads g_u), the row's metrics multiplied (no divisions)
             const int n = 2 * M;
             const size_t rb = (size_t)row * n;
             const bool hi = zg + 1 < g.nz, lo = zg > 0;
@@ -326,22 +327,17 @@ k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny,
             const double2 h0 = *reinterpret_cast<const double2*>(hp + rb + 2 * e);
             const double2 hu = *reinterpret_cast<const double2*>(hp + rb + (size_t)hi * plane + 2 * e);
             const double2 hd = *reinterpret_cast<const double2*>(hp + rb - (size_t)lo * plane + 2 * e);
-            const double idz = 1.0 / g.dz[zg];
-            const double dzc_t = g.dzc[hi ? zg + 1 : zg], dzc_b = g.dzc[zg];
-            const double dz_u = g.dz[hi ? zg + 1 : zg], dz_d = g.dz[lo ? zg - 1 : zg];
-            const double o_u = g.o[zg + 1], o_d = g.o[zg], dzk = g.dz[zg];
+            const double idz = g.idz[zg], o_u = g.o[zg + 1], o_d = g.o[zg];
+            const double idz_u = g.idz[hi ? zg + 1 : zg], idz_d = g.idz[lo ? zg - 1 : zg];
+            const double sx = idz / g.dx, sy = idz / g.dy;
             auto cell = [&](double u0, double u1, double v0, double v1, double w0, double w1, double c0, double cu,
                             double cd) {
-                const double du = (u1 - u0) * idz / g.dx;
-                const double dv = (v1 - v0) * idz / g.dy;
-                const double tt = hi ? w1 / dzc_t : 0.0;
-                const double bb = lo ? w0 / dzc_b : 0.0;
-                double val = du + dv + (tt - bb) / dzk;
+                double val = (u1 - u0) * sx + (v1 - v0) * sy + (w1 * o_u - w0 * o_d) * idz;
                 if (rin.gp) {
                     const double hc = c0 * idz;
-                    const double fp = hi ? (cu / dz_u - hc) * o_u : 0.0;
-                    const double fm = lo ? (hc - cd / dz_d) * o_d : 0.0;
-                    val += rin.div_scale * (hc - rin.adj_c * ((fp - fm) / dzk));
+                    const double fp = (cu * idz_u - hc) * o_u;
+                    const double fm = (hc - cd * idz_d) * o_d;
+                    val += rin.div_scale * (hc - rin.adj_c * ((fp - fm) * idz));
                 }
                 return val;
             };

@@ -141,121 +141,170 @@ __global__ void __launch_bounds__(256) k_cn_factor(GridDev g, CnFactorJobs jobs)
     }
 }
 
-// Tiled CN solve: a block holds 64 consecutive columns (one per lane) and all n rows,
-// wave w owning rows [w KZ, w KZ + KZ).  With the shared LU factors the forward sweep
-// y_r = x_r - l_r y_{r-1} and the backward sweep d_r = invd_r (y_r - c_r d_{r+1}) are
-// affine maps whose slopes do not depend on the column, so each wave runs its chunk
-// from a zero entry value, the chunk results are combined across waves through LDS, and
-// each wave adds (running product of slopes) x (true entry value).  Every value is read
-// and written once.  One launch per field: with the factors a __restrict__ kernel argument
-// their per-row loads are scalar loads (selecting them per block from an argument struct
-// turned them into vector loads, 1.35 -> 1.87 ms per field at 768^2 x 512).
+// Tiled CN solve: a block holds 32 consecutive columns and all n <= 512 rows, split into
+// up to 32 z-chunks of KZ rows; each wave holds two chunks (lanes 0-31 and 32-63, each half
+// reading 256-byte rows), so a lane keeps KZ = 16 rows of a 512-row column and two blocks
+// fit one CU (64 VGPRs): one block's loads run under the other's sweeps (0.96 ms per field
+// at 768^2 x 512, against 1.10 ms with 64 columns and 32 rows per lane, one block per CU).
+// With the shared LU factors the forward sweep y_r = x_r - l_r y_{r-1} and the backward
+// sweep d_r = invd_r (y_r - c_r d_{r+1}) are affine maps whose slopes do not depend on the
+// column, so each chunk runs from a zero entry value, the chunk results are combined across
+// chunks through LDS, and each row adds (product of slopes) x (true entry value).  Every
+// value is read and written once.  The factors (and V, 1/V) are staged in LDS, as are the
+// within-chunk slope products; the halves' rows differ, so neither can be a scalar operand.
+// Rows past the column's end reuse the last row's factors (its backward coupling is zero,
+// so nothing flows back from them): they read zero and are not stored.  One launch per
+// field.
 //   CN_PUT: out = C^-1 in on the solved rows (face walls untouched; in may alias out)
 //   CN_SET: as CN_PUT, and the two wall rows of face fields zeroed
 //   CN_T:   out = V C^-1 V^-1 in (V = dz for centre fields, dzc for interior faces), face
 //           walls zeroed; with out2, also out2 = c2 out
+constexpr int kCnHalfRows = 512;
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
 template <int KZ, int MODE>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
 k_cn_tiled(GridDev g, int kind, const double* __restrict__ fac, const double* __restrict__ wv,
-           const double* __restrict__ iwv, const double* in, double* out, double* out2, double c2) {
-    __shared__ double bs[16][64];
-    __shared__ double as[16];
+          const double* __restrict__ iwv, const double* in, double* out, double* out2, double c2) {
+    __shared__ double bs[32][32];
+    __shared__ double pf[kCnHalfRows], pbk[kCnHalfRows];   // running slopes within each chunk
+    __shared__ double f_l[kCnHalfRows], f_d[kCnHalfRows], f_c[kCnHalfRows];
+    __shared__ double f_w[MODE == CN_T ? kCnHalfRows : 1], f_iw[MODE == CN_T ? kCnHalfRows : 1];
     const size_t plane = (size_t)g.nx * g.ny;
     const int n = kind == 0 ? g.nz : g.nz - 1;
     const int ko = kind == 0 ? 0 : 1;
-    const double* l = fac;
-    const double* invd = fac + n;
-    const double* cs = fac + 2 * n;
-    // the wave index is uniform, so the per-row factors (and CN_T's weights V and 1/V, also
-    // __restrict__ arguments) are scalar loads
-    const int lane = threadIdx.x & 63, nwave = blockDim.x >> 6;
+    const int nch = (blockDim.x >> 6) * 2;
+    // factors of rows 0 .. nch KZ - 1 (rows past the end repeat the last row's)
+    for (int q = threadIdx.x; q < nch * KZ; q += blockDim.x) {
+        const int r = min(q, n - 1);
+        f_l[q] = fac[r];
+        f_d[q] = fac[n + r];
+        f_c[q] = fac[2 * n + r];
+        if constexpr (MODE == CN_T) {
+            f_w[q] = wv[r + ko];
+            f_iw[q] = iwv[r + ko];
+        }
+    }
+    const int lane = threadIdx.x & 63, hf = lane >> 5, cl = lane & 31;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const size_t col = (size_t)xcd_remap(blockIdx.x, gridDim.x) * 64 + lane;
-    const bool valid = col < plane;
-    const size_t base = (size_t)ko * plane + col;
-    const size_t basec = (size_t)ko * plane + (valid ? col : 0);   // in range for every lane
-    const int r0 = wave * KZ;
+    const int ch = 2 * wave + hf;            // this lane's chunk
+    const int c0 = xcd_remap(blockIdx.x, gridDim.x) * 32;   // the block's first column
+    const bool valid = c0 + cl < (int)plane;
+    const int r0 = ch * KZ;
+    // this chunk's rows of the staged tables (LDS reads at each use; the barriers between the
+    // phases keep them from being held in registers across a phase)
+    const double* vl = f_l + r0;
+    const double* vd = f_d + r0;
+    const double* vc = f_c + r0;
+    const double* vw = f_w + (MODE == CN_T ? r0 : 0);
+    const double* viw = f_iw + (MODE == CN_T ? r0 : 0);
+    // Buffer accesses: base at the wave's first row and the block's first column, the lane's
+    // offset (its half's chunk, its column) in one register, the row in a scalar offset.  The
+    // buffer ends at the column's last row n - 1 (clamped to 4 GiB, which a wave's 2 KZ rows
+    // can only exceed when all of them lie inside), so rows past it read zero and their stores
+    // are dropped.
+    const int rw = 2 * wave * KZ;
+    const size_t pb = ((size_t)ko + rw) * plane + c0;
+    const size_t lim = n > rw ? (size_t)(n - rw) * plane * sizeof(double) : 0;
+    const int nrec = (int)(lim > 0xffffffffull ? 0xffffffffull : lim);
+    const int voff = (int)(((size_t)hf * KZ * plane + cl) * sizeof(double));
+    const int soff = (int)(plane * sizeof(double));
+    const __amdgpu_buffer_rsrc_t rin = __builtin_amdgcn_make_buffer_rsrc((void*)(in + pb), (short)0, nrec, 0x00020000);
     double x[KZ];
-    // unconditional loads (clamped row and column) of which every lane's are in flight
-    // together; values of rows r >= n and of lanes past the plane are never used
 #pragma unroll
-    for (int i = 0; i < KZ; ++i) x[i] = in[basec + (size_t)min(r0 + i, n - 1) * plane];
+    for (int i = 0; i < KZ; ++i)
+        x[i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rin, valid ? voff : 0, i * soff, 0));
 #pragma unroll
     for (int i = 0; i < KZ; ++i) anchor(x[i]);
+    __syncthreads();   // tables staged
+    // The slopes of the affine sweeps do not depend on the column: within each chunk, the
+    // product of -l from its first row down to row r (forward) and of -c invd from its last
+    // row up to row r (backward), formed once per block; a chunk's whole slope is the
+    // product at its far end.
+    if (threadIdx.x < nch) {
+        const int rb = threadIdx.x * KZ;
+        double q = 1.0;
+        for (int i = 0; i < KZ; ++i) {
+            q *= -f_l[rb + i];
+            pf[rb + i] = q;
+        }
+        q = 1.0;
+        for (int i = KZ - 1; i >= 0; --i) {
+            q *= -f_c[rb + i] * f_d[rb + i];
+            pbk[rb + i] = q;
+        }
+    }
     if constexpr (MODE == CN_T) {
 #pragma unroll
-        for (int i = 0; i < KZ; ++i)
-            if (r0 + i < n) x[i] *= iwv[r0 + i + ko];
+        for (int i = 0; i < KZ; ++i) x[i] *= viw[i];
     }
-    // forward sweep from a zero entry value
-    double b = 0.0, a = 1.0;
+    // forward sweep from a zero entry value (the table reads are fenced in groups of four, so
+    // that the compiler does not hoist a whole phase's reads into registers)
+    double b = 0.0;
 #pragma unroll
     for (int i = 0; i < KZ; ++i) {
-        const int r = r0 + i;
-        if (r < n) {
-            b = x[i] - l[r] * b;   // l[0] = 0
-            a *= -l[r];
-            x[i] = b;
-        }
+        if (i % 4 == 0) asm volatile("" ::: "memory");
+        b = x[i] - vl[i] * b;   // l[0] = 0
+        x[i] = b;
     }
-    bs[wave][lane] = b;
-    if (lane == 0) as[wave] = a;
+    bs[ch][cl] = b;
     __syncthreads();
     double yin = 0.0;
-    for (int v = 0; v < wave; ++v) yin = as[v] * yin + bs[v][lane];
-    double pr = 1.0;
+#pragma unroll 4
+    for (int v = 0; v < nch - 1; ++v) {
+        const double t = pf[v * KZ + KZ - 1] * yin + bs[v][cl];
+        yin = v < ch ? t : yin;
+    }
+    const double* vpf = pf + r0;
 #pragma unroll
     for (int i = 0; i < KZ; ++i) {
-        const int r = r0 + i;
-        if (r < n) {
-            pr *= -l[r];
-            x[i] += pr * yin;
-        }
+        if (i % 4 == 0) asm volatile("" ::: "memory");
+        x[i] += vpf[i] * yin;
     }
     __syncthreads();
     // backward sweep from a zero entry value (cs[n-1] = 0)
     b = 0.0;
-    a = 1.0;
 #pragma unroll
     for (int i = KZ - 1; i >= 0; --i) {
-        const int r = r0 + i;
-        if (r < n) {
-            b = (x[i] - cs[r] * b) * invd[r];
-            a *= -cs[r] * invd[r];
-            x[i] = b;
-        }
+        if (i % 4 == 3) asm volatile("" ::: "memory");
+        b = (x[i] - vc[i] * b) * vd[i];
+        x[i] = b;
     }
-    bs[wave][lane] = b;
-    if (lane == 0) as[wave] = a;
+    bs[ch][cl] = b;
     __syncthreads();
     double din = 0.0;
-    for (int v = nwave - 1; v > wave; --v) din = as[v] * din + bs[v][lane];
-    pr = 1.0;
+#pragma unroll 4
+    for (int v = nch - 1; v > 0; --v) {
+        const double t = pbk[v * KZ] * din + bs[v][cl];
+        din = v > ch ? t : din;
+    }
+    const double* vpb = pbk + r0;
 #pragma unroll
     for (int i = KZ - 1; i >= 0; --i) {
-        const int r = r0 + i;
-        if (r < n) {
-            pr *= -cs[r] * invd[r];
-            x[i] += pr * din;
-        }
+        if (i % 4 == 3) asm volatile("" ::: "memory");
+        x[i] += vpb[i] * din;
     }
     if (!valid) return;
     if (MODE != CN_T) out2 = nullptr;
+    const __amdgpu_buffer_rsrc_t rout = __builtin_amdgcn_make_buffer_rsrc((void*)(out + pb), (short)0, nrec, 0x00020000);
 #pragma unroll
     for (int i = 0; i < KZ; ++i) {
-        const int r = r0 + i;
-        if (r < n) {
-            const size_t o = base + (size_t)r * plane;
-            if (MODE == CN_T) {
-                const double y = x[i] * wv[r + ko];
-                out[o] = y;
-                if (out2) out2[o] = c2 * y;
-            } else {
-                out[o] = x[i];
-            }
+        if (MODE == CN_T) {
+            const double y = x[i] * vw[i];
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, y), rout, voff, i * soff, 0);
+        } else {
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, x[i]), rout, voff, i * soff, 0);
         }
     }
-    if (MODE != CN_PUT && kind == 1 && wave == 0) {
+    if (out2) {
+        const __amdgpu_buffer_rsrc_t rout2 = __builtin_amdgcn_make_buffer_rsrc((void*)(out2 + pb), (short)0, nrec, 0x00020000);
+#pragma unroll
+        for (int i = 0; i < KZ; ++i) {
+            const double y = c2 * (x[i] * vw[i]);
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, y), rout2, voff, i * soff, 0);
+        }
+    }
+    const size_t col = (size_t)c0 + cl;
+    if (MODE != CN_PUT && kind == 1 && ch == 0) {
         out[col] = 0.0;
         out[(size_t)g.nz * plane + col] = 0.0;
         if (out2) {
@@ -265,7 +314,8 @@ k_cn_tiled(GridDev g, int kind, const double* __restrict__ fac, const double* __
     }
 }
 
-// Lane-per-column form for columns taller than the tiled kernel holds (one job per launch).
+// Lane-per-column form for columns taller than the tiled kernel holds (nz > 512; one job per
+// launch).
 //   put:   out = C^-1 in on the solved rows (in may alias out; face walls untouched)
 //   trans: out = V C^-1 V^-1 in, face walls zeroed (and out2 = c2 out when given)
 __global__ void __launch_bounds__(256) k_cn_column(GridDev g, CnJob jb, int trans) {
@@ -307,29 +357,21 @@ __global__ void __launch_bounds__(256) k_cn_column(GridDev g, CnJob jb, int tran
     }
 }
 
-// Rows per wave of the tiled kernel for columns of up to nz rows (16 waves at most); 0 when
-// the columns are taller than 16 x 32 rows.
-static int cn_rows_per_wave(int nz) {
-    for (int c : {4, 8, 16, 32})
-        if ((nz + c - 1) / c <= 16) return c;
-    return 0;
-}
-
 template <int MODE>
-static hipError_t cn_tiled_launch(const GridDev& g, const CnJob& j, int kz, hipStream_t st) {
+static hipError_t cn_tiled_launch(const GridDev& g, const CnJob& j, hipStream_t st) {
     const size_t plane = (size_t)g.nx * g.ny;
     const int n = j.kind == 0 ? g.nz : g.nz - 1;
-    const dim3 grid((unsigned)((plane + 63) / 64));
-    const dim3 block(64 * ((n + kz - 1) / kz));
-    // CN_T's weights: V = dz (centre rows) or dzc (interior faces), and 1/V
+    const int kz = n <= 128 ? 4 : (n <= 256 ? 8 : 16);
+    const int nch = (n + kz - 1) / kz;
+    const dim3 grid((unsigned)((plane + 31) / 32));
+    const dim3 block(64 * ((nch + 1) / 2));
     const double* wv = j.kind == 0 ? g.dz : g.dzc;
     const double* iwv = j.kind == 0 ? g.idz : g.o;
 #define PS_CN_ARGS g, j.kind, j.fac, wv, iwv, j.in, j.out, j.out2, j.c2
     switch (kz) {
         case 4: hipLaunchKernelGGL((k_cn_tiled<4, MODE>), grid, block, 0, st, PS_CN_ARGS); break;
         case 8: hipLaunchKernelGGL((k_cn_tiled<8, MODE>), grid, block, 0, st, PS_CN_ARGS); break;
-        case 16: hipLaunchKernelGGL((k_cn_tiled<16, MODE>), grid, block, 0, st, PS_CN_ARGS); break;
-        default: hipLaunchKernelGGL((k_cn_tiled<32, MODE>), grid, block, 0, st, PS_CN_ARGS); break;
+        default: hipLaunchKernelGGL((k_cn_tiled<16, MODE>), grid, block, 0, st, PS_CN_ARGS); break;
     }
 #undef PS_CN_ARGS
     return hipGetLastError();
@@ -455,24 +497,23 @@ k_adj_rhs(const double* __restrict__ gu, const double* __restrict__ gv, const do
     const int ip = (i + 1 == g.nx) ? 0 : i + 1;
     const int jp = (j + 1 == g.ny) ? 0 : j + 1;
     // unconditional loads (a missing z neighbour reads the cell itself, gp absent reads
-    // gu), absent terms selected away: all loads in flight together
+    // gu), absent terms weighted by o = 0 (walls) or selected away: all loads in flight
+    // together; the same arithmetic as the fused loader of the x transform
     const bool lo = k > 0, hi = k + 1 < g.nz;
-    const double idz = 1.0 / g.dz[k];
+    const double idz = g.idz[k], o_u = g.o[k + 1], o_d = g.o[k];
+    const double idz_u = g.idz[hi ? k + 1 : k], idz_d = g.idz[lo ? k - 1 : k];
+    const double sx = idz / g.dx, sy = idz / g.dy;
     const double gu0 = gu[id], gu1 = gu[(size_t)k * plane + (size_t)j * g.nx + ip];
     const double gv0 = gv[id], gv1 = gv[(size_t)k * plane + (size_t)jp * g.nx + i];
     const double gwt = gw[id + plane], gwb = gw[id];
     const double* hp = gp ? gp : gu;
     const double h0 = hp[id], hu = hp[hi ? id + plane : id], hd = hp[lo ? id - plane : id];
-    const double du = (gu1 - gu0) * idz / g.dx;
-    const double dv = (gv1 - gv0) * idz / g.dy;
-    const double wt = hi ? gwt / g.dzc[k + 1] : 0.0;
-    const double wb = lo ? gwb / g.dzc[k] : 0.0;
-    double val = du + dv + (wt - wb) / g.dz[k];
+    double val = (gu1 - gu0) * sx + (gv1 - gv0) * sy + (gwt * o_u - gwb * o_d) * idz;
     if (gp) {
         const double hc = h0 * idz;
-        const double fp = hi ? (hu / g.dz[k + 1] - hc) * g.o[k + 1] : 0.0;
-        const double fm = lo ? (hc - hd / g.dz[k - 1]) * g.o[k] : 0.0;
-        val += inv_s * (hc - c * ((fp - fm) / g.dz[k]));
+        const double fp = (hu * idz_u - hc) * o_u;
+        const double fm = (hc - hd * idz_d) * o_d;
+        val += inv_s * (hc - c * ((fp - fm) * idz));
     }
     f[id] = val;
 }
@@ -493,8 +534,9 @@ k_adj_update(const double* __restrict__ gu, const double* __restrict__ gv, const
     const double pjm = phi[(size_t)k * plane + (size_t)jm * g.nx + i];
     const double pkm = phi[lo ? id - plane : id];
     const double gu0 = gu[id], gv0 = gv[id], gw0 = gw[id];
-    ou[id] = gu0 - g.dz[k] * ((pc - pim) / g.dx);
-    ov[id] = gv0 - g.dz[k] * ((pc - pjm) / g.dy);
+    const double idx = 1.0 / g.dx, idy = 1.0 / g.dy;
+    ou[id] = gu0 - g.dz[k] * ((pc - pim) * idx);
+    ov[id] = gv0 - g.dz[k] * ((pc - pjm) * idy);
     ow[id] = lo ? gw0 - (pc - pkm) : 0.0;
     if (k + 1 == g.nz) ow[id + plane] = 0.0;
 }
@@ -620,14 +662,13 @@ hipError_t launch_cn_factor(const GridDev& g, const CnFactorJobs& jobs, hipStrea
 
 hipError_t launch_cn_jobs(const GridDev& g, int mode, const CnJobs& jobs, hipStream_t st) {
     if (jobs.n < 1 || jobs.n > 4) return hipErrorInvalidValue;
-    const int kz = cn_rows_per_wave(g.nz);
-    if (kz > 0) {
+    if (g.nz <= kCnHalfRows) {
         for (int q = 0; q < jobs.n; ++q) {
             hipError_t e;
             switch (mode) {
-                case CN_PUT: e = cn_tiled_launch<CN_PUT>(g, jobs.j[q], kz, st); break;
-                case CN_SET: e = cn_tiled_launch<CN_SET>(g, jobs.j[q], kz, st); break;
-                default: e = cn_tiled_launch<CN_T>(g, jobs.j[q], kz, st); break;
+                case CN_PUT: e = cn_tiled_launch<CN_PUT>(g, jobs.j[q], st); break;
+                case CN_SET: e = cn_tiled_launch<CN_SET>(g, jobs.j[q], st); break;
+                default: e = cn_tiled_launch<CN_T>(g, jobs.j[q], st); break;
             }
             if (e != hipSuccess) return e;
         }

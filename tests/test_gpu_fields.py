@@ -166,8 +166,9 @@ def test_project_adjoint_vs_autograd(with_p):
 @pytest.mark.parametrize("with_p", [False, True])
 def test_project_adjoint_fused_rhs(shape, with_p):
     """FP64 projection adjoints form the solve's right-hand side inside the x transform; with
-    the finiteness check it is stored first by its own kernel (the same arithmetic).  Both
-    match the oracle's VJP, and each other to rounding."""
+    the finiteness check it is stored first by its own kernel (the same formula; the two
+    compilations may contract it into FMAs differently).  Both match the oracle's VJP, and
+    each other to the rounding of the right-hand side amplified by the solve (1e-13)."""
     nx, ny, nz = shape
     banner(f"project adjoint fused rhs {shape} with_p={with_p}")
     g, fused = grids(nx, ny, nz, 2.0, 2.0)
@@ -186,7 +187,7 @@ def test_project_adjoint_fused_rhs(shape, with_p):
     outs = [plan.project_adjoint(*_cuda(gu, gv, gw), gp.to("cuda") if with_p else None, s, c)
             for plan in (fused, stored)]
     for a, b in zip(*outs):
-        assert rel(a, b) < 1e-14
+        assert rel(a, b) < 1e-13
     du, dv, dw = outs[0]
     assert rel(du, ref[0]) < 1e-12 and rel(dv, ref[1]) < 1e-12
     assert rel(dw[1:-1], ref[2][1:-1]) < 1e-12
