@@ -330,16 +330,17 @@ k_xfwd(const double* __restrict__ f, cx<T>* __restrict__ out, int nrows, int ny,
             const double idz = g.idz[zg], o_u = g.o[zg + 1], o_d = g.o[zg];
             const double idz_u = g.idz[hi ? zg + 1 : zg], idz_d = g.idz[lo ? zg - 1 : zg];
             const double sx = idz / g.dx, sy = idz / g.dy;
+            // the pressure terms are formed unconditionally and weighted by zero without g_p:
+            // a term under a branch would sink its loads into the branch, and the wave would
+            // wait for them there
+            const double gw = rin.gp ? rin.div_scale : 0.0;
             auto cell = [&](double u0, double u1, double v0, double v1, double w0, double w1, double c0, double cu,
                             double cd) {
-                double val = (u1 - u0) * sx + (v1 - v0) * sy + (w1 * o_u - w0 * o_d) * idz;
-                if (rin.gp) {
-                    const double hc = c0 * idz;
-                    const double fp = (cu * idz_u - hc) * o_u;
-                    const double fm = (hc - cd * idz_d) * o_d;
-                    val += rin.div_scale * (hc - rin.adj_c * ((fp - fm) * idz));
-                }
-                return val;
+                const double val = (u1 - u0) * sx + (v1 - v0) * sy + (w1 * o_u - w0 * o_d) * idz;
+                const double hc = c0 * idz;
+                const double fp = (cu * idz_u - hc) * o_u;
+                const double fm = (hc - cd * idz_d) * o_d;
+                return val + gw * (hc - rin.adj_c * ((fp - fm) * idz));
             };
             v.x = cell(uc.x, uc.y, vc.x, vp.x, wb.x, wt.x, h0.x, hu.x, hd.x);
             v.y = cell(uc.y, ur, vc.y, vp.y, wb.y, wt.y, h0.y, hu.y, hd.y);

@@ -508,14 +508,13 @@ k_adj_rhs(const double* __restrict__ gu, const double* __restrict__ gv, const do
     const double gwt = gw[id + plane], gwb = gw[id];
     const double* hp = gp ? gp : gu;
     const double h0 = hp[id], hu = hp[hi ? id + plane : id], hd = hp[lo ? id - plane : id];
-    double val = (gu1 - gu0) * sx + (gv1 - gv0) * sy + (gwt * o_u - gwb * o_d) * idz;
-    if (gp) {
-        const double hc = h0 * idz;
-        const double fp = (hu * idz_u - hc) * o_u;
-        const double fm = (hc - hd * idz_d) * o_d;
-        val += inv_s * (hc - c * ((fp - fm) * idz));
-    }
-    f[id] = val;
+    const double val = (gu1 - gu0) * sx + (gv1 - gv0) * sy + (gwt * o_u - gwb * o_d) * idz;
+    // pressure terms formed unconditionally, weighted by zero without gp (no branch to sink
+    // their loads into)
+    const double hc = h0 * idz;
+    const double fp = (hu * idz_u - hc) * o_u;
+    const double fm = (hc - hd * idz_d) * o_d;
+    f[id] = val + (gp ? inv_s : 0.0) * (hc - c * ((fp - fm) * idz));
 }
 
 __global__ void __launch_bounds__(256)
