@@ -235,7 +235,10 @@ k_cn_tiled(GridDev g, int kind, const double* __restrict__ fac, const double* __
     }
     if constexpr (MODE == CN_T) {
 #pragma unroll
-        for (int i = 0; i < KZ; ++i) x[i] *= viw[i];
+        for (int i = 0; i < KZ; ++i) {
+            if (i % 4 == 0) asm volatile("" ::: "memory");
+            x[i] *= viw[i];
+        }
     }
     // forward sweep from a zero entry value (the table reads are fenced in groups of four, so
     // that the compiler does not hoist a whole phase's reads into registers)
@@ -286,21 +289,18 @@ k_cn_tiled(GridDev g, int kind, const double* __restrict__ fac, const double* __
     if (!valid) return;
     if (MODE != CN_T) out2 = nullptr;
     const __amdgpu_buffer_rsrc_t rout = __builtin_amdgcn_make_buffer_rsrc((void*)(out + pb), (short)0, nrec, 0x00020000);
+    // (out2 is uniform: a scalar branch per row; each row's value dies after its stores)
+    const __amdgpu_buffer_rsrc_t rout2 =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(out2 ? out2 + pb : out + pb), (short)0, nrec, 0x00020000);
 #pragma unroll
     for (int i = 0; i < KZ; ++i) {
         if (MODE == CN_T) {
+            if (i % 4 == 0) asm volatile("" ::: "memory");
             const double y = x[i] * vw[i];
             __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, y), rout, voff, i * soff, 0);
+            if (out2) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, c2 * y), rout2, voff, i * soff, 0);
         } else {
             __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, x[i]), rout, voff, i * soff, 0);
-        }
-    }
-    if (out2) {
-        const __amdgpu_buffer_rsrc_t rout2 = __builtin_amdgcn_make_buffer_rsrc((void*)(out2 + pb), (short)0, nrec, 0x00020000);
-#pragma unroll
-        for (int i = 0; i < KZ; ++i) {
-            const double y = c2 * (x[i] * vw[i]);
-            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, y), rout2, voff, i * soff, 0);
         }
     }
     const size_t col = (size_t)c0 + cl;
