@@ -94,6 +94,7 @@ struct ps_plan_s {
     size_t npts;          // nx * ny * nz
     size_t plane;         // nx * ny
     double sum_dz;
+    double dzz_max;       // max over rows of the off-diagonal sum of Dzz (centre and face)
     // host metrics
     std::vector<double> zf, dz, dzc, o, dzw, lamx, lamy, inv_dz, inv_dzw;
     // device tables (one allocation)
@@ -304,6 +305,10 @@ const double kRho[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
 
 // Crank-Nicolson factor slots (3 (nz+1) doubles each): 0 centre, 1 face, 2 face (diffusivity)
 double* cn_slot(ps_plan_t p, int s) { return p->cnfac + (size_t)s * 3 * (p->nz + 1); }
+
+// Largest beta times Dzz's row sum for which the substep solves q* = C^-1 (C q + rhs): the
+// solve's rounding, relative to q, then stays near 1e-13 (eps times the operator's spread).
+constexpr double kCnSetFormMax = 256.0;
 
 // Factors of a substep's three Crank-Nicolson operators (one launch): slot 0 the velocity's
 // centre rows, slot 1 its face rows (w), slot 2 the temperature's face rows.
@@ -616,10 +621,14 @@ ps_status substep_impl(ps_plan_t p, int l, double dt, double nu, double kappa, d
     a.rho = rho;
     a.alp = alp;
     const double bnu = alp * dt * nu / 2.0, bka = alp * dt * kappa / 2.0;
-    a.bnu = bnu;
-    a.bka = bka;
+    // q* = C^-1 (C q + rhs) reads one field less than q* = q + C^-1 rhs, but its rounding is
+    // relative to q rather than to the increment: it is used while C stays close to the
+    // identity (beta times Dzz's largest row sum <= kCnSetFormMax), the add form otherwise
+    const bool set_form = std::max(bnu, bka) * p->dzz_max <= kCnSetFormMax;
+    a.cq = set_form ? 1 : 0;
+    a.bnu = set_form ? bnu : 0.0;
+    a.bka = set_form ? bka : 0.0;
     PS_HIP(launch_explicit(p->gd, a, st), "explicit terms");
-    // the explicit kernel wrote s = C q + rhs: q* = C^-1 s, all fields in one launch
     PS_HIP(substep_factors(p, bnu, bka, st), "cn factor");
     CnJobs jobs{};
     jobs.j[0] = CnJob{cn_slot(p, 0), ru, u, nullptr, 0.0, PS_CENTER};
@@ -627,7 +636,7 @@ ps_status substep_impl(ps_plan_t p, int l, double dt, double nu, double kappa, d
     jobs.j[2] = CnJob{cn_slot(p, 1), rw, w, nullptr, 0.0, PS_FACE};
     jobs.j[3] = CnJob{cn_slot(p, 2), rt, t, nullptr, 0.0, PS_FACE};
     jobs.n = advance_t ? 4 : 3;
-    PS_HIP(launch_cn_jobs(p->gd, CN_PUT, jobs, st), "cn solves");
+    PS_HIP(launch_cn_jobs(p->gd, set_form ? CN_PUT : CN_ADD, jobs, st), "cn solves");
     return project(p, u, v, w, pr, nullptr, alp * dt, bnu, stream, info);
 }
 
@@ -694,6 +703,12 @@ ps_status poisson_plan_create(ps_plan_t* out, int nx, int ny, int nz, double lx,
         sdz += p->dz[k];
     }
     p->sum_dz = sdz;
+    // largest off-diagonal sum of Dzz's rows (centre and interior-face operators): beta times it
+    // bounds how far the Crank-Nicolson operator I - beta Dzz is from the identity
+    double dmax = 0.0;
+    for (int k = 0; k < nz; ++k) dmax = std::max(dmax, 1.0 / (p->dzw[k] * p->dz[k]) + 1.0 / (p->dzw[k + 1] * p->dz[k]));
+    for (int k = 1; k < nz; ++k) dmax = std::max(dmax, 1.0 / (p->dz[k - 1] * p->dzc[k]) + 1.0 / (p->dz[k] * p->dzc[k]));
+    p->dzz_max = dmax;
     const long double pi = 3.141592653589793238462643383279502884L;
     p->lamx.resize(nx / 2 + 1);
     for (int k = 0; k <= nx / 2; ++k) {
@@ -1333,6 +1348,7 @@ struct ps_mr_s {
     MrDev md;
     void* d_tab = nullptr;
     double* cnfac;        // Crank-Nicolson factors of the temperature grid, 3 (nzf + 1)
+    double dzz_max;       // max over interior faces of Dzz's off-diagonal sum on the temperature grid
     double* buf = nullptr;
     double *u0, *v0, *w0, *u1, *v1, *w1, *rt, *h, *tc;
 };
@@ -1418,6 +1434,8 @@ ps_status mr_create(ps_mr_t* out, ps_plan_t p, int rx, int ry, int rz, int nsub)
     dzwf[0] = 0.5 * dzf[0];
     dzwf[nzf] = 0.5 * dzf[nzf - 1];
     for (int k = 0; k <= nzf; ++k) idzwf[k] = 1.0 / dzwf[k];
+    m->dzz_max = 0.0;
+    for (int k = 1; k < nzf; ++k) m->dzz_max = std::max(m->dzz_max, 1.0 / (dzf[k - 1] * dzcf[k]) + 1.0 / (dzf[k] * dzcf[k]));
     // slope stencil distances and local pseudo-inverses per momentum level
     const int ns = rx * ry * rz;
     std::vector<double> zc(nz), zhm(nz), zhp(nz), linv((size_t)nz * ns * ns);
@@ -1569,19 +1587,22 @@ ps_status mr_tstep(ps_mr_t m, double dt, double kappa, const double* const* v0, 
             a.gam = gam;
             a.rho = rho;
             a.alp = alp;
-            a.bka = alp * dts * kappa / 2.0;
+            const double bka = alp * dts * kappa / 2.0;
+            const bool set_form = bka * m->dzz_max <= kCnSetFormMax;   // as in the momentum substep
+            a.cq = set_form ? 1 : 0;
+            a.bka = set_form ? bka : 0.0;
             PS_HIP(launch_mr_explicit_t(m->gf, a, st), "temperature explicit terms");
             CnFactorJobs fj{};
             fj.fac[0] = m->cnfac;
-            fj.beta[0] = a.bka;
+            fj.beta[0] = bka;
             fj.kind[0] = PS_FACE;
             fj.n = 1;
             PS_HIP(launch_cn_factor(m->gf, fj, st), "cn factor");
-            // rt holds C T + rhs: T* = C^-1 rt on the interior faces
+            // rt holds C T + rhs (T* = C^-1 rt) or rhs alone (T* = T + C^-1 rt)
             CnJobs jobs{};
             jobs.j[0] = CnJob{m->cnfac, m->rt, tf, nullptr, 0.0, PS_FACE};
             jobs.n = 1;
-            PS_HIP(launch_cn_jobs(m->gf, CN_PUT, jobs, st), "cn solve T");
+            PS_HIP(launch_cn_jobs(m->gf, set_form ? CN_PUT : CN_ADD, jobs, st), "cn solve T");
         }
     return PS_OK;
 }

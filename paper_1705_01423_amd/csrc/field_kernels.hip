@@ -156,6 +156,7 @@ __global__ void __launch_bounds__(256) k_cn_factor(GridDev g, CnFactorJobs jobs)
 // so nothing flows back from them): they read zero and are not stored.  One launch per
 // field.
 //   CN_PUT: out = C^-1 in on the solved rows (face walls untouched; in may alias out)
+//   CN_ADD: out += C^-1 in on the solved rows (the old values read in groups of four rows)
 //   CN_SET: as CN_PUT, and the two wall rows of face fields zeroed
 //   CN_T:   out = V C^-1 V^-1 in (V = dz for centre fields, dzc for interior faces), face
 //           walls zeroed; with out2, also out2 = c2 out
@@ -292,6 +293,23 @@ k_cn_tiled(GridDev g, int kind, const double* __restrict__ fac, const double* __
     // (out2 is uniform: a scalar branch per row; each row's value dies after its stores)
     const __amdgpu_buffer_rsrc_t rout2 =
         __builtin_amdgcn_make_buffer_rsrc((void*)(out2 ? out2 + pb : out + pb), (short)0, nrec, 0x00020000);
+    if constexpr (MODE == CN_ADD) {
+        // rows in groups of four: their old values loaded together, then added and stored
+#pragma unroll
+        for (int i0 = 0; i0 < KZ; i0 += 4) {
+            double ov[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                ov[i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rout, voff, (i0 + i) * soff, 0));
+#pragma unroll
+            for (int i = 0; i < 4; ++i) anchor(ov[i]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, ov[i] + x[i0 + i]), rout, voff,
+                                                      (i0 + i) * soff, 0);
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < KZ; ++i) {
         if (MODE == CN_T) {
@@ -316,9 +334,10 @@ k_cn_tiled(GridDev g, int kind, const double* __restrict__ fac, const double* __
 
 // Lane-per-column form for columns taller than the tiled kernel holds (nz > 512; one job per
 // launch).
-//   put:   out = C^-1 in on the solved rows (in may alias out; face walls untouched)
-//   trans: out = V C^-1 V^-1 in, face walls zeroed (and out2 = c2 out when given)
-__global__ void __launch_bounds__(256) k_cn_column(GridDev g, CnJob jb, int trans) {
+//   mode 0: out = C^-1 in on the solved rows (in may alias out; face walls untouched)
+//   mode 1: out = V C^-1 V^-1 in, face walls zeroed (and out2 = c2 out when given)
+//   mode 2: out += C^-1 in on the solved rows, in used as scratch
+__global__ void __launch_bounds__(256) k_cn_column(GridDev g, CnJob jb, int mode) {
     const size_t plane = (size_t)g.nx * g.ny;
     const size_t col = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (col >= plane) return;
@@ -329,6 +348,23 @@ __global__ void __launch_bounds__(256) k_cn_column(GridDev g, CnJob jb, int tran
     const double* l = jb.fac;
     const double* invd = jb.fac + n;
     const double* cs = jb.fac + 2 * n;
+    const int trans = mode == 1;
+    if (mode == 2) {
+        double* r = const_cast<double*>(jb.in) + (size_t)ko * plane + col;
+        double* q = jb.out + (size_t)ko * plane + col;
+        double y = r[0];
+        for (int k = 1; k < n; ++k) {
+            y = r[(size_t)k * plane] - l[k] * y;
+            r[(size_t)k * plane] = y;
+        }
+        double d = y * invd[n - 1];
+        q[(size_t)(n - 1) * plane] += d;
+        for (int k = n - 2; k >= 0; --k) {
+            d = (r[(size_t)k * plane] - cs[k] * d) * invd[k];
+            q[(size_t)k * plane] += d;
+        }
+        return;
+    }
     const double* r = jb.in + (size_t)ko * plane + col;
     double* x = jb.out + (size_t)ko * plane + col;
     double y = trans ? r[0] / wv[ko] : r[0];
@@ -666,6 +702,7 @@ hipError_t launch_cn_jobs(const GridDev& g, int mode, const CnJobs& jobs, hipStr
             hipError_t e;
             switch (mode) {
                 case CN_PUT: e = cn_tiled_launch<CN_PUT>(g, jobs.j[q], st); break;
+                case CN_ADD: e = cn_tiled_launch<CN_ADD>(g, jobs.j[q], st); break;
                 case CN_SET: e = cn_tiled_launch<CN_SET>(g, jobs.j[q], st); break;
                 default: e = cn_tiled_launch<CN_T>(g, jobs.j[q], st); break;
             }
@@ -676,7 +713,8 @@ hipError_t launch_cn_jobs(const GridDev& g, int mode, const CnJobs& jobs, hipStr
     const size_t plane = (size_t)g.nx * g.ny;
     for (int q = 0; q < jobs.n; ++q) {
         CnJob jb = jobs.j[q];
-        hipLaunchKernelGGL(k_cn_column, dim3(nblocks(plane, 256)), dim3(256), 0, st, g, jb, mode == CN_T ? 1 : 0);
+        hipLaunchKernelGGL(k_cn_column, dim3(nblocks(plane, 256)), dim3(256), 0, st, g, jb,
+                           mode == CN_T ? 1 : (mode == CN_ADD ? 2 : 0));
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         if (mode == CN_SET && jb.kind == 1) {

@@ -215,7 +215,8 @@ k_mr_restrict(const double* __restrict__ tf, double* __restrict__ tc, int nx, in
 // z-marching over 32 x 8 column tiles with a three-plane LDS ring of u, v, w, T (the velocity
 // staged as (1 - th) vel0 + th vel1), as in k_explicit.  Writes the Crank-Nicolson input
 // rt = C T + dt [gamma H + rho Hprev + alpha kappa Dzz T] on interior faces (C = I - bka Dzz~,
-// Dzz~ with zero wall values; walls 0, never read by the solve) and H (optional).
+// Dzz~ with zero wall values; walls 0, never read by the solve), or the bracket alone when
+// cq = 0 (bka is then 0 too), and H (optional).
 constexpr int kMtTX = 32, kMtTY = 8, kMtZSEG = 64;
 
 template <int NF, int TX, int TY>
@@ -351,7 +352,8 @@ __global__ void __launch_bounds__(kMtTX * kMtTY) k_mr_explicit_t(MrTArgs a, Grid
                                    (k + 1 == nz ? tkp * m_idz[mq + 1] * idzc : 0.0);
                 double r = a.gam * h + a.alp * (a.ka * dzz);
                 if (a.rho != 0.0) r += a.rho * hp;
-                __builtin_nontemporal_store(tc + (a.dt * r - a.bka * dzh), a.rt + id);
+                const double rr = a.dt * r - a.bka * dzh;
+                __builtin_nontemporal_store(a.cq ? tc + rr : rr, a.rt + id);
                 if (a.hout) __builtin_nontemporal_store(h, a.hout + id);
             }
             if (k + 1 == nz) {

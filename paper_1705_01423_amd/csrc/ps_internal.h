@@ -267,10 +267,12 @@ hipError_t launch_cn_factor(const GridDev& g, const CnFactorJobs& jobs, hipStrea
 // Crank-Nicolson column solves with factored operators C = I - beta Dzz, up to four fields
 // (one launch each).
 //   CN_PUT: out = C^-1 in on the solved rows (face walls untouched; in may alias out)
+//   CN_ADD: out += C^-1 in on the solved rows (in and out distinct; columns taller than 512
+//           rows use in as scratch)
 //   CN_SET: as CN_PUT, and the wall rows of face fields zeroed
 //   CN_T:   out = V C^-1 V^-1 in (the transpose: V = dz for centre fields, dzc for faces),
 //           face walls zeroed; with out2 != NULL also out2 = c2 out
-enum { CN_PUT = 0, CN_SET = 1, CN_T = 2 };
+enum { CN_PUT = 0, CN_SET = 1, CN_T = 2, CN_ADD = 3 };
 struct CnJob {
     const double* fac;
     const double* in;
@@ -299,10 +301,11 @@ hipError_t launch_absmax(const double* p, size_t n, size_t plane, const double* 
 struct SubstepArgs {
     const double *u, *v, *w, *t, *p;
     const double *hpu, *hpv, *hpw, *hpt;   // previous H (rho != 0)
-    double *ru, *rv, *rw, *rt;             // Crank-Nicolson inputs C q + rhs
+    double *ru, *rv, *rw, *rt;             // Crank-Nicolson inputs: C q + rhs (cq = 1) or rhs (cq = 0)
     double *hu, *hv, *hw, *ht;             // this substep's H (optional)
     double dt, nu, ka, gam, rho, alp;
-    double bnu, bka;                       // Crank-Nicolson beta of the velocity and of T
+    double bnu, bka;                       // Crank-Nicolson beta of the velocity and of T (0 when cq = 0)
+    int cq;
 };
 
 struct SubstepAdjArgs {
@@ -332,9 +335,10 @@ struct MrTArgs {
     const double *u1, *v1, *w1;  // ... and at its end
     const double* t;             // temperature (fine z-faces)
     const double* hp;            // previous substep's H (rho != 0)
-    double* rt;                  // Crank-Nicolson input C T + rhs (C = I - bka Dzz~)
+    double* rt;                  // Crank-Nicolson input: C T + rhs (C = I - bka Dzz~; cq = 1) or rhs
     double* hout;                // this substep's H (optional; may alias hp)
     double th, dt, ka, gam, rho, alp, bka;
+    int cq;
 };
 bool mr_factors_supported(int rx, int ry, int rz);
 hipError_t launch_mr_prolong(const GridDev& g, const MrDev& m, const double* u, const double* v, const double* w,

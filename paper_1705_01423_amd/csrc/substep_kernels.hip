@@ -7,7 +7,9 @@
 // The explicit kernel writes s_q = C q + rhs_q with C = I - alpha dt nu/2 Dzz~ (Dzz~: Dzz
 // with zero wall values, the operator of the Crank-Nicolson rows), so that the solve is
 // q* = C^-1 s_q: the same q* = q + C^-1 rhs_q, but the solve reads one field and writes
-// one instead of reading two (8 B per point and field less).
+// one instead of reading two (8 B per point and field less).  Its rounding is relative to q,
+// not to the increment, so when C is far from the identity (large beta over fine wall
+// cells) the kernel writes rhs_q itself and the solve adds (cq = 0).
 //   projection of (u*, v*, w*) with s = alpha dt, c = alpha dt nu / 2
 //
 // Advection A is the conservative central form on the staggered grid: for each
@@ -359,7 +361,7 @@ __global__ void __launch_bounds__(kExTX * kExTY) PS_EX_ATTR k_explicit(SubstepAr
                 const double gp = (L(FP, 0, 0, 0) - L(FP, 0, 0, -1)) * idx;
                 double r = cg * h - ca * gp + cdn * dzz;
                 if (a.rho != 0.0) r += cr * hp[0];
-                st_out(a.ru + (id), uc + r);
+                st_out(a.ru + (id), a.cq ? uc + r : r);
                 if (a.hu) st_out(a.hu + (id), h);
             }
             // (the three blocks run one after the other: their LDS reads are not hoisted
@@ -384,7 +386,7 @@ __global__ void __launch_bounds__(kExTX * kExTY) PS_EX_ATTR k_explicit(SubstepAr
                 const double gp = (L(FP, 0, 0, 0) - L(FP, 0, -1, 0)) * idy;
                 double r = cg * h - ca * gp + cdn * dzz;
                 if (a.rho != 0.0) r += cr * hp[1];
-                st_out(a.rv + (id), vc + r);
+                st_out(a.rv + (id), a.cq ? vc + r : r);
                 if (a.hv) st_out(a.hv + (id), h);
             }
             PS_EX_FENCE();
@@ -425,7 +427,7 @@ __global__ void __launch_bounds__(kExTX * kExTY) PS_EX_ATTR k_explicit(SubstepAr
                     const double gp = (L(FP, 0, 0, 0) - p_km) * idzc;
                     double r = cg * h - ca * gp + can * dzz - a.bnu * dzh;
                     if (a.rho != 0.0) r += cr * hp[2];
-                    st_out(a.rw + (id), wc + r);
+                    st_out(a.rw + (id), a.cq ? wc + r : r);
                     if (a.hw) st_out(a.hw + (id), h);
                 }
                 // T
@@ -439,7 +441,7 @@ __global__ void __launch_bounds__(kExTX * kExTY) PS_EX_ATTR k_explicit(SubstepAr
                                        (k + 1 == nz ? tkp * idzk * idzc : 0.0);
                     double r = cg * h + cak * dzz - a.bka * dzh;
                     if (a.rho != 0.0) r += cr * hp[3];
-                    st_out(a.rt + (id), tc + r);
+                    st_out(a.rt + (id), a.cq ? tc + r : r);
                     if (a.ht) st_out(a.ht + (id), h);
                 }
             }
