@@ -320,9 +320,10 @@ __global__ void __launch_bounds__(kMtTX * kMtTY) k_mr_explicit_t(MrTArgs a, Grid
         put(k + 1);
         __syncthreads();
         const size_t id = (size_t)k * plane + (size_t)j * g.nx + i;
-        // previous H (substep 1 reads T in its place and drops it), then the next plane's
-        // prefetch, both unconditional (the last step fetches a clamped plane it never stores)
-        const double hp = (a.rho != 0.0 ? a.hp : a.t)[valid ? id : (size_t)k * plane];
+        // previous H (substep 1 reads T's first value, one cache line for every lane, in its place
+        // and drops it), then the next plane's prefetch, both unconditional (the last step
+        // fetches a clamped plane it never stores)
+        const double hp = (a.rho != 0.0 ? a.hp : a.t)[a.rho != 0.0 ? (valid ? id : (size_t)k * plane) : 0];
         asm volatile("" ::: "memory");
         fetch(k + 2);
         if (valid) {
