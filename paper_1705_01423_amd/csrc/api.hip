@@ -311,9 +311,11 @@ double* cn_slot(ps_plan_t p, int s) { return p->cnfac + (size_t)s * 3 * (p->nz +
 constexpr double kCnSetFormMax = 256.0;
 
 // Factors of a substep's three Crank-Nicolson operators (one launch): slot 0 the velocity's
-// centre rows, slot 1 its face rows (w), slot 2 the temperature's face rows.
-hipError_t substep_factors(ps_plan_t p, double bnu, double bka, hipStream_t st) {
+// centre rows, slot 1 its face rows (w), slot 2 the temperature's face rows; of their
+// transposes for the adjoint.
+hipError_t substep_factors(ps_plan_t p, double bnu, double bka, hipStream_t st, bool transpose = false) {
     CnFactorJobs fj{};
+    fj.trans = transpose ? 1 : 0;
     fj.fac[0] = cn_slot(p, 0);
     fj.beta[0] = bnu;
     fj.kind[0] = PS_CENTER;
@@ -1099,7 +1101,7 @@ ps_status rk3_substep_adjoint(ps_plan_t p, int l, double dt, double nu, double k
     if (hprev_fused)
         for (int q = 0; q < 4; ++q) h2[q] = g_hprev[q];
     const double crho = dt * rho;
-    PS_HIP(substep_factors(p, bnu, bka, st), "cn factor");
+    PS_HIP(substep_factors(p, bnu, bka, st, true), "cn factor (transposed)");
     CnJobs jobs{};
     jobs.j[0] = CnJob{cn_slot(p, 0), du, lu, h2[0], crho, PS_CENTER};
     jobs.j[1] = CnJob{cn_slot(p, 0), dv, lv, h2[1], crho, PS_CENTER};

@@ -102,13 +102,15 @@ __global__ void k_scale_planes(const double* in, double* out,
 // kind 0 (centre): n = nz rows, wall half a cell beyond the end centres.
 // kind 1 (face):   n = nz - 1 interior faces.
 // The off-diagonal coupling coefficients are formed in parallel into LDS (nz <= 2048),
-// then one thread runs the LU recurrence; one block per factorisation (up to four).
+// then one thread runs the LU recurrence; one block per factorisation (up to four), of C or
+// (trans) of its transpose.
 __global__ void __launch_bounds__(256) k_cn_factor(GridDev g, CnFactorJobs jobs) {
-    __shared__ double am_s[2048], ap_s[2048];
+    __shared__ double am_s[2048], ap_s[2048], sub_s[2048], sup_s[2048];
     const int jy = blockIdx.x;
     const int kind = jy == 0 ? jobs.kind[0] : (jy == 1 ? jobs.kind[1] : (jy == 2 ? jobs.kind[2] : jobs.kind[3]));
     const double beta = jy == 0 ? jobs.beta[0] : (jy == 1 ? jobs.beta[1] : (jy == 2 ? jobs.beta[2] : jobs.beta[3]));
     double* fac = jy == 0 ? jobs.fac[0] : (jy == 1 ? jobs.fac[1] : (jy == 2 ? jobs.fac[2] : jobs.fac[3]));
+    const bool tr = jobs.trans != 0;
     const int n = kind == 0 ? g.nz : g.nz - 1;
     for (int r = threadIdx.x; r < n; r += blockDim.x) {
         if (kind == 0) {
@@ -121,23 +123,29 @@ __global__ void __launch_bounds__(256) k_cn_factor(GridDev g, CnFactorJobs jobs)
         }
     }
     __syncthreads();
+    // C couples row r to r - 1 by -beta am_r and to r + 1 by -beta ap_r; its transpose couples
+    // row r to r - 1 by -beta ap_{r-1} and to r + 1 by -beta am_{r+1}.  The couplings are formed
+    // in parallel; the LU recurrence then only reads them.
+    double* cs = fac + 2 * n;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) {
+        sub_s[r] = (r == 0) ? 0.0 : -beta * (tr ? ap_s[r - 1] : am_s[r]);
+        const double sup = (r == n - 1) ? 0.0 : -beta * (tr ? am_s[r + 1] : ap_s[r]);
+        sup_s[r] = sup;
+        cs[r] = sup;
+    }
+    __syncthreads();
     if (threadIdx.x != 0) return;
     double* l = fac;
     double* invd = fac + n;
-    double* cs = fac + 2 * n;
     double dprev = 1.0, cprev = 0.0;
     for (int r = 0; r < n; ++r) {
-        const double am = am_s[r], ap = ap_s[r];
-        const double diag = 1.0 + beta * (am + ap);
-        const double sub = (r == 0) ? 0.0 : -beta * am;
-        const double sup = (r == n - 1) ? 0.0 : -beta * ap;
-        const double lr = (r == 0) ? 0.0 : sub / dprev;
+        const double diag = 1.0 + beta * (am_s[r] + ap_s[r]);
+        const double lr = (r == 0) ? 0.0 : sub_s[r] / dprev;
         const double d = diag - lr * cprev;
         l[r] = lr;
         invd[r] = 1.0 / d;
-        cs[r] = sup;
         dprev = d;
-        cprev = sup;
+        cprev = sup_s[r];
     }
 }
 
@@ -150,26 +158,26 @@ __global__ void __launch_bounds__(256) k_cn_factor(GridDev g, CnFactorJobs jobs)
 // sweep d_r = invd_r (y_r - c_r d_{r+1}) are affine maps whose slopes do not depend on the
 // column, so each chunk runs from a zero entry value, the chunk results are combined across
 // chunks through LDS, and each row adds (product of slopes) x (true entry value).  Every
-// value is read and written once.  The factors (and V, 1/V) are staged in LDS, as are the
-// within-chunk slope products; the halves' rows differ, so neither can be a scalar operand.
+// value is read and written once.  The factors are staged in LDS, as are the within-chunk
+// slope products; the halves' rows differ, so neither can be a scalar operand.
 // Rows past the column's end reuse the last row's factors (its backward coupling is zero,
 // so nothing flows back from them): they read zero and are not stored.  One launch per
 // field.
 //   CN_PUT: out = C^-1 in on the solved rows (face walls untouched; in may alias out)
 //   CN_ADD: out += C^-1 in on the solved rows (the old values read in groups of four rows)
 //   CN_SET: as CN_PUT, and the two wall rows of face fields zeroed
-//   CN_T:   out = V C^-1 V^-1 in (V = dz for centre fields, dzc for interior faces), face
-//           walls zeroed; with out2, also out2 = c2 out
+//   CN_T:   out = C^-T in, given the factors of C^T (the transpose of the solve, which
+//           also equals V C^-1 V^-1 with V = dz for centre fields, dzc for interior faces);
+//           face walls zeroed; with out2, also out2 = c2 out
 constexpr int kCnHalfRows = 512;
 typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
-template <int KZ, int MODE>
+template <int KZ, int MODE, bool O2 = false>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
-k_cn_tiled(GridDev g, int kind, const double* __restrict__ fac, const double* __restrict__ wv,
-          const double* __restrict__ iwv, const double* in, double* out, double* out2, double c2) {
+k_cn_tiled(GridDev g, int kind, const double* __restrict__ fac, const double* in, double* out, double* out2,
+           double c2) {
     __shared__ double bs[32][32];
     __shared__ double pf[kCnHalfRows], pbk[kCnHalfRows];   // running slopes within each chunk
     __shared__ double f_l[kCnHalfRows], f_d[kCnHalfRows], f_c[kCnHalfRows];
-    __shared__ double f_w[MODE == CN_T ? kCnHalfRows : 1], f_iw[MODE == CN_T ? kCnHalfRows : 1];
     const size_t plane = (size_t)g.nx * g.ny;
     const int n = kind == 0 ? g.nz : g.nz - 1;
     const int ko = kind == 0 ? 0 : 1;
@@ -180,10 +188,6 @@ k_cn_tiled(GridDev g, int kind, const double* __restrict__ fac, const double* __
         f_l[q] = fac[r];
         f_d[q] = fac[n + r];
         f_c[q] = fac[2 * n + r];
-        if constexpr (MODE == CN_T) {
-            f_w[q] = wv[r + ko];
-            f_iw[q] = iwv[r + ko];
-        }
     }
     const int lane = threadIdx.x & 63, hf = lane >> 5, cl = lane & 31;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -196,8 +200,6 @@ k_cn_tiled(GridDev g, int kind, const double* __restrict__ fac, const double* __
     const double* vl = f_l + r0;
     const double* vd = f_d + r0;
     const double* vc = f_c + r0;
-    const double* vw = f_w + (MODE == CN_T ? r0 : 0);
-    const double* viw = f_iw + (MODE == CN_T ? r0 : 0);
     // Buffer accesses: base at the wave's first row and the block's first column, the lane's
     // offset (its half's chunk, its column) in one register, the row in a scalar offset.  The
     // buffer ends at the column's last row n - 1 (clamped to 4 GiB, which a wave's 2 KZ rows
@@ -232,13 +234,6 @@ k_cn_tiled(GridDev g, int kind, const double* __restrict__ fac, const double* __
         for (int i = KZ - 1; i >= 0; --i) {
             q *= -f_c[rb + i] * f_d[rb + i];
             pbk[rb + i] = q;
-        }
-    }
-    if constexpr (MODE == CN_T) {
-#pragma unroll
-        for (int i = 0; i < KZ; ++i) {
-            if (i % 4 == 0) asm volatile("" ::: "memory");
-            x[i] *= viw[i];
         }
     }
     // forward sweep from a zero entry value (the table reads are fenced in groups of four, so
@@ -288,11 +283,10 @@ k_cn_tiled(GridDev g, int kind, const double* __restrict__ fac, const double* __
         x[i] += vpb[i] * din;
     }
     if (!valid) return;
-    if (MODE != CN_T) out2 = nullptr;
+    // the second output only in its own instantiation (O2), which keeps it out of the others'
+    // registers
+    if (!(MODE == CN_T && O2)) out2 = nullptr;
     const __amdgpu_buffer_rsrc_t rout = __builtin_amdgcn_make_buffer_rsrc((void*)(out + pb), (short)0, nrec, 0x00020000);
-    // (out2 is uniform: a scalar branch per row; each row's value dies after its stores)
-    const __amdgpu_buffer_rsrc_t rout2 =
-        __builtin_amdgcn_make_buffer_rsrc((void*)(out2 ? out2 + pb : out + pb), (short)0, nrec, 0x00020000);
     if constexpr (MODE == CN_ADD) {
         // rows in groups of four: their old values loaded together, then added and stored
 #pragma unroll
@@ -311,15 +305,13 @@ k_cn_tiled(GridDev g, int kind, const double* __restrict__ fac, const double* __
         return;
     }
 #pragma unroll
-    for (int i = 0; i < KZ; ++i) {
-        if (MODE == CN_T) {
-            if (i % 4 == 0) asm volatile("" ::: "memory");
-            const double y = x[i] * vw[i];
-            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, y), rout, voff, i * soff, 0);
-            if (out2) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, c2 * y), rout2, voff, i * soff, 0);
-        } else {
-            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, x[i]), rout, voff, i * soff, 0);
-        }
+    for (int i = 0; i < KZ; ++i)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, x[i]), rout, voff, i * soff, 0);
+    if constexpr (MODE == CN_T && O2) {
+        const __amdgpu_buffer_rsrc_t rout2 = __builtin_amdgcn_make_buffer_rsrc((void*)(out2 + pb), (short)0, nrec, 0x00020000);
+#pragma unroll
+        for (int i = 0; i < KZ; ++i)
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, c2 * x[i]), rout2, voff, i * soff, 0);
     }
     const size_t col = (size_t)c0 + cl;
     if (MODE != CN_PUT && kind == 1 && ch == 0) {
@@ -335,7 +327,7 @@ k_cn_tiled(GridDev g, int kind, const double* __restrict__ fac, const double* __
 // Lane-per-column form for columns taller than the tiled kernel holds (nz > 512; one job per
 // launch).
 //   mode 0: out = C^-1 in on the solved rows (in may alias out; face walls untouched)
-//   mode 1: out = V C^-1 V^-1 in, face walls zeroed (and out2 = c2 out when given)
+//   mode 1: as mode 0 with the factors of C^T, face walls zeroed (and out2 = c2 out when given)
 //   mode 2: out += C^-1 in on the solved rows, in used as scratch
 __global__ void __launch_bounds__(256) k_cn_column(GridDev g, CnJob jb, int mode) {
     const size_t plane = (size_t)g.nx * g.ny;
@@ -344,7 +336,6 @@ __global__ void __launch_bounds__(256) k_cn_column(GridDev g, CnJob jb, int mode
     const int kind = jb.kind;
     const int n = kind == 0 ? g.nz : g.nz - 1;
     const int ko = kind == 0 ? 0 : 1;
-    const double* wv = kind == 0 ? g.dz : g.dzc;
     const double* l = jb.fac;
     const double* invd = jb.fac + n;
     const double* cs = jb.fac + 2 * n;
@@ -367,18 +358,17 @@ __global__ void __launch_bounds__(256) k_cn_column(GridDev g, CnJob jb, int mode
     }
     const double* r = jb.in + (size_t)ko * plane + col;
     double* x = jb.out + (size_t)ko * plane + col;
-    double y = trans ? r[0] / wv[ko] : r[0];
+    double y = r[0];
     x[0] = y;
     for (int k = 1; k < n; ++k) {
-        const double rk = trans ? r[(size_t)k * plane] / wv[k + ko] : r[(size_t)k * plane];
-        y = rk - l[k] * y;
+        y = r[(size_t)k * plane] - l[k] * y;
         x[(size_t)k * plane] = y;
     }
     double d = y * invd[n - 1];
-    x[(size_t)(n - 1) * plane] = trans ? d * wv[n - 1 + ko] : d;
+    x[(size_t)(n - 1) * plane] = d;
     for (int k = n - 2; k >= 0; --k) {
         d = (x[(size_t)k * plane] - cs[k] * d) * invd[k];
-        x[(size_t)k * plane] = trans ? d * wv[k + ko] : d;
+        x[(size_t)k * plane] = d;
     }
     double* x2 = jb.out2 ? jb.out2 + (size_t)ko * plane + col : nullptr;
     if (trans && x2)
@@ -401,13 +391,22 @@ static hipError_t cn_tiled_launch(const GridDev& g, const CnJob& j, hipStream_t 
     const int nch = (n + kz - 1) / kz;
     const dim3 grid((unsigned)((plane + 31) / 32));
     const dim3 block(64 * ((nch + 1) / 2));
-    const double* wv = j.kind == 0 ? g.dz : g.dzc;
-    const double* iwv = j.kind == 0 ? g.idz : g.o;
-#define PS_CN_ARGS g, j.kind, j.fac, wv, iwv, j.in, j.out, j.out2, j.c2
-    switch (kz) {
-        case 4: hipLaunchKernelGGL((k_cn_tiled<4, MODE>), grid, block, 0, st, PS_CN_ARGS); break;
-        case 8: hipLaunchKernelGGL((k_cn_tiled<8, MODE>), grid, block, 0, st, PS_CN_ARGS); break;
-        default: hipLaunchKernelGGL((k_cn_tiled<16, MODE>), grid, block, 0, st, PS_CN_ARGS); break;
+#define PS_CN_ARGS g, j.kind, j.fac, j.in, j.out, j.out2, j.c2
+    bool o2 = false;
+    if constexpr (MODE == CN_T) o2 = j.out2 != nullptr;
+    if constexpr (MODE == CN_T) if (o2) {
+        switch (kz) {
+            case 4: hipLaunchKernelGGL((k_cn_tiled<4, MODE, true>), grid, block, 0, st, PS_CN_ARGS); break;
+            case 8: hipLaunchKernelGGL((k_cn_tiled<8, MODE, true>), grid, block, 0, st, PS_CN_ARGS); break;
+            default: hipLaunchKernelGGL((k_cn_tiled<16, MODE, true>), grid, block, 0, st, PS_CN_ARGS); break;
+        }
+    }
+    if (!o2) {
+        switch (kz) {
+            case 4: hipLaunchKernelGGL((k_cn_tiled<4, MODE>), grid, block, 0, st, PS_CN_ARGS); break;
+            case 8: hipLaunchKernelGGL((k_cn_tiled<8, MODE>), grid, block, 0, st, PS_CN_ARGS); break;
+            default: hipLaunchKernelGGL((k_cn_tiled<16, MODE>), grid, block, 0, st, PS_CN_ARGS); break;
+        }
     }
 #undef PS_CN_ARGS
     return hipGetLastError();

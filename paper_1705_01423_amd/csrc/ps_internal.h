@@ -255,13 +255,14 @@ hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, int ncu,
 hipError_t launch_scale(const double* in, double* out, double c, size_t n, hipStream_t st);
 hipError_t launch_scale_planes(const GridDev& g, const double* in, double* out, const double* zs, int nplanes,
                                size_t plane, hipStream_t st);
-// Factorisations of I - beta Dzz for up to four (kind, beta) pairs, one block each:
-// fac[q] = [l (n), invd (n), c (n)], n = nz (centre) or nz - 1 (face).
+// Factorisations of C = I - beta Dzz (or, trans != 0, of C^T) for up to four (kind, beta)
+// pairs, one block each: fac[q] = [l (n), invd (n), c (n)], n = nz (centre) or nz - 1 (face).
 struct CnFactorJobs {
     double* fac[4];
     double beta[4];
     int kind[4];
     int n;
+    int trans;
 };
 hipError_t launch_cn_factor(const GridDev& g, const CnFactorJobs& jobs, hipStream_t st);
 // Crank-Nicolson column solves with factored operators C = I - beta Dzz, up to four fields
@@ -270,8 +271,8 @@ hipError_t launch_cn_factor(const GridDev& g, const CnFactorJobs& jobs, hipStrea
 //   CN_ADD: out += C^-1 in on the solved rows (in and out distinct; columns taller than 512
 //           rows use in as scratch)
 //   CN_SET: as CN_PUT, and the wall rows of face fields zeroed
-//   CN_T:   out = V C^-1 V^-1 in (the transpose: V = dz for centre fields, dzc for faces),
-//           face walls zeroed; with out2 != NULL also out2 = c2 out
+//   CN_T:   out = C^-T in with the factors of C^T (the transpose of the solve), face walls
+//           zeroed; with out2 != NULL also out2 = c2 out
 enum { CN_PUT = 0, CN_SET = 1, CN_T = 2, CN_ADD = 3 };
 struct CnJob {
     const double* fac;
