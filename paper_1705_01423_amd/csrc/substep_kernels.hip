@@ -39,6 +39,21 @@ __device__ __forceinline__ void st_out(double* p, double v) {
         *p = v;
 }
 
+// Buffer accesses of one plane: the base (a field's plane, the same for the whole block) in
+// scalar registers and the lane's byte offset in one vector register, so that no per-access
+// 64-bit address arithmetic is spent (the plane offsets stay below 2^31 bytes).
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const double* base, size_t plane) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(plane * sizeof(double)), 0x00020000);
+}
+__device__ __forceinline__ double ld_plane(__amdgpu_buffer_rsrc_t r, unsigned boff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)boff, 0, 0));
+}
+__device__ __forceinline__ void st_plane(double* base, size_t plane, unsigned boff, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), plane_rsrc(base, plane), (int)boff, 0,
+                                          PS_EX_NT_STORE ? 2 : 0);   // 2: the non-temporal hint
+}
+
 }  // namespace
 
 
@@ -71,7 +86,8 @@ struct Ring {
         double v[NQ][NF];
     };
     struct Cols {
-        unsigned off[NQ];   // j * nx + i of the halo cell (a cell inside the tile for q >= PL)
+        unsigned off[NQ];    // j * nx + i of the halo cell (a cell inside the tile for q >= PL)
+        unsigned boff[NQ];   // the same in bytes
     };
     __device__ __forceinline__ static Cols columns(const GridDev& g, int i0, int j0) {
         Cols c;
@@ -83,6 +99,7 @@ struct Ring {
             gj = gj < 0 ? gj + g.ny : gj % g.ny;
             gi = gi < 0 ? gi + g.nx : gi % g.nx;
             c.off[qi] = (unsigned)gj * (unsigned)g.nx + (unsigned)gi;
+            c.boff[qi] = c.off[qi] * (unsigned)sizeof(double);
         }
         return c;
     }
@@ -158,9 +175,9 @@ struct WinRing {
             const int kc = k < 0 ? 0 : (k > g.nz - 1 ? g.nz - 1 : k);
             const int kf = k < 0 ? 0 : (k > g.nz ? g.nz : k);
             st.ok[f] = k >= 0 && (k < g.nz || (face[f] && k == g.nz));
-            const double* base_f = F[f] + (size_t)(face[f] ? kf : kc) * plane;
+            const __amdgpu_buffer_rsrc_t rs = plane_rsrc(F[f] + (size_t)(face[f] ? kf : kc) * plane, plane);
 #pragma unroll
-            for (int qi = 0; qi < NQ; ++qi) st.v[qi][f] = base_f[cols.off[qi]];
+            for (int qi = 0; qi < NQ; ++qi) st.v[qi][f] = ld_plane(rs, cols.boff[qi]);
         }
     }
     __device__ __forceinline__ void put(const int (&kk)[NF], const bool (&want)[NF], const Stage& st) {
@@ -301,6 +318,7 @@ __global__ void __launch_bounds__(kExTX * kExTY) PS_EX_ATTR k_explicit(SubstepAr
     }
     // own-column values at k - 1 of w (face), T (face) and p (cell); zero below the box
     const size_t own = valid ? (size_t)j * g.nx + i : 0;
+    const unsigned own_b = (unsigned)(own * sizeof(double));   // the thread's column in bytes
     double w_km = 0.0, t_km = 0.0, p_km = 0.0;
     if (kb > 0) {
         w_km = a.w[(size_t)(kb - 1) * plane + own];
@@ -313,7 +331,7 @@ __global__ void __launch_bounds__(kExTX * kExTY) PS_EX_ATTR k_explicit(SubstepAr
             R.put(pk, kAll, st);
         }
         __syncthreads();
-        const size_t id = (size_t)k * plane + (size_t)j * g.nx + i;
+        const size_t kp = (size_t)k * plane;   // this step's plane
         // Previous-substep H of this cell, loaded before the next plane's prefetch (cells
         // outside the box read the plane's first cell).  These loads and the prefetch are
         // unconditional (substep 1 has no H: it reads the first value of u, one cache line for
@@ -322,12 +340,13 @@ __global__ void __launch_bounds__(kExTX * kExTY) PS_EX_ATTR k_explicit(SubstepAr
         // and so wait for the whole prefetch.  (Reading u at the cell instead cost HBM traffic:
         // substep 1 fetched 74 B per point against 40 B of state.)
         const bool use_hp = a.rho != 0.0;
-        const size_t ih = use_hp ? (valid ? id : (size_t)k * plane) : 0;
+        const size_t hk = use_hp ? (size_t)k * plane : 0;
+        const unsigned hoff = use_hp ? own_b : 0u;
         double hp[4];
-        hp[0] = (use_hp ? a.hpu : a.u)[ih];
-        hp[1] = (use_hp ? a.hpv : a.u)[ih];
-        hp[2] = (use_hp ? a.hpw : a.u)[ih];
-        hp[3] = (use_hp ? a.hpt : a.u)[ih];
+        hp[0] = ld_plane(plane_rsrc((use_hp ? a.hpu : a.u) + hk, plane), hoff);
+        hp[1] = ld_plane(plane_rsrc((use_hp ? a.hpv : a.u) + hk, plane), hoff);
+        hp[2] = ld_plane(plane_rsrc((use_hp ? a.hpw : a.u) + hk, plane), hoff);
+        hp[3] = ld_plane(plane_rsrc((use_hp ? a.hpt : a.u) + hk, plane), hoff);
         asm volatile("" ::: "memory");   // issue order: H first, then the prefetch
         {
             const int pn[NF] = {k + 2, k + 2, k + 2, k + 2, k + 1};
@@ -363,8 +382,8 @@ __global__ void __launch_bounds__(kExTX * kExTY) PS_EX_ATTR k_explicit(SubstepAr
                 const double gp = (L(FP, 0, 0, 0) - L(FP, 0, 0, -1)) * idx;
                 double r = cg * h - ca * gp + cdn * dzz;
                 if (a.rho != 0.0) r += cr * hp[0];
-                st_out(a.ru + (id), a.cq ? uc + r : r);
-                if (a.hu) st_out(a.hu + (id), h);
+                st_plane(a.ru + kp, plane, own_b, a.cq ? uc + r : r);
+                if (a.hu) st_plane(a.hu + kp, plane, own_b, h);
             }
             // (the three blocks run one after the other: their LDS reads are not hoisted
             // together, which keeps the register count, and the occupancy, where the window's
@@ -388,18 +407,18 @@ __global__ void __launch_bounds__(kExTX * kExTY) PS_EX_ATTR k_explicit(SubstepAr
                 const double gp = (L(FP, 0, 0, 0) - L(FP, 0, -1, 0)) * idy;
                 double r = cg * h - ca * gp + cdn * dzz;
                 if (a.rho != 0.0) r += cr * hp[1];
-                st_out(a.rv + (id), a.cq ? vc + r : r);
-                if (a.hv) st_out(a.hv + (id), h);
+                st_plane(a.rv + kp, plane, own_b, a.cq ? vc + r : r);
+                if (a.hv) st_plane(a.hv + kp, plane, own_b, h);
             }
             PS_EX_FENCE();
             // ---- w and T at (x-centre i, y-centre j, z-face k), interior faces ----
             // (rt NULL: the temperature is not advanced, only its buoyancy is used)
             const bool with_t = a.rt != nullptr;
             if (k == 0) {
-                st_out(a.rw + (id), 0.0);
-                if (with_t) st_out(a.rt + (id), 0.0);
-                if (a.hw) st_out(a.hw + (id), 0.0);
-                if (a.ht && with_t) st_out(a.ht + (id), 0.0);
+                st_plane(a.rw + kp, plane, own_b, 0.0);
+                if (with_t) st_plane(a.rt + kp, plane, own_b, 0.0);
+                if (a.hw) st_plane(a.hw + kp, plane, own_b, 0.0);
+                if (a.ht && with_t) st_plane(a.ht + kp, plane, own_b, 0.0);
             } else {
                 const double dzm = m_dz[mq], dzp = m_dz[mq + 1], idzc = m_o[mq];   // o = 1/dzc (interior face)
                 // volume-weighted horizontal transport on the side faces (times 2 dzc)
@@ -429,8 +448,8 @@ __global__ void __launch_bounds__(kExTX * kExTY) PS_EX_ATTR k_explicit(SubstepAr
                     const double gp = (L(FP, 0, 0, 0) - p_km) * idzc;
                     double r = cg * h - ca * gp + can * dzz - a.bnu * dzh;
                     if (a.rho != 0.0) r += cr * hp[2];
-                    st_out(a.rw + (id), a.cq ? wc + r : r);
-                    if (a.hw) st_out(a.hw + (id), h);
+                    st_plane(a.rw + kp, plane, own_b, a.cq ? wc + r : r);
+                    if (a.hw) st_plane(a.hw + kp, plane, own_b, h);
                 }
                 // T
                 if (with_t) {
@@ -443,16 +462,15 @@ __global__ void __launch_bounds__(kExTX * kExTY) PS_EX_ATTR k_explicit(SubstepAr
                                        (k + 1 == nz ? tkp * idzk * idzc : 0.0);
                     double r = cg * h + cak * dzz - a.bka * dzh;
                     if (a.rho != 0.0) r += cr * hp[3];
-                    st_out(a.rt + (id), a.cq ? tc + r : r);
-                    if (a.ht) st_out(a.ht + (id), h);
+                    st_plane(a.rt + kp, plane, own_b, a.cq ? tc + r : r);
+                    if (a.ht) st_plane(a.ht + kp, plane, own_b, h);
                 }
             }
             if (k + 1 == nz) {
-                const size_t top = id + plane;
-                st_out(a.rw + (top), 0.0);
-                if (with_t) st_out(a.rt + (top), 0.0);
-                if (a.hw) st_out(a.hw + (top), 0.0);
-                if (a.ht && with_t) st_out(a.ht + (top), 0.0);
+                st_plane(a.rw + kp + plane, plane, own_b, 0.0);
+                if (with_t) st_plane(a.rt + kp + plane, plane, own_b, 0.0);
+                if (a.hw) st_plane(a.hw + kp + plane, plane, own_b, 0.0);
+                if (a.ht && with_t) st_plane(a.ht + kp + plane, plane, own_b, 0.0);
             }
         }
         w_km = w_kc;
