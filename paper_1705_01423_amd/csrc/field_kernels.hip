@@ -169,15 +169,15 @@ __global__ void __launch_bounds__(256) k_cn_factor(GridDev g, CnFactorJobs jobs)
 //   CN_T:   out = C^-T in, given the factors of C^T (the transpose of the solve, which
 //           also equals V C^-1 V^-1 with V = dz for centre fields, dzc for interior faces);
 //           face walls zeroed; with out2, also out2 = c2 out
-constexpr int kCnHalfRows = 512;
-typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+constexpr int kCnTiledRows = 512;   // the tallest column the tiled solve holds
+using u32x2_t = vec2_t<unsigned int>;
 template <int KZ, int MODE, bool O2 = false>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
 k_cn_tiled(GridDev g, int kind, const double* __restrict__ fac, const double* in, double* out, double* out2,
            double c2) {
-    __shared__ double bs[32][32];
-    __shared__ double pf[kCnHalfRows], pbk[kCnHalfRows];   // running slopes within each chunk
-    __shared__ double f_l[kCnHalfRows], f_d[kCnHalfRows], f_c[kCnHalfRows];
+    __shared__ double bs[32][33];   // (padded: the two halves of a wave write rows 256 B apart)
+    __shared__ double pf[kCnTiledRows], pbk[kCnTiledRows];   // running slopes within each chunk
+    __shared__ double f_l[kCnTiledRows], f_d[kCnTiledRows], f_c[kCnTiledRows];
     const size_t plane = (size_t)g.nx * g.ny;
     const int n = kind == 0 ? g.nz : g.nz - 1;
     const int ko = kind == 0 ? 0 : 1;
@@ -696,7 +696,7 @@ hipError_t launch_cn_factor(const GridDev& g, const CnFactorJobs& jobs, hipStrea
 
 hipError_t launch_cn_jobs(const GridDev& g, int mode, const CnJobs& jobs, hipStream_t st) {
     if (jobs.n < 1 || jobs.n > 4) return hipErrorInvalidValue;
-    if (g.nz <= kCnHalfRows) {
+    if (g.nz <= kCnTiledRows) {
         for (int q = 0; q < jobs.n; ++q) {
             hipError_t e;
             switch (mode) {

@@ -42,7 +42,7 @@ __device__ __forceinline__ void st_out(double* p, double v) {
 // Buffer accesses of one plane: the base (a field's plane, the same for the whole block) in
 // scalar registers and the lane's byte offset in one vector register, so that no per-access
 // 64-bit address arithmetic is spent (the plane offsets stay below 2^31 bytes).
-typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+using u32x2_t = vec2_t<unsigned int>;
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const double* base, size_t plane) {
     return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(plane * sizeof(double)), 0x00020000);
 }
