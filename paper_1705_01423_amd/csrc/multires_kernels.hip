@@ -67,18 +67,21 @@ k_mr_prolong(const double* __restrict__ u, const double* __restrict__ v, const d
     anchor(wU); anchor(wUxp); anchor(wUxm); anchor(wUyp); anchor(wUym);
     // wall-normal slopes at the coarse centre: three-point formula, the no-slip wall value 0
     // at the wall as the outer point
+    // Every quotient below divides by one of a few spacings: one reciprocal each, then
+    // products (an FP64 quotient costs about ten VALU instructions, a product one)
     const double hm = m.zhm[k], hp = m.zhp[k];
+    const double izs = 1.0 / (hm * hp * (hm + hp)), ix2 = 0.5 / g.dx, iy2 = 0.5 / g.dy;
     auto zsl = [&](double qm, double qc, double qp) {
         qm = lo ? qm : 0.0;
         qp = hi ? qp : 0.0;
-        return (hm * hm * (qp - qc) + hp * hp * (qc - qm)) / (hm * hp * (hm + hp));
+        return (hm * hm * (qp - qc) + hp * hp * (qc - qm)) * izs;
     };
-    const double syL = (uLyp - uLym) / (2 * g.dy), szL = zsl(uLzm, uL, uLzp);
-    const double syR = (uRyp - uRym) / (2 * g.dy), szR = zsl(uRzm, uR, uRzp);
-    const double sxF = (vFxp - vFxm) / (2 * g.dx), szF = zsl(vFzm, vF, vFzp);
-    const double sxB = (vBxp - vBxm) / (2 * g.dx), szB = zsl(vBzm, vB, vBzp);
-    const double sxD = (wDxp - wDxm) / (2 * g.dx), syD = (wDyp - wDym) / (2 * g.dy);
-    const double sxU = (wUxp - wUxm) / (2 * g.dx), syU = (wUyp - wUym) / (2 * g.dy);
+    const double syL = (uLyp - uLym) * iy2, szL = zsl(uLzm, uL, uLzp);
+    const double syR = (uRyp - uRym) * iy2, szR = zsl(uRzm, uR, uRzp);
+    const double sxF = (vFxp - vFxm) * ix2, szF = zsl(vFzm, vF, vFzp);
+    const double sxB = (vBxp - vBxm) * ix2, szB = zsl(vBzm, vB, vBzp);
+    const double sxD = (wDxp - wDxm) * ix2, syD = (wDyp - wDym) * iy2;
+    const double sxU = (wUxp - wUxm) * ix2, syU = (wUyp - wUym) * iy2;
     const double dzk = g.dz[k];
     double ex[RX], ey[RY], ez[RZ];
 #pragma unroll
@@ -122,18 +125,20 @@ k_mr_prolong(const double* __restrict__ u, const double* __restrict__ v, const d
     if constexpr (NS > 1) {
         // sub-cell divergences, then psi = (L_loc)^+ r and the correction -(G psi) on the
         // interior faces; sub-cell (a, b, c) has index (c RY + b) RX + a
-        const double dxf = m.dxf, dyf = m.dyf;
+        const double ixf = 1.0 / m.dxf, iyf = 1.0 / m.dyf;
+        double izf[RZ];
+#pragma unroll
+        for (int c = 0; c < RZ; ++c) izf[c] = 1.0 / m.dzf[k * RZ + c];
         double r[NS];
 #pragma unroll
         for (int c = 0; c < RZ; ++c) {
-            const double dzf = m.dzf[k * RZ + c];
 #pragma unroll
             for (int b = 0; b < RY; ++b)
 #pragma unroll
                 for (int a = 0; a < RX; ++a)
-                    r[(c * RY + b) * RX + a] = ((fu[a + 1][b][c] - fu[a][b][c]) / dxf +
-                                                (fv[a][b + 1][c] - fv[a][b][c]) / dyf) +
-                                               (fw[a][b][c + 1] - fw[a][b][c]) / dzf;
+                    r[(c * RY + b) * RX + a] = ((fu[a + 1][b][c] - fu[a][b][c]) * ixf +
+                                                (fv[a][b + 1][c] - fv[a][b][c]) * iyf) +
+                                               (fw[a][b][c + 1] - fw[a][b][c]) * izf[c];
         }
         const double* L = m.linv + (size_t)k * NS * NS;   // uniform per block: scalar loads
         double psi[NS];
@@ -150,22 +155,22 @@ k_mr_prolong(const double* __restrict__ u, const double* __restrict__ v, const d
             for (int b = 0; b < RY; ++b)
 #pragma unroll
                 for (int a = 1; a < RX; ++a)
-                    fu[a][b][c] -= (psi[(c * RY + b) * RX + a] - psi[(c * RY + b) * RX + a - 1]) / dxf;
+                    fu[a][b][c] -= (psi[(c * RY + b) * RX + a] - psi[(c * RY + b) * RX + a - 1]) * ixf;
 #pragma unroll
         for (int c = 0; c < RZ; ++c)
 #pragma unroll
             for (int b = 1; b < RY; ++b)
 #pragma unroll
                 for (int a = 0; a < RX; ++a)
-                    fv[a][b][c] -= (psi[(c * RY + b) * RX + a] - psi[(c * RY + b - 1) * RX + a]) / dyf;
+                    fv[a][b][c] -= (psi[(c * RY + b) * RX + a] - psi[(c * RY + b - 1) * RX + a]) * iyf;
 #pragma unroll
         for (int c = 1; c < RZ; ++c) {
-            const double dzc = m.dzf[k * RZ + c];   // sub-cells of one coarse cell: equal heights
+            // sub-cells of one coarse cell: equal heights, so the face spacing is the height
 #pragma unroll
             for (int b = 0; b < RY; ++b)
 #pragma unroll
                 for (int a = 0; a < RX; ++a)
-                    fw[a][b][c] -= (psi[(c * RY + b) * RX + a] - psi[((c - 1) * RY + b) * RX + a]) / dzc;
+                    fw[a][b][c] -= (psi[(c * RY + b) * RX + a] - psi[((c - 1) * RY + b) * RX + a]) * izf[c];
         }
     }
     // this cell's faces of the fine grid: its lower x, y and z coarse faces and the interior ones
