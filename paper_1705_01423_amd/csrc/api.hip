@@ -566,11 +566,43 @@ ps_status static_scratch(int device, void** out) {
     return PS_OK;
 }
 
+// The projection; pr_src (nullptr: pr) is the pressure the update starts from, so that a
+// substep can write its pressure to another buffer than the one it read.
+ps_status project_impl(ps_plan_t p, double* u, double* v, double* w, double* pr, double* phi_out, double s,
+                       double c, void* stream, ps_info* info, const double* pr_src) {
+    PS_CHECK(check_plan(p));
+    PS_CHECK(check_ptr(u, "u"));
+    PS_CHECK(check_ptr(v, "v"));
+    PS_CHECK(check_ptr(w, "w"));
+    PS_CHECK(check_ptr(pr, "p", true));
+    PS_CHECK(check_ptr(phi_out, "phi_out", true));
+    if (!(s > 0) || !std::isfinite(s)) return fail(PS_EINVAL, "s must be positive");
+    if (!(c >= 0) || !std::isfinite(c)) return fail(PS_EINVAL, "c must be non-negative");
+    hipStream_t st = (hipStream_t)stream;
+    double* phi = phi_out ? phi_out : p->phibuf;
+    ps_status r;
+    if (p->prec == PS_FP64 && !(p->flags & (PS_FLAG_CHECK_FINITE | PS_FLAG_STRICT_COMPAT))) {
+        // the divergence is formed inside the x transform and never stored
+        const DivSrc d{u, v, w, 1.0 / s, false, nullptr, 0.0};
+        r = solve_impl(p, nullptr, phi, nullptr, nullptr, st, info, &d);
+    } else {
+        // the refinement's residual (and the finiteness and compatibility checks) need the
+        // right-hand side stored
+        PS_HIP(launch_divergence(p->gd, u, v, w, p->fbuf, 1.0 / s, st), "divergence");
+        r = solve_impl(p, p->fbuf, phi, nullptr, nullptr, st, info);
+    }
+    if (r != PS_OK && r != PS_ENOTCONVERGED) return r;
+    PS_HIP(launch_project_update(p->gd, u, v, w, pr, phi, s, c, st, pr_src), "projection update");
+    return r;
+}
+
 // One substep; advance_t = false leaves T as given (its buoyancy is still applied): the
-// momentum part of a step whose temperature is advanced elsewhere.
+// momentum part of a step whose temperature is advanced elsewhere.  src (nullptr: in place)
+// names the state {u, v, w, T, p} the substep starts from; the new state is written to
+// (u, v, w, t, pr), which must not overlap src unless a field is its own source.
 ps_status substep_impl(ps_plan_t p, int l, double dt, double nu, double kappa, double* u, double* v, double* w,
                        double* t, double* pr, const double* const* h_prev, double* const* h_out, void* stream,
-                       ps_info* info, bool advance_t) {
+                       ps_info* info, bool advance_t, const double* const* src = nullptr) {
     PS_CHECK(check_plan(p));
     if (l < 1 || l > 3) return fail(PS_EINVAL, "substep index l=%d must be 1, 2 or 3", l);
     if (!(dt > 0) || !std::isfinite(dt)) return fail(PS_EINVAL, "dt must be positive");
@@ -594,12 +626,19 @@ ps_status substep_impl(ps_plan_t p, int l, double dt, double nu, double kappa, d
     double* rv = sub_field(p, 1);
     double* rw = sub_field(p, 2);
     double* rt = sub_field(p, 3);
+    if (src)
+        for (int q = 0; q < 5; ++q) PS_CHECK(check_ptr(src[q], "src[q]"));
+    const double* s_u = src ? src[0] : u;
+    const double* s_v = src ? src[1] : v;
+    const double* s_w = src ? src[2] : w;
+    const double* s_t = src ? src[3] : t;
+    const double* s_p = src ? src[4] : pr;
     SubstepArgs a{};
-    a.u = u;
-    a.v = v;
-    a.w = w;
-    a.t = t;
-    a.p = pr;
+    a.u = s_u;
+    a.v = s_v;
+    a.w = s_w;
+    a.t = s_t;
+    a.p = s_p;
     if (rho != 0.0) {
         a.hpu = h_prev[0];
         a.hpv = h_prev[1];
@@ -632,6 +671,32 @@ ps_status substep_impl(ps_plan_t p, int l, double dt, double nu, double kappa, d
     a.bka = set_form ? bka : 0.0;
     PS_HIP(launch_explicit(p->gd, a, st), "explicit terms");
     PS_HIP(substep_factors(p, bnu, bka, st), "cn factor");
+    // the set form writes q* from C q + rhs alone; the add form and an unadvanced T need the
+    // old values in the destination first
+    const size_t bc = p->npts * sizeof(double), bf = (p->npts + p->plane) * sizeof(double);
+    auto seed = [&](double* dst, const double* from, size_t bytes) -> ps_status {
+        if (dst != from) PS_HIP(hipMemcpyAsync(dst, from, bytes, hipMemcpyDeviceToDevice, st), "copy state");
+        return PS_OK;
+    };
+    if (!set_form) {
+        PS_CHECK(seed(u, s_u, bc));
+        PS_CHECK(seed(v, s_v, bc));
+        PS_CHECK(seed(w, s_w, bf));
+    }
+    if (!set_form || !advance_t) PS_CHECK(seed(t, s_t, bf));
+    // the set-form solve writes the interior rows of face fields only: their wall planes
+    // (w = 0, the wall temperatures) come from the source
+    auto seed_walls = [&](double* dst, const double* from) -> ps_status {
+        if (dst == from) return PS_OK;
+        const size_t pb = p->plane * sizeof(double), top = p->npts;
+        PS_HIP(hipMemcpyAsync(dst, from, pb, hipMemcpyDeviceToDevice, st), "copy wall plane");
+        PS_HIP(hipMemcpyAsync(dst + top, from + top, pb, hipMemcpyDeviceToDevice, st), "copy wall plane");
+        return PS_OK;
+    };
+    if (set_form) {
+        PS_CHECK(seed_walls(w, s_w));
+        if (advance_t) PS_CHECK(seed_walls(t, s_t));
+    }
     CnJobs jobs{};
     jobs.j[0] = CnJob{cn_slot(p, 0), ru, u, nullptr, 0.0, PS_CENTER};
     jobs.j[1] = CnJob{cn_slot(p, 0), rv, v, nullptr, 0.0, PS_CENTER};
@@ -639,7 +704,7 @@ ps_status substep_impl(ps_plan_t p, int l, double dt, double nu, double kappa, d
     jobs.j[3] = CnJob{cn_slot(p, 2), rt, t, nullptr, 0.0, PS_FACE};
     jobs.n = advance_t ? 4 : 3;
     PS_HIP(launch_cn_jobs(p->gd, set_form ? CN_PUT : CN_ADD, jobs, st), "cn solves");
-    return project(p, u, v, w, pr, nullptr, alp * dt, bnu, stream, info);
+    return project_impl(p, u, v, w, pr, nullptr, alp * dt, bnu, stream, info, s_p);
 }
 
 }  // namespace
@@ -875,30 +940,7 @@ ps_status poisson_solve_static(ps_plan_t p, const double* f, double* phi, void* 
 ps_status project(ps_plan_t p, double* u, double* v, double* w, double* pr, double* phi_out, double s, double c,
                   void* stream, ps_info* info) {
     PS_RANGE("project");
-    PS_CHECK(check_plan(p));
-    PS_CHECK(check_ptr(u, "u"));
-    PS_CHECK(check_ptr(v, "v"));
-    PS_CHECK(check_ptr(w, "w"));
-    PS_CHECK(check_ptr(pr, "p", true));
-    PS_CHECK(check_ptr(phi_out, "phi_out", true));
-    if (!(s > 0) || !std::isfinite(s)) return fail(PS_EINVAL, "s must be positive");
-    if (!(c >= 0) || !std::isfinite(c)) return fail(PS_EINVAL, "c must be non-negative");
-    hipStream_t st = (hipStream_t)stream;
-    double* phi = phi_out ? phi_out : p->phibuf;
-    ps_status r;
-    if (p->prec == PS_FP64 && !(p->flags & (PS_FLAG_CHECK_FINITE | PS_FLAG_STRICT_COMPAT))) {
-        // the divergence is formed inside the x transform and never stored
-        const DivSrc d{u, v, w, 1.0 / s, false, nullptr, 0.0};
-        r = solve_impl(p, nullptr, phi, nullptr, nullptr, st, info, &d);
-    } else {
-        // the refinement's residual (and the finiteness and compatibility checks) need the
-        // right-hand side stored
-        PS_HIP(launch_divergence(p->gd, u, v, w, p->fbuf, 1.0 / s, st), "divergence");
-        r = solve_impl(p, p->fbuf, phi, nullptr, nullptr, st, info);
-    }
-    if (r != PS_OK && r != PS_ENOTCONVERGED) return r;
-    PS_HIP(launch_project_update(p->gd, u, v, w, pr, phi, s, c, st), "projection update");
-    return r;
+    return project_impl(p, u, v, w, pr, phi_out, s, c, stream, info, nullptr);
 }
 
 ps_status project_adjoint(ps_plan_t p, const double* g_u, const double* g_v, const double* g_w, const double* g_p,
@@ -1192,22 +1234,20 @@ ps_status rk3_step_adjoint(ps_plan_t p, double dt, double nu, double kappa, cons
     const double* ghc[4] = {gh[0], gh[1], gh[2], gh[3]};
     const double* gh2c[4] = {gh2[0], gh2[1], gh2[2], gh2[3]};
     hipStream_t st = (hipStream_t)stream;
-    const size_t bytes_c = p->npts * sizeof(double), bytes_f = (p->npts + p->plane) * sizeof(double);
-    const size_t fb[5] = {bytes_c, bytes_c, bytes_f, bytes_f, bytes_c};
-    // forward recomputation from the stored input: states after substeps 1 and 2
+    // forward recomputation from the stored input: states after substeps 1 and 2 (each substep
+    // reads the state before it and writes the next one to its own buffers)
     Range phase("forward recomputation");
-    for (int q = 0; q < 5; ++q)
-        PS_HIP(hipMemcpyAsync(s1[q], in[q], fb[q], hipMemcpyDeviceToDevice, st), "copy state");
     ps_status worst = PS_OK;
     auto note = [&](ps_status r) {
         if (r == PS_ENOTCONVERGED && worst == PS_OK) worst = r;
         return r == PS_OK || r == PS_ENOTCONVERGED;
     };
-    ps_status r = rk3_substep(p, 1, dt, nu, kappa, s1[0], s1[1], s1[2], s1[3], s1[4], nullptr, h, stream, nullptr);
+    const double* s1c[5] = {s1[0], s1[1], s1[2], s1[3], s1[4]};
+    ps_status r = substep_impl(p, 1, dt, nu, kappa, s1[0], s1[1], s1[2], s1[3], s1[4], nullptr, h, stream, nullptr,
+                               true, in);
     if (!note(r)) return r;
-    for (int q = 0; q < 5; ++q)
-        PS_HIP(hipMemcpyAsync(s2[q], s1[q], fb[q], hipMemcpyDeviceToDevice, st), "copy state");
-    r = rk3_substep(p, 2, dt, nu, kappa, s2[0], s2[1], s2[2], s2[3], s2[4], hc, nullptr, stream, nullptr);
+    r = substep_impl(p, 2, dt, nu, kappa, s2[0], s2[1], s2[2], s2[3], s2[4], hc, nullptr, stream, nullptr, true,
+                     s1c);
     if (!note(r)) return r;
     phase.next("reverse sweep");
     // reverse sweep: substep 3 at s2, substep 2 at s1 (with the cotangent of H^2), substep 1

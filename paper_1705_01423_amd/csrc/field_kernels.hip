@@ -33,10 +33,10 @@ k_divergence(const double* __restrict__ u, const double* __restrict__ v, const d
 }
 
 // u -= s (phi_i - phi_{i-1})/dx; v likewise; interior w -= s (phi_k - phi_{k-1})/dzc_k;
-// p += phi - c Dzz phi (zero-flux walls); phi_out = phi (optional copy).
+// p = ps + phi - c Dzz phi (zero-flux walls; ps is p itself for the in-place update).
 __global__ void __launch_bounds__(256)
-k_project_update(double* __restrict__ u, double* __restrict__ v, double* __restrict__ w, double* __restrict__ p,
-                 const double* __restrict__ phi, GridDev g, double s, double c) {
+k_project_update(double* __restrict__ u, double* __restrict__ v, double* __restrict__ w, double* p,
+                 const double* ps, const double* __restrict__ phi, GridDev g, double s, double c) {
     int i, j, k;
     if (!stencil_cell(g, i, j, k)) return;
     const size_t id = ((size_t)k * g.ny + j) * g.nx + i;
@@ -52,7 +52,7 @@ k_project_update(double* __restrict__ u, double* __restrict__ v, double* __restr
     const double pkm = phi[lo ? id - plane : id];
     const double pkp = phi[hi ? id + plane : id];
     const double uo = u[id], vo = v[id], wo = w[id];
-    const double po = (p ? p : phi)[id];
+    const double po = (p ? ps : phi)[id];
     u[id] = uo - s * ((pc - pim) * (1.0 / g.dx));
     v[id] = vo - s * ((pc - pjm) * (1.0 / g.dy));
     // fm: the z gradient at face k (o = 1/dzc at interior faces); the bottom wall face keeps
@@ -595,8 +595,9 @@ hipError_t launch_divergence(const GridDev& g, const double* u, const double* v,
 }
 
 hipError_t launch_project_update(const GridDev& g, double* u, double* v, double* w, double* p, const double* phi,
-                                 double s, double c, hipStream_t st) {
-    hipLaunchKernelGGL(k_project_update, dim3(stencil_blocks(g)), dim3(kStencilBlock), 0, st, u, v, w, p, phi, g, s, c);
+                                 double s, double c, hipStream_t st, const double* p_src) {
+    hipLaunchKernelGGL(k_project_update, dim3(stencil_blocks(g)), dim3(kStencilBlock), 0, st, u, v, w, p,
+                       p_src ? p_src : p, phi, g, s, c);
     return hipGetLastError();
 }
 

@@ -238,8 +238,10 @@ bool fft_length_supported(int n);
 // Field kernels (FP64).
 hipError_t launch_divergence(const GridDev& g, const double* u, const double* v, const double* w,
                              double* f, double scale, hipStream_t st);
+// p_src: the pressure before the update (nullptr: p itself); p = p_src + phi - c Dzz phi
 hipError_t launch_project_update(const GridDev& g, double* u, double* v, double* w, double* p,
-                                 const double* phi, double s, double c, hipStream_t st);
+                                 const double* phi, double s, double c, hipStream_t st,
+                                 const double* p_src = nullptr);
 // flag[0] |= 1 when some value of p[0..n) is not finite
 hipError_t launch_nonfinite(const double* p, size_t n, unsigned* flag, hipStream_t st);
 hipError_t launch_adj_rhs(const GridDev& g, const double* gu, const double* gv, const double* gw, const double* gp,

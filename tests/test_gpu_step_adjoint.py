@@ -134,6 +134,40 @@ def test_step_adjoint_shapes(shape):
         assert rel(a, b) < 1e-11, name
 
 
+def _dzz_max(zf):
+    """Largest off-diagonal row sum of the wall-normal second difference (centre and face rows)."""
+    zf = np.asarray(zf)
+    dz = np.diff(zf)
+    nz = dz.size
+    dzc = 0.5 * (dz[:-1] + dz[1:])
+    dzw = np.concatenate([[dz[0] / 2], dzc, [dz[-1] / 2]])
+    centre = max(1 / (dzw[k] * dz[k]) + 1 / (dzw[k + 1] * dz[k]) for k in range(nz))
+    face = max(1 / (dz[k - 1] * dzc[k - 1]) + 1 / (dz[k] * dzc[k - 1]) for k in range(1, nz))
+    return max(centre, face)
+
+
+def test_step_adjoint_stiff_wall_normal():
+    """Wall-normal diffusion stiff enough that every substep's Crank-Nicolson solve takes the
+    increment form q + C^-1 rhs (beta max Dzz above 256), so that the forward recomputation's
+    substeps seed their output state from the input before the solve."""
+    banner("step adjoint stiff wall-normal diffusion")
+    g, plan = grids(8, 6, 32, precision="fp64")
+    dt, nu, ka = 2e-2, 0.2, 0.16
+    dzz = _dzz_max(g.zf)
+    alphas = (8 / 15, 2 / 15, 1 / 3)   # gamma_l + rho_l of the three substeps
+    assert min(alphas) * dt * min(nu, ka) / 2 * dzz > 256
+    state = _rb(plan, 81)
+    cot = _cot([x.shape for x in state], np.random.default_rng(82))
+    xs = [a.clone().requires_grad_(True) for a in state]
+    out = ts.rk3_step(xs, g, dt, nu, ka, differentiable=True)
+    ref = torch.autograd.grad(sum((a * b).sum() for a, b in zip(out, cot)), xs)
+    got = plan.step_adjoint(dt, nu, ka, *_cuda(state), _cuda(cot))
+    for name, a, b in zip("uvwTp", got, ref):
+        a, b = _interior(name, a, b)
+        print(f"stiff step adjoint {name}: rel {rel(a, b):.3e}", flush=True)
+        assert rel(a, b) < 1e-10, name
+
+
 def test_step_fn_and_substep_fn_finite_difference():
     """StepFn / SubstepFn backward (the hand-written adjoints) against central differences
     of the library's forward step; the map is smooth (quadratic advection), so h = 1e-4
