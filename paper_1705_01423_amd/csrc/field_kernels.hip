@@ -413,26 +413,31 @@ static hipError_t cn_tiled_launch(const GridDev& g, const CnJob& j, hipStream_t 
 }
 
 // ---- CFL (Listing 1) ------------------------------------------------------
-// A fixed grid of blocks strides over the rows; each block reduces its maximum and
-// posts it with one atomic max (non-negative doubles order like their bit patterns, and
-// every NaN pattern lies above +Inf).  The maximum propagates NaN (fmax would drop it), so
-// a non-finite velocity gives a non-finite Courant number.
+// Each block reduces the maximum over its rows and posts it with one atomic max
+// (non-negative doubles order like their bit patterns, and every NaN pattern lies above
+// +Inf).  The maximum propagates NaN (fmax would drop it), so a non-finite velocity gives a
+// non-finite Courant number.
 constexpr int kCflBlocks = 2048;
 __device__ __forceinline__ double nan_max(double q, double c) { return (c > q || c != c) ? c : q; }
-// Blocks stride over the (y, z) rows, threads along x; the loads of up to four x
-// positions per thread are issued together (clamped indices, unused values dropped).
+// Each block walks the rows of one y index upward through one segment of the z range,
+// threads along x; the loads of up to four x positions per thread are issued together
+// (clamped indices, unused values dropped).  Blocks are numbered so that neighbouring y
+// indices run on one XCD: the next-row v values a block reads are its neighbour's own row,
+// and the w row of plane k + 1 is read again by the same block at k + 1, both from that
+// XCD's L2 (each field then crosses HBM about once).
 __global__ void __launch_bounds__(256)
 k_cfl(const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w, GridDev g,
-      unsigned long long* __restrict__ out) {
+      int nseg, unsigned long long* __restrict__ out) {
     __shared__ double wmax[4];
     const size_t plane = (size_t)g.nx * g.ny;
-    const int nrows = g.ny * g.nz;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int j = blk % g.ny, seg = blk / g.ny;
+    const int jp = (j + 1 == g.ny) ? 0 : j + 1;
+    const int kb = (int)((long long)seg * g.nz / nseg), ke = (int)((long long)(seg + 1) * g.nz / nseg);
     constexpr int E = 4;
     double q = 0.0;
-    for (int r = blockIdx.x; r < nrows; r += gridDim.x) {
-        const int k = r / g.ny, j = r - k * g.ny;
-        const int jp = (j + 1 == g.ny) ? 0 : j + 1;
-        const size_t rb = (size_t)r * g.nx, rn = ((size_t)k * g.ny + jp) * g.nx;
+    for (int k = kb; k < ke; ++k) {
+        const size_t rb = ((size_t)k * g.ny + j) * g.nx, rn = ((size_t)k * g.ny + jp) * g.nx;
         const double dzk = g.dz[k];
         for (int i0 = threadIdx.x; i0 < g.nx; i0 += E * blockDim.x) {
             double uc[E], un[E], vc[E], vn[E], wb[E], wt[E];
@@ -744,8 +749,12 @@ hipError_t launch_cfl(const GridDev& g, const double* u, const double* v, const 
                       hipStream_t st) {
     hipError_t e = launch_fill(out, 1, 1e-8, st);
     if (e != hipSuccess) return e;
-    const int nb = (int)std::min<size_t>((size_t)kCflBlocks, (size_t)g.ny * g.nz);
-    hipLaunchKernelGGL(k_cfl, dim3(nb), dim3(256), 0, st, u, v, w, g, reinterpret_cast<unsigned long long*>(out));
+    // z segments per y index: about kCflBlocks blocks in all (one resident round of 256-thread
+    // blocks), at least one and at most nz
+    const int nseg = std::max(1, std::min(g.nz, kCflBlocks / g.ny));
+    const int nb = g.ny * nseg;
+    hipLaunchKernelGGL(k_cfl, dim3(nb), dim3(256), 0, st, u, v, w, g, nseg,
+                       reinterpret_cast<unsigned long long*>(out));
     return hipGetLastError();
 }
 
