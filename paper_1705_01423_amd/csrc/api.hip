@@ -570,6 +570,7 @@ ps_status static_scratch(int device, void** out) {
 // substep can write its pressure to another buffer than the one it read.
 ps_status project_impl(ps_plan_t p, double* u, double* v, double* w, double* pr, double* phi_out, double s,
                        double c, void* stream, ps_info* info, const double* pr_src) {
+    PS_RANGE("project");
     PS_CHECK(check_plan(p));
     PS_CHECK(check_ptr(u, "u"));
     PS_CHECK(check_ptr(v, "v"));
@@ -939,7 +940,6 @@ ps_status poisson_solve_static(ps_plan_t p, const double* f, double* phi, void* 
 
 ps_status project(ps_plan_t p, double* u, double* v, double* w, double* pr, double* phi_out, double s, double c,
                   void* stream, ps_info* info) {
-    PS_RANGE("project");
     return project_impl(p, u, v, w, pr, phi_out, s, c, stream, info, nullptr);
 }
 
