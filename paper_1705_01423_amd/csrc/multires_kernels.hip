@@ -32,13 +32,13 @@ __device__ __forceinline__ double sub_offset(int b, double h) {
     return ((b + 0.5) / R - 0.5) * h;
 }
 
+// The fine faces of momentum cell (i, j, k).
 template <int RX, int RY, int RZ>
-__global__ void __launch_bounds__(kStencilBlock)
-k_mr_prolong(const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w,
-             double* __restrict__ uf, double* __restrict__ vf, double* __restrict__ wf, GridDev g, MrDev m) {
+__device__ __forceinline__ void prolong_cell(const double* __restrict__ u, const double* __restrict__ v,
+                                             const double* __restrict__ w, double* __restrict__ uf,
+                                             double* __restrict__ vf, double* __restrict__ wf, const GridDev& g,
+                                             const MrDev& m, int i, int j, int k) {
     constexpr int NS = RX * RY * RZ;
-    int i, j, k;
-    if (!stencil_cell(g, i, j, k)) return;
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     const size_t plane = (size_t)nx * ny;
     const int im = (i == 0) ? nx - 1 : i - 1, ip = (i + 1 == nx) ? 0 : i + 1;
@@ -195,6 +195,24 @@ k_mr_prolong(const double* __restrict__ u, const double* __restrict__ v, const d
             for (int a = 0; a < RX; ++a) mr_st(wf + row + a, fw[a][b][RZ]);
         }
     }
+}
+
+// One block per run of kMrPx consecutive x of one (y, z) row of momentum cells, one thread per
+// cell (128-thread runs leave no thread idle at nx = 384 or 768, where 256-thread runs left a
+// quarter idle); neighbouring y rows of one z level are numbered to run on one XCD.
+constexpr int kMrPx = 128;
+template <int RX, int RY, int RZ>
+__global__ void __launch_bounds__(kMrPx)
+k_mr_prolong(const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w,
+             double* __restrict__ uf, double* __restrict__ vf, double* __restrict__ wf, GridDev g, MrDev m) {
+    int r = xcd_remap(blockIdx.x, gridDim.x);
+    const int nxs = (g.nx + kMrPx - 1) / kMrPx;
+    const int xs = r % nxs;
+    r /= nxs;
+    const int j = r % g.ny, k = r / g.ny;
+    const int i = xs * kMrPx + (int)threadIdx.x;
+    if (i >= g.nx) return;
+    prolong_cell<RX, RY, RZ>(u, v, w, uf, vf, wf, g, m, i, j, k);
 }
 
 // tc[k][j][i] = mean of tf[rz k][ry j + b][rx i + a], k = 0..nz (one thread per coarse face point)
@@ -378,7 +396,8 @@ bool mr_factors_supported(int rx, int ry, int rz) {
 
 hipError_t launch_mr_prolong(const GridDev& g, const MrDev& m, const double* u, const double* v, const double* w,
                              double* uf, double* vf, double* wf, hipStream_t st) {
-    const dim3 grid(stencil_blocks(g)), block(kStencilBlock);
+    const int nxs = (g.nx + kMrPx - 1) / kMrPx;
+    const dim3 grid((unsigned)nxs * (unsigned)g.ny * (unsigned)g.nz), block(kMrPx);
 #define PS_MR_CASE(X, Y, Z)                                                                          \
     if (m.rx == X && m.ry == Y && m.rz == Z) {                                                       \
         hipLaunchKernelGGL((k_mr_prolong<X, Y, Z>), grid, block, 0, st, u, v, w, uf, vf, wf, g, m); \
