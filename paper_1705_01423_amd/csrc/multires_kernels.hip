@@ -271,8 +271,13 @@ __global__ void __launch_bounds__(kMtTX * kMtTY) k_mr_explicit_t(MrTArgs a, Grid
     const int i = i0 + R.tx, j = j0 + R.ty;
     const bool valid = i < g.nx && j < g.ny;
     const size_t plane = (size_t)g.nx * g.ny;
-    // periodic column offsets of this thread's halo cells (the same for every plane)
+    // periodic column offsets of this thread's halo cells (the same for every plane), and which
+    // of them each velocity component is read at: u at x offsets 0 and +1 of its own row, v at
+    // y offsets 0 and +1 of its own column, w in its own column only (T at every halo cell).
+    // The others are not loaded (their ring entries stay zero and are never read), so that the
+    // cache lines only the halo touches are fetched for T alone.
     unsigned off[NQ];
+    bool need_u[NQ], need_v[NQ], need_w[NQ];
 #pragma unroll
     for (int qi = 0; qi < NQ; ++qi) {
         const int q = min((int)threadIdx.x + qi * TX * TY, PL - 1);
@@ -281,6 +286,10 @@ __global__ void __launch_bounds__(kMtTX * kMtTY) k_mr_explicit_t(MrTArgs a, Grid
         gj = gj < 0 ? gj + g.ny : gj % g.ny;
         gi = gi < 0 ? gi + g.nx : gi % g.nx;
         off[qi] = (unsigned)gj * (unsigned)g.nx + (unsigned)gi;
+        const bool in_x = hx >= 1 && hx <= TX, in_y = hy >= 1 && hy <= TY;
+        need_u[qi] = in_y && hx >= 1;
+        need_v[qi] = in_x && hy >= 1;
+        need_w[qi] = in_x && in_y;
     }
     const double th = a.th, th1 = 1.0 - a.th;
     // plane kk of every field into registers, both velocity time levels as loaded; put()
@@ -297,12 +306,19 @@ __global__ void __launch_bounds__(kMtTX * kMtTY) k_mr_explicit_t(MrTArgs a, Grid
 #pragma unroll
         for (int qi = 0; qi < NQ; ++qi) {
             const size_t oc = pc + off[qi], of = pf + off[qi];
-            s0[qi][FU] = a.u0[oc];
-            s1[qi][FU] = a.u1[oc];
-            s0[qi][FV] = a.v0[oc];
-            s1[qi][FV] = a.v1[oc];
-            s0[qi][FW] = a.w0[of];
-            s1[qi][FW] = a.w1[of];
+            s0[qi][FU] = s1[qi][FU] = s0[qi][FV] = s1[qi][FV] = s0[qi][FW] = s1[qi][FW] = 0.0;
+            if (need_u[qi]) {
+                s0[qi][FU] = a.u0[oc];
+                s1[qi][FU] = a.u1[oc];
+            }
+            if (need_v[qi]) {
+                s0[qi][FV] = a.v0[oc];
+                s1[qi][FV] = a.v1[oc];
+            }
+            if (need_w[qi]) {
+                s0[qi][FW] = a.w0[of];
+                s1[qi][FW] = a.w1[of];
+            }
             stt[qi] = a.t[of];
         }
     };
