@@ -235,12 +235,13 @@ k_mr_restrict(const double* __restrict__ tf, double* __restrict__ tc, int nx, in
 }
 
 // ---- explicit terms of the temperature equation on its own grid ------------------------
-// z-marching over 32 x 8 column tiles with a three-plane LDS ring of u, v, w, T (the velocity
+// z-marching over 64 x 4 column tiles with a three-plane LDS ring of u, v, w, T (the velocity
 // staged as (1 - th) vel0 + th vel1), as in k_explicit.  Writes the Crank-Nicolson input
 // rt = C T + dt [gamma H + rho Hprev + alpha kappa Dzz T] on interior faces (C = I - bka Dzz~,
 // Dzz~ with zero wall values; walls 0, never read by the solve), or the bracket alone when
 // cq = 0 (bka is then 0 too), and H (optional).
-constexpr int kMtTX = 32, kMtTY = 8, kMtZSEG = 64;
+// (64 x 4 against 32 x 8 and 16 x 16 for the coupled step at 768^2 x 512: 48.9 / 49.4 / 51.5 ms)
+constexpr int kMtTX = 64, kMtTY = 4, kMtZSEG = 64;
 
 template <int NF, int TX, int TY>
 struct MtRing {
