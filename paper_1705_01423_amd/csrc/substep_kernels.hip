@@ -561,6 +561,19 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
     // that every load of the stage stays in flight together
     double sgh[NQ][4];
     bool sok[NF];   // whether the staged plane exists, per field (uniform)
+    // Which halo cells each state field is read at (the stencil below): T and w at x and y
+    // offsets -1 and 0 only, u at y offsets -1 and 0, v at x offsets -1 and 0; lambda and gH
+    // at the whole cross.  The others are not loaded (their ring entries are never read), so
+    // that cache lines only an unread halo side touches are not fetched.
+    bool need_lo[NQ], need_u[NQ], need_v[NQ];
+#pragma unroll
+    for (int qi = 0; qi < NQ; ++qi) {
+        const int q = min((int)threadIdx.x + qi * TX * TY, (TX + 2) * (TY + 2) - 1);
+        const int hy = q / (TX + 2), hx = q - hy * (TX + 2);
+        need_u[qi] = hy <= TY;
+        need_v[qi] = hx <= TX;
+        need_lo[qi] = hx <= TX && hy <= TY;
+    }
     auto fetch = [&](int kk, typename RingT::Stage& st) {
         const int kc = kk < 0 ? 0 : (kk > nz - 1 ? nz - 1 : kk);
         const int kf = kk < 0 ? 0 : (kk > nz ? nz : kk);
@@ -570,7 +583,10 @@ __global__ void __launch_bounds__(kAdTX * kAdTY) k_explicit_adj(SubstepAdjArgs a
             const size_t po = (size_t)(face[f] ? kf : kc) * plane;
 #pragma unroll
             for (int qi = 0; qi < NQ; ++qi) {
-                st.v[qi][f] = F[f][po + cols.off[qi]];
+                const bool need = f == FU ? need_u[qi] : (f == FV ? need_v[qi] : (f <= FT ? need_lo[qi] : true));
+                double x = 0.0;
+                if (need) x = F[f][po + cols.off[qi]];
+                st.v[qi][f] = x;
                 if (f >= FMU) sgh[qi][f - FMU] = with_gh ? GH[f - FMU][po + cols.off[qi]] : 0.0;
             }
         }
